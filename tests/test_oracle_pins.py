@@ -1,0 +1,342 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test ties an oracle function to something other than itself: a second
+independent construction, a closed form, a printed value of the paper, a
+brute-force count, or an invariant the paper states.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gbs, operators, dense, mpo, mps as M, dmrg, flops
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _small_problem(N=3, seed=0, r=(0.5, 0.3, 0.7)):
+    U = W.haar_unitary(N, np.random.default_rng(seed))
+    return np.array(r[:N], dtype=float), U
+
+
+# --------------------------------------------------------------- Hamiltonian
+@pytest.mark.parametrize("D", [3, 4])
+def test_quadrature_form_equals_bogoliubov_form(D):
+    """eq. GBSHamiltonian (quadratures) == eq. CentralEquation (sum b^dag b)."""
+    r, U = _small_problem()
+    al, be, ga = gbs.coefficients(r, U)
+    Hq = dense.php_quadrature(al, be, ga, D)
+    Hb = dense.php_bogoliubov(r, U, D)
+    assert np.abs(Hq - Hb).max() < 1e-12
+
+
+def test_hamiltonian_annihilates_output_state():
+    """H|psi> = 0 (eq. CentralEquation): H built on a (D+2)-box, applied to the
+    exact amplitudes, vanishes on the inner D-box (H moves each n_k by <= 2)."""
+    r, U = _small_problem()
+    al, be, ga = gbs.coefficients(r, U)
+    D = 4
+    H = dense.php_quadrature(al, be, ga, D + 2)
+    psi = gbs.exact_amplitudes(r, U, D + 2).reshape(-1)
+    res = (H @ psi).reshape((D + 2,) * 3)[:D, :D, :D]
+    assert np.abs(res).max() < 1e-12
+    assert np.abs(psi).max() > 0.1
+
+
+def test_commutator_defect_golden():
+    """SM Sec. 5 prints [X, P] = i diag(1, ..., 1, 1-D) for D x D matrices."""
+    for line in open(os.path.join(GOLD, "commutator_defect.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        vals = [float(v) for v in line.split()]
+        D, diag = int(vals[0]), np.array(vals[1:])
+        X, P = operators.quadratures(D)
+        C = X @ P - P @ X
+        assert np.abs(C - 1j * np.diag(diag)).max() < 1e-12
+
+
+def test_local_square_uses_d_plus_4():
+    """SM Sec. 5: X^2 built at D+4 then truncated equals the exact compression
+    P X^2 P (tridiagonal band of the infinite matrix), unlike (PXP)^2."""
+    D = 5
+    Xb, _ = operators.quadratures(D + 4)
+    X, _, S = operators.local_operators(D, 2.0, 0.0, 0.0)
+    # S = 1/2 * 2 X^2 - 1/2 -> X^2 = S + 1/2
+    X2 = S + 0.5 * np.eye(D)
+    exact = np.zeros((D, D))
+    for n in range(D):
+        exact[n, n] = n + 0.5
+        if n + 2 < D:
+            exact[n, n + 2] = exact[n + 2, n] = 0.5 * math.sqrt((n + 1) * (n + 2))
+    assert np.abs(X2 - exact).max() < 1e-13
+    assert np.abs((X @ X) - exact).max() > 0.1   # the naive square differs
+
+
+# --------------------------------------------------------------- amplitudes
+def test_recursion_matches_hafnian():
+    """Amplitude recursion == brute-force hafnian <n|psi> (Sec. II.A)."""
+    for N, r in ((3, (0.5, 0.3, 0.7)), (4, (0.4, 0.6, 0.5, 0.8))):
+        r_, U = _small_problem(N, seed=N, r=r)
+        psi = gbs.exact_amplitudes(r_, U, 4)
+        rng = np.random.default_rng(7)
+        checked = 0
+        for _ in range(40):
+            n = tuple(int(v) for v in rng.integers(0, 4, N))
+            if sum(n) > 10:
+                continue
+            h = gbs.amplitude_hafnian(n, r_, U)
+            assert abs(psi[n] - h) < 1e-12
+            checked += 1
+        assert checked > 20
+
+
+def test_single_mode_closed_form():
+    """N = 1: P(2n) = (2n)!/(4^n n!^2) tanh^{2n} r / cosh r, P(odd) = 0; ED of
+    the truncated single-mode H at D = 40 gives E0 ~ 0 and the same vector."""
+    r = np.array([0.5])
+    U = np.eye(1, dtype=complex)
+    psi = gbs.exact_amplitudes(r, U, 30)
+    P = np.abs(psi) ** 2
+    Pc = gbs.single_mode_probabilities(0.5, 30)
+    assert np.abs(P - Pc).max() < 1e-14
+    assert abs(psi[2] / psi[0] - (-math.tanh(0.5)) * math.sqrt(2) / 2) < 1e-14
+    al, be, ga = gbs.coefficients(r, U)
+    H = dense.php_quadrature(al, be, ga, 40)
+    ev, vec = dense.ground_states(H, 4)
+    assert abs(ev[0]) < 1e-11
+    # harmonic spectrum (eq. generalizedCCR): 0, 1, 2, 3
+    assert np.abs(ev - np.arange(4)).max() < 1e-7   # truncation raises them slightly
+    v = vec[:, 0] * np.sign(vec[0, 0].real)
+    assert np.abs(np.abs(v[:30]) ** 2 - Pc).max() < 1e-11
+
+
+# --------------------------------------------------------------- MPO
+def test_mpo_bond_dimensions_and_boundary_cores():
+    """SM Sec. 8: w_s = 2 + 2 min(s, N-s); boundary cores as printed."""
+    gold = {}
+    for line in open(os.path.join(GOLD, "mpo_boundary_cores.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        gold[k] = [int(x) for x in v]
+    for N in range(2, 12):
+        w, kinds = mpo.structure(N)
+        assert w[0] == 1 and w[N] == 1
+        for s in range(1, N):
+            assert w[s] == 2 + 2 * min(s, N - s)
+        # L_1 = (X_1, P_1, 1, S_1): row S of core 1 over columns X_1, P_1, S, F
+        if N >= 3:
+            assert list(kinds[0][0]) == gold["L1"]
+        # R_N^T = (X_N, P_N, 1, S_N): column F of core N over rows Xw_N, Pw_N, F, S
+        if N >= 2:
+            assert list(kinds[N - 1][:, 0]) == gold["RN"]
+
+
+@pytest.mark.parametrize("N,D", [(1, 5), (2, 4), (3, 4), (4, 3), (5, 3)])
+def test_mpo_contracts_to_php(N, D):
+    """The MPO (SM Sec. 8) contracts to the dense PHP of eq. GBSHamiltonian,
+    including the paper's worked N = 5 case."""
+    U = W.haar_unitary(N, np.random.default_rng(N + 10))
+    r = np.linspace(0.3, 0.8, N)
+    al, be, ga = gbs.coefficients(r, U)
+    ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+    Hm = mpo.to_dense(mpo.cores(al, be, ga, ops))
+    Hq = dense.php_quadrature(al, be, ga, D)
+    assert np.abs(Hm - Hq).max() < 1e-12
+
+
+def test_mpo_vacuum_is_number_operator():
+    """r = 0: H = sum_k a_k^dag a_k for any interferometer (Sec. II.C.1,
+    H_|0>): the MPO contracts to diag(sum n) with integer entries."""
+    N, D = 4, 3
+    U = W.haar_unitary(N, np.random.default_rng(3))
+    al, be, ga = gbs.coefficients(np.zeros(N), U)
+    ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+    Hm = mpo.to_dense(mpo.cores(al, be, ga, ops))
+    n = np.indices((D,) * N).reshape(N, -1).sum(0)
+    assert np.abs(Hm - np.diag(n)).max() < 1e-12
+
+
+def test_mpo_kind_table_is_positional():
+    """U = identity makes every cross coefficient vanish; the kind table is
+    unchanged (a zero coefficient never removes a block)."""
+    N = 6
+    w, kinds = mpo.structure(N)
+    al, be, ga = gbs.coefficients(np.full(N, 0.4), np.eye(N, dtype=complex))
+    for s in range(1, N + 1):
+        rows, cols, E = mpo.core_entries(N, s, al, be, ga)
+        K = np.zeros((len(rows), len(cols)), dtype=np.int8)
+        for (rl, cl), (kind, _, _) in E.items():
+            K[rows.index(rl), cols.index(cl)] = kind
+        assert np.array_equal(K, kinds[s - 1])
+
+
+def test_core_counts():
+    N = 9
+    m = mpo.middle_site(N)
+    w, kinds = mpo.structure(N)
+    for s in range(1, N + 1):
+        n_op, n_sc = flops.core_counts(kinds[s - 1])
+        if s < m:
+            assert (n_op, n_sc) == (2 * s + 1, 0)
+        elif s == m:
+            assert (n_op, n_sc) == (1 + 2 * (m - 1) + 2 * (N - m), 4 * (m - 1) * (N - m))
+        else:
+            assert (n_op, n_sc) == (2 * (N - s) + 3, 0)
+
+
+# --------------------------------------------------------------- ED + truncation
+def _cfg_n4():
+    r, U = W.workload_problem("gbs_n4_d6_chi16")
+    return r, U, gbs.coefficients(r, U)
+
+
+def test_ed_truncation_properties():
+    """SM Sec. 1 and Sec. II.E: E0 >= 0, non-increasing in D (interlacing),
+    matches the oracle-written golden values, E0 <= <Ppsi|H|Ppsi>/|Ppsi|^2,
+    F >= 1 - E0, and the ground state has even total photon number."""
+    r, U, (al, be, ga) = _cfg_n4()
+    gold = {}
+    for line in open(os.path.join(GOLD, "cfg_n4_ed.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        D, e = line.split()
+        gold[int(D)] = float(e)
+    prev = np.inf
+    for D in (3, 4, 5, 6):
+        H = dense.php_quadrature(al, be, ga, D)
+        ev, vec = dense.ground_states(H, 2)
+        assert ev[0] >= -1e-12
+        assert ev[0] <= prev + 1e-12
+        prev = ev[0]
+        assert abs(ev[0] - gold[D]) < 1e-10
+    psiP = gbs.exact_amplitudes(r, U, 6).reshape(-1)
+    ray = float(np.vdot(psiP, H @ psiP).real / np.vdot(psiP, psiP).real)
+    assert ev[0] <= ray
+    F = abs(np.vdot(psiP, vec[:, 0])) ** 2
+    assert F >= 1 - ev[0]
+    n = np.indices((6,) * 4).reshape(4, -1).sum(0)
+    assert np.sum(np.abs(vec[n % 2 == 1, 0]) ** 2) < 1e-20
+    # first excitation near 1 (harmonic spectrum, raised by truncation)
+    assert 0.99 < ev[1] < 1.2
+
+
+# --------------------------------------------------------------- DMRG
+def _cfg_n4_mpo(D=6):
+    r, U, (al, be, ga) = _cfg_n4()
+    ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(4)]
+    return r, U, mpo.cores(al, be, ga, ops), dense.php_quadrature(al, be, ga, D)
+
+
+def test_dmrg_full_rank_matches_ed():
+    """chi = 36 is the full Schmidt rank for N = 4, D = 6: two-site DMRG
+    reaches the ED ground energy and distribution (Sec. II.D, II.E)."""
+    r, U, Ws, H = _cfg_n4_mpo()
+    ev, vec = dense.ground_states(H, 1)
+    m0 = W.random_mps(4, 6, 36, 1000)
+    out, st = dmrg.dmrg(m0, Ws, 36, 3, tol=1e-12)
+    assert abs(st[-1]["energy"] - ev[0]) < 1e-12
+    P = M.probabilities(out)
+    assert np.abs(P - np.abs(vec[:, 0]) ** 2).max() < 1e-12
+
+
+def test_dmrg_truncated_is_variational():
+    """chi = 16: E_DMRG >= E_ED, the excess bounded by 50x the ED discarded
+    Schmidt weight at the middle cut (eq. SurrogateEpsChi), sweep energies
+    non-increasing up to the discarded weight."""
+    r, U, Ws, H = _cfg_n4_mpo()
+    ev, vec = dense.ground_states(H, 1)
+    sv = np.linalg.svd(vec[:, 0].reshape(36, 36), compute_uv=False)
+    tail = float(np.sum(sv[16:] ** 2))
+    m0 = W.random_mps(4, 6, 16, 1000)
+    out, st = dmrg.dmrg(m0, Ws, 16, 4, tol=1e-12)
+    E = st[-1]["energy"]
+    assert E >= ev[0] - 1e-12
+    assert E - ev[0] <= 50 * tail
+    for a, b in zip(st, st[1:]):
+        assert b["energy"] <= a["energy"] + max(a["max_discarded"], 1e-12)
+
+
+def test_dmrg_vacuum_product_state():
+    """r = 0: the vacuum is exact at chi = 1 with <H> = 0."""
+    N, D = 5, 4
+    U = W.haar_unitary(N, np.random.default_rng(5))
+    al, be, ga = gbs.coefficients(np.zeros(N), U)
+    ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+    Ws = mpo.cores(al, be, ga, ops)
+    m0 = W.random_mps(N, D, 1, 3)
+    out, st = dmrg.dmrg(m0, Ws, 1, 2, tol=1e-13)
+    assert abs(st[-1]["energy"]) < 1e-12
+
+
+def test_energy_two_ways():
+    """<H> by environment contraction == sum_k ||b_k psi||^2 (eq.
+    CentralEquation as a sum of squares); both non-negative."""
+    r, U = _small_problem()
+    al, be, ga = gbs.coefficients(r, U)
+    D = 4
+    ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(3)]
+    Ws = mpo.cores(al, be, ga, ops)
+    for seed in (1, 2):
+        m = W.random_mps(3, D, 8, seed)
+        e1 = dmrg.energy(m, Ws)
+        e2 = dmrg.energy_bogoliubov(m, r, U, D)
+        assert e1 > 0 and e2 > 0
+        assert abs(e1 - e2) < 1e-12 * max(1.0, abs(e1))
+
+
+def test_fidelity_bound_from_energy():
+    """F >= 1 - <H> (Sec. II.E) for DMRG states of the full-space H."""
+    r, U, Ws, H = _cfg_n4_mpo()
+    m0 = W.random_mps(4, 6, 16, 1000)
+    out, st = dmrg.dmrg(m0, Ws, 16, 2, tol=1e-12)
+    c = M.to_dense(out)
+    c = c / np.linalg.norm(c)
+    psi = gbs.exact_amplitudes(r, U, 6).reshape(-1)
+    F = abs(np.vdot(psi, c)) ** 2
+    assert F >= 1 - st[-1]["energy"]
+
+
+def test_marginals_match_dense():
+    r, U, Ws, H = _cfg_n4_mpo(D=4)
+    m = W.random_mps(4, 4, 8, 11)
+    P = np.abs(M.to_dense(m)) ** 2
+    P = (P / P.sum()).reshape((4,) * 4)
+    marg = M.marginals(m)
+    for j in range(4):
+        axes = tuple(a for a in range(4) if a != j)
+        assert np.abs(marg[j] - P.sum(axis=axes)).max() < 1e-13
+
+
+def test_lanczos_matches_eigh():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((60, 60)) + 1j * rng.standard_normal((60, 60))
+    A = A + A.conj().T
+    lam, x, k, conv = dmrg.lanczos_lowest(lambda v: A @ v, rng.standard_normal(60) + 0j, tol=1e-12)
+    assert conv
+    assert abs(lam - np.linalg.eigvalsh(A)[0]) < 1e-10
+    assert np.linalg.norm(A @ x - lam * x) < 1e-10
+
+
+# --------------------------------------------------------------- flops
+def test_flop_formula_counts_naive_contraction():
+    """The matvec formula equals the multiply-adds of the naive 4-stage
+    contraction (L, W_s, W_{s+1}, R) with identity blocks free and scalar
+    blocks costing one multiply per element, counted by explicit loops."""
+    N = 5
+    w, kinds = mpo.structure(N)
+    d, cl, cr = 3, 4, 5
+    for s in range(1, N):
+        Ks, Ks1 = kinds[s - 1], kinds[s]
+        wl, wr = w[s - 1], w[s + 1]
+        macs = wl * cl * cl * d * d * cr          # L x theta
+        for K in (Ks, Ks1):
+            for v in K.reshape(-1):
+                if 2 <= v <= 5:
+                    macs += d * d * d * cl * cr   # d x d operator on one leg
+                elif v == 6:
+                    macs += d * d * cl * cr
+        macs += wr * cl * d * d * cr * cr         # x R
+        assert flops.matvec_flops(d, cl, cr, wl, wr, Ks, Ks1) == 8 * macs
