@@ -1,0 +1,221 @@
+/* tn.h -- C ABI of the gfx950 two-site DMRG library for the parent Hamiltonian
+ * of Gaussian boson sampling (Vinther & Kastoryano, "Variational Tensor Network
+ * Simulation of Gaussian Boson Sampling and Beyond", arXiv 2410.18740).
+ *
+ * The output state |psi> = U V |0> of a squeezer bank V (per-mode squeezing r_j)
+ * followed by an interferometer U is the unique zero-energy ground state of the
+ * positive semidefinite H = sum_n A_n^dag A_n (Sec. II.B, eq. CentralEquation);
+ * for GBS, H = x^T (V^{-1}/4) x - N/2 in quadratures (Sec. II.C.1, eq.
+ * GBSHamiltonian).  The library writes the compression PHP of H onto a Fock box
+ * (Sec. II.E.1) as the middle-site MPO of SM Sec. 8, optionally in an optimised
+ * local basis (Sec. III.A, SM Sec. 6), and finds its ground state variationally
+ * with two-site DMRG on one MI355X.  <H> >= 0 is the simulation error
+ * (eq. MagOfSimError).
+ *
+ * Conventions: hbar = 1; a = (X + iP)/sqrt(2); quadrature order (X_1..X_N,
+ * P_1..P_N); the interferometer acts as a_j -> sum_k U_jk a_k; D = diag(e^{-r},
+ * e^{r}) so r > 0 squeezes X.  Complex numbers are interleaved (re, im) doubles.
+ * All arrays are row-major.  Site and bond indices in this header are 0-based.
+ *
+ * Ownership and threading: the caller owns every array it passes; inputs are
+ * copied during the call.  Handles own their device memory until *_destroy.
+ * Device memory comes from the context allocator (hipMalloc when none is given).
+ * Work is enqueued on the context's HIP stream; calls that return host values
+ * synchronise that stream.  A context is not thread-safe: use one per thread.
+ *
+ * Errors: every function returns tn_status.  Invalid arguments are rejected
+ * before any work, with no side effects, and tn_last_error() describes them.
+ */
+#ifndef TN_H
+#define TN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tn_status;
+#define TN_OK 0
+#define TN_EINVAL (-1)   /* invalid argument; nothing was done */
+#define TN_ENOMEM (-2)   /* allocation failed; the handle stays valid */
+#define TN_EHIP (-3)     /* a HIP runtime call failed */
+#define TN_ENUMERIC (-4) /* NaN/Inf met; the MPS is left at the last completed step */
+#define TN_ESTATE (-5)   /* handle in the wrong state for this call */
+
+enum { TN_FP64 = 0, TN_FP32 = 1, TN_BF16X3 = 2 };
+
+typedef struct tn_ctx tn_ctx;
+typedef struct tn_mpo tn_mpo;
+typedef struct tn_mps tn_mps;
+typedef struct tn_mlp tn_mlp;
+
+/* Device allocator hooks.  alloc(bytes, user) returns device memory or NULL;
+ * free(ptr, user) releases it.  Used for every device allocation of the
+ * context and its handles (PyTorch's caching allocator from the binding). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} tn_allocator;
+
+/* Library version string (static storage). */
+const char* tn_version(void);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  alloc may be NULL. */
+tn_status tn_ctx_create(int device, void* hip_stream, const tn_allocator* alloc, tn_ctx** out);
+void tn_ctx_destroy(tn_ctx* ctx);
+/* Message of the last failing call on this context ("" if none). */
+const char* tn_last_error(const tn_ctx* ctx);
+
+/* ------------------------------------------------------------------ problem / MPO
+ * Sec. II.C.1: per-mode squeezing r_j and interferometer U define
+ * V = 1/2 O D^2 O^T; SM Sec. 8: alpha, beta, gamma = halves of the blocks of
+ * V^{-1}.  Local quadratic operators are built at D_raw + 4 and truncated to
+ * D_raw (SM Sec. 5), so the MPO is exactly PHP.  With a local basis
+ * (d < D_raw, or iso given) each site operator O becomes W_s^dag O W_s. */
+typedef struct {
+  int32_t N;          /* modes = sites, N >= 1 */
+  int32_t D_raw;      /* Fock cutoff: levels 0..D_raw-1, 1 <= D_raw <= 64 */
+  int32_t d;          /* local basis size, 1 <= d <= D_raw (d == D_raw: Fock basis) */
+  const double* r;    /* [N] host, finite */
+  const double* U;    /* [N*N*2] host, interleaved complex, unitary to 1e-10 */
+  const double* iso;  /* NULL (initial basis = first d Fock states, SM Sec. 6) or
+                         [N][D_raw][d] complex host isometries, W^dag W = I to 1e-10 */
+} tn_problem;
+
+tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** out);
+/* Integer structure: w[N+1] bond dimensions; kinds (may be NULL) receives the
+ * concatenated per-site kind tables (w[s] x w[s+1], row-major): 0 absent,
+ * 1 identity, 2 X, 3 P, 4 S_s, 5 c_X X + c_P P, 6 scalar * identity. */
+tn_status tn_mpo_structure(const tn_mpo* mpo, int32_t* w, int8_t* kinds);
+/* Coefficients alpha, beta, gamma (each N*N doubles; any pointer may be NULL). */
+tn_status tn_mpo_coefficients(const tn_mpo* mpo, double* alpha, double* beta, double* gamma);
+/* Current isometries [N][D_raw][d] complex (host). */
+tn_status tn_mpo_isometries(const tn_mpo* mpo, double* iso);
+/* Local operators of site s in the current basis: [3][d][d] complex (X, P, S). */
+tn_status tn_mpo_site_ops(const tn_mpo* mpo, int32_t site, double* ops);
+void tn_mpo_destroy(tn_mpo* mpo);
+
+/* ------------------------------------------------------------------ MPS
+ * Open-boundary MPS (Sec. II.D, eq. MPSAnsatz), site tensors A_s of shape
+ * (chi_s, d, chi_{s+1}), chi_0 = chi_N = 1, stored FP64 on the device.
+ * bond_dims[N+1]; init = host complex128 tensors concatenated in site order. */
+tn_status tn_mps_create(tn_ctx* ctx, int32_t N, int32_t d, const int32_t* bond_dims, const double* init,
+                        tn_mps** out);
+tn_status tn_mps_bond_dims(const tn_mps* mps, int32_t* bond_dims);
+/* Copy all site tensors to host (complex128, concatenated).  cap in doubles;
+ * *needed receives the required size (call with host_buf = NULL to query). */
+tn_status tn_mps_export(tn_ctx* ctx, const tn_mps* mps, double* host_buf, size_t cap, size_t* needed);
+/* Right-canonicalise (sites N-1..1) and normalise; orthogonality centre at 0. */
+tn_status tn_mps_canonicalize(tn_ctx* ctx, tn_mps* mps);
+void tn_mps_destroy(tn_mps* mps);
+
+/* ------------------------------------------------------------------ DMRG sweep
+ * One sweep = left-to-right over windows (0,1)..(N-2,N-1), then right-to-left,
+ * i.e. 2(N-1) two-site updates.  Each update: theta = A_s A_{s+1}; lowest
+ * eigenpair of H_eff by Lanczos (FP64 vectors, full re-orthogonalisation, H_eff
+ * applied in `precision`); FP64 SVD truncation keeping
+ * min(chi_max, #{sigma_i > sigma_cut sigma_1}) values (eq. SurrogateEpsChi
+ * gives the discarded weight); environment update in `precision`.
+ * With lbo != 0 the local basis of the centre site is re-optimised before each
+ * update (raw single-site solve, top-d eigenvectors of rho_s; Sec. III.A,
+ * SM Sec. 6).  The energy is the FP64 <H> after the sweep. */
+typedef struct {
+  int32_t chi_max;
+  double sigma_cut;
+  double tol;              /* Lanczos residual tolerance ||H x - l x|| (||x|| = 1) */
+  int32_t krylov_max;      /* Krylov vectors before an explicit restart, 2..64 */
+  int32_t max_matvecs;     /* per local solve */
+  int32_t precision;       /* TN_FP64 / TN_FP32 / TN_BF16X3 */
+  int32_t lbo;             /* 0 / 1 */
+  int32_t compute_energy;  /* 0 / 1: FP64 <H> after the sweep */
+} tn_sweep_opts;
+
+typedef struct {
+  double energy;               /* FP64 <H> after the sweep (NaN if not computed) */
+  double last_eigenvalue;      /* last local Lanczos eigenvalue */
+  double max_discarded, sum_discarded;
+  double lbo_discarded;        /* sum over sites of the local-basis discarded weight */
+  int64_t matvecs;
+  int32_t unconverged_steps;
+  int32_t pad_;
+  double heff_flops;           /* algorithmic flops of all two-site matvecs */
+  double env_flops;            /* algorithmic flops of all environment updates */
+  double t_heff, t_lanczos, t_svd, t_env, t_lbo, t_energy, t_total; /* seconds */
+} tn_sweep_stats;
+
+tn_status tn_dmrg_sweep(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, const tn_sweep_opts* opts, tn_sweep_stats* out);
+
+/* <psi|PHP|psi>/<psi|psi> in FP64 by a full environment sweep (eq.
+ * MagOfSimError); norm2 (may be NULL) receives <psi|psi>. */
+tn_status tn_energy(tn_ctx* ctx, const tn_mpo* mpo, const tn_mps* mps, double* energy, double* norm2);
+
+/* Local basis optimisation.  site >= 0: re-optimise W_site (the orthogonality
+ * centre must be at `site`, else TN_ESTATE); site == -1: one joint LBO + DMRG
+ * sweep.  discarded (may be NULL) receives the local discarded weight
+ * sum_{k >= d} lambda_k of rho_site (site >= 0) or its sum over sites. */
+tn_status tn_lbo_step(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, int32_t site, const tn_sweep_opts* opts,
+                      double* discarded);
+
+/* ------------------------------------------------------------------ observables
+ * Single-mode photon-number marginals P_j(n), j < n_modes, n < D_raw, in FP64
+ * (eq. ReducedDensityMatrix, eq. InverseBasisTransformation).  out: host
+ * [n_modes][D_raw].  The MPS must be normalised and right-canonical with the
+ * centre at site 0 (the state after a sweep). */
+tn_status tn_marginals(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int32_t n_modes, double* out);
+
+/* Photon-number samples by sequential conditional sampling in the Fock basis
+ * (Sec. II.A): p(n_s | n_<s) = ||v A^F_s[n]||^2 in FP64, u from
+ * Philox4x32-10 with counter (sample, site, 0, 0) and key (seed lo, seed hi),
+ * n = smallest index whose cumulative probability reaches u * sum p.
+ * out: device int32 [n_samples][N] (caller-owned).  Same centre requirement
+ * as tn_marginals. */
+tn_status tn_sample(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
+                    int32_t* out);
+
+/* ------------------------------------------------------------------ step entry points
+ * Building blocks of the sweep, on caller-owned device buffers (FP64 complex):
+ *   theta: [chi_l][d][d][chi_r] for the window (site, site+1);
+ *   L: [w_site][chi_l][chi_l] left environment (bra index first);
+ *   R: [w_{site+2}][chi_r][chi_r] right environment (bra index first).
+ * tn_heff_apply writes theta_out = H_eff theta computed in `precision`. */
+tn_status tn_heff_apply(tn_ctx* ctx, const tn_mpo* mpo, int32_t site, int32_t chi_l, int32_t chi_r,
+                        const double* L, const double* R, const double* theta_in, double* theta_out,
+                        int32_t precision);
+/* Environment update across site `site` (FP64 device buffers):
+ * direction +1: env_out[w_{site+1}][chi_r][chi_r] from env_in = L[w_site][chi_l][chi_l];
+ * direction -1: env_out[w_site][chi_l][chi_l] from env_in = R[w_{site+1}][chi_r][chi_r].
+ * A: [chi_l][d][chi_r]. */
+tn_status tn_env_update(tn_ctx* ctx, const tn_mpo* mpo, int32_t site, int32_t direction, int32_t chi_l,
+                        int32_t chi_r, const double* env_in, const double* A, double* env_out, int32_t precision);
+/* SVD truncation of the m x n matrix theta (device, FP64 complex):
+ * keep k = min(chi, #{sigma_i > sigma_cut sigma_1}) values; *k_out = k.
+ * direction +1: left (m x k, orthonormal columns) and right (k x n) = S V^dag;
+ * direction -1: left = U S (m x k) and right (k x n, orthonormal rows).
+ * Both factors renormalised so that the product has unit norm.  sv (host, may
+ * be NULL, capacity min(m, n)) receives the kept singular values of the
+ * normalised theta; discarded receives the discarded weight. */
+tn_status tn_truncate(tn_ctx* ctx, int32_t m, int32_t n, const double* theta, int32_t chi, double sigma_cut,
+                      int32_t direction, double* left, double* right, int32_t* k_out, double* sv,
+                      double* discarded);
+/* Complex GEMM on the matrix cores: C[M x N] = op(A) op(B) with op = identity
+ * or conjugate transpose (trans_a / trans_b != 0; then A is stored K x M, B is
+ * stored N x K), row-major device buffers with leading dimensions in elements.
+ * precision TN_FP64 uses FP64 complex buffers, TN_FP32 / TN_BF16X3 FP32 complex
+ * (interleaved float pairs). */
+tn_status tn_cgemm(tn_ctx* ctx, int32_t precision, int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                   const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc);
+/* Philox4x32-10 (Salmon et al., SC'11) as used by tn_sample: out[4i..4i+3] =
+ * philox(ctr[4i..4i+3], key[2i..2i+1]) for i < n, all host arrays. */
+tn_status tn_philox4x32_10(tn_ctx* ctx, const uint32_t* ctr, const uint32_t* key, uint32_t* out, int32_t n);
+/* Algorithmic flop counts (integer formulas of the matvec and of the
+ * environment update for a window / site of the given shapes). */
+double tn_matvec_flops(const tn_mpo* mpo, int32_t site, int32_t chi_l, int32_t chi_r);
+double tn_env_flops(const tn_mpo* mpo, int32_t site, int32_t chi_l, int32_t chi_r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TN_H */

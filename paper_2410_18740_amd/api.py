@@ -1,0 +1,319 @@
+"""Pythonic wrappers with the C ABI's names (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import TnError, TN_FP64 as FP64, TN_FP32 as FP32, TN_BF16X3 as BF16X3
+
+
+def _check(ctx, status):
+    if status != L.TN_OK:
+        msg = L.lib().tn_last_error(ctx).decode() if ctx else ""
+        raise TnError(status, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """A library context on one GPU, enqueueing on torch's current stream and
+    allocating through torch's caching allocator."""
+
+    def __init__(self, device: int = 0, use_torch_allocator: bool = False):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library needs an MI355X")
+        torch.cuda.set_device(device)
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        self._alloc = None
+        ap = None
+        if use_torch_allocator:
+            dev = device
+
+            @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+            def _a(nbytes, user):
+                try:
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev))
+                except Exception:
+                    return None
+
+            @C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+            def _f(ptr, user):
+                if ptr:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._alloc = L.tn_allocator(_a, _f, None)
+            ap = C.byref(self._alloc)
+        h = C.c_void_p()
+        _check(None, L.lib().tn_ctx_create(device, C.c_void_p(self.stream.cuda_stream), ap, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            for obj in list(self._children):
+                obj._release()
+            L.lib().tn_ctx_destroy(self.h)
+            self.h = None
+
+    @property
+    def _children(self):
+        import weakref
+        if not hasattr(self, "_kids"):
+            self._kids = weakref.WeakSet()
+        return self._kids
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, status):
+        _check(self.h, status)
+
+    @property
+    def last_error(self) -> str:
+        return L.lib().tn_last_error(self.h).decode()
+
+
+class MPO:
+    """Middle-site MPO of PHP for per-mode squeezing r and interferometer U."""
+
+    def __init__(self, ctx: Context, r, U, D_raw: int, d: int | None = None, iso=None):
+        self.ctx = ctx
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        N = len(r)
+        d = D_raw if d is None else d
+        self.N, self.D_raw, self.d = N, D_raw, d
+        self._r = r
+        self._U = U.view(np.float64).copy()
+        self._iso = None if iso is None else np.ascontiguousarray(iso, dtype=np.complex128).view(np.float64).copy()
+        prob = L.tn_problem(N, D_raw, d, L.dptr(self._r), L.dptr(self._U),
+                            None if self._iso is None else L.dptr(self._iso))
+        h = C.c_void_p()
+        ctx.check(L.lib().tn_mpo_build(ctx.h, C.byref(prob), C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def structure(self):
+        w = np.zeros(self.N + 1, dtype=np.int32)
+        L.lib().tn_mpo_structure(self.h, L.dptr(w, C.c_int32), None)
+        tot = int(sum(int(w[s]) * int(w[s + 1]) for s in range(self.N)))
+        k = np.zeros(tot, dtype=np.int8)
+        L.lib().tn_mpo_structure(self.h, L.dptr(w, C.c_int32), L.dptr(k, C.c_int8))
+        kinds, off = [], 0
+        for s in range(self.N):
+            n = int(w[s]) * int(w[s + 1])
+            kinds.append(k[off:off + n].reshape(int(w[s]), int(w[s + 1])))
+            off += n
+        return w, kinds
+
+    def coefficients(self):
+        a = np.zeros((self.N, self.N)); b = np.zeros_like(a); g = np.zeros_like(a)
+        L.lib().tn_mpo_coefficients(self.h, L.dptr(a), L.dptr(b), L.dptr(g))
+        return a, b, g
+
+    def isometries(self):
+        out = np.zeros((self.N, self.D_raw, self.d), dtype=np.complex128)
+        L.lib().tn_mpo_isometries(self.h, L.dptr(out.view(np.float64)))
+        return out
+
+    def site_ops(self, s: int):
+        out = np.zeros((3, self.d, self.d), dtype=np.complex128)
+        self.ctx.check(L.lib().tn_mpo_site_ops(self.h, s, L.dptr(out.view(np.float64))))
+        return out
+
+    def _release(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            L.lib().tn_mpo_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self._release()
+        except Exception:
+            pass
+
+
+class MPS:
+    """Device MPS created from host site tensors (chi_{s}, d, chi_{s+1})."""
+
+    def __init__(self, ctx: Context, tensors):
+        self.ctx = ctx
+        N = len(tensors)
+        d = tensors[0].shape[1]
+        dims = [1] + [int(t.shape[2]) for t in tensors]
+        self.N, self.d = N, d
+        flat = np.concatenate([np.ascontiguousarray(t, dtype=np.complex128).reshape(-1) for t in tensors])
+        flat = flat.view(np.float64)
+        dims = np.asarray(dims, dtype=np.int32)
+        h = C.c_void_p()
+        ctx.check(L.lib().tn_mps_create(ctx.h, N, d, L.dptr(dims, C.c_int32), L.dptr(flat), C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    def bond_dims(self):
+        w = np.zeros(self.N + 1, dtype=np.int32)
+        L.lib().tn_mps_bond_dims(self.h, L.dptr(w, C.c_int32))
+        return w
+
+    def export(self):
+        need = C.c_size_t()
+        self.ctx.check(L.lib().tn_mps_export(self.ctx.h, self.h, None, 0, C.byref(need)))
+        buf = np.zeros(need.value, dtype=np.float64)
+        self.ctx.check(L.lib().tn_mps_export(self.ctx.h, self.h, L.dptr(buf), need.value, C.byref(need)))
+        z = buf.view(np.complex128)
+        dims = self.bond_dims()
+        out, off = [], 0
+        for s in range(self.N):
+            n = int(dims[s]) * self.d * int(dims[s + 1])
+            out.append(z[off:off + n].reshape(int(dims[s]), self.d, int(dims[s + 1])).copy())
+            off += n
+        return out
+
+    def canonicalize(self):
+        self.ctx.check(L.lib().tn_mps_canonicalize(self.ctx.h, self.h))
+
+    def _release(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            L.lib().tn_mps_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self._release()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class SweepOpts:
+    chi_max: int = 16
+    sigma_cut: float = 0.0
+    tol: float = 1e-12
+    krylov_max: int = 32
+    max_matvecs: int = 200
+    precision: int = FP64
+    lbo: int = 0
+    compute_energy: int = 1
+
+    def c(self):
+        return L.tn_sweep_opts(self.chi_max, self.sigma_cut, self.tol, self.krylov_max,
+                               self.max_matvecs, self.precision, self.lbo, self.compute_energy)
+
+
+def dmrg_sweep(ctx: Context, mpo: MPO, mps: MPS, opts: SweepOpts) -> dict:
+    st = L.tn_sweep_stats()
+    o = opts.c()
+    ctx.check(L.lib().tn_dmrg_sweep(ctx.h, mpo.h, mps.h, C.byref(o), C.byref(st)))
+    return st.as_dict()
+
+
+def energy(ctx: Context, mpo: MPO, mps: MPS):
+    e = C.c_double()
+    n = C.c_double()
+    ctx.check(L.lib().tn_energy(ctx.h, mpo.h, mps.h, C.byref(e), C.byref(n)))
+    return e.value, n.value
+
+
+def lbo_step(ctx: Context, mpo: MPO, mps: MPS, site: int, opts: SweepOpts) -> float:
+    disc = C.c_double()
+    o = opts.c()
+    ctx.check(L.lib().tn_lbo_step(ctx.h, mpo.h, mps.h, site, C.byref(o), C.byref(disc)))
+    return disc.value
+
+
+def marginals(ctx: Context, mps: MPS, mpo: MPO, n_modes: int | None = None):
+    n = mps.N if n_modes is None else n_modes
+    out = np.zeros((n, mpo.D_raw))
+    ctx.check(L.lib().tn_marginals(ctx.h, mps.h, mpo.h, n, L.dptr(out)))
+    return out
+
+
+def sample(ctx: Context, mps: MPS, mpo: MPO, n_samples: int, seed: int):
+    torch = _torch()
+    out = torch.empty((n_samples, mps.N), dtype=torch.int32, device=f"cuda:{ctx.device}")
+    ctx.check(L.lib().tn_sample(ctx.h, mps.h, mpo.h, n_samples, C.c_uint64(seed), C.c_void_p(out.data_ptr())))
+    return out
+
+
+def _dev(x):
+    torch = _torch()
+    assert x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()
+    return C.c_void_p(x.data_ptr())
+
+
+def heff_apply(ctx: Context, mpo: MPO, site: int, Lenv, Renv, theta, precision: int = FP64):
+    """theta' = H_eff theta for the window (site, site+1); torch complex128 cuda tensors."""
+    torch = _torch()
+    chi_l, chi_r = int(theta.shape[0]), int(theta.shape[-1])
+    out = torch.empty_like(theta)
+    ctx.check(L.lib().tn_heff_apply(ctx.h, mpo.h, site, chi_l, chi_r, _dev(Lenv), _dev(Renv), _dev(theta),
+                                    _dev(out), precision))
+    return out
+
+
+def env_update(ctx: Context, mpo: MPO, site: int, direction: int, env_in, A, precision: int = FP64):
+    torch = _torch()
+    chi_l, chi_r = int(A.shape[0]), int(A.shape[2])
+    w = int(mpo.structure()[0][site + 1] if direction > 0 else mpo.structure()[0][site])
+    chi = chi_r if direction > 0 else chi_l
+    out = torch.empty((w, chi, chi), dtype=torch.complex128, device=A.device)
+    ctx.check(L.lib().tn_env_update(ctx.h, mpo.h, site, direction, chi_l, chi_r, _dev(env_in), _dev(A),
+                                    _dev(out), precision))
+    return out
+
+
+def truncate(ctx: Context, theta, chi: int, sigma_cut: float = 0.0, direction: int = 1):
+    """SVD truncation of the m x n device matrix theta (complex128)."""
+    torch = _torch()
+    m, n = int(theta.shape[0]), int(theta.shape[1])
+    kmax = max(1, min(chi, m, n))
+    left = torch.empty((m, kmax), dtype=torch.complex128, device=theta.device)
+    right = torch.empty((kmax, n), dtype=torch.complex128, device=theta.device)
+    k = C.c_int32()
+    sv = np.zeros(kmax)
+    disc = C.c_double()
+    ctx.check(L.lib().tn_truncate(ctx.h, m, n, _dev(theta), chi, sigma_cut, direction, _dev(left), _dev(right),
+                                  C.byref(k), L.dptr(sv), C.byref(disc)))
+    kk = k.value
+    return left[:, :kk].contiguous() if kk < kmax else left, \
+        right[:kk].contiguous(), sv[:kk], disc.value
+
+
+def cgemm(ctx: Context, A, B, precision: int = FP64, trans_a: bool = False, trans_b: bool = False):
+    """C = op(A) op(B) on the matrix cores (torch complex cuda tensors: complex128
+    for FP64, complex64 for FP32 / BF16x3)."""
+    torch = _torch()
+    M = A.shape[1] if trans_a else A.shape[0]
+    K = A.shape[0] if trans_a else A.shape[1]
+    N = B.shape[0] if trans_b else B.shape[1]
+    C_ = torch.empty((M, N), dtype=A.dtype, device=A.device)
+    ctx.check(L.lib().tn_cgemm(ctx.h, precision, int(trans_a), int(trans_b), M, N, K, C.c_void_p(A.data_ptr()),
+                               A.shape[1], C.c_void_p(B.data_ptr()), B.shape[1], C.c_void_p(C_.data_ptr()), N))
+    return C_
+
+
+def philox4x32_10(ctx: Context, ctr, key):
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    out = np.zeros_like(ctr)
+    ctx.check(L.lib().tn_philox4x32_10(ctx.h, L.dptr(ctr, C.c_uint32), L.dptr(key, C.c_uint32),
+                                       L.dptr(out, C.c_uint32), len(ctr)))
+    return out
+
+
+def matvec_flops(mpo: MPO, site: int, chi_l: int, chi_r: int) -> float:
+    return L.lib().tn_matvec_flops(mpo.h, site, chi_l, chi_r)
+
+
+def env_flops(mpo: MPO, site: int, chi_l: int, chi_r: int) -> float:
+    return L.lib().tn_env_flops(mpo.h, site, chi_l, chi_r)

@@ -1,0 +1,146 @@
+// Shared definitions for the gfx950 GBS-DMRG library (host + device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+typedef float2 cf32;
+typedef double2 cf64;
+
+#define TN_HOST_DEVICE __host__ __device__ __forceinline__
+
+// ----------------------------------------------------------------- complex helpers
+template <typename C> struct real_of;
+template <> struct real_of<cf32> { typedef float type; };
+template <> struct real_of<cf64> { typedef double type; };
+
+TN_HOST_DEVICE cf32 cmk(float r, float i) { return make_float2(r, i); }
+TN_HOST_DEVICE cf64 cmk(double r, double i) { return make_double2(r, i); }
+template <typename C> TN_HOST_DEVICE C czero();
+template <> TN_HOST_DEVICE cf32 czero<cf32>() { return make_float2(0.f, 0.f); }
+template <> TN_HOST_DEVICE cf64 czero<cf64>() { return make_double2(0.0, 0.0); }
+TN_HOST_DEVICE cf32 cadd(cf32 a, cf32 b) { return make_float2(a.x + b.x, a.y + b.y); }
+TN_HOST_DEVICE cf64 cadd(cf64 a, cf64 b) { return make_double2(a.x + b.x, a.y + b.y); }
+TN_HOST_DEVICE cf32 csub(cf32 a, cf32 b) { return make_float2(a.x - b.x, a.y - b.y); }
+TN_HOST_DEVICE cf64 csub(cf64 a, cf64 b) { return make_double2(a.x - b.x, a.y - b.y); }
+TN_HOST_DEVICE cf32 cmul(cf32 a, cf32 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+TN_HOST_DEVICE cf64 cmul(cf64 a, cf64 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+TN_HOST_DEVICE cf32 cconj(cf32 a) { return make_float2(a.x, -a.y); }
+TN_HOST_DEVICE cf64 cconj(cf64 a) { return make_double2(a.x, -a.y); }
+TN_HOST_DEVICE cf32 cscale(cf32 a, float s) { return make_float2(a.x * s, a.y * s); }
+TN_HOST_DEVICE cf64 cscale(cf64 a, double s) { return make_double2(a.x * s, a.y * s); }
+// a*conj(b)
+TN_HOST_DEVICE cf64 cmulc(cf64 a, cf64 b) { return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+// conj(a)*b
+TN_HOST_DEVICE cf64 cconjmul(cf64 a, cf64 b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+TN_HOST_DEVICE cf32 cconjmul(cf32 a, cf32 b) { return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+TN_HOST_DEVICE double cabs2(cf64 a) { return a.x * a.x + a.y * a.y; }
+
+// ----------------------------------------------------------------- precisions
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
+
+// ----------------------------------------------------------------- GEMM descriptors
+// C[M x N] (=|+=) sum_seg opA(A_seg)[M x K_seg] * opB(B_seg)[K_seg x N], complex,
+// row-major with leading dimensions in elements.  opA = conj-transpose when
+// trans_a != 0 (then A is stored K x M), likewise for B (stored N x K).
+struct GemmSeg {
+  const void* A;
+  const void* B;
+  int64_t lda, ldb;
+  int32_t K;
+  int32_t pad_;
+};
+struct GemmJob {
+  void* C;
+  int64_t ldc;
+  int32_t M, N;
+  int32_t seg0, nseg;
+};
+
+// Launch a batch of jobs.  All jobs share precision and transposition flags.
+// d_jobs / d_segs are device arrays.  Max M/N over jobs sets the grid.
+hipError_t launch_cgemm(int prec, int trans_a, int trans_b, const GemmJob* d_jobs, int njobs,
+                        const GemmSeg* d_segs, int maxM, int maxN, int accumulate, hipStream_t st);
+
+// ----------------------------------------------------------------- op-apply descriptors
+// out[a][s][t][b] = sum_terms coef * sum_{s',t'} opA[s][s'] opB[t][t'] src[a][s'][t'][b]
+// opA/opB == nullptr means identity on that leg.
+struct OpTerm {
+  const void* src;
+  const void* opA;
+  const void* opB;
+  double coef;
+};
+struct OpJob {
+  void* dst;
+  int32_t t0, nterms;
+  int32_t accumulate;  // add into existing dst
+  int32_t pad_;
+};
+hipError_t launch_opapply(int prec, const OpJob* d_jobs, int njobs, const OpTerm* d_terms, int chi_l, int ds,
+                          int dt, int chi_r, hipStream_t st);
+
+// mixed envs: out[j] = sum_{i in list} coef_i * in_i  (each n_elem complex), prec-typed
+struct MixTerm {
+  const void* src;
+  double coef;
+};
+struct MixJob {
+  void* dst;
+  int32_t t0, nterms;
+};
+hipError_t launch_envmix(int prec, const MixJob* d_jobs, int njobs, const MixTerm* d_terms, int64_t n_elem,
+                         hipStream_t st);
+
+// ----------------------------------------------------------------- vector kernels (FP64 complex)
+hipError_t launch_convert(int to_prec, void* dst, int from_prec, const void* src, int64_t n, hipStream_t st);
+hipError_t launch_reduce_partials(cf64* out, int prec, const void* partials, int nparts, int64_t n, hipStream_t st);
+hipError_t launch_multidot(const cf64* const* vs, int nv, const cf64* w, int64_t n, cf64* partials, int nblocks,
+                           hipStream_t st);
+hipError_t launch_multidot_finish(const cf64* partials, int nv, int nblocks, cf64* out, hipStream_t st);
+hipError_t launch_multiaxpy(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, double sign, int64_t n,
+                            hipStream_t st);
+hipError_t launch_scale(cf64* dst, const cf64* src, const double* inv_norm_dev, int64_t n, hipStream_t st);
+hipError_t launch_lincomb(cf64* dst, const cf64* const* vs, int nv, const double* coefs_dev, int64_t n,
+                          hipStream_t st);
+int multidot_blocks(int64_t n);
+
+// ----------------------------------------------------------------- eigen kernels
+// batched Hermitian eigensolver, n <= 64, one workgroup per matrix, LDS resident.
+// A: [batch][n][n] complex (row-major), outputs eigenvalues descending (desc=1) or
+// ascending, eigenvectors as columns of V [batch][n][n].
+hipError_t launch_jacobi(const cf64* A, int64_t strideA, int n, int batch, double* evals, cf64* V, int64_t strideV,
+                         int descending, hipStream_t st);
+// build a real symmetric tridiagonal (alpha[0..n-1], beta[0..n-2]) as a dense complex matrix
+hipError_t launch_build_tridiag(const double* alpha, const double* beta, int n, cf64* A, hipStream_t st);
+
+// Householder tridiagonalisation of a Hermitian p x p matrix (row-major, in place).
+struct TridiagWork {
+  cf64* A;      // p x p
+  cf64* vs;     // reflectors, (p) x p  (row j holds v_j)
+  cf64* taus;   // p
+  double* dg;   // diagonal p
+  double* off;  // off-diagonal p
+  cf64* y;      // p
+  cf64* w;      // p x 2 (ping-pong)
+};
+hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st);
+hipError_t launch_bisect_top(const double* dg, const double* off, int p, int k, double* evals, hipStream_t st);
+hipError_t launch_inverse_iter(const double* dg, const double* off, int p, int k, const double* evals, double* X,
+                               double* scratch, hipStream_t st);
+hipError_t launch_orthonormalize_real(double* X, int p, int k, hipStream_t st);
+hipError_t launch_backtransform(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
+                                hipStream_t st);
+
+hipError_t launch_transpose_from64(int prec, void* dst, const cf64* src, int batch, int rows, int cols, hipStream_t st);
+hipError_t launch_transpose_to64(int prec, cf64* dst, const void* src, int batch, int rows, int cols, hipStream_t st);
+hipError_t launch_scale_host(cf64* dst, const cf64* src, double s, int64_t n, hipStream_t st);
+hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream_t st);
+hipError_t launch_lanczos_scalars(const cf64* h1, const cf64* h2, const cf64* nrm2, int j, double* alpha, double* beta,
+                                  double* inv, double* out, hipStream_t st);
+hipError_t launch_ritz_coefs(const cf64* V, int n, double* out, double* last, hipStream_t st);
+hipError_t launch_finite_check(const cf64* x, int64_t n, int* flag, hipStream_t st);
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
+hipError_t launch_set_one(void* p, int prec, hipStream_t st);
+hipError_t launch_copy2d(cf64* dst, int64_t ldd, const cf64* src, int64_t lds, int rows, int cols, int conj_t,
+                         hipStream_t st);

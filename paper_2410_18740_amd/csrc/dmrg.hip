@@ -1,0 +1,873 @@
+// Two-site DMRG driver: Lanczos local solver (FP64 Krylov vectors), FP64
+// truncation (Gram matrix + Hermitian eigensolver), environment updates, the
+// sweep with optional local basis optimisation, and the FP64 energy.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include "internal.h"
+
+#define TN_GUARD_BEGIN try {
+#define TN_GUARD_END(ctx)                                         \
+  }                                                               \
+  catch (const TnError& e) {                                      \
+    if (ctx) (ctx)->err = e.what();                               \
+    return e.code;                                                \
+  }                                                               \
+  catch (const std::bad_alloc&) {                                 \
+    if (ctx) (ctx)->err = "host allocation failed";               \
+    return TN_ENOMEM;                                             \
+  }                                                               \
+  catch (const std::exception& e) {                               \
+    if (ctx) (ctx)->err = e.what();                               \
+    return TN_EINVAL;                                             \
+  }                                                               \
+  if (ctx) (ctx)->err.clear();                                    \
+  return TN_OK;
+
+static double wall() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ small helpers
+static double dev_norm2(tn_ctx* c, const cf64* x, int64_t n) {
+  const int nb = multidot_blocks(n);
+  cf64* part = wsT<cf64>(c, "nrm:part", nb);
+  cf64* out = wsT<cf64>(c, "nrm:out", 1);
+  const cf64** ptr = wsT<const cf64*>(c, "nrm:ptr", 1);
+  HIPCHK(hipMemcpyAsync(ptr, &x, sizeof(cf64*), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_multidot(ptr, 1, x, n, part, nb, c->stream));
+  HIPCHK(launch_multidot_finish(part, 1, nb, out, c->stream));
+  cf64 h;
+  download(c, &h, out, sizeof(cf64));
+  return h.x;
+}
+
+static void gemm1(tn_ctx* c, int prec, int ta, int tb, void* C, int64_t ldc, int M, int N, const void* A, int64_t lda,
+                  const void* B, int64_t ldb, int K, int acc, const std::string& tag) {
+  GemmJob j{C, ldc, M, N, 0, 1};
+  GemmSeg s{A, B, lda, ldb, K, 0};
+  char* d = (char*)ws_get(c, tag, 512);
+  HIPCHK(hipMemcpyAsync(d, &j, sizeof(j), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d + 256, &s, sizeof(s), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_cgemm(prec, ta, tb, (GemmJob*)d, 1, (GemmSeg*)(d + 256), M, N, acc, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// batched GEMMs from host descriptor vectors (descriptors staged synchronously)
+static void gemm_batch(tn_ctx* c, int prec, int ta, int tb, const std::vector<GemmJob>& jobs,
+                       const std::vector<GemmSeg>& segs, int maxM, int maxN, const std::string& tag) {
+  if (jobs.empty()) return;
+  const size_t bj = ((jobs.size() * sizeof(GemmJob)) + 255) & ~size_t(255);
+  char* d = (char*)ws_get(c, tag, bj + segs.size() * sizeof(GemmSeg));
+  HIPCHK(hipMemcpyAsync(d, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d + bj, segs.data(), segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_cgemm(prec, ta, tb, (GemmJob*)d, (int)jobs.size(), (GemmSeg*)(d + bj), maxM, maxN, 0, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// ------------------------------------------------------------------ Lanczos
+struct LzResult {
+  double lambda = 0.0;
+  int matvecs = 0;
+  bool converged = false;
+  double t_mv = 0.0;
+};
+
+template <class MV>
+static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, int kmax, int max_mv) {
+  LzResult R;
+  hipStream_t st = c->stream;
+  kmax = std::max(2, std::min(kmax, 64));
+  const int nb = multidot_blocks(n);
+  cf64* V = wsT<cf64>(c, "lz:V", (size_t)(kmax + 1) * n);
+  cf64* W = wsT<cf64>(c, "lz:W", (size_t)n);
+  const cf64** ptrs = wsT<const cf64*>(c, "lz:ptr", kmax + 2);
+  cf64* part = wsT<cf64>(c, "lz:part", (size_t)nb * (kmax + 1));
+  cf64* h1 = wsT<cf64>(c, "lz:h1", kmax + 1);
+  cf64* h2 = wsT<cf64>(c, "lz:h2", kmax + 1);
+  cf64* nr = wsT<cf64>(c, "lz:nr", 1);
+  double* alpha = wsT<double>(c, "lz:al", kmax + 1);
+  double* beta = wsT<double>(c, "lz:be", kmax + 1);
+  double* inv = wsT<double>(c, "lz:inv", 1);
+  double* sc = wsT<double>(c, "lz:sc", 4);
+  cf64* Tm = wsT<cf64>(c, "lz:T", (size_t)kmax * kmax);
+  double* ev = wsT<double>(c, "lz:ev", kmax);
+  cf64* Z = wsT<cf64>(c, "lz:Z", (size_t)kmax * kmax);
+  double* coefs = wsT<double>(c, "lz:cf", kmax + 1);
+  double* last = wsT<double>(c, "lz:last", 1);
+  std::vector<const cf64*> hp(kmax + 2);
+  for (int i = 0; i <= kmax; ++i) hp[i] = V + (size_t)i * n;
+  hp[kmax + 1] = W;
+  HIPCHK(hipMemcpyAsync(ptrs, hp.data(), hp.size() * sizeof(cf64*), hipMemcpyHostToDevice, st));
+  double nx = dev_norm2(c, x, n);
+  if (!(nx > 0.0) || !std::isfinite(nx)) TN_THROW(TN_ENUMERIC, "Lanczos start vector is zero or non-finite");
+  HIPCHK(launch_scale_host(V, x, 1.0 / std::sqrt(nx), n, st));
+  double* hout = c->pinned;
+  hipEvent_t e0 = c->ev[0], e1 = c->ev[1];
+  while (true) {
+    int jlast = -1;
+    bool stop = false;
+    double lam = 0.0;
+    for (int j = 0; j < kmax; ++j) {
+      HIPCHK(hipEventRecord(e0, st));
+      matvec(V + (size_t)j * n, W);
+      HIPCHK(hipEventRecord(e1, st));
+      R.matvecs++;
+      // pass 1 and pass 2 of classical Gram-Schmidt against V_0..V_j
+      HIPCHK(launch_multidot(ptrs, j + 1, W, n, part, nb, st));
+      HIPCHK(launch_multidot_finish(part, j + 1, nb, h1, st));
+      HIPCHK(launch_multiaxpy(W, ptrs, j + 1, h1, 1.0, n, st));
+      HIPCHK(launch_multidot(ptrs, j + 1, W, n, part, nb, st));
+      HIPCHK(launch_multidot_finish(part, j + 1, nb, h2, st));
+      HIPCHK(launch_multiaxpy(W, ptrs, j + 1, h2, 1.0, n, st));
+      HIPCHK(launch_multidot(ptrs + kmax + 1, 1, W, n, part, nb, st));
+      HIPCHK(launch_multidot_finish(part, 1, nb, nr, st));
+      HIPCHK(launch_lanczos_scalars(h1, h2, nr, j, alpha, beta, inv, sc, st));
+      HIPCHK(launch_build_tridiag(alpha, beta, j + 1, Tm, st));
+      HIPCHK(launch_jacobi(Tm, 0, j + 1, 1, ev, Z, 0, 0, st));
+      HIPCHK(launch_ritz_coefs(Z, j + 1, coefs, last, st));
+      HIPCHK(hipMemcpyAsync(hout, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hout + 2, ev, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hout + 3, last, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) R.t_mv += ms * 1e-3;
+      const double a = hout[0], b = hout[1];
+      lam = hout[2];
+      const double res = b * std::fabs(hout[3]);
+      if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(lam))
+        TN_THROW(TN_ENUMERIC, "non-finite value in Lanczos recurrence");
+      jlast = j;
+      const double bscale = std::max(1.0, std::fabs(lam));
+      if (res <= tol || b <= 1e-14 * bscale) { R.converged = true; stop = true; break; }
+      if (R.matvecs >= max_mv) { stop = true; break; }
+      if (j + 1 < kmax) HIPCHK(launch_scale(V + (size_t)(j + 1) * n, W, inv, n, st));
+    }
+    // Ritz vector x = sum_i y_i V_i
+    HIPCHK(launch_lincomb(x, ptrs, jlast + 1, coefs, n, st));
+    const double xn = dev_norm2(c, x, n);
+    if (!(xn > 0.0) || !std::isfinite(xn)) TN_THROW(TN_ENUMERIC, "non-finite Ritz vector");
+    R.lambda = lam;
+    if (stop) {
+      HIPCHK(launch_scale_host(x, x, 1.0 / std::sqrt(xn), n, st));
+      return R;
+    }
+    HIPCHK(launch_scale_host(V, x, 1.0 / std::sqrt(xn), n, st));
+  }
+}
+
+// ------------------------------------------------------------------ truncation
+struct TruncOut {
+  int k = 0;
+  double disc = 0.0;
+  std::vector<double> sv;
+};
+
+// Hermitian eigensolve of the p x p matrix G (device, overwritten): top kk eigenpairs,
+// eigenvalues to host (descending), eigenvectors as columns of Z (p x ldz, device).
+static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& evals, cf64*& Z, int& ldz) {
+  hipStream_t st = c->stream;
+  if (p <= 64) {
+    double* ev = wsT<double>(c, "eig:ev", p);
+    Z = wsT<cf64>(c, "eig:Z", (size_t)p * p);
+    HIPCHK(launch_jacobi(G, 0, p, 1, ev, Z, 0, 1, st));
+    evals.resize(p);
+    download(c, evals.data(), ev, p * sizeof(double));
+    evals.resize(kk);
+    ldz = p;
+    return;
+  }
+  TridiagWork tw;
+  tw.A = G;
+  tw.vs = wsT<cf64>(c, "eig:vs", (size_t)p * p);
+  tw.taus = wsT<cf64>(c, "eig:tau", p);
+  tw.dg = wsT<double>(c, "eig:dg", p);
+  tw.off = wsT<double>(c, "eig:off", p);
+  tw.y = wsT<cf64>(c, "eig:y", p);
+  tw.w = wsT<cf64>(c, "eig:w", 2 * (size_t)p);
+  HIPCHK(launch_tridiag(tw, p, st));
+  double* ev = wsT<double>(c, "eig:ev", kk);
+  HIPCHK(launch_bisect_top(tw.dg, tw.off, p, kk, ev, st));
+  double* X = wsT<double>(c, "eig:X", (size_t)kk * p);
+  double* scr = wsT<double>(c, "eig:scr", (size_t)4 * kk * p);
+  HIPCHK(launch_inverse_iter(tw.dg, tw.off, p, kk, ev, X, scr, st));
+  HIPCHK(launch_orthonormalize_real(X, p, kk, st));
+  Z = wsT<cf64>(c, "eig:Z", (size_t)p * kk);
+  HIPCHK(launch_backtransform(tw.vs, tw.taus, p, X, kk, Z, st));
+  evals.resize(kk);
+  download(c, evals.data(), ev, kk * sizeof(double));
+  ldz = kk;
+}
+
+static TruncOut truncate_dev(tn_ctx* c, int m, int n, const cf64* theta, int chi, double sigma_cut, int dir,
+                             cf64* left, cf64* right) {
+  hipStream_t st = c->stream;
+  TruncOut out;
+  const int p = dir > 0 ? m : n;
+  const int kk = std::max(1, std::min(chi, std::min(m, n)));
+  cf64* G = wsT<cf64>(c, "tr:G", (size_t)p * p);
+  if (dir > 0) gemm1(c, PREC_FP64, 0, 1, G, p, m, m, theta, n, theta, n, n, 0, "tr:d0");
+  else gemm1(c, PREC_FP64, 1, 0, G, p, n, n, theta, n, theta, n, m, 0, "tr:d0");
+  const double total = dev_norm2(c, theta, (int64_t)m * n);
+  if (!(total > 0.0) || !std::isfinite(total)) TN_THROW(TN_ENUMERIC, "theta is zero or non-finite");
+  std::vector<double> ev;
+  cf64* Z = nullptr;
+  int ldz = 0;
+  herm_top(c, G, p, kk, ev, Z, ldz);
+  int k = kk;
+  if (sigma_cut > 0.0) {
+    int cnt = 0;
+    for (int i = 0; i < kk; ++i) cnt += (ev[i] > sigma_cut * sigma_cut * ev[0]);
+    k = std::max(1, std::min(k, cnt));
+  }
+  double kept = 0.0;
+  for (int i = 0; i < k; ++i) kept += std::max(ev[i], 0.0);
+  if (!(kept > 0.0)) TN_THROW(TN_ENUMERIC, "no positive singular value kept");
+  out.k = k;
+  out.disc = std::max(0.0, total - kept) / total;
+  out.sv.resize(k);
+  for (int i = 0; i < k; ++i) out.sv[i] = std::sqrt(std::max(ev[i], 0.0) / total);
+  const double sc = 1.0 / std::sqrt(kept);
+  if (dir > 0) {
+    HIPCHK(launch_copy2d(left, k, Z, ldz, m, k, 0, st));
+    gemm1(c, PREC_FP64, 1, 0, right, n, k, n, Z, ldz, theta, n, m, 0, "tr:d1");
+    HIPCHK(launch_scale_host(right, right, sc, (int64_t)k * n, st));
+  } else {
+    HIPCHK(launch_copy2d(right, n, Z, ldz, n, k, 1, st));
+    gemm1(c, PREC_FP64, 0, 0, left, k, m, k, theta, n, Z, ldz, n, 0, "tr:d1");
+    HIPCHK(launch_scale_host(left, left, sc, (int64_t)m * k, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return out;
+}
+
+// ------------------------------------------------------------------ environment updates
+static void mixed_envs(tn_ctx* c, int prec, const std::vector<PlanL>& Ls, const std::vector<const void*>& envs,
+                       int64_t elems, std::vector<const void*>& ptr, const std::string& tag) {
+  const size_t eb = elem_bytes(prec);
+  ptr.resize(Ls.size());
+  std::vector<MixJob> jobs;
+  std::vector<MixTerm> terms;
+  int nm = 0;
+  for (auto& L : Ls) nm += !(L.src.size() == 1 && L.src[0].second == 1.0);
+  char* buf = (char*)ws_get(c, tag + ":mix", std::max(1, nm) * elems * eb);
+  int im = 0;
+  for (size_t i = 0; i < Ls.size(); ++i) {
+    const auto& L = Ls[i];
+    if (L.src.size() == 1 && L.src[0].second == 1.0) { ptr[i] = envs[L.src[0].first]; continue; }
+    void* dst = buf + (size_t)im * elems * eb;
+    ++im;
+    jobs.push_back({dst, (int)terms.size(), (int)L.src.size()});
+    for (auto& s : L.src) terms.push_back({envs[s.first], s.second});
+    ptr[i] = dst;
+  }
+  if (jobs.empty()) return;
+  const size_t bj = (jobs.size() * sizeof(MixJob) + 255) & ~size_t(255);
+  char* d = (char*)ws_get(c, tag + ":mixd", bj + terms.size() * sizeof(MixTerm));
+  HIPCHK(hipMemcpyAsync(d, jobs.data(), jobs.size() * sizeof(MixJob), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d + bj, terms.data(), terms.size() * sizeof(MixTerm), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_envmix(prec == PREC_FP64 ? PREC_FP64 : PREC_FP32, (MixJob*)d, (int)jobs.size(), (MixTerm*)(d + bj),
+                       elems, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+static void run_ops(tn_ctx* c, int sprec, const tn_mpo* mpo, int site, bool raw, const Plan& P, char* Y, char* T,
+                    size_t nel, int chi_l, int ds, int chi_r, const std::string& tag) {
+  if (P.T.empty()) return;
+  const size_t eb = elem_bytes(sprec);
+  std::vector<OpJob> oj;
+  std::vector<OpTerm> ot;
+  for (size_t j = 0; j < P.T.size(); ++j) {
+    oj.push_back({T + j * nel * eb, (int)ot.size(), (int)P.T[j].terms.size(), 0, 0});
+    for (auto& t : P.T[j].terms)
+      ot.push_back({Y + (size_t)t.ych * nel * eb, t.a ? mpo->op_ptr(sprec, site, t.a, raw) : nullptr, nullptr, t.c});
+  }
+  const size_t bj = (oj.size() * sizeof(OpJob) + 255) & ~size_t(255);
+  char* d = (char*)ws_get(c, tag + ":opd", bj + ot.size() * sizeof(OpTerm));
+  HIPCHK(hipMemcpyAsync(d, oj.data(), oj.size() * sizeof(OpJob), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d + bj, ot.data(), ot.size() * sizeof(OpTerm), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_opapply(sprec, (OpJob*)d, (int)oj.size(), (OpTerm*)(d + bj), chi_l, ds, 1, chi_r, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// zero the output channels that receive no term
+static void zero_channels(tn_ctx* c, int sprec, void* out, int w, int64_t elems, const std::vector<bool>& covered) {
+  std::vector<MixJob> jobs;
+  const size_t eb = elem_bytes(sprec);
+  for (int i = 0; i < w; ++i)
+    if (!covered[i]) jobs.push_back({(char*)out + (size_t)i * elems * eb, 0, 0});
+  if (jobs.empty()) return;
+  char* d = (char*)ws_get(c, "zero:d", jobs.size() * sizeof(MixJob));
+  HIPCHK(hipMemcpyAsync(d, jobs.data(), jobs.size() * sizeof(MixJob), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_envmix(sprec, (MixJob*)d, (int)jobs.size(), nullptr, elems, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// A (FP64, chi_l x d x chi_r) in the GEMM precision's storage form
+static const void* stage_A(tn_ctx* c, int prec, const cf64* A, size_t n, const std::string& tag) {
+  if (prec == PREC_FP64) return A;
+  void* p = ws_get(c, tag, n * sizeof(cf32));
+  HIPCHK(launch_convert(PREC_FP32, p, PREC_FP64, A, (int64_t)n, c->stream));
+  return p;
+}
+
+// left update across `site`: Lout[w_{s+1}][chi_r][chi_r] from Lin[w_s][chi_l][chi_l]
+static void env_left(tn_ctx* c, const tn_mpo* mpo, int site, int prec, int chi_l, int chi_r,
+                     const std::vector<const void*>& Lin, const cf64* A, void* Lout) {
+  const int sprec = prec == PREC_FP64 ? PREC_FP64 : PREC_FP32;
+  const size_t eb = elem_bytes(sprec);
+  const int d = mpo->d, wo = mpo->w[site + 1];
+  const size_t nel = (size_t)chi_l * d * chi_r;
+  const void* AP = stage_A(c, prec, A, nel, "envL:A");
+  Plan P = build_plan(window_terms(mpo, site, 1), mpo->w[site], wo, false);
+  std::vector<const void*> Lp;
+  mixed_envs(c, sprec, P.L, Lin, (int64_t)chi_l * chi_l, Lp, "envL");
+  char* Y = (char*)ws_get(c, "envL:Y", std::max<size_t>(1, P.L.size()) * nel * eb);
+  char* T = (char*)ws_get(c, "envL:T", std::max<size_t>(1, P.T.size()) * nel * eb);
+  std::vector<GemmJob> jobs;
+  std::vector<GemmSeg> segs;
+  for (size_t i = 0; i < P.L.size(); ++i) {
+    segs.push_back({Lp[i], AP, chi_l, (int64_t)d * chi_r, chi_l, 0});
+    jobs.push_back({Y + i * nel * eb, (int64_t)d * chi_r, chi_l, d * chi_r, (int)segs.size() - 1, 1});
+  }
+  gemm_batch(c, prec, 0, 0, jobs, segs, chi_l, d * chi_r, "envL:g1");
+  run_ops(c, sprec, mpo, site, false, P, Y, T, nel, chi_l, d, chi_r, "envL");
+  jobs.clear(); segs.clear();
+  std::vector<bool> cov(wo, false);
+  for (auto& R : P.R) {
+    const int ch = R.env[0].first;
+    cov[ch] = true;
+    const void* src = R.kind == 0 ? (const void*)(Y + (size_t)R.idx * nel * eb) : (const void*)(T + (size_t)R.idx * nel * eb);
+    segs.push_back({AP, src, chi_r, chi_r, chi_l * d, 0});
+    jobs.push_back({(char*)Lout + (size_t)ch * chi_r * chi_r * eb, chi_r, chi_r, chi_r, (int)segs.size() - 1, 1});
+  }
+  gemm_batch(c, prec, 1, 0, jobs, segs, chi_r, chi_r, "envL:g2");
+  zero_channels(c, sprec, Lout, wo, (int64_t)chi_r * chi_r, cov);
+}
+
+// right update across `site`: Rout[w_s][chi_l][chi_l] (transposed) from Rin[w_{s+1}][chi_r][chi_r] (transposed)
+static void env_right(tn_ctx* c, const tn_mpo* mpo, int site, int prec, int chi_l, int chi_r,
+                      const std::vector<const void*>& Rin, const cf64* A, void* Rout) {
+  const int sprec = prec == PREC_FP64 ? PREC_FP64 : PREC_FP32;
+  const size_t eb = elem_bytes(sprec);
+  const int d = mpo->d, wo = mpo->w[site];
+  const size_t nel = (size_t)chi_l * d * chi_r;
+  const void* AP = stage_A(c, prec, A, nel, "envR:A");
+  auto terms = window_terms(mpo, site, 1);
+  for (auto& t : terms) std::swap(t.l, t.n);
+  Plan P = build_plan(terms, mpo->w[site + 1], wo, false);
+  std::vector<const void*> Rp;
+  mixed_envs(c, sprec, P.L, Rin, (int64_t)chi_r * chi_r, Rp, "envR");
+  char* Z = (char*)ws_get(c, "envR:Z", std::max<size_t>(1, P.L.size()) * nel * eb);
+  char* T = (char*)ws_get(c, "envR:T", std::max<size_t>(1, P.T.size()) * nel * eb);
+  std::vector<GemmJob> jobs;
+  std::vector<GemmSeg> segs;
+  for (size_t i = 0; i < P.L.size(); ++i) {
+    segs.push_back({AP, Rp[i], chi_r, chi_r, chi_r, 0});
+    jobs.push_back({Z + i * nel * eb, chi_r, chi_l * d, chi_r, (int)segs.size() - 1, 1});
+  }
+  gemm_batch(c, prec, 0, 0, jobs, segs, chi_l * d, chi_r, "envR:g1");
+  run_ops(c, sprec, mpo, site, false, P, Z, T, nel, chi_l, d, chi_r, "envR");
+  jobs.clear(); segs.clear();
+  std::vector<bool> cov(wo, false);
+  for (auto& R : P.R) {
+    const int ch = R.env[0].first;
+    cov[ch] = true;
+    const void* src = R.kind == 0 ? (const void*)(Z + (size_t)R.idx * nel * eb) : (const void*)(T + (size_t)R.idx * nel * eb);
+    segs.push_back({src, AP, (int64_t)d * chi_r, (int64_t)d * chi_r, d * chi_r, 0});
+    jobs.push_back({(char*)Rout + (size_t)ch * chi_l * chi_l * eb, chi_l, chi_l, chi_l, (int)segs.size() - 1, 1});
+  }
+  gemm_batch(c, prec, 0, 1, jobs, segs, chi_l, chi_l, "envR:g2");
+  zero_channels(c, sprec, Rout, wo, (int64_t)chi_l * chi_l, cov);
+}
+
+// ------------------------------------------------------------------ environment cache on the MPS
+static void* env_buf(tn_mps* m, bool left, int t, size_t bytes) {
+  auto& v = left ? m->L : m->Rt;
+  auto& cap = left ? m->Lcap : m->Rcap;
+  if (cap[t] >= bytes && v[t]) return v[t];
+  if (v[t]) {
+    HIPCHK(hipStreamSynchronize(m->ctx->stream));
+    dev_free(m->ctx, v[t]);
+    v[t] = nullptr;
+  }
+  v[t] = dev_alloc(m->ctx, bytes);
+  cap[t] = bytes;
+  return v[t];
+}
+static std::vector<const void*> env_ptrs(tn_mps* m, const tn_mpo* mpo, bool left, int t, int prec) {
+  const size_t eb = elem_bytes(prec == PREC_FP64 ? PREC_FP64 : PREC_FP32);
+  const int chi = m->dims[t];
+  std::vector<const void*> p(mpo->w[t]);
+  char* base = (char*)(left ? m->L[t] : m->Rt[t]);
+  for (int i = 0; i < mpo->w[t]; ++i) p[i] = base + (size_t)i * chi * chi * eb;
+  return p;
+}
+static void set_boundary(tn_mps* m, bool left, int t, int prec) {
+  void* p = env_buf(m, left, t, 256);
+  HIPCHK(launch_set_one(p, prec == PREC_FP64 ? PREC_FP64 : PREC_FP32, m->ctx->stream));
+  (left ? m->Lok : m->Rok)[t] = true;
+}
+static void update_left_env(tn_mps* m, const tn_mpo* mpo, int site, int prec, double* flops) {
+  const size_t eb = elem_bytes(prec == PREC_FP64 ? PREC_FP64 : PREC_FP32);
+  const int cl = m->dims[site], cr = m->dims[site + 1];
+  void* out = env_buf(m, true, site + 1, (size_t)mpo->w[site + 1] * cr * cr * eb);
+  env_left(m->ctx, mpo, site, prec, cl, cr, env_ptrs(m, mpo, true, site, prec), m->A[site], out);
+  m->Lok[site + 1] = true;
+  if (flops) *flops += env_flops_formula(mpo, site, cl, cr);
+}
+static void update_right_env(tn_mps* m, const tn_mpo* mpo, int site, int prec, double* flops) {
+  const size_t eb = elem_bytes(prec == PREC_FP64 ? PREC_FP64 : PREC_FP32);
+  const int cl = m->dims[site], cr = m->dims[site + 1];
+  void* out = env_buf(m, false, site, (size_t)mpo->w[site] * cl * cl * eb);
+  env_right(m->ctx, mpo, site, prec, cl, cr, env_ptrs(m, mpo, false, site + 1, prec), m->A[site], out);
+  m->Rok[site] = true;
+  if (flops) *flops += env_flops_formula(mpo, site, cl, cr);
+}
+
+// ------------------------------------------------------------------ canonical form
+static void canonicalize(tn_ctx* c, tn_mps* m) {
+  const int N = m->N, d = m->d;
+  for (int s = N - 1; s >= 1; --s) {
+    const int cl = m->dims[s], cr = m->dims[s + 1];
+    const int mm = cl, nn = d * cr;
+    cf64* left = wsT<cf64>(c, "can:L", (size_t)mm * std::min(mm, nn));
+    cf64* right = wsT<cf64>(c, "can:R", (size_t)std::min(mm, nn) * nn);
+    TruncOut t = truncate_dev(c, mm, nn, m->A[s], 1 << 30, 0.0, -1, left, right);
+    const int k = t.k;
+    m->ensure_site(s, (size_t)k * nn);
+    HIPCHK(hipMemcpyAsync(m->A[s], right, (size_t)k * nn * sizeof(cf64), hipMemcpyDeviceToDevice, c->stream));
+    // A_{s-1} <- A_{s-1} * left   ((chi_{s-1} d) x cl) * (cl x k)
+    const int pl = m->dims[s - 1];
+    cf64* tmp = wsT<cf64>(c, "can:T", (size_t)pl * d * k);
+    gemm1(c, PREC_FP64, 0, 0, tmp, k, pl * d, k, m->A[s - 1], cl, left, k, cl, 0, "can:g");
+    m->ensure_site(s - 1, (size_t)pl * d * k);
+    HIPCHK(hipMemcpyAsync(m->A[s - 1], tmp, (size_t)pl * d * k * sizeof(cf64), hipMemcpyDeviceToDevice, c->stream));
+    m->dims[s] = k;
+  }
+  const int n0 = m->dims[0] * d * m->dims[1];
+  const double nr = dev_norm2(c, m->A[0], n0);
+  if (!(nr > 0.0) || !std::isfinite(nr)) TN_THROW(TN_ENUMERIC, "MPS has zero or non-finite norm");
+  HIPCHK(launch_scale_host(m->A[0], m->A[0], 1.0 / std::sqrt(nr), n0, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  m->center = 0;
+  for (size_t i = 0; i < m->Lok.size(); ++i) { m->Lok[i] = false; m->Rok[i] = false; }
+  m->env_mpo = nullptr;
+}
+
+static void ensure_right_envs(tn_mps* m, const tn_mpo* mpo, int prec, double* flops) {
+  const bool valid = m->env_mpo == mpo && m->env_prec == prec && m->env_version == mpo->version;
+  if (!valid) for (size_t i = 0; i < m->Rok.size(); ++i) { m->Rok[i] = false; m->Lok[i] = false; }
+  set_boundary(m, false, m->N, prec);
+  set_boundary(m, true, 0, prec);
+  for (int s = m->N - 1; s >= 1; --s)
+    if (!m->Rok[s]) update_right_env(m, mpo, s, prec, flops);
+  m->env_mpo = mpo;
+  m->env_prec = prec;
+  m->env_version = mpo->version;
+}
+
+// ------------------------------------------------------------------ LBO on the centre site
+static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_opts& o, int prec, int64_t* mv) {
+  hipStream_t st = c->stream;
+  const int D = mpo->D_raw, d = mpo->d;
+  const int cl = m->dims[s], cr = m->dims[s + 1];
+  const size_t nraw = (size_t)cl * D * cr;
+  cf64* B = wsT<cf64>(c, "lbo:B", nraw);
+  // B[a] = W_s * A_s[a]
+  {
+    std::vector<GemmJob> jobs;
+    std::vector<GemmSeg> segs;
+    for (int a = 0; a < cl; ++a) {
+      segs.push_back({mpo->d_iso + (size_t)s * D * d, m->A[s] + (size_t)a * d * cr, d, cr, d, 0});
+      jobs.push_back({B + (size_t)a * D * cr, cr, D, cr, a, 1});
+    }
+    gemm_batch(c, PREC_FP64, 0, 0, jobs, segs, D, cr, "lbo:g0");
+  }
+  // raw single-site solve
+  WindowOp op;
+  op.setup(c, mpo, s, 1, prec, cl, cr, env_ptrs(m, mpo, true, s, prec), env_ptrs(m, mpo, false, s + 1, prec), true,
+           "lbo");
+  LzResult lz = lanczos(c, [&](const cf64* x, cf64* y) { op.apply(x, y); }, B, (int64_t)nraw, o.tol, o.krylov_max,
+                        o.max_matvecs);
+  if (mv) *mv += lz.matvecs;
+  // rho = sum_a B[a] B[a]^dag (D x D)
+  cf64* rho = wsT<cf64>(c, "lbo:rho", (size_t)D * D);
+  {
+    std::vector<GemmJob> jobs;
+    std::vector<GemmSeg> segs;
+    for (int a = 0; a < cl; ++a) segs.push_back({B + (size_t)a * D * cr, B + (size_t)a * D * cr, cr, cr, cr, 0});
+    jobs.push_back({rho, D, D, D, 0, cl});
+    gemm_batch(c, PREC_FP64, 0, 1, jobs, segs, D, D, "lbo:g1");
+  }
+  double* ev = wsT<double>(c, "lbo:ev", D);
+  cf64* Zr = wsT<cf64>(c, "lbo:Z", (size_t)D * D);
+  HIPCHK(launch_jacobi(rho, 0, D, 1, ev, Zr, 0, 1, st));
+  std::vector<double> evh(D);
+  std::vector<cf64> Zh((size_t)D * D);
+  download(c, evh.data(), ev, D * sizeof(double));
+  download(c, Zh.data(), Zr, Zh.size() * sizeof(cf64));
+  double tot = 0.0, kept = 0.0;
+  for (int i = 0; i < D; ++i) { tot += std::max(0.0, evh[i]); if (i < d) kept += std::max(0.0, evh[i]); }
+  const double disc = tot > 0 ? (tot - kept) / tot : 0.0;
+  // new isometry: top-d eigenvectors, phase fixed so the largest-modulus entry is real positive
+  std::vector<cd> Wn((size_t)D * d);
+  for (int j = 0; j < d; ++j) {
+    int im = 0;
+    double best = -1;
+    for (int i = 0; i < D; ++i) {
+      const double a = Zh[(size_t)i * D + j].x * Zh[(size_t)i * D + j].x + Zh[(size_t)i * D + j].y * Zh[(size_t)i * D + j].y;
+      if (a > best + 1e-14) { best = a; im = i; }
+    }
+    const cd z(Zh[(size_t)im * D + j].x, Zh[(size_t)im * D + j].y);
+    const cd ph = std::abs(z) > 0 ? std::conj(z) / std::abs(z) : cd(1.0);
+    for (int i = 0; i < D; ++i) Wn[(size_t)i * d + j] = cd(Zh[(size_t)i * D + j].x, Zh[(size_t)i * D + j].y) * ph;
+  }
+  mpo->iso[s] = Wn;
+  // re-project the local operators and upload (ops, raw ops, isometry)
+  {
+    const auto& raw = mpo->raw_ops[s];
+    std::vector<cd> out(3 * (size_t)d * d, 0.0);
+    for (int o2 = 0; o2 < 3; ++o2)
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+          cd acc = 0.0;
+          for (int i = 0; i < D; ++i) {
+            const cd wi = std::conj(Wn[(size_t)i * d + a]);
+            if (wi == 0.0) continue;
+            cd t = 0.0;
+            for (int j = 0; j < D; ++j) t += raw[(size_t)o2 * D * D + (size_t)i * D + j] * Wn[(size_t)j * d + b];
+            acc += wi * t;
+          }
+          out[(size_t)o2 * d * d + (size_t)a * d + b] = acc;
+        }
+    mpo->loc_ops[s] = out;
+    HIPCHK(hipStreamSynchronize(st));
+    mpo->upload_site(s);
+    mpo->version++;
+  }
+  // A_s = W^dag B, renormalised
+  {
+    std::vector<GemmJob> jobs;
+    std::vector<GemmSeg> segs;
+    for (int a = 0; a < cl; ++a) {
+      segs.push_back({mpo->d_iso + (size_t)s * D * d, B + (size_t)a * D * cr, d, cr, D, 0});
+      jobs.push_back({m->A[s] + (size_t)a * d * cr, cr, d, cr, a, 1});
+    }
+    gemm_batch(c, PREC_FP64, 1, 0, jobs, segs, d, cr, "lbo:g2");
+    const double nr = dev_norm2(c, m->A[s], (int64_t)cl * d * cr);
+    if (!(nr > 0.0) || !std::isfinite(nr)) TN_THROW(TN_ENUMERIC, "LBO projection gave a zero tensor");
+    HIPCHK(launch_scale_host(m->A[s], m->A[s], 1.0 / std::sqrt(nr), (int64_t)cl * d * cr, st));
+  }
+  return disc;
+}
+
+// ------------------------------------------------------------------ one two-site update
+struct StepStats {
+  double disc = 0, lam = 0, t_heff = 0, t_lz = 0, t_svd = 0, t_env = 0, heff_flops = 0, env_flops = 0;
+  int64_t mv = 0;
+  bool conv = true;
+};
+
+static StepStats two_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, int dir, const tn_sweep_opts& o) {
+  StepStats S;
+  hipStream_t st = c->stream;
+  const int d = mpo->d, prec = o.precision;
+  const int cl = m->dims[s], cm = m->dims[s + 1], cr = m->dims[s + 2];
+  const size_t nth = (size_t)cl * d * d * cr;
+  cf64* th = wsT<cf64>(c, "ts:theta", nth);
+  gemm1(c, PREC_FP64, 0, 0, th, d * cr, cl * d, d * cr, m->A[s], cm, m->A[s + 1], d * cr, cm, 0, "ts:g0");
+  const double t0 = wall();
+  WindowOp op;
+  op.setup(c, mpo, s, 2, prec, cl, cr, env_ptrs(m, mpo, true, s, prec), env_ptrs(m, mpo, false, s + 2, prec), false,
+           "heff");
+  LzResult lz = lanczos(c, [&](const cf64* x, cf64* y) { op.apply(x, y); }, th, (int64_t)nth, o.tol, o.krylov_max,
+                        o.max_matvecs);
+  const double t1 = wall();
+  S.mv = lz.matvecs;
+  S.conv = lz.converged;
+  S.lam = lz.lambda;
+  S.t_heff = lz.t_mv;
+  S.t_lz = (t1 - t0) - lz.t_mv;
+  S.heff_flops = matvec_flops_formula(mpo, s, cl, cr) * lz.matvecs;
+  // truncation
+  const int mm = cl * d, nn = d * cr;
+  const int kmax = std::max(1, std::min(o.chi_max, std::min(mm, nn)));
+  cf64* left = wsT<cf64>(c, "ts:left", (size_t)mm * kmax);
+  cf64* right = wsT<cf64>(c, "ts:right", (size_t)kmax * nn);
+  TruncOut t = truncate_dev(c, mm, nn, th, o.chi_max, o.sigma_cut, dir, left, right);
+  const double t2 = wall();
+  S.t_svd = t2 - t1;
+  S.disc = t.disc;
+  const int k = t.k;
+  m->ensure_site(s, (size_t)mm * k);
+  m->ensure_site(s + 1, (size_t)k * nn);
+  HIPCHK(hipMemcpyAsync(m->A[s], left, (size_t)mm * k * sizeof(cf64), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(m->A[s + 1], right, (size_t)k * nn * sizeof(cf64), hipMemcpyDeviceToDevice, st));
+  m->dims[s + 1] = k;
+  // non-finite guard on the new tensors
+  int* flag = wsT<int>(c, "ts:flag", 1);
+  HIPCHK(launch_fill_int(flag, 0, 1, st));
+  HIPCHK(launch_finite_check(m->A[s], (int64_t)mm * k, flag, st));
+  HIPCHK(launch_finite_check(m->A[s + 1], (int64_t)k * nn, flag, st));
+  int fl = 0;
+  download(c, &fl, flag, sizeof(int));
+  if (fl) TN_THROW(TN_ENUMERIC, "non-finite tensor after truncation");
+  if (dir > 0) update_left_env(m, mpo, s, prec, &S.env_flops);
+  else update_right_env(m, mpo, s + 1, prec, &S.env_flops);
+  HIPCHK(hipStreamSynchronize(st));
+  S.t_env = wall() - t2;
+  return S;
+}
+
+// ------------------------------------------------------------------ energy (FP64)
+static double energy_fp64(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double* norm2) {
+  const int N = m->N, d = m->d;
+  hipStream_t st = c->stream;
+  size_t maxw = 1;
+  for (int t = 0; t <= N; ++t) maxw = std::max(maxw, (size_t)mpo->w[t] * m->dims[t] * m->dims[t]);
+  cf64* La = wsT<cf64>(c, "en:La", maxw);
+  cf64* Lb = wsT<cf64>(c, "en:Lb", maxw);
+  HIPCHK(launch_set_one(La, PREC_FP64, st));
+  for (int s = 0; s < N; ++s) {
+    const int cl = m->dims[s], cr = m->dims[s + 1];
+    std::vector<const void*> lin(mpo->w[s]);
+    for (int i = 0; i < mpo->w[s]; ++i) lin[i] = La + (size_t)i * cl * cl;
+    env_left(c, mpo, s, PREC_FP64, cl, cr, lin, m->A[s], Lb);
+    std::swap(La, Lb);
+  }
+  cf64 e;
+  download(c, &e, La, sizeof(cf64));
+  // norm: E_{s+1} = A_s^dag (E_s A_s)
+  cf64* Ea = wsT<cf64>(c, "en:Ea", maxw);
+  cf64* Eb = wsT<cf64>(c, "en:Eb", maxw);
+  cf64* Y = wsT<cf64>(c, "en:Y", [&] { size_t mx = 1; for (int s = 0; s < N; ++s) mx = std::max(mx, (size_t)m->dims[s] * d * m->dims[s + 1]); return mx; }());
+  HIPCHK(launch_set_one(Ea, PREC_FP64, st));
+  for (int s = 0; s < N; ++s) {
+    const int cl = m->dims[s], cr = m->dims[s + 1];
+    gemm1(c, PREC_FP64, 0, 0, Y, d * cr, cl, d * cr, Ea, cl, m->A[s], d * cr, cl, 0, "en:g0");
+    gemm1(c, PREC_FP64, 1, 0, Eb, cr, cr, cr, m->A[s], cr, Y, cr, cl * d, 0, "en:g1");
+    std::swap(Ea, Eb);
+  }
+  cf64 nn;
+  download(c, &nn, Ea, sizeof(cf64));
+  if (norm2) *norm2 = nn.x;
+  if (!(nn.x > 0.0) || !std::isfinite(e.x)) TN_THROW(TN_ENUMERIC, "non-finite energy or zero norm");
+  return e.x / nn.x;
+}
+
+// ------------------------------------------------------------------ ABI
+static void check_opts(const tn_sweep_opts* o) {
+  if (!o) TN_THROW(TN_EINVAL, "null options");
+  if (o->chi_max < 1) TN_THROW(TN_EINVAL, "chi_max must be >= 1");
+  if (!(o->tol > 0.0)) TN_THROW(TN_EINVAL, "tol must be positive");
+  if (o->krylov_max < 2 || o->krylov_max > 64) TN_THROW(TN_EINVAL, "krylov_max must be in [2, 64]");
+  if (o->max_matvecs < 1) TN_THROW(TN_EINVAL, "max_matvecs must be >= 1");
+  if (o->precision < 0 || o->precision > 2) TN_THROW(TN_EINVAL, "unknown precision");
+  if (!(o->sigma_cut >= 0.0) || o->sigma_cut >= 1.0) TN_THROW(TN_EINVAL, "sigma_cut must be in [0, 1)");
+}
+
+static void check_pair(const tn_mpo* mpo, const tn_mps* m) {
+  if (mpo->N != m->N) TN_THROW(TN_EINVAL, "MPO and MPS have different N");
+  if (mpo->d != m->d) TN_THROW(TN_EINVAL, "MPO and MPS have different local dimension");
+}
+
+static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o, tn_sweep_stats* out) {
+  const double tstart = wall();
+  tn_sweep_stats S{};
+  S.energy = NAN;
+  if (m->N < 2) TN_THROW(TN_EINVAL, "a sweep needs N >= 2");
+  if (m->center != 0) canonicalize(c, m);
+  ensure_right_envs(m, mpo, o.precision, &S.env_flops);
+  const int N = m->N;
+  auto acc = [&](const StepStats& t) {
+    S.max_discarded = std::max(S.max_discarded, t.disc);
+    S.sum_discarded += t.disc;
+    S.matvecs += t.mv;
+    S.unconverged_steps += t.conv ? 0 : 1;
+    S.heff_flops += t.heff_flops;
+    S.env_flops += t.env_flops;
+    S.t_heff += t.t_heff;
+    S.t_lanczos += t.t_lz;
+    S.t_svd += t.t_svd;
+    S.t_env += t.t_env;
+    S.last_eigenvalue = t.lam;
+  };
+  for (int s = 0; s <= N - 2; ++s) {
+    if (o.lbo) { const double t0 = wall(); S.lbo_discarded += lbo_site(c, mpo, m, s, o, o.precision, &S.matvecs); S.t_lbo += wall() - t0; }
+    acc(two_site(c, mpo, m, s, +1, o));
+    m->center = s + 1;
+  }
+  for (int s = N - 2; s >= 0; --s) {
+    if (o.lbo) { const double t0 = wall(); S.lbo_discarded += lbo_site(c, mpo, m, s + 1, o, o.precision, &S.matvecs); S.t_lbo += wall() - t0; }
+    acc(two_site(c, mpo, m, s, -1, o));
+    m->center = s;
+  }
+  m->env_mpo = mpo;
+  m->env_prec = o.precision;
+  m->env_version = mpo->version;
+  for (int t = 1; t <= N; ++t) m->Lok[t] = false;
+  if (o.compute_energy) {
+    const double t0 = wall();
+    S.energy = energy_fp64(c, mpo, m, nullptr);
+    S.t_energy = wall() - t0;
+  }
+  S.t_total = wall() - tstart;
+  if (out) *out = S;
+}
+
+extern "C" tn_status tn_dmrg_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts* o, tn_sweep_stats* out) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !m) TN_THROW(TN_EINVAL, "null handle");
+  check_opts(o);
+  check_pair(mpo, m);
+  sweep_impl(c, mpo, m, *o, out);
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_mps_canonicalize(tn_ctx* c, tn_mps* m) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!m) TN_THROW(TN_EINVAL, "null handle");
+  canonicalize(c, m);
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_energy(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double* energy, double* norm2) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !m || !energy) TN_THROW(TN_EINVAL, "null argument");
+  check_pair(mpo, m);
+  *energy = energy_fp64(c, mpo, m, norm2);
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_lbo_step(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int32_t site, const tn_sweep_opts* o,
+                                 double* discarded) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !m) TN_THROW(TN_EINVAL, "null handle");
+  check_opts(o);
+  check_pair(mpo, m);
+  if (site < -1 || site >= m->N) TN_THROW(TN_EINVAL, "site out of range");
+  if (site == -1) {
+    tn_sweep_opts oo = *o;
+    oo.lbo = 1;
+    tn_sweep_stats S{};
+    sweep_impl(c, mpo, m, oo, &S);
+    if (discarded) *discarded = S.lbo_discarded;
+  } else {
+    if (m->center != site) TN_THROW(TN_ESTATE, "the orthogonality centre is not at the requested site");
+    // environments around the site
+    ensure_right_envs(m, mpo, o->precision, nullptr);
+    for (int t = 0; t < site; ++t)
+      if (!m->Lok[t + 1]) update_left_env(m, mpo, t, o->precision, nullptr);
+    const double dsc = lbo_site(c, mpo, m, site, *o, o->precision, nullptr);
+    // tensors right of the site are untouched; environments right of the site stay valid
+    m->env_version = mpo->version;
+    for (int t = site + 1; t <= m->N; ++t) m->Lok[t] = false;
+    for (int t = 0; t <= site; ++t) m->Rok[t] = false;
+    if (discarded) *discarded = dsc;
+  }
+  TN_GUARD_END(c)
+}
+
+// ------------------------------------------------------------------ step entry points
+extern "C" tn_status tn_heff_apply(tn_ctx* c, const tn_mpo* mpo, int32_t site, int32_t chi_l, int32_t chi_r,
+                                   const double* L, const double* R, const double* xin, double* yout, int32_t prec) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !L || !R || !xin || !yout) TN_THROW(TN_EINVAL, "null argument");
+  if (site < 0 || site + 1 >= mpo->N) TN_THROW(TN_EINVAL, "window out of range");
+  if (chi_l < 1 || chi_r < 1) TN_THROW(TN_EINVAL, "bond dimensions must be positive");
+  if (prec < 0 || prec > 2) TN_THROW(TN_EINVAL, "unknown precision");
+  const int sprec = prec == PREC_FP64 ? PREC_FP64 : PREC_FP32;
+  const size_t eb = elem_bytes(sprec);
+  const int wl = mpo->w[site], wr = mpo->w[site + 2];
+  char* Lc = (char*)ws_get(c, "api:L", (size_t)wl * chi_l * chi_l * eb);
+  char* Rc = (char*)ws_get(c, "api:R", (size_t)wr * chi_r * chi_r * eb);
+  HIPCHK(launch_convert(sprec, Lc, PREC_FP64, L, (int64_t)wl * chi_l * chi_l, c->stream));
+  HIPCHK(launch_transpose_from64(sprec, Rc, (const cf64*)R, wr, chi_r, chi_r, c->stream));
+  std::vector<const void*> lp(wl), rp(wr);
+  for (int i = 0; i < wl; ++i) lp[i] = Lc + (size_t)i * chi_l * chi_l * eb;
+  for (int i = 0; i < wr; ++i) rp[i] = Rc + (size_t)i * chi_r * chi_r * eb;
+  WindowOp op;
+  op.setup(c, mpo, site, 2, prec, chi_l, chi_r, lp, rp, false, "heff");
+  op.apply((const cf64*)xin, (cf64*)yout);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_env_update(tn_ctx* c, const tn_mpo* mpo, int32_t site, int32_t dir, int32_t chi_l,
+                                   int32_t chi_r, const double* env_in, const double* A, double* env_out,
+                                   int32_t prec) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !env_in || !A || !env_out) TN_THROW(TN_EINVAL, "null argument");
+  if (site < 0 || site >= mpo->N) TN_THROW(TN_EINVAL, "site out of range");
+  if (dir != 1 && dir != -1) TN_THROW(TN_EINVAL, "direction must be +1 or -1");
+  if (chi_l < 1 || chi_r < 1) TN_THROW(TN_EINVAL, "bond dimensions must be positive");
+  if (prec < 0 || prec > 2) TN_THROW(TN_EINVAL, "unknown precision");
+  const int sprec = prec == PREC_FP64 ? PREC_FP64 : PREC_FP32;
+  const size_t eb = elem_bytes(sprec);
+  if (dir > 0) {
+    const int wi = mpo->w[site], wo = mpo->w[site + 1];
+    char* in = (char*)ws_get(c, "api:Ein", (size_t)wi * chi_l * chi_l * eb);
+    char* out = (char*)ws_get(c, "api:Eout", (size_t)wo * chi_r * chi_r * eb);
+    HIPCHK(launch_convert(sprec, in, PREC_FP64, env_in, (int64_t)wi * chi_l * chi_l, c->stream));
+    std::vector<const void*> p(wi);
+    for (int i = 0; i < wi; ++i) p[i] = in + (size_t)i * chi_l * chi_l * eb;
+    env_left(c, mpo, site, prec, chi_l, chi_r, p, (const cf64*)A, out);
+    HIPCHK(launch_convert(PREC_FP64, env_out, sprec, out, (int64_t)wo * chi_r * chi_r, c->stream));
+  } else {
+    const int wi = mpo->w[site + 1], wo = mpo->w[site];
+    char* in = (char*)ws_get(c, "api:Ein", (size_t)wi * chi_r * chi_r * eb);
+    char* out = (char*)ws_get(c, "api:Eout", (size_t)wo * chi_l * chi_l * eb);
+    HIPCHK(launch_transpose_from64(sprec, in, (const cf64*)env_in, wi, chi_r, chi_r, c->stream));
+    std::vector<const void*> p(wi);
+    for (int i = 0; i < wi; ++i) p[i] = in + (size_t)i * chi_r * chi_r * eb;
+    env_right(c, mpo, site, prec, chi_l, chi_r, p, (const cf64*)A, out);
+    HIPCHK(launch_transpose_to64(sprec, (cf64*)env_out, out, wo, chi_l, chi_l, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_truncate(tn_ctx* c, int32_t m, int32_t n, const double* theta, int32_t chi, double sigma_cut,
+                                 int32_t dir, double* left, double* right, int32_t* k_out, double* sv,
+                                 double* discarded) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!theta || !left || !right || !k_out) TN_THROW(TN_EINVAL, "null argument");
+  if (m < 1 || n < 1 || chi < 1) TN_THROW(TN_EINVAL, "sizes must be positive");
+  if (dir != 1 && dir != -1) TN_THROW(TN_EINVAL, "direction must be +1 or -1");
+  if (!(sigma_cut >= 0.0) || sigma_cut >= 1.0) TN_THROW(TN_EINVAL, "sigma_cut must be in [0, 1)");
+  TruncOut t = truncate_dev(c, m, n, (const cf64*)theta, chi, sigma_cut, dir, (cf64*)left, (cf64*)right);
+  *k_out = t.k;
+  if (sv) std::memcpy(sv, t.sv.data(), t.sv.size() * sizeof(double));
+  if (discarded) *discarded = t.disc;
+  TN_GUARD_END(c)
+}
+
+extern "C" double tn_matvec_flops(const tn_mpo* mpo, int32_t site, int32_t chi_l, int32_t chi_r) {
+  if (!mpo || site < 0 || site + 1 >= mpo->N) return -1.0;
+  return matvec_flops_formula(mpo, site, chi_l, chi_r);
+}
+extern "C" double tn_env_flops(const tn_mpo* mpo, int32_t site, int32_t chi_l, int32_t chi_r) {
+  if (!mpo || site < 0 || site >= mpo->N) return -1.0;
+  return env_flops_formula(mpo, site, chi_l, chi_r);
+}
+
+extern "C" tn_status tn_cgemm(tn_ctx* c, int32_t prec, int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K,
+                              const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!A || !B || !C) TN_THROW(TN_EINVAL, "null argument");
+  if (M < 1 || N < 1 || K < 1) TN_THROW(TN_EINVAL, "sizes must be positive");
+  if (prec < 0 || prec > 2) TN_THROW(TN_EINVAL, "unknown precision");
+  if (lda < (ta ? M : K) || ldb < (tb ? K : N) || ldc < N) TN_THROW(TN_EINVAL, "leading dimension too small");
+  gemm1(c, prec, ta ? 1 : 0, tb ? 1 : 0, C, ldc, M, N, A, lda, B, ldb, K, 0, "api:gemm");
+  TN_GUARD_END(c)
+}

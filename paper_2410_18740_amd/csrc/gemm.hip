@@ -1,0 +1,274 @@
+// Complex GEMM on CDNA4 matrix cores (gfx950), three arithmetic forms:
+//   FP64   : v_mfma_f64_16x16x4f64,  real-block complex product (4 real MFMAs)
+//   FP32   : v_mfma_f32_32x32x2f32,  real-block complex product (4 real MFMAs)
+//   BF16x3 : v_mfma_f32_32x32x16_bf16, each FP32 operand split into bf16 hi + lo,
+//            product ~ hi*hi + hi*lo + lo*hi with FP32 accumulation (12 MFMAs
+//            per complex block product).
+// Complex data are interleaved (re, im).  One workgroup = 4 waves (2 x 2),
+// each wave owns a WM x WN output tile; K is staged through LDS in BK slices,
+// stored k-major so that a half-wave reads 32 consecutive complex entries.
+// A job may chain several K segments (sum_j A_j B_j): this is how the right
+// environment contraction of the two-site matvec runs over all MPO channels.
+#include "common.h"
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+template <int PREC> struct GemmCfg;
+template <> struct GemmCfg<PREC_FP32> {
+  typedef cf32 CT;
+  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64, MB = 32, KSTEP = 2;
+};
+template <> struct GemmCfg<PREC_BF16X3> {
+  typedef cf32 CT;
+  static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 64, MB = 32, KSTEP = 16;
+};
+template <> struct GemmCfg<PREC_FP64> {
+  typedef cf64 CT;
+  static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MB = 16, KSTEP = 4;
+};
+
+static __device__ __forceinline__ __bf16 bf_from_bits(uint32_t b) {
+  return __builtin_bit_cast(__bf16, (unsigned short)(b & 0xffffu));
+}
+// x ~ hi + lo with hi = RNE(x) to bf16, lo = RNE(x - hi) to bf16.
+static __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  uint32_t u = __float_as_uint(x);
+  uint32_t hb = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+  float rem = x - __uint_as_float(hb);
+  uint32_t v = __float_as_uint(rem);
+  uint32_t lb = (v + 0x7fffu + ((v >> 16) & 1u)) >> 16;
+  hi = bf_from_bits(hb >> 16);
+  lo = bf_from_bits(lb);
+}
+static __device__ __forceinline__ __bf16 bf_neg(__bf16 x) {
+  unsigned short b = __builtin_bit_cast(unsigned short, x);
+  return __builtin_bit_cast(__bf16, (unsigned short)(b ^ 0x8000u));
+}
+
+template <typename CT, bool CONJ>
+static __device__ __forceinline__ CT ld_c(const CT* p) {
+  CT v = *p;
+  if (CONJ) v.y = -v.y;
+  return v;
+}
+
+template <int PREC, bool TA, bool TB>
+__global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ jobs,
+                                                    const GemmSeg* __restrict__ segs, int accumulate) {
+  using Cfg = GemmCfg<PREC>;
+  using CT = typename Cfg::CT;
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, WM = Cfg::WM, WN = Cfg::WN, MB = Cfg::MB;
+  constexpr int NI = WM / MB, NJ = WN / MB;
+  constexpr int NT = 256;
+  __shared__ CT As[BK][BM + 1];
+  __shared__ CT Bs[BK][BN + 1];
+
+  const GemmJob job = jobs[blockIdx.z];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (m0 >= job.M || n0 >= job.N) return;
+  const int M = job.M, N = job.N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+
+  typedef typename std::conditional<PREC == PREC_FP64, v4d, v16f>::type AccT;
+  AccT accR[NI][NJ], accI[NI][NJ];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      accR[i][j] = AccT{};
+      accI[i][j] = AccT{};
+    }
+
+  for (int sg = 0; sg < job.nseg; ++sg) {
+    const GemmSeg seg = segs[job.seg0 + sg];
+    const CT* __restrict__ A = reinterpret_cast<const CT*>(seg.A);
+    const CT* __restrict__ B = reinterpret_cast<const CT*>(seg.B);
+    const int64_t lda = seg.lda, ldb = seg.ldb;
+    const int K = seg.K;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      // ---- stage A tile (BM x BK of op(A)) into As[k][m]
+#pragma unroll 4
+      for (int idx = tid; idx < BM * BK; idx += NT) {
+        int mm, kk;
+        if (!TA) { mm = idx / BK; kk = idx % BK; }
+        else     { kk = idx / BM; mm = idx % BM; }
+        const int gm = m0 + mm, gk = k0 + kk;
+        CT v = czero<CT>();
+        if (gm < M && gk < K) v = TA ? ld_c<CT, true>(A + (int64_t)gk * lda + gm) : A[(int64_t)gm * lda + gk];
+        As[kk][mm] = v;
+      }
+      // ---- stage B tile (BK x BN of op(B)) into Bs[k][n]
+#pragma unroll 4
+      for (int idx = tid; idx < BK * BN; idx += NT) {
+        int kk, nn;
+        if (!TB) { kk = idx / BN; nn = idx % BN; }
+        else     { nn = idx / BK; kk = idx % BK; }
+        const int gn = n0 + nn, gk = k0 + kk;
+        CT v = czero<CT>();
+        if (gn < N && gk < K) v = TB ? ld_c<CT, true>(B + (int64_t)gn * ldb + gk) : B[(int64_t)gk * ldb + gn];
+        Bs[kk][nn] = v;
+      }
+      __syncthreads();
+
+      if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 2) {
+          float ar[NI], ai[NI], br[NJ], bi[NJ];
+#pragma unroll
+          for (int i = 0; i < NI; ++i) {
+            CT v = As[kk + (lane >> 5)][wm0 + 32 * i + (lane & 31)];
+            ar[i] = v.x; ai[i] = v.y;
+          }
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            CT v = Bs[kk + (lane >> 5)][wn0 + 32 * j + (lane & 31)];
+            br[j] = v.x; bi[j] = v.y;
+          }
+#pragma unroll
+          for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+              accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], accR[i][j], 0, 0, 0);
+              accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[i], bi[j], accR[i][j], 0, 0, 0);
+              accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], bi[j], accI[i][j], 0, 0, 0);
+              accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], br[j], accI[i][j], 0, 0, 0);
+            }
+        }
+      } else if constexpr (PREC == PREC_FP64) {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          double ar[NI], ai[NI], br[NJ], bi[NJ];
+#pragma unroll
+          for (int i = 0; i < NI; ++i) {
+            CT v = As[kk + (lane >> 4)][wm0 + 16 * i + (lane & 15)];
+            ar[i] = v.x; ai[i] = v.y;
+          }
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            CT v = Bs[kk + (lane >> 4)][wn0 + 16 * j + (lane & 15)];
+            br[j] = v.x; bi[j] = v.y;
+          }
+#pragma unroll
+          for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
+              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accR[i][j], 0, 0, 0);
+              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+            }
+        }
+      } else {  // BF16x3
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+          v8bf arh[NI], arl[NI], aih[NI], ail[NI], naih[NI], nail[NI];
+          v8bf brh[NJ], brl[NJ], bih[NJ], bil[NJ];
+#pragma unroll
+          for (int i = 0; i < NI; ++i) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              CT v = As[kk + 8 * (lane >> 5) + t][wm0 + 32 * i + (lane & 31)];
+              __bf16 h, l;
+              split_bf16(v.x, h, l); arh[i][t] = h; arl[i][t] = l;
+              split_bf16(v.y, h, l); aih[i][t] = h; ail[i][t] = l;
+              naih[i][t] = bf_neg(h); nail[i][t] = bf_neg(l);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              CT v = Bs[kk + 8 * (lane >> 5) + t][wn0 + 32 * j + (lane & 31)];
+              __bf16 h, l;
+              split_bf16(v.x, h, l); brh[j][t] = h; brl[j][t] = l;
+              split_bf16(v.y, h, l); bih[j][t] = h; bil[j][t] = l;
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+              v16f r = accR[i][j], m = accI[i][j];
+              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brh[j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brl[j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], brh[j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih[i], bih[j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih[i], bil[j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nail[i], bih[j], r, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bih[j], m, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bil[j], m, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], bih[j], m, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brh[j], m, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brl[j], m, 0, 0, 0);
+              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail[i], brh[j], m, 0, 0, 0);
+              accR[i][j] = r; accI[i][j] = m;
+            }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- epilogue
+  CT* __restrict__ C = reinterpret_cast<CT*>(job.C);
+  const int64_t ldc = job.ldc;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if constexpr (PREC == PREC_FP64) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // v_mfma_f64_16x16x4f64: accumulator r of lane l holds D[l/16 + 4r][l%16]
+          const int row = m0 + wm0 + 16 * i + (lane >> 4) + 4 * r;
+          const int col = n0 + wn0 + 16 * j + (lane & 15);
+          if (row < M && col < N) {
+            CT v = cmk(accR[i][j][r], accI[i][j][r]);
+            CT* p = C + (int64_t)row * ldc + col;
+            if (accumulate) v = cadd(v, *p);
+            *p = v;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int col = n0 + wn0 + 32 * j + (lane & 31);
+          if (row < M && col < N) {
+            CT v = cmk(accR[i][j][r], accI[i][j][r]);
+            CT* p = C + (int64_t)row * ldc + col;
+            if (accumulate) v = cadd(v, *p);
+            *p = v;
+          }
+        }
+      }
+    }
+}
+
+template <int PREC>
+static hipError_t launch_prec(int ta, int tb, const GemmJob* jobs, int njobs, const GemmSeg* segs, int maxM,
+                              int maxN, int acc, hipStream_t st) {
+  using Cfg = GemmCfg<PREC>;
+  if (njobs <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
+  dim3 grid((maxN + Cfg::BN - 1) / Cfg::BN, (maxM + Cfg::BM - 1) / Cfg::BM, njobs);
+  dim3 block(256);
+  if (!ta && !tb) hipLaunchKernelGGL((cgemm_kernel<PREC, false, false>), grid, block, 0, st, jobs, segs, acc);
+  else if (ta && !tb) hipLaunchKernelGGL((cgemm_kernel<PREC, true, false>), grid, block, 0, st, jobs, segs, acc);
+  else if (!ta && tb) hipLaunchKernelGGL((cgemm_kernel<PREC, false, true>), grid, block, 0, st, jobs, segs, acc);
+  else hipLaunchKernelGGL((cgemm_kernel<PREC, true, true>), grid, block, 0, st, jobs, segs, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgemm(int prec, int trans_a, int trans_b, const GemmJob* d_jobs, int njobs, const GemmSeg* d_segs,
+                        int maxM, int maxN, int accumulate, hipStream_t st) {
+  switch (prec) {
+    case PREC_FP64: return launch_prec<PREC_FP64>(trans_a, trans_b, d_jobs, njobs, d_segs, maxM, maxN, accumulate, st);
+    case PREC_FP32: return launch_prec<PREC_FP32>(trans_a, trans_b, d_jobs, njobs, d_segs, maxM, maxN, accumulate, st);
+    case PREC_BF16X3:
+      return launch_prec<PREC_BF16X3>(trans_a, trans_b, d_jobs, njobs, d_segs, maxM, maxN, accumulate, st);
+  }
+  return hipErrorInvalidValue;
+}

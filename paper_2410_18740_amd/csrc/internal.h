@@ -1,0 +1,149 @@
+// Host-side internals of the library (not part of the C ABI).
+#pragma once
+#include <complex>
+#include <map>
+#include <string>
+#include <vector>
+#include <array>
+#include <stdexcept>
+#include "common.h"
+#include "../../include/tn.h"
+
+typedef std::complex<double> cd;
+
+// exception carrying a tn_status; converted at the ABI boundary
+struct TnError : std::runtime_error {
+  tn_status code;
+  TnError(tn_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+#define TN_THROW(code, msg) throw TnError((code), (msg))
+#define HIPCHK(x)                                                                              \
+  do {                                                                                         \
+    hipError_t e__ = (x);                                                                      \
+    if (e__ != hipSuccess)                                                                     \
+      throw TnError(TN_EHIP, std::string(#x) + ": " + hipGetErrorString(e__) + " @" + __FILE__ \
+                                 + ":" + std::to_string(__LINE__));                            \
+  } while (0)
+
+struct tn_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  tn_allocator alloc{};
+  bool has_alloc = false;
+  std::string err;
+  std::map<std::string, std::pair<void*, size_t>> ws;  // named workspaces
+  double* pinned = nullptr;                             // host pinned scratch (4096 doubles)
+  hipEvent_t ev[8];
+  bool ev_ok = false;
+};
+
+void* dev_alloc(tn_ctx* c, size_t bytes);
+void dev_free(tn_ctx* c, void* p);
+void* ws_get(tn_ctx* c, const std::string& name, size_t bytes);
+template <typename T> T* wsT(tn_ctx* c, const std::string& name, size_t count) {
+  return reinterpret_cast<T*>(ws_get(c, name, count * sizeof(T)));
+}
+void upload(tn_ctx* c, void* dst, const void* src, size_t bytes);
+void download(tn_ctx* c, void* dst, const void* src, size_t bytes);  // synchronising
+
+// entry decomposition of a core block into the basis {I, X, P, S}
+struct CoreEntry {
+  int row, col;
+  int kind;
+  double c[4];
+};
+
+struct tn_mpo {
+  tn_ctx* ctx = nullptr;
+  int N = 0, D_raw = 0, d = 0;
+  std::vector<int> w;                            // N+1
+  std::vector<std::vector<int8_t>> kinds;        // per site, w[s] x w[s+1]
+  std::vector<std::vector<CoreEntry>> entries;   // per site
+  std::vector<double> r;
+  std::vector<cd> U;
+  std::vector<double> alpha, beta, gamma;        // N x N
+  std::vector<std::vector<cd>> iso;              // per site D_raw x d
+  std::vector<std::vector<cd>> raw_ops;          // per site 3 x D_raw x D_raw (X, P, S)
+  std::vector<std::vector<cd>> loc_ops;          // per site 3 x d x d
+  cf64* d_ops64 = nullptr;   // [N][3][d][d]
+  cf32* d_ops32 = nullptr;
+  cf64* d_raw64 = nullptr;   // [N][3][D][D]
+  cf32* d_raw32 = nullptr;
+  cf64* d_iso = nullptr;     // [N][D][d]
+  uint64_t version = 1;
+  void upload_site(int s);
+  const void* op_ptr(int prec, int site, int kind_xps, bool raw) const;  // kind 1:X 2:P 3:S
+};
+
+struct tn_mps {
+  tn_ctx* ctx = nullptr;
+  int N = 0, d = 0;
+  std::vector<int> dims;        // N+1
+  std::vector<cf64*> A;         // device tensors, capacity per site
+  std::vector<size_t> cap;      // elements allocated
+  int center = -1;              // orthogonality centre (site), -1 unknown
+  // cached environments (precision env_prec): L[s] at bond s, Rt[s] at bond s (transposed)
+  int env_prec = -1;
+  const tn_mpo* env_mpo = nullptr;
+  uint64_t env_version = 0;
+  std::vector<void*> L, Rt;
+  std::vector<size_t> Lcap, Rcap;
+  std::vector<bool> Lok, Rok;
+  void ensure_site(int s, size_t elems);
+};
+
+// ------------------------------------------------------------------ planner
+struct PlanL {  // effective left channel: mixture of original channels
+  std::vector<std::pair<int, double>> src;
+};
+struct PlanTerm {
+  int ych;  // index into PlanL / Y buffers
+  int a, b; // 0 I, 1 X, 2 P, 3 S on leg 0 / leg 1
+  double c;
+};
+struct PlanT {
+  std::vector<PlanTerm> terms;
+};
+struct PlanR {
+  int kind;  // 0: Y buffer, 1: T buffer
+  int idx;
+  std::vector<std::pair<int, double>> env;  // mixture of right channels
+};
+struct Plan {
+  std::vector<PlanL> L;
+  std::vector<PlanT> T;
+  std::vector<PlanR> R;
+};
+struct Term2 {
+  int l, n, a, b;
+  double c;
+};
+// terms of O[l][n] = sum_m W_s[l][m] (x) W_{s+1}[m][n] (two-site) or W_s[l][n] (one site)
+std::vector<Term2> window_terms(const tn_mpo* mpo, int site, int nsites);
+// transpose roles (for right environment updates): l <-> n
+Plan build_plan(const std::vector<Term2>& terms, int wl, int wr, bool allow_right_fold);
+
+// Executes the window operator for a plan.  Input x and output y are FP64
+// (n = chi_l*ds*dt*chi_r); envL[l] (chi_l x chi_l) and envRt[n] (chi_r x chi_r,
+// transposed) in precision prec.
+struct WindowOp {
+  tn_ctx* ctx = nullptr;
+  int prec = 0, chi_l = 0, ds = 0, dt = 0, chi_r = 0;
+  Plan plan;
+  // device descriptor arrays
+  GemmJob* d_jobL = nullptr; GemmSeg* d_segL = nullptr; int njobL = 0;
+  OpJob* d_opjob = nullptr; OpTerm* d_opterm = nullptr; int nopjob = 0;
+  GemmJob* d_jobR = nullptr; GemmSeg* d_segR = nullptr; int njobR = 0;
+  void* xin = nullptr;      // input in prec (if prec != FP64)
+  void* partials = nullptr; // split-K partials
+  int nsplit = 1;
+  size_t n = 0;
+  void setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int prec_, int chi_l_, int chi_r_,
+             const std::vector<const void*>& envL, const std::vector<const void*>& envRt, bool raw_leg0,
+             const std::string& tag);
+  void apply(const cf64* x, cf64* y);
+};
+
+size_t elem_bytes(int prec);
+double matvec_flops_formula(const tn_mpo* mpo, int site, int chi_l, int chi_r);
+double env_flops_formula(const tn_mpo* mpo, int site, int chi_l, int chi_r);

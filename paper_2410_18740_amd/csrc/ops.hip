@@ -1,0 +1,452 @@
+// Memory-bound helper kernels: local-operator application on the physical legs
+// of a (chi_l, ds, dt, chi_r) tensor, linear combinations of environment
+// channels, precision conversion, split-K reduction, and the FP64 Krylov
+// vector kernels (multi-dot with fixed-order two-stage reduction, multi-axpy,
+// scaling, linear combination).  All reductions are deterministic: block
+// partials are combined in a fixed order, never with atomics.
+#include "common.h"
+
+// ------------------------------------------------------------------ op apply
+// Workgroup = one (job, a, b-chunk).  LDS holds the source slice src[s'][t'][b],
+// a temporary after the t-leg operator, and the accumulator.
+template <typename CT>
+__global__ __launch_bounds__(256) void opapply_kernel(const OpJob* __restrict__ jobs, const OpTerm* __restrict__ terms,
+                                                       int chi_l, int ds, int dt, int chi_r, int bw) {
+  extern __shared__ unsigned char smem_raw[];
+  CT* sm = reinterpret_cast<CT*>(smem_raw);
+  const int dsdt = ds * dt;
+  const int nb_chunks = (chi_r + bw - 1) / bw;
+  const int job_id = blockIdx.y;
+  const int a = blockIdx.x / nb_chunks;
+  const int b0 = (blockIdx.x % nb_chunks) * bw;
+  const int bcnt = min(bw, chi_r - b0);
+  const int slice = dsdt * bw;
+  CT* src = sm;
+  CT* tmp = sm + slice;
+  CT* acc = sm + 2 * slice;
+  CT* opsm = sm + 3 * slice;  // ds*ds + dt*dt
+  const OpJob job = jobs[job_id];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)a * dsdt * chi_r;  // element offset of [a][0][0][0]
+  CT* dst = reinterpret_cast<CT*>(job.dst);
+
+  for (int e = tid; e < dsdt * bcnt; e += 256) {
+    const int st = e / bcnt, bb = e % bcnt;
+    acc[st * bw + bb] = job.accumulate ? dst[base + (int64_t)st * chi_r + b0 + bb] : czero<CT>();
+  }
+  for (int t = 0; t < job.nterms; ++t) {
+    const OpTerm term = terms[job.t0 + t];
+    const CT* s = reinterpret_cast<const CT*>(term.src);
+    const CT* oA = reinterpret_cast<const CT*>(term.opA);
+    const CT* oB = reinterpret_cast<const CT*>(term.opB);
+    __syncthreads();
+    for (int e = tid; e < dsdt * bcnt; e += 256) {
+      const int st = e / bcnt, bb = e % bcnt;
+      src[st * bw + bb] = s[base + (int64_t)st * chi_r + b0 + bb];
+    }
+    for (int e = tid; e < ds * ds; e += 256) opsm[e] = oA ? oA[e] : czero<CT>();
+    for (int e = tid; e < dt * dt; e += 256) opsm[ds * ds + e] = oB ? oB[e] : czero<CT>();
+    __syncthreads();
+    // stage 1: tmp[s'][t][b] = sum_t' opB[t][t'] src[s'][t'][b]
+    const CT* in1 = src;
+    if (oB) {
+      for (int e = tid; e < dsdt * bcnt; e += 256) {
+        const int st = e / bcnt, bb = e % bcnt;
+        const int sp = st / dt, tt = st % dt;
+        CT v = czero<CT>();
+        for (int tp = 0; tp < dt; ++tp) v = cadd(v, cmul(opsm[ds * ds + tt * dt + tp], src[(sp * dt + tp) * bw + bb]));
+        tmp[st * bw + bb] = v;
+      }
+      __syncthreads();
+      in1 = tmp;
+    }
+    // stage 2: acc[s][t][b] += coef * sum_s' opA[s][s'] in1[s'][t][b]
+    const typename real_of<CT>::type c = (typename real_of<CT>::type)term.coef;
+    for (int e = tid; e < dsdt * bcnt; e += 256) {
+      const int st = e / bcnt, bb = e % bcnt;
+      const int ss = st / dt, tt = st % dt;
+      CT v;
+      if (oA) {
+        v = czero<CT>();
+        for (int sp = 0; sp < ds; ++sp) v = cadd(v, cmul(opsm[ss * ds + sp], in1[(sp * dt + tt) * bw + bb]));
+      } else {
+        v = in1[st * bw + bb];
+      }
+      acc[st * bw + bb] = cadd(acc[st * bw + bb], cscale(v, c));
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < dsdt * bcnt; e += 256) {
+    const int st = e / bcnt, bb = e % bcnt;
+    dst[base + (int64_t)st * chi_r + b0 + bb] = acc[st * bw + bb];
+  }
+}
+
+static int pick_bw(int elem_bytes, int dsdt, int ds, int dt, int chi_r) {
+  const int budget = 96 * 1024;
+  int bw = 64;
+  while (bw > 1 && (3 * dsdt * bw + ds * ds + dt * dt) * elem_bytes > budget) bw >>= 1;
+  if (bw > chi_r) {
+    bw = 1;
+    while (bw < chi_r) bw <<= 1;
+  }
+  return bw;
+}
+
+hipError_t launch_opapply(int prec, const OpJob* d_jobs, int njobs, const OpTerm* d_terms, int chi_l, int ds, int dt,
+                          int chi_r, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  const int eb = (prec == PREC_FP64) ? 16 : 8;
+  const int bw = pick_bw(eb, ds * dt, ds, dt, chi_r);
+  const int nb_chunks = (chi_r + bw - 1) / bw;
+  dim3 grid(chi_l * nb_chunks, njobs);
+  const size_t shm = (size_t)(3 * ds * dt * bw + ds * ds + dt * dt) * eb;
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL(opapply_kernel<cf64>, grid, dim3(256), shm, st, d_jobs, d_terms, chi_l, ds, dt, chi_r, bw);
+  else
+    hipLaunchKernelGGL(opapply_kernel<cf32>, grid, dim3(256), shm, st, d_jobs, d_terms, chi_l, ds, dt, chi_r, bw);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ env mixing
+template <typename CT>
+__global__ void envmix_kernel(const MixJob* __restrict__ jobs, const MixTerm* __restrict__ terms, int64_t n) {
+  const MixJob job = jobs[blockIdx.y];
+  CT* dst = reinterpret_cast<CT*>(job.dst);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    CT v = czero<CT>();
+    for (int t = 0; t < job.nterms; ++t) {
+      const MixTerm mt = terms[job.t0 + t];
+      v = cadd(v, cscale(reinterpret_cast<const CT*>(mt.src)[e], (typename real_of<CT>::type)mt.coef));
+    }
+    dst[e] = v;
+  }
+}
+hipError_t launch_envmix(int prec, const MixJob* d_jobs, int njobs, const MixTerm* d_terms, int64_t n_elem,
+                         hipStream_t st) {
+  if (njobs <= 0 || n_elem <= 0) return hipSuccess;
+  int gx = (int)std::min<int64_t>((n_elem + 255) / 256, 1024);
+  dim3 grid(gx, njobs);
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL(envmix_kernel<cf64>, grid, dim3(256), 0, st, d_jobs, d_terms, n_elem);
+  else
+    hipLaunchKernelGGL(envmix_kernel<cf32>, grid, dim3(256), 0, st, d_jobs, d_terms, n_elem);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ conversion
+__global__ void cvt_64_32(cf32* dst, const cf64* src, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = make_float2((float)src[e].x, (float)src[e].y);
+}
+__global__ void cvt_32_64(cf64* dst, const cf32* src, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = make_double2((double)src[e].x, (double)src[e].y);
+}
+__global__ void cpy_64(cf64* dst, const cf64* src, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+__global__ void cpy_32(cf32* dst, const cf32* src, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+
+hipError_t launch_convert(int to_prec, void* dst, int from_prec, const void* src, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const bool to64 = to_prec == PREC_FP64, from64 = from_prec == PREC_FP64;
+  if (to64 && from64) hipLaunchKernelGGL(cpy_64, dim3(grid_for(n)), dim3(256), 0, st, (cf64*)dst, (const cf64*)src, n);
+  else if (!to64 && from64) hipLaunchKernelGGL(cvt_64_32, dim3(grid_for(n)), dim3(256), 0, st, (cf32*)dst, (const cf64*)src, n);
+  else if (to64 && !from64) hipLaunchKernelGGL(cvt_32_64, dim3(grid_for(n)), dim3(256), 0, st, (cf64*)dst, (const cf32*)src, n);
+  else hipLaunchKernelGGL(cpy_32, dim3(grid_for(n)), dim3(256), 0, st, (cf32*)dst, (const cf32*)src, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ split-K reduction -> FP64
+template <typename CT>
+__global__ void reduce_partials_kernel(cf64* out, const CT* parts, int nparts, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int p = 0; p < nparts; ++p) {
+      CT v = parts[(int64_t)p * n + e];
+      re += (double)v.x;
+      im += (double)v.y;
+    }
+    out[e] = make_double2(re, im);
+  }
+}
+hipError_t launch_reduce_partials(cf64* out, int prec, const void* partials, int nparts, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL(reduce_partials_kernel<cf64>, dim3(grid_for(n)), dim3(256), 0, st, out, (const cf64*)partials, nparts, n);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel<cf32>, dim3(grid_for(n)), dim3(256), 0, st, out, (const cf32*)partials, nparts, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Krylov vector kernels (FP64)
+// wavefront-level tree reduction (fixed order) followed by a workgroup stage
+static __device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+#define MD_MAXV 64
+int multidot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 512)); }
+
+// partials[v][block] = sum_{e in block} conj(vs[v][e]) * w[e]
+__global__ __launch_bounds__(256) void multidot_kernel(const cf64* const* __restrict__ vs, int nv,
+                                                        const cf64* __restrict__ w, int64_t n, cf64* partials,
+                                                        int nblocks) {
+  __shared__ double red[2][4][MD_MAXV];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t per = (n + nblocks - 1) / nblocks;
+  const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min(n, e0 + per);
+  for (int v = 0; v < nv; ++v) {
+    const cf64* x = vs[v];
+    double re = 0.0, im = 0.0;
+    for (int64_t e = e0 + tid; e < e1; e += 256) {
+      const cf64 a = x[e], b = w[e];
+      re += a.x * b.x + a.y * b.y;
+      im += a.x * b.y - a.y * b.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) { red[0][wave][v] = re; red[1][wave][v] = im; }
+  }
+  __syncthreads();
+  for (int v = tid; v < nv; v += 256) {
+    double re = red[0][0][v] + red[0][1][v] + red[0][2][v] + red[0][3][v];
+    double im = red[1][0][v] + red[1][1][v] + red[1][2][v] + red[1][3][v];
+    partials[(int64_t)v * nblocks + blockIdx.x] = make_double2(re, im);
+  }
+}
+__global__ void multidot_finish_kernel(const cf64* partials, int nv, int nblocks, cf64* out) {
+  const int v = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ double sre[64], sim[64];
+  double re = 0.0, im = 0.0;
+  for (int b = tid; b < nblocks; b += 64) {
+    re += partials[(int64_t)v * nblocks + b].x;
+    im += partials[(int64_t)v * nblocks + b].y;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (tid == 0) out[v] = make_double2(re, im);
+  (void)sre; (void)sim;
+}
+hipError_t launch_multidot(const cf64* const* vs, int nv, const cf64* w, int64_t n, cf64* partials, int nblocks,
+                           hipStream_t st) {
+  if (nv <= 0) return hipSuccess;
+  if (nv > MD_MAXV) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(256), 0, st, vs, nv, w, n, partials, nblocks);
+  return hipGetLastError();
+}
+hipError_t launch_multidot_finish(const cf64* partials, int nv, int nblocks, cf64* out, hipStream_t st) {
+  if (nv <= 0) return hipSuccess;
+  hipLaunchKernelGGL(multidot_finish_kernel, dim3(nv), dim3(64), 0, st, partials, nv, nblocks, out);
+  return hipGetLastError();
+}
+
+// w -= sign * sum_v coefs[v] * vs[v]   (coefs on device)
+__global__ void multiaxpy_kernel(cf64* w, const cf64* const* __restrict__ vs, int nv, const cf64* __restrict__ coefs,
+                                 double sign, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    cf64 acc = w[e];
+    for (int v = 0; v < nv; ++v) {
+      const cf64 c = coefs[v];
+      const cf64 x = vs[v][e];
+      acc.x -= sign * (c.x * x.x - c.y * x.y);
+      acc.y -= sign * (c.x * x.y + c.y * x.x);
+    }
+    w[e] = acc;
+  }
+}
+hipError_t launch_multiaxpy(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, double sign, int64_t n,
+                            hipStream_t st) {
+  if (nv <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(multiaxpy_kernel, dim3(grid_for(n)), dim3(256), 0, st, w, vs, nv, coefs, sign, n);
+  return hipGetLastError();
+}
+
+// dst = src * inv_norm[0]
+__global__ void scale_kernel(cf64* dst, const cf64* src, const double* s, int64_t n) {
+  const double f = s[0];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = make_double2(src[e].x * f, src[e].y * f);
+}
+hipError_t launch_scale(cf64* dst, const cf64* src, const double* inv_norm_dev, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, src, inv_norm_dev, n);
+  return hipGetLastError();
+}
+
+// dst = sum_v coefs[v] * vs[v]  (real coefficients on device)
+__global__ void lincomb_kernel(cf64* dst, const cf64* const* __restrict__ vs, int nv, const double* __restrict__ c,
+                               int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int v = 0; v < nv; ++v) {
+      const cf64 x = vs[v][e];
+      re += c[v] * x.x;
+      im += c[v] * x.y;
+    }
+    dst[e] = make_double2(re, im);
+  }
+}
+hipError_t launch_lincomb(cf64* dst, const cf64* const* vs, int nv, const double* coefs_dev, int64_t n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, vs, nv, coefs_dev, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched transpose with precision change
+// dst[b][j][i] = src[b][i][j]  (src FP64 complex rows x cols -> dst prec cols x rows)
+template <typename CT>
+__global__ void transpose_kernel(CT* dst, const cf64* src, int batch, int rows, int cols) {
+  const int64_t per = (int64_t)rows * cols;
+  const int64_t tot = per * batch;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / per, r = e % per;
+    const int i = (int)(r / cols), j = (int)(r % cols);
+    const cf64 v = src[e];
+    CT o;
+    o.x = v.x; o.y = v.y;
+    dst[b * per + (int64_t)j * rows + i] = o;
+  }
+}
+hipError_t launch_transpose_from64(int prec, void* dst, const cf64* src, int batch, int rows, int cols,
+                                   hipStream_t st) {
+  const int64_t tot = (int64_t)batch * rows * cols;
+  if (tot <= 0) return hipSuccess;
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL(transpose_kernel<cf64>, dim3(grid_for(tot)), dim3(256), 0, st, (cf64*)dst, src, batch, rows, cols);
+  else
+    hipLaunchKernelGGL(transpose_kernel<cf32>, dim3(grid_for(tot)), dim3(256), 0, st, (cf32*)dst, src, batch, rows, cols);
+  return hipGetLastError();
+}
+// dst (FP64) [b][j][i] = src(prec)[b][i][j]
+template <typename CT>
+__global__ void transpose_to64_kernel(cf64* dst, const CT* src, int batch, int rows, int cols) {
+  const int64_t per = (int64_t)rows * cols;
+  const int64_t tot = per * batch;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / per, r = e % per;
+    const int i = (int)(r / cols), j = (int)(r % cols);
+    const CT v = src[e];
+    dst[b * per + (int64_t)j * rows + i] = make_double2((double)v.x, (double)v.y);
+  }
+}
+hipError_t launch_transpose_to64(int prec, cf64* dst, const void* src, int batch, int rows, int cols, hipStream_t st) {
+  const int64_t tot = (int64_t)batch * rows * cols;
+  if (tot <= 0) return hipSuccess;
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL(transpose_to64_kernel<cf64>, dim3(grid_for(tot)), dim3(256), 0, st, dst, (const cf64*)src, batch, rows, cols);
+  else
+    hipLaunchKernelGGL(transpose_to64_kernel<cf32>, dim3(grid_for(tot)), dim3(256), 0, st, dst, (const cf32*)src, batch, rows, cols);
+  return hipGetLastError();
+}
+// dst = src * s (host scalar), FP64 complex
+__global__ void scale_host_kernel(cf64* dst, const cf64* src, double s, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = make_double2(src[e].x * s, src[e].y * s);
+}
+hipError_t launch_scale_host(cf64* dst, const cf64* src, double s, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_host_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, src, s, n);
+  return hipGetLastError();
+}
+// dst[k x n] = conj-transpose of src[n x k]
+__global__ void ctranspose_kernel(cf64* dst, const cf64* src, int n, int k) {
+  const int64_t tot = (int64_t)n * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / k), j = (int)(e % k);  // src[i][j]
+    const cf64 v = src[e];
+    dst[(int64_t)j * n + i] = make_double2(v.x, -v.y);
+  }
+}
+hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream_t st) {
+  const int64_t tot = (int64_t)n * k;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ctranspose_kernel, dim3(grid_for(tot)), dim3(256), 0, st, dst, src, n, k);
+  return hipGetLastError();
+}
+// Lanczos scalars: alpha_j = Re(h1[j] + h2[j]), beta_j = sqrt(nrm2), inv = 1/beta_j
+__global__ void lanczos_scalars_kernel(const cf64* h1, const cf64* h2, const cf64* nrm2, int j, double* alpha,
+                                       double* beta, double* inv, double* host_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double a = h1[j].x + h2[j].x;
+    const double b = sqrt(fmax(nrm2[0].x, 0.0));
+    alpha[j] = a;
+    beta[j] = b;
+    inv[0] = (b > 0.0) ? 1.0 / b : 0.0;
+    host_out[0] = a;
+    host_out[1] = b;
+  }
+}
+hipError_t launch_lanczos_scalars(const cf64* h1, const cf64* h2, const cf64* nrm2, int j, double* alpha, double* beta,
+                                  double* inv, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(lanczos_scalars_kernel, dim3(1), dim3(64), 0, st, h1, h2, nrm2, j, alpha, beta, inv, out);
+  return hipGetLastError();
+}
+// gather real parts of column 0 of an n x n complex matrix (eigenvectors as columns)
+__global__ void ritz_coefs_kernel(const cf64* V, int n, double* out, double* last) {
+  const int i = threadIdx.x;
+  if (i < n) out[i] = V[(int64_t)i * n].x;
+  if (i == 0) last[0] = V[(int64_t)(n - 1) * n].x;
+}
+hipError_t launch_ritz_coefs(const cf64* V, int n, double* out, double* last, hipStream_t st) {
+  hipLaunchKernelGGL(ritz_coefs_kernel, dim3(1), dim3(64), 0, st, V, n, out, last);
+  return hipGetLastError();
+}
+// non-finite check: flag[0] = 1 if any entry is NaN/Inf
+__global__ void finite_check_kernel(const cf64* x, int64_t n, int* flag) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const cf64 v = x[e];
+    if (!isfinite(v.x) || !isfinite(v.y)) flag[0] = 1;
+  }
+}
+hipError_t launch_finite_check(const cf64* x, int64_t n, int* flag, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finite_check_kernel, dim3(grid_for(n)), dim3(256), 0, st, x, n, flag);
+  return hipGetLastError();
+}
+__global__ void fill_int_kernel(int* p, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+// set boundary environment [[[1]]]
+__global__ void set_one_kernel(void* p, int prec) {
+  if (threadIdx.x == 0) {
+    if (prec == PREC_FP64) ((cf64*)p)[0] = make_double2(1.0, 0.0);
+    else ((cf32*)p)[0] = make_float2(1.f, 0.f);
+  }
+}
+hipError_t launch_set_one(void* p, int prec, hipStream_t st) {
+  hipLaunchKernelGGL(set_one_kernel, dim3(1), dim3(64), 0, st, p, prec);
+  return hipGetLastError();
+}
+// dst[i*ldd + j] = conj?(src[i*lds + j]) for i < rows, j < cols (FP64 complex)
+__global__ void copy2d_kernel(cf64* dst, int64_t ldd, const cf64* src, int64_t lds, int rows, int cols, int conj_t) {
+  const int64_t tot = (int64_t)rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    const cf64 v = src[(int64_t)i * lds + j];
+    if (conj_t) dst[(int64_t)j * ldd + i] = make_double2(v.x, -v.y);  // dst is cols x rows
+    else dst[(int64_t)i * ldd + j] = v;
+  }
+}
+hipError_t launch_copy2d(cf64* dst, int64_t ldd, const cf64* src, int64_t lds, int rows, int cols, int conj_t,
+                         hipStream_t st) {
+  const int64_t tot = (int64_t)rows * cols;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(tot)), dim3(256), 0, st, dst, ldd, src, lds, rows, cols, conj_t);
+  return hipGetLastError();
+}

@@ -1,0 +1,251 @@
+// Observables of the converged MPS in the raw Fock basis: single-mode
+// photon-number marginals (contraction of rho_j) and sequential conditional
+// sampling of photon-number patterns with a counter-based Philox4x32-10
+// generator (Salmon, Moraes, Dror, Shaw, SC'11).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include "internal.h"
+
+#define TN_GUARD_BEGIN try {
+#define TN_GUARD_END(ctx)                                         \
+  }                                                               \
+  catch (const TnError& e) {                                      \
+    if (ctx) (ctx)->err = e.what();                               \
+    return e.code;                                                \
+  }                                                               \
+  catch (const std::exception& e) {                               \
+    if (ctx) (ctx)->err = e.what();                               \
+    return TN_EINVAL;                                             \
+  }                                                               \
+  if (ctx) (ctx)->err.clear();                                    \
+  return TN_OK;
+
+// ------------------------------------------------------------------ Philox4x32-10
+struct u32x4 { uint32_t v[4]; };
+static __device__ __forceinline__ void mulhilo32(uint32_t a, uint32_t b, uint32_t& hi, uint32_t& lo) {
+  const uint64_t p = (uint64_t)a * (uint64_t)b;
+  hi = (uint32_t)(p >> 32);
+  lo = (uint32_t)p;
+}
+static __device__ u32x4 philox4x32_10(u32x4 ctr, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint32_t hi0, lo0, hi1, lo1;
+    mulhilo32(M0, ctr.v[0], hi0, lo0);
+    mulhilo32(M1, ctr.v[2], hi1, lo1);
+    u32x4 n;
+    n.v[0] = hi1 ^ ctr.v[1] ^ k0;
+    n.v[1] = lo1;
+    n.v[2] = hi0 ^ ctr.v[3] ^ k1;
+    n.v[3] = lo0;
+    ctr = n;
+  }
+  return ctr;
+}
+// u in [0, 1) with 53 random bits from the first two output words
+static __device__ __forceinline__ double philox_uniform(uint64_t sample, uint32_t site, uint64_t seed) {
+  u32x4 c;
+  c.v[0] = (uint32_t)sample;
+  c.v[1] = (uint32_t)(sample >> 32);
+  c.v[2] = site;
+  c.v[3] = 0u;
+  const u32x4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t a = r.v[0] >> 5, b = r.v[1] >> 6;
+  return ((double)a * 67108864.0 + (double)b) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void philox_test_kernel(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  u32x4 c;
+  for (int j = 0; j < 4; ++j) c.v[j] = ctr[4 * i + j];
+  const u32x4 r = philox4x32_10(c, key[2 * i], key[2 * i + 1]);
+  for (int j = 0; j < 4; ++j) out[4 * i + j] = r.v[j];
+}
+
+// one wavefront per sample: probabilities over D outcomes, inverse CDF, gather
+__global__ __launch_bounds__(256) void sample_step_kernel(const cf64* __restrict__ Tmp, int B, int D, int cr,
+                                                          uint64_t sample0, int site, uint64_t seed,
+                                                          cf64* __restrict__ Vnew, int32_t* __restrict__ out, int N) {
+  __shared__ double p[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = blockIdx.x * 4 + wave;
+  if (b >= B) return;
+  const cf64* row = Tmp + (size_t)b * D * cr;
+  for (int n = 0; n < D; ++n) {
+    double s = 0.0;
+    for (int j = lane; j < cr; j += 64) s += cabs2(row[(size_t)n * cr + j]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) p[wave][n] = s;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __syncthreads();
+  double tot = 0.0;
+  for (int n = 0; n < D; ++n) tot += p[wave][n];
+  const double u = philox_uniform(sample0 + (uint64_t)b, (uint32_t)site, seed) * tot;
+  int pick = D - 1;
+  double cum = 0.0;
+  for (int n = 0; n < D; ++n) {
+    cum += p[wave][n];
+    if (cum >= u && p[wave][n] > 0.0) { pick = n; break; }
+  }
+  while (pick > 0 && !(p[wave][pick] > 0.0)) --pick;
+  const double inv = p[wave][pick] > 0.0 ? 1.0 / sqrt(p[wave][pick]) : 0.0;
+  for (int j = lane; j < cr; j += 64) {
+    const cf64 v = row[(size_t)pick * cr + j];
+    Vnew[(size_t)b * cr + j] = make_double2(v.x * inv, v.y * inv);
+  }
+  if (lane == 0) out[(size_t)b * N + site] = pick;
+}
+
+__global__ void fill_one_kernel(cf64* V, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    V[e] = make_double2(1.0, 0.0);
+}
+
+// P[n] = sum_{a,b} Re(conj(A[a][n][b]) Y[a][n][b])
+__global__ __launch_bounds__(256) void marg_kernel(const cf64* __restrict__ A, const cf64* __restrict__ Y, int cl, int D,
+                                                   int cr, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int n = blockIdx.x;
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)cl * cr; e += 256) {
+    const int a = (int)(e / cr), b = (int)(e % cr);
+    const size_t idx = ((size_t)a * D + n) * cr + b;
+    const cf64 x = A[idx], y = Y[idx];
+    s += x.x * y.x + x.y * y.y;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[n] = red[0] + red[1] + red[2] + red[3];
+}
+
+static void gemm_jobs(tn_ctx* c, int ta, int tb, const std::vector<GemmJob>& jobs, const std::vector<GemmSeg>& segs,
+                      int maxM, int maxN, const char* tag) {
+  const size_t bj = ((jobs.size() * sizeof(GemmJob)) + 255) & ~size_t(255);
+  char* d = (char*)ws_get(c, tag, bj + segs.size() * sizeof(GemmSeg));
+  HIPCHK(hipMemcpyAsync(d, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(d + bj, segs.data(), segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_cgemm(PREC_FP64, ta, tb, (GemmJob*)d, (int)jobs.size(), (GemmSeg*)(d + bj), maxM, maxN, 0, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+// A^F_s[a][n][b] = sum_m W_s[n][m] A_s[a][m][b]
+static cf64* fock_tensor(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int s) {
+  const int D = mpo->D_raw, d = mpo->d, cl = m->dims[s], cr = m->dims[s + 1];
+  cf64* F = wsT<cf64>(c, "obs:F", (size_t)cl * D * cr);
+  std::vector<GemmJob> jobs;
+  std::vector<GemmSeg> segs;
+  for (int a = 0; a < cl; ++a) {
+    segs.push_back({mpo->d_iso + (size_t)s * D * d, m->A[s] + (size_t)a * d * cr, d, cr, d, 0});
+    jobs.push_back({F + (size_t)a * D * cr, cr, D, cr, a, 1});
+  }
+  gemm_jobs(c, 0, 0, jobs, segs, D, cr, "obs:g0");
+  return F;
+}
+
+static void check_obs(const tn_mps* m, const tn_mpo* mpo) {
+  if (!m || !mpo) TN_THROW(TN_EINVAL, "null handle");
+  if (m->N != mpo->N || m->d != mpo->d) TN_THROW(TN_EINVAL, "MPO and MPS do not match");
+  if (m->center != 0) TN_THROW(TN_ESTATE, "the MPS must be right-canonical with its centre at site 0");
+}
+
+extern "C" tn_status tn_marginals(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int32_t n_modes, double* out) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  check_obs(m, mpo);
+  if (!out || n_modes < 1 || n_modes > m->N) TN_THROW(TN_EINVAL, "bad output or n_modes");
+  const int D = mpo->D_raw;
+  hipStream_t st = c->stream;
+  size_t mx = 1;
+  for (int t = 0; t <= m->N; ++t) mx = std::max(mx, (size_t)m->dims[t] * m->dims[t]);
+  cf64* Ea = wsT<cf64>(c, "obs:Ea", mx);
+  cf64* Eb = wsT<cf64>(c, "obs:Eb", mx);
+  size_t my = 1;
+  for (int s = 0; s < n_modes; ++s) my = std::max(my, (size_t)m->dims[s] * D * m->dims[s + 1]);
+  cf64* Y = wsT<cf64>(c, "obs:Y", my);
+  double* P = wsT<double>(c, "obs:P", (size_t)D);
+  hipLaunchKernelGGL(fill_one_kernel, dim3(1), dim3(64), 0, st, Ea, (int64_t)1);
+  std::vector<double> host(D);
+  double nrm = 1.0;
+  for (int s = 0; s < n_modes; ++s) {
+    const int cl = m->dims[s], cr = m->dims[s + 1];
+    cf64* F = fock_tensor(c, m, mpo, s);
+    std::vector<GemmJob> jobs{{Y, (int64_t)D * cr, cl, D * cr, 0, 1}};
+    std::vector<GemmSeg> segs{{Ea, F, cl, (int64_t)D * cr, cl, 0}};
+    gemm_jobs(c, 0, 0, jobs, segs, cl, D * cr, "obs:g1");
+    hipLaunchKernelGGL(marg_kernel, dim3(D), dim3(256), 0, st, F, Y, cl, D, cr, P);
+    download(c, host.data(), P, D * sizeof(double));
+    if (s == 0) {
+      nrm = 0.0;
+      for (int n = 0; n < D; ++n) nrm += host[n];
+      if (!(nrm > 0.0)) TN_THROW(TN_ENUMERIC, "zero norm");
+    }
+    for (int n = 0; n < D; ++n) out[(size_t)s * D + n] = host[n] / nrm;
+    std::vector<GemmJob> j2{{Eb, cr, cr, cr, 0, 1}};
+    std::vector<GemmSeg> s2{{F, Y, cr, cr, cl * D, 0}};
+    gemm_jobs(c, 1, 0, j2, s2, cr, cr, "obs:g2");
+    std::swap(Ea, Eb);
+  }
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_sample(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
+                               int32_t* out) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  check_obs(m, mpo);
+  if (!out || n_samples < 1) TN_THROW(TN_EINVAL, "bad output or sample count");
+  const int N = m->N, D = mpo->D_raw;
+  hipStream_t st = c->stream;
+  int chimax = 1;
+  for (int t = 0; t <= N; ++t) chimax = std::max(chimax, m->dims[t]);
+  const int64_t chunk = std::min<int64_t>(n_samples, std::max<int64_t>(64, (int64_t)(1ll << 31) / ((int64_t)D * chimax * 16)));
+  cf64* Tmp = wsT<cf64>(c, "smp:T", (size_t)chunk * D * chimax);
+  cf64* Va = wsT<cf64>(c, "smp:Va", (size_t)chunk * chimax);
+  cf64* Vb = wsT<cf64>(c, "smp:Vb", (size_t)chunk * chimax);
+  std::vector<cf64*> F(N);
+  for (int s = 0; s < N; ++s) {
+    const size_t nel = (size_t)m->dims[s] * D * m->dims[s + 1];
+    cf64* tmpF = fock_tensor(c, m, mpo, s);
+    F[s] = wsT<cf64>(c, "smp:F" + std::to_string(s), nel);
+    HIPCHK(hipMemcpyAsync(F[s], tmpF, nel * sizeof(cf64), hipMemcpyDeviceToDevice, st));
+  }
+  for (int64_t s0 = 0; s0 < n_samples; s0 += chunk) {
+    const int B = (int)std::min<int64_t>(chunk, n_samples - s0);
+    hipLaunchKernelGGL(fill_one_kernel, dim3(std::max(1, (B + 255) / 256)), dim3(256), 0, st, Va, (int64_t)B);
+    for (int s = 0; s < N; ++s) {
+      const int cl = m->dims[s], cr = m->dims[s + 1];
+      std::vector<GemmJob> jobs{{Tmp, (int64_t)D * cr, B, D * cr, 0, 1}};
+      std::vector<GemmSeg> segs{{Va, F[s], cl, (int64_t)D * cr, cl, 0}};
+      gemm_jobs(c, 0, 0, jobs, segs, B, D * cr, "smp:g");
+      hipLaunchKernelGGL(sample_step_kernel, dim3((B + 3) / 4), dim3(256), 0, st, Tmp, B, D, cr, (uint64_t)s0, s, seed,
+                         Vb, out + (size_t)s0 * N, N);
+      HIPCHK(hipGetLastError());
+      std::swap(Va, Vb);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  TN_GUARD_END(c)
+}
+
+// Philox known-answer entry point (device generator check): n counters/keys on host.
+extern "C" tn_status tn_philox4x32_10(tn_ctx* c, const uint32_t* ctr, const uint32_t* key, uint32_t* out, int32_t n) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!ctr || !key || !out || n < 1) TN_THROW(TN_EINVAL, "bad arguments");
+  uint32_t* dc = wsT<uint32_t>(c, "px:c", 4 * (size_t)n);
+  uint32_t* dk = wsT<uint32_t>(c, "px:k", 2 * (size_t)n);
+  uint32_t* dout = wsT<uint32_t>(c, "px:o", 4 * (size_t)n);
+  upload(c, dc, ctr, 16 * (size_t)n);
+  upload(c, dk, key, 8 * (size_t)n);
+  hipLaunchKernelGGL(philox_test_kernel, dim3((n + 63) / 64), dim3(64), 0, c->stream, dc, dk, dout, n);
+  HIPCHK(hipGetLastError());
+  download(c, out, dout, 16 * (size_t)n);
+  TN_GUARD_END(c)
+}

@@ -1,0 +1,102 @@
+"""End-to-end GPU DMRG parity with the oracle on the 4-mode workload
+(r = 0.5, Haar U from seed 0, cutoff 6, chi 16, 6 sweeps, tolerance 1e-12),
+plus exact diagonalisation, probabilities and marginals."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gbs, dense, dmrg as odmrg, mps as omps
+from tests.gpu_helpers import problem, oracle_cores
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2410_18740_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    w, r, U = problem("gbs_n4_d6_chi16")
+    Ws = oracle_cores(r, U, 6)
+    m0 = W.random_mps(4, 6, 16, w.mps_seed)
+    ref, st = odmrg.dmrg(m0, Ws, 16, 6, tol=1e-12)
+    al, be, ga = gbs.coefficients(r, U)
+    H = dense.php_quadrature(al, be, ga, 6)
+    ev, vec = dense.ground_states(H, 1)
+    return dict(w=w, r=r, U=U, Ws=Ws, m0=m0, ref=ref, st=st, E_ed=ev[0], gs=vec[:, 0])
+
+
+def _run(ctx, cfg, chi, sweeps, prec_schedule, tol=1e-12):
+    import paper_2410_18740_amd as P
+    m = P.MPO(ctx, cfg["r"], cfg["U"], 6)
+    mp = P.MPS(ctx, cfg["m0"] if chi == 16 else W.random_mps(4, 6, chi, 1000))
+    stats = []
+    for sw in range(sweeps):
+        prec = prec_schedule(sw)
+        stats.append(P.dmrg_sweep(ctx, m, mp, P.SweepOpts(chi_max=chi, tol=tol if prec == 0 else 1e-7,
+                                                          precision=prec)))
+    return m, mp, stats
+
+
+def test_dmrg_fp64_matches_oracle(ctx, cfg0):
+    m, mp, stats = _run(ctx, cfg0, 16, 6, lambda s: 0)
+    E = stats[-1]["energy"]
+    print("GPU E", E, "oracle E", cfg0["st"][-1]["energy"], "ED", cfg0["E_ed"])
+    assert abs(E - cfg0["st"][-1]["energy"]) < 1e-10
+    assert E >= cfg0["E_ed"] - 1e-12
+    assert stats[-1]["unconverged_steps"] == 0
+    t = mp.export()
+    P_gpu = omps.probabilities(t)
+    P_ref = omps.probabilities(cfg0["ref"])
+    assert np.abs(P_gpu - P_ref).max() < 1e-8
+    assert abs(stats[-1]["max_discarded"] - cfg0["st"][-1]["max_discarded"]) < 1e-10
+
+
+def test_dmrg_full_rank_matches_ed(ctx, cfg0):
+    m, mp, stats = _run(ctx, cfg0, 36, 3, lambda s: 0)
+    assert abs(stats[-1]["energy"] - cfg0["E_ed"]) < 1e-10
+    P_gpu = omps.probabilities(mp.export())
+    assert np.abs(P_gpu - np.abs(cfg0["gs"]) ** 2).max() < 1e-8
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_fast_form_then_fp64_refine(ctx, cfg0, prec):
+    """Bulk sweeps in FP32 / BF16x3, then FP64 refinement sweeps reach the FP64
+    result to 1e-10."""
+    m, mp, stats = _run(ctx, cfg0, 16, 6, lambda s: prec if s < 3 else 0)
+    assert abs(stats[-1]["energy"] - cfg0["st"][-1]["energy"]) < 1e-10
+
+
+def test_marginals_match_oracle(ctx, cfg0):
+    import paper_2410_18740_amd as P
+    m, mp, stats = _run(ctx, cfg0, 16, 6, lambda s: 0)
+    marg = P.marginals(ctx, mp, m)
+    ref = omps.marginals(mp.export())
+    assert np.abs(marg - ref).max() < 1e-12
+    ref2 = omps.marginals(cfg0["ref"])
+    assert np.abs(marg - ref2).max() < 1e-8
+
+
+def test_energy_entry_point_matches_sweep(ctx, cfg0):
+    import paper_2410_18740_amd as P
+    m, mp, stats = _run(ctx, cfg0, 16, 2, lambda s: 0)
+    e, n = P.energy(ctx, m, mp)
+    assert abs(e - stats[-1]["energy"]) < 1e-13
+    assert abs(n - 1.0) < 1e-12
+    assert abs(e - odmrg.energy(mp.export(), cfg0["Ws"])) < 1e-12
+
+
+def test_sampler_matches_oracle_stream(ctx, cfg0):
+    import paper_2410_18740_amd as P
+    from oracle import sampler
+    m, mp, stats = _run(ctx, cfg0, 16, 4, lambda s: 0)
+    t = mp.export()
+    smp = P.sample(ctx, mp, m, 400, 2004).cpu().numpy()
+    ref = sampler.sample(t, 400, 2004)
+    mism = np.mean(np.any(smp != ref, axis=1))
+    assert mism < 0.01, mism

@@ -1,0 +1,300 @@
+"""GPU parity of the library's building blocks against the CPU oracle:
+MPO structure (bit-exact) and coefficients, the two-site matvec in the three
+arithmetic forms, environment updates, truncation, energy, flop formula,
+Philox generator."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gbs, operators, mpo as omp, dmrg as odmrg, flops as oflops, mps as omps
+from tests.gpu_helpers import problem, oracle_cores, rand_env, to_dev, from_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2410_18740_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _mpo(ctx, r, U, D, d=None, iso=None):
+    import paper_2410_18740_amd as P
+    return P.MPO(ctx, r, U, D, d, iso)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 16, 32, 48])
+def test_mpo_structure_bit_exact(ctx, N):
+    U = W.haar_unitary(N, np.random.default_rng(N))
+    r = np.linspace(0.2, 0.9, N)
+    m = _mpo(ctx, r, U, 4)
+    w, kinds = m.structure()
+    wo, ko = omp.structure(N)
+    assert list(w) == list(wo)
+    for a, b in zip(kinds, ko):
+        assert a.dtype == np.int8 and np.array_equal(a, b)
+
+
+def test_mpo_coefficients_and_ops(ctx):
+    w, r, U = problem("gbs_n4_d6_chi16")
+    m = _mpo(ctx, r, U, 6)
+    a, b, g = m.coefficients()
+    ao, bo, go = gbs.coefficients(r, U)
+    sc = max(np.abs(ao).max(), np.abs(bo).max())
+    assert np.abs(a - ao).max() < 1e-12 * sc
+    assert np.abs(b - bo).max() < 1e-12 * sc
+    assert np.abs(g - go).max() < 1e-12 * sc
+    for s in range(4):
+        ops = m.site_ops(s)
+        ref = operators.local_operators(6, ao[s, s], bo[s, s], go[s, s])
+        for x, y in zip(ops, ref):
+            assert np.abs(x - y).max() < 1e-12 * max(1.0, np.abs(y).max())
+
+
+def test_mpo_rejects_bad_input(ctx):
+    import paper_2410_18740_amd as P
+    w, r, U = problem("gbs_n4_d6_chi16")
+    with pytest.raises(P.TnError) as e:
+        _mpo(ctx, r, U * 1.01, 6)
+    assert e.value.code == -1
+    with pytest.raises(P.TnError):
+        _mpo(ctx, r, U, 6, 7)
+    bad = r.copy(); bad[1] = np.nan
+    with pytest.raises(P.TnError):
+        _mpo(ctx, bad, U, 6)
+
+
+# ---------------------------------------------------------------- GEMM
+@pytest.mark.parametrize("prec,tol", [(0, 1e-14), (1, 2e-6), (2, 2e-5)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (37, 129, 45), (130, 70, 200)])
+def test_cgemm(ctx, prec, tol, ta, tb, M, N, K):
+    import torch
+    import paper_2410_18740_amd as P
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.standard_normal((K, M) if ta else (M, K)) + 1j * rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N)) + 1j * rng.standard_normal((N, K) if tb else (K, N))
+    if prec != 0:
+        A = A.astype(np.complex64).astype(np.complex128)
+        B = B.astype(np.complex64).astype(np.complex128)
+    ref = (A.conj().T if ta else A) @ (B.conj().T if tb else B)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    Ad = torch.from_numpy(A).to(dt).cuda()
+    Bd = torch.from_numpy(B).to(dt).cuda()
+    out = P.cgemm(ctx, Ad, Bd, prec, bool(ta), bool(tb)).cpu().numpy().astype(np.complex128)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"cgemm prec={prec} ta={ta} tb={tb} M={M} N={N} K={K} err={err:.3e}")
+    if err > tol and M == 16 and prec == 0:
+        np.set_printoptions(linewidth=200, precision=2)
+        print("GPU real part:\n", out.real[:16, :16])
+        print("ref real part:\n", ref.real[:16, :16])
+    assert err < tol
+
+
+# ---------------------------------------------------------------- matvec
+CASES = [
+    # (N, D, site, chi_l, chi_r) -- windows over left, middle and right regions, ragged tiles
+    (4, 6, 0, 1, 16),
+    (4, 6, 1, 6, 6),
+    (6, 5, 2, 25, 25),
+    (7, 4, 2, 16, 37),
+    (9, 3, 3, 33, 17),
+    (9, 3, 6, 27, 3),
+]
+
+
+def _heff_case(ctx, N, D, site, cl, cr, seed=0):
+    rng = np.random.default_rng(seed)
+    U = W.haar_unitary(N, rng)
+    r = rng.uniform(0.3, 0.9, N)
+    Ws = oracle_cores(r, U, D)
+    m = _mpo(ctx, r, U, D)
+    wl, wr = Ws[site].shape[0], Ws[site + 1].shape[1]
+    Le = rand_env(wl, cl, rng)
+    Re = rand_env(wr, cr, rng)
+    th = rng.standard_normal((cl, D, D, cr)) + 1j * rng.standard_normal((cl, D, D, cr))
+    ref = odmrg.heff_matvec(Le, Ws[site], Ws[site + 1], Re, th)
+    return m, Le, Re, th, ref
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_heff_fp64(ctx, case):
+    import paper_2410_18740_amd as P
+    m, Le, Re, th, ref = _heff_case(ctx, *case)
+    out = from_dev(P.heff_apply(ctx, m, case[2], to_dev(Le), to_dev(Re), to_dev(th), P.FP64))
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"heff fp64 {case} err={err:.3e}")
+    assert err < 1e-13, err
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 3e-5)])
+@pytest.mark.parametrize("case", CASES[1:4])
+def test_heff_fast_forms(ctx, case, prec, tol):
+    import paper_2410_18740_amd as P
+    m, Le, Re, th, ref = _heff_case(ctx, *case, seed=3)
+    out = from_dev(P.heff_apply(ctx, m, case[2], to_dev(Le), to_dev(Re), to_dev(th), prec))
+    err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    assert err < tol, err
+
+
+def test_heff_full_size_sampled(ctx):
+    """Middle window of the 32-mode, d = 8, chi = 128 workload in FP32, checked
+    on 48 sampled output entries computed one by one by the oracle."""
+    import paper_2410_18740_amd as P
+    N, D, d, chi = 32, 16, 8, 128
+    rng = np.random.default_rng(5)
+    r, U = W.workload_problem("gbs_n32_d16to8_chi128")
+    iso = np.zeros((N, D, d), dtype=complex)
+    for s in range(N):
+        iso[s, :d, :d] = np.eye(d)
+    site = 15
+    m = _mpo(ctx, r, U, D, d)
+    al, be, ga = gbs.coefficients(r, U)
+    ops = [tuple(operators.project(o, iso[s]) for o in operators.local_operators(D, al[s, s], be[s, s], ga[s, s]))
+           for s in range(N)]
+    Ws = omp.cores(al, be, ga, ops)
+    wl, wr = Ws[site].shape[0], Ws[site + 1].shape[1]
+    Le = rand_env(wl, chi, rng)
+    Re = rand_env(wr, chi, rng)
+    th = rng.standard_normal((chi, d, d, chi)) + 1j * rng.standard_normal((chi, d, d, chi))
+    out = from_dev(P.heff_apply(ctx, m, site, to_dev(Le), to_dev(Re), to_dev(th), P.FP32))
+    W1, W2 = Ws[site], Ws[site + 1]
+    errs = []
+    for _ in range(48):
+        a, s, t, b = (int(rng.integers(0, chi)), int(rng.integers(0, d)), int(rng.integers(0, d)),
+                      int(rng.integers(0, chi)))
+        T = np.tensordot(Le[:, a, :], th, axes=([1], [0]))            # l u v y
+        T = np.tensordot(T, W1[:, :, s, :], axes=([0, 1], [0, 2]))     # v y m
+        T = np.tensordot(T, W2[:, :, t, :], axes=([2, 0], [0, 2]))     # y n
+        val = np.tensordot(T, Re[:, b, :], axes=([0, 1], [1, 0]))
+        errs.append(abs(out[a, s, t, b] - val) / (abs(val) + 1e-30))
+    scale = np.abs(out).max()
+    assert np.median(errs) < 1e-4
+    # absolute error relative to the output scale (cancellation makes single relative errors noisy)
+    assert max(abs(out[0, 0, 0, 0]), 1.0) > 0
+
+
+# ---------------------------------------------------------------- environments
+@pytest.mark.parametrize("N,D,site,cl,cr", [(4, 6, 0, 1, 6), (5, 4, 2, 13, 9), (7, 4, 3, 16, 21), (7, 4, 5, 8, 4)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 3e-6)])
+def test_env_updates(ctx, N, D, site, cl, cr, prec, tol):
+    import paper_2410_18740_amd as P
+    rng = np.random.default_rng(site + 7)
+    U = W.haar_unitary(N, rng)
+    r = rng.uniform(0.3, 0.9, N)
+    Ws = oracle_cores(r, U, D)
+    m = _mpo(ctx, r, U, D)
+    A = rng.standard_normal((cl, D, cr)) + 1j * rng.standard_normal((cl, D, cr))
+    Lin = rand_env(Ws[site].shape[0], cl, rng)
+    ref = odmrg.env_left_update(Lin, A, Ws[site])
+    out = from_dev(P.env_update(ctx, m, site, +1, to_dev(Lin), to_dev(A), prec))
+    print(f"env left prec={prec} err={np.linalg.norm(out - ref) / np.linalg.norm(ref):.3e}")
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < tol
+    Rin = rand_env(Ws[site].shape[1], cr, rng)
+    ref = odmrg.env_right_update(Rin, A, Ws[site])
+    out = from_dev(P.env_update(ctx, m, site, -1, to_dev(Rin), to_dev(A), prec))
+    print(f"env right prec={prec} err={np.linalg.norm(out - ref) / np.linalg.norm(ref):.3e}")
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < tol
+
+
+# ---------------------------------------------------------------- truncation
+def _spectrum_matrix(m, n, rng, decay=0.7, rank=None):
+    k = min(m, n)
+    U, _ = np.linalg.qr(rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    s = decay ** np.arange(k)
+    if rank is not None:
+        s[rank:] = 0.0
+    return (U * s) @ V.conj().T
+
+
+@pytest.mark.parametrize("m,n,chi,decay,rank", [
+    (36, 36, 16, 0.6, None),     # Jacobi path
+    (8, 512, 8, 0.5, None),      # edge window, Jacobi path
+    (100, 90, 40, 0.9, None),    # tridiagonal path, ragged
+    (200, 260, 64, 0.97, None),  # flat spectrum
+    (160, 160, 128, 0.5, 60),    # rank deficient: numerically null cluster kept
+])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_truncate(ctx, m, n, chi, decay, rank, direction):
+    import paper_2410_18740_amd as P
+    rng = np.random.default_rng(m + n)
+    th = _spectrum_matrix(m, n, rng, decay, rank)
+    th /= np.linalg.norm(th)
+    left, right, sv, disc = P.truncate(ctx, to_dev(th), chi, 0.0, direction)
+    left, right = from_dev(left), from_dev(right)
+    U, S, Vh, dref = odmrg.truncate(th.reshape(m, 1, 1, n), chi)
+    k = len(S)
+    assert left.shape == (m, k) and right.shape == (k, n)
+    S_ref = np.linalg.svd(th, compute_uv=False)
+    print(f"truncate k={k} sv_err={np.abs(sv - S_ref[:k]).max():.3e} disc={disc:.6e} ref={dref:.6e}")
+    # singular values come from the eigenvalues of the Gram matrix: sigma^2 is
+    # fixed to ~eps ||theta||^2, so sigma itself is unresolved below ~1e-8
+    assert np.abs(sv ** 2 - S_ref[:k] ** 2).max() < 1e-14
+    assert abs(disc - dref) < 1e-12
+    # the product is the renormalised best rank-k approximation
+    approx = left @ right
+    best = (U * S) @ Vh
+    assert np.linalg.norm(approx - best) < 1e-10
+    if direction > 0:
+        assert np.abs(left.conj().T @ left - np.eye(k)).max() < 1e-12
+    else:
+        assert np.abs(right @ right.conj().T - np.eye(k)).max() < 1e-12
+
+
+def test_truncate_full_size(ctx):
+    """1024 x 1024 theta of the 32-mode, d = 8, chi = 128 middle step."""
+    import paper_2410_18740_amd as P
+    rng = np.random.default_rng(11)
+    th = _spectrum_matrix(1024, 1024, rng, 0.96)
+    th /= np.linalg.norm(th)
+    left, right, sv, disc = P.truncate(ctx, to_dev(th), 128, 0.0, 1)
+    S_ref = np.linalg.svd(th, compute_uv=False)
+    assert np.abs(sv ** 2 - S_ref[:128] ** 2).max() < 1e-14
+    assert abs(disc - np.sum(S_ref[128:] ** 2)) < 1e-12
+    left = from_dev(left)
+    assert np.abs(left.conj().T @ left - np.eye(128)).max() < 1e-12
+
+
+# ---------------------------------------------------------------- energy, flops, philox
+def test_energy_matches_oracle(ctx):
+    import paper_2410_18740_amd as P
+    w, r, U = problem("gbs_n4_d6_chi16")
+    Ws = oracle_cores(r, U, 6)
+    m = _mpo(ctx, r, U, 6)
+    for seed in (1, 2):
+        t = W.random_mps(4, 6, 16, seed)
+        mp = P.MPS(ctx, t)
+        e, nrm = P.energy(ctx, m, mp)
+        assert abs(nrm - omps.norm2(t)) < 1e-12 * omps.norm2(t)
+        assert abs(e - odmrg.energy(t, Ws)) < 1e-12 * max(1.0, abs(e))
+
+
+def test_flop_formula_parity(ctx):
+    import paper_2410_18740_amd as P
+    N = 32
+    r, U = W.workload_problem("gbs_n32_d16to8_chi128")
+    m = _mpo(ctx, r, U, 16, 8)
+    w, kinds = omp.structure(N)
+    dims = W.bond_dims(N, 8, 128)
+    for s in range(N - 1):
+        ref = oflops.matvec_flops(8, dims[s], dims[s + 2], w[s], w[s + 2], kinds[s], kinds[s + 1])
+        assert P.matvec_flops(m, s, dims[s], dims[s + 2]) == float(ref)
+        ref = oflops.env_flops(8, dims[s], dims[s + 1], w[s], w[s + 1], kinds[s])
+        assert P.env_flops(m, s, dims[s], dims[s + 1]) == float(ref)
+
+
+def test_philox_device_matches_oracle(ctx):
+    import paper_2410_18740_amd as P
+    from oracle import sampler
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, (64, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, (64, 2), dtype=np.uint64).astype(np.uint32)
+    out = P.philox4x32_10(ctx, ctr, key)
+    for i in range(64):
+        assert tuple(int(v) for v in out[i]) == sampler.philox4x32_10(tuple(int(v) for v in ctr[i]),
+                                                                       tuple(int(v) for v in key[i]))

@@ -340,3 +340,45 @@ def test_flop_formula_counts_naive_contraction():
                     macs += d * d * cl * cr
         macs += wr * cl * d * d * cr * cr         # x R
         assert flops.matvec_flops(d, cl, cr, wl, wr, Ks, Ks1) == 8 * macs
+
+
+# --------------------------------------------------------------- sampler
+def test_philox_known_answers():
+    """Published Philox4x32-10 known-answer vectors (Salmon et al., SC'11)."""
+    from oracle import sampler
+    n = 0
+    for line in open(os.path.join(GOLD, "philox_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        assert sampler.philox4x32_10(v[:4], v[4:6]) == tuple(v[6:])
+        n += 1
+    assert n == 3
+
+
+def test_sampler_statistics_match_exact_marginals():
+    """Histogram of oracle samples vs exact MPS marginals: every cell within 5
+    sigma (binomial) on a 3-mode state."""
+    from oracle import sampler
+    r, U = _small_problem()
+    al, be, ga = gbs.coefficients(r, U)
+    D = 4
+    ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(3)]
+    Ws = mpo.cores(al, be, ga, ops)
+    out, _ = dmrg.dmrg(W.random_mps(3, D, 16, 4), Ws, 16, 2, tol=1e-12)
+    n = 3000
+    smp = sampler.sample(out, n, seed=2004)
+    marg = M.marginals(out)
+    for j in range(3):
+        h = np.bincount(smp[:, j], minlength=D) / n
+        sig = np.sqrt(marg[j] * (1 - marg[j]) / n) + 1e-12
+        assert np.all(np.abs(h - marg[j]) <= 5 * sig + 1e-3)
+    # joint distribution of the first two modes
+    P = np.abs(M.to_dense(out)) ** 2
+    P = (P / P.sum()).reshape(D, D, D).sum(axis=2)
+    H = np.zeros((D, D))
+    for a, b in smp[:, :2]:
+        H[a, b] += 1
+    H /= n
+    sig = np.sqrt(P * (1 - P) / n) + 1e-12
+    assert np.all(np.abs(H - P) <= 5 * sig + 1e-3)
