@@ -1,0 +1,175 @@
+"""Benchmark: two-site DMRG sweeps with joint local basis optimisation on the
+32-mode GBS workload (raw Fock cutoff 16 compressed to an 8-dim local basis,
+chi = 128), on one MI355X.
+
+One step = one full sweep (2(N-1) two-site updates with a local-basis update
+of the centre site before each, Lanczos in FP64 with the matvec in the chosen
+form, FP64 truncation, environment updates) plus the FP64 <H> evaluation.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DMRG sweep s + H_eff TFLOP/s (N=32,d=16,χ=128) to <H> ≤1e-8, vs plain FP64"
+PEAKS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense matrix-core peaks
+FORMS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gbs_n32_d16to8_chi128")
+    ap.add_argument("--form", default="fp32", choices=list(FORMS))
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--no-lbo", action="store_true")
+    ap.add_argument("--max-matvecs", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare", action="store_true", help="also time one sweep in each other form")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, r, U, budget_s=20.0):
+    """The FP64 oracle's two-site matvec on the middle window of the same
+    workload, timed on the host cores."""
+    from oracle import gbs, operators, mpo as omp, dmrg as odmrg, flops as oflops
+    import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    N, D, d, chi = w.N, w.D_raw, w.d, w.chi
+    al, be, ga = gbs.coefficients(r, U)
+    iso = np.zeros((D, d), dtype=complex)
+    iso[:d, :d] = np.eye(d)
+    ops = [tuple(operators.project(o, iso) for o in operators.local_operators(D, al[s, s], be[s, s], ga[s, s]))
+           for s in range(N)]
+    Ws = omp.cores(al, be, ga, ops)
+    site = N // 2 - 1
+    dims = W.bond_dims(N, d, chi)
+    cl, cr = dims[site], dims[site + 2]
+    rng = np.random.default_rng(0)
+    Le = rng.standard_normal((Ws[site].shape[0], cl, cl)) + 1j * rng.standard_normal((Ws[site].shape[0], cl, cl))
+    Re = rng.standard_normal((Ws[site + 1].shape[1], cr, cr)) + 1j * rng.standard_normal((Ws[site + 1].shape[1], cr, cr))
+    th = rng.standard_normal((cl, d, d, cr)) + 1j * rng.standard_normal((cl, d, d, cr))
+    wst, kinds = omp.structure(N)
+    fl = oflops.matvec_flops(d, cl, cr, wst[site], wst[site + 2], kinds[site], kinds[site + 1])
+    n, t0 = 0, time.perf_counter()
+    while True:
+        odmrg.heff_matvec(Le, Ws[site], Ws[site + 1], Re, th)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 8:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": fl * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} FP64 NumPy two-site matvecs of the middle window (site {site}, chi {cl}x{cr}, d {d}) "
+                      f"of the same workload, {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the sharded design is described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2410_18740_amd as P
+    import workloads as W
+
+    w = W.WORKLOADS[a.workload]
+    r, U = W.workload_problem(a.workload)
+    prec = FORMS[a.form]
+    # Lanczos: the energy error of an inexact local eigenvector is quadratic in
+    # its residual, so a moderate residual and a small Krylov budget per step
+    # suffice inside sweeps (the FP64 <H> after each sweep is the judge).
+    tol = a.tol if a.tol is not None else (1e-8 if prec == 0 else 1e-6)
+    ctx = P.Context(0)
+    mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
+    mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
+    opts = P.SweepOpts(chi_max=w.chi, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec,
+                       lbo=0 if a.no_lbo else 1, compute_energy=1)
+    log = []
+    for i in range(a.warmup):
+        s = P.dmrg_sweep(ctx, mpo, mps, opts)
+        log.append(("warmup", s["energy"], s["t_total"]))
+        print(f"warmup sweep {i}: <H> = {s['energy']:.6e}, {s['t_total']:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        s = P.dmrg_sweep(ctx, mpo, mps, opts)
+        stats.append(s)
+        print(f"timed sweep {i}: <H> = {s['energy']:.6e}, {s['t_total']:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    heff = sum(s["heff_flops"] for s in stats)
+    value = heff / wall / 1e12
+    # roofline of the dominant kernel (the MFMA GEMM) from HIP events over one more sweep
+    ctx.profile(1)
+    sp = P.dmrg_sweep(ctx, mpo, mps, opts)
+    pr = ctx.profile(-1)
+    ctx.profile(0)
+    gemm_ms = pr["ms_gemm_l"] + pr["ms_gemm_r"]
+    launches = 2 * pr["matvecs"]
+    achieved = (pr["flops_l"] + pr["flops_r"]) / (gemm_ms * 1e-3) / 1e12
+    peak = PEAKS[a.form]
+    matvec_ms = sum(pr[k] for k in ("ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce"))
+    extra = {
+        "sweep_s": wall / a.steps,
+        "energy": stats[-1]["energy"],
+        "heff_kernel_tflops": pr["flops_matvec"] / (matvec_ms * 1e-3) / 1e12,
+        "phase_s": {k: sum(s[k] for s in stats) / a.steps for k in
+                    ("t_heff", "t_lanczos", "t_svd", "t_env", "t_lbo", "t_energy")},
+        "matvecs_per_sweep": sum(s["matvecs"] for s in stats) / a.steps,
+        "gemm_launch_avg_ms": gemm_ms / max(1, launches),
+        "matvec_phase_ms": {k: pr[k] / max(1, pr["matvecs"]) for k in
+                            ("ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce")},
+    }
+    if a.compare:
+        for f, p in FORMS.items():
+            if f == a.form:
+                continue
+            o2 = P.SweepOpts(**{**opts.__dict__, "precision": p, "tol": 1e-8 if p == 0 else 1e-6})
+            s2 = P.dmrg_sweep(ctx, mpo, mps, o2)
+            extra[f"sweep_s_{f}"] = s2["t_total"]
+            extra[f"heff_tflops_{f}"] = s2["heff_flops"] / max(1e-9, s2["t_heff"]) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[a.form],
+        "data": "synthetic (seeded Haar interferometer and squeezing, random-normal initial MPS)",
+        "config": {"workload": a.workload, "N": w.N, "D_raw": w.D_raw, "d": w.d, "chi": w.chi,
+                   "form": a.form + ("" if a.no_lbo else "+lbo"), "lanczos_tol": tol},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "cgemm_kernel (left and right environment contractions of the matvec)"},
+        "extra": extra,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, r, U)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

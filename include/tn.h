@@ -68,6 +68,15 @@ tn_status tn_ctx_create(int device, void* hip_stream, const tn_allocator* alloc,
 void tn_ctx_destroy(tn_ctx* ctx);
 /* Message of the last failing call on this context ("" if none). */
 const char* tn_last_error(const tn_ctx* ctx);
+/* Kernel timing of the window matvec.  When profiling is on, every matvec
+ * records HIP events around its launches on the context stream and waits for
+ * them (so it serialises the host).  out (may be NULL, 11 doubles) receives the
+ * accumulated milliseconds of [convert, left contraction GEMM, operator kernel,
+ * right contraction GEMM, split-K reduction], the matvec count, the
+ * algorithmic flops of the left contraction, of the right contraction and of
+ * the whole matvec (the integer formula), and the algorithmic bytes of the two
+ * GEMMs.  mode: -1 read only, 0 stop and reset, 1 start (after reset). */
+tn_status tn_profile(tn_ctx* ctx, int32_t mode, double* out);
 
 /* ------------------------------------------------------------------ problem / MPO
  * Sec. II.C.1: per-mode squeezing r_j and interferometer U define

@@ -96,6 +96,7 @@ def lib():
         "tn_heff_apply": (i32, [vp, vp, i32, i32, i32, vp, vp, vp, vp, i32]),
         "tn_env_update": (i32, [vp, vp, i32, i32, i32, i32, vp, vp, vp, i32]),
         "tn_truncate": (i32, [vp, i32, i32, vp, i32, dbl, i32, vp, vp, P(i32), P(dbl), P(dbl)]),
+        "tn_profile": (i32, [vp, i32, P(dbl)]),
         "tn_cgemm": (i32, [vp, i32, i32, i32, i32, i32, i32, vp, i64, vp, i64, vp, i64]),
         "tn_philox4x32_10": (i32, [vp, P(C.c_uint32), P(C.c_uint32), P(C.c_uint32), i32]),
         "tn_matvec_flops": (dbl, [vp, i32, i32, i32]),

@@ -78,6 +78,14 @@ class Context:
     def check(self, status):
         _check(self.h, status)
 
+    def profile(self, mode: int = -1) -> dict:
+        """mode -1 read, 0 stop+reset, 1 start (reset first)."""
+        out = np.zeros(11)
+        self.check(L.lib().tn_profile(self.h, mode, L.dptr(out)))
+        keys = ["ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce", "matvecs",
+                "flops_l", "flops_r", "flops_matvec", "bytes_l", "bytes_r"]
+        return dict(zip(keys, out.tolist()))
+
     @property
     def last_error(self) -> str:
         return L.lib().tn_last_error(self.h).decode()

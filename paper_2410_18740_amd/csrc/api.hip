@@ -92,6 +92,7 @@ extern "C" tn_status tn_ctx_create(int device, void* hip_stream, const tn_alloca
   }
   bool ok = true;
   for (int i = 0; i < 8; ++i) ok = ok && (hipEventCreate(&c->ev[i]) == hipSuccess);
+  for (int i = 0; i < 6; ++i) ok = ok && (hipEventCreate(&c->pev[i]) == hipSuccess);
   c->ev_ok = ok;
   *out = c;
   return TN_OK;
@@ -103,12 +104,33 @@ extern "C" void tn_ctx_destroy(tn_ctx* c) {
   for (auto& kv : c->ws) dev_free(c, kv.second.first);
   c->ws.clear();
   if (c->pinned) (void)hipHostFree(c->pinned);
-  if (c->ev_ok)
+  if (c->ev_ok) {
     for (int i = 0; i < 8; ++i) (void)hipEventDestroy(c->ev[i]);
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(c->pev[i]);
+  }
   delete c;
 }
 
 extern "C" const char* tn_last_error(const tn_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
+  if (!c) return TN_EINVAL;
+  if (out) {
+    for (int i = 0; i < 5; ++i) out[i] = c->prof_ms[i];
+    out[5] = (double)c->prof_n;
+    for (int i = 0; i < 3; ++i) out[6 + i] = c->prof_flops[i];
+    out[9] = c->prof_bytes[0];
+    out[10] = c->prof_bytes[1];
+  }
+  if (mode >= 0) {
+    c->prof = mode > 0;
+    for (int i = 0; i < 5; ++i) c->prof_ms[i] = 0.0;
+    for (int i = 0; i < 3; ++i) c->prof_flops[i] = 0.0;
+    c->prof_bytes[0] = c->prof_bytes[1] = 0.0;
+    c->prof_n = 0;
+  }
+  return TN_OK;
+}
 
 // ------------------------------------------------------------------ problem set-up (host FP64)
 // Bond channel layout of the middle-site MPO (SM Sec. 8), 1-based sites, m = ceil(N/2).

@@ -123,12 +123,14 @@ struct TridiagWork {
   double* off;  // off-diagonal p
   cf64* y;      // p
   cf64* w;      // p x 2 (ping-pong)
+  unsigned int* counter;  // one device counter (workgroups finished)
 };
 hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st);
 hipError_t launch_bisect_top(const double* dg, const double* off, int p, int k, double* evals, hipStream_t st);
 hipError_t launch_inverse_iter(const double* dg, const double* off, int p, int k, const double* evals, double* X,
                                double* scratch, hipStream_t st);
-hipError_t launch_orthonormalize_real(double* X, int p, int k, hipStream_t st);
+hipError_t launch_orthonormalize_real(double* X, int p, int k, int j0, hipStream_t st);
+hipError_t launch_ortho_check(const double* X, int p, int k, double tol, int* bad, hipStream_t st);
 hipError_t launch_backtransform(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
                                 hipStream_t st);
 
@@ -136,11 +138,12 @@ hipError_t launch_transpose_from64(int prec, void* dst, const cf64* src, int bat
 hipError_t launch_transpose_to64(int prec, cf64* dst, const void* src, int batch, int rows, int cols, hipStream_t st);
 hipError_t launch_scale_host(cf64* dst, const cf64* src, double s, int64_t n, hipStream_t st);
 hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream_t st);
-hipError_t launch_lanczos_scalars(const cf64* h1, const cf64* h2, const cf64* nrm2, int j, double* alpha, double* beta,
-                                  double* inv, double* out, hipStream_t st);
+hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, double* alpha, double* beta, double* inv,
+                               double* coefs, double* out, hipStream_t st);
 hipError_t launch_ritz_coefs(const cf64* V, int n, double* out, double* last, hipStream_t st);
 hipError_t launch_finite_check(const cf64* x, int64_t n, int* flag, hipStream_t st);
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 hipError_t launch_set_one(void* p, int prec, hipStream_t st);
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 hipError_t launch_copy2d(cf64* dst, int64_t ldd, const cf64* src, int64_t lds, int rows, int cols, int conj_t,
                          hipStream_t st);

@@ -82,24 +82,28 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
   const int nb = multidot_blocks(n);
   cf64* V = wsT<cf64>(c, "lz:V", (size_t)(kmax + 1) * n);
   cf64* W = wsT<cf64>(c, "lz:W", (size_t)n);
-  const cf64** ptrs = wsT<const cf64*>(c, "lz:ptr", kmax + 2);
-  cf64* part = wsT<cf64>(c, "lz:part", (size_t)nb * (kmax + 1));
-  cf64* h1 = wsT<cf64>(c, "lz:h1", kmax + 1);
-  cf64* h2 = wsT<cf64>(c, "lz:h2", kmax + 1);
-  cf64* nr = wsT<cf64>(c, "lz:nr", 1);
+  // pointer tables: ptrs = [V_0..V_kmax]; tabW[j] = [V_0..V_j, W]
+  const cf64** ptrs = wsT<const cf64*>(c, "lz:ptr", kmax + 1);
+  const cf64** tabW = wsT<const cf64*>(c, "lz:tabW", (size_t)kmax * (kmax + 2));
+  cf64* part = wsT<cf64>(c, "lz:part", (size_t)nb * (kmax + 2));
+  cf64* h1 = wsT<cf64>(c, "lz:h1", kmax + 2);
+  cf64* h2 = wsT<cf64>(c, "lz:h2", kmax + 2);
   double* alpha = wsT<double>(c, "lz:al", kmax + 1);
   double* beta = wsT<double>(c, "lz:be", kmax + 1);
   double* inv = wsT<double>(c, "lz:inv", 1);
   double* sc = wsT<double>(c, "lz:sc", 4);
-  cf64* Tm = wsT<cf64>(c, "lz:T", (size_t)kmax * kmax);
-  double* ev = wsT<double>(c, "lz:ev", kmax);
-  cf64* Z = wsT<cf64>(c, "lz:Z", (size_t)kmax * kmax);
   double* coefs = wsT<double>(c, "lz:cf", kmax + 1);
-  double* last = wsT<double>(c, "lz:last", 1);
-  std::vector<const cf64*> hp(kmax + 2);
-  for (int i = 0; i <= kmax; ++i) hp[i] = V + (size_t)i * n;
-  hp[kmax + 1] = W;
-  HIPCHK(hipMemcpyAsync(ptrs, hp.data(), hp.size() * sizeof(cf64*), hipMemcpyHostToDevice, st));
+  {
+    std::vector<const cf64*> hp(kmax + 1);
+    for (int i = 0; i <= kmax; ++i) hp[i] = V + (size_t)i * n;
+    std::vector<const cf64*> ht((size_t)kmax * (kmax + 2));
+    for (int j = 0; j < kmax; ++j) {
+      for (int i = 0; i <= j; ++i) ht[(size_t)j * (kmax + 2) + i] = V + (size_t)i * n;
+      ht[(size_t)j * (kmax + 2) + j + 1] = W;
+    }
+    HIPCHK(hipMemcpyAsync(ptrs, hp.data(), hp.size() * sizeof(cf64*), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(tabW, ht.data(), ht.size() * sizeof(cf64*), hipMemcpyHostToDevice, st));
+  }
   double nx = dev_norm2(c, x, n);
   if (!(nx > 0.0) || !std::isfinite(nx)) TN_THROW(TN_ENUMERIC, "Lanczos start vector is zero or non-finite");
   HIPCHK(launch_scale_host(V, x, 1.0 / std::sqrt(nx), n, st));
@@ -114,22 +118,17 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
       matvec(V + (size_t)j * n, W);
       HIPCHK(hipEventRecord(e1, st));
       R.matvecs++;
-      // pass 1 and pass 2 of classical Gram-Schmidt against V_0..V_j
+      // two passes of classical Gram-Schmidt against V_0..V_j; the second pass
+      // also returns <w, w>, from which ||w|| after the pass follows
       HIPCHK(launch_multidot(ptrs, j + 1, W, n, part, nb, st));
       HIPCHK(launch_multidot_finish(part, j + 1, nb, h1, st));
       HIPCHK(launch_multiaxpy(W, ptrs, j + 1, h1, 1.0, n, st));
-      HIPCHK(launch_multidot(ptrs, j + 1, W, n, part, nb, st));
-      HIPCHK(launch_multidot_finish(part, j + 1, nb, h2, st));
+      const cf64* const* tw = tabW + (size_t)j * (kmax + 2);
+      HIPCHK(launch_multidot(tw, j + 2, W, n, part, nb, st));
+      HIPCHK(launch_multidot_finish(part, j + 2, nb, h2, st));
       HIPCHK(launch_multiaxpy(W, ptrs, j + 1, h2, 1.0, n, st));
-      HIPCHK(launch_multidot(ptrs + kmax + 1, 1, W, n, part, nb, st));
-      HIPCHK(launch_multidot_finish(part, 1, nb, nr, st));
-      HIPCHK(launch_lanczos_scalars(h1, h2, nr, j, alpha, beta, inv, sc, st));
-      HIPCHK(launch_build_tridiag(alpha, beta, j + 1, Tm, st));
-      HIPCHK(launch_jacobi(Tm, 0, j + 1, 1, ev, Z, 0, 0, st));
-      HIPCHK(launch_ritz_coefs(Z, j + 1, coefs, last, st));
-      HIPCHK(hipMemcpyAsync(hout, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(hout + 2, ev, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(hout + 3, last, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(launch_lanczos_step(h1, h2, j, alpha, beta, inv, coefs, sc, st));
+      HIPCHK(hipMemcpyAsync(hout, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) R.t_mv += ms * 1e-3;
@@ -186,13 +185,24 @@ static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& eva
   tw.off = wsT<double>(c, "eig:off", p);
   tw.y = wsT<cf64>(c, "eig:y", p);
   tw.w = wsT<cf64>(c, "eig:w", 2 * (size_t)p);
+  tw.counter = wsT<unsigned int>(c, "eig:cnt", 1);
   HIPCHK(launch_tridiag(tw, p, st));
   double* ev = wsT<double>(c, "eig:ev", kk);
   HIPCHK(launch_bisect_top(tw.dg, tw.off, p, kk, ev, st));
   double* X = wsT<double>(c, "eig:X", (size_t)kk * p);
   double* scr = wsT<double>(c, "eig:scr", (size_t)4 * kk * p);
   HIPCHK(launch_inverse_iter(tw.dg, tw.off, p, kk, ev, X, scr, st));
-  HIPCHK(launch_orthonormalize_real(X, p, kk, st));
+  // inverse iteration gives orthogonal vectors for separated eigenvalues; restore
+  // orthonormality (two-pass Gram-Schmidt) from the first defective column on
+  int* bad = wsT<int>(c, "eig:bad", kk);
+  HIPCHK(launch_fill_int(bad, 0, kk, st));
+  HIPCHK(launch_ortho_check(X, p, kk, 1e-13, bad, st));
+  std::vector<int> hb(kk);
+  download(c, hb.data(), bad, kk * sizeof(int));
+  int j0 = kk;
+  for (int j = 0; j < kk; ++j)
+    if (hb[j]) { j0 = j; break; }
+  HIPCHK(launch_orthonormalize_real(X, p, kk, j0, st));
   Z = wsT<cf64>(c, "eig:Z", (size_t)p * kk);
   HIPCHK(launch_backtransform(tw.vs, tw.taus, p, X, kk, Z, st));
   evals.resize(kk);

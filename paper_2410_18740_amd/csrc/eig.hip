@@ -11,6 +11,7 @@
 #include "common.h"
 
 #define JAC_N 64
+#define HIPCHK_DEV(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
 static __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -181,23 +182,21 @@ hipError_t launch_build_tridiag(const double* alpha, const double* beta, int n, 
 }
 
 // ------------------------------------------------------------------ Householder tridiagonalisation
-// Step A (one workgroup, 1024 threads), for column j:
-//   if j > 0: w_{j-1} = y_{j-1} - 1/2 tau_{j-1} (y^H v) v_{j-1}
+// Reflector step for column j (any workgroup size that is a multiple of 64):
+//   if j > 0: w_{j-1} = y_{j-1} - 1/2 tau_{j-1} (y^H v_{j-1}) v_{j-1}
 //   current column j (rows >= j) = conj(row j) minus the pending rank-2 update
-//   reflector: H^H x = beta e_1, beta real (LAPACK zlarfg conventions)
-__global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64* __restrict__ vs,
-                                                       cf64* __restrict__ taus, double* __restrict__ dg,
-                                                       double* __restrict__ off, const cf64* __restrict__ y,
-                                                       cf64* __restrict__ wbuf, int p, int j) {
-  __shared__ double red[2][16];
-  __shared__ cf64 bc[4];
+//   reflector with H^H x = beta e_1, beta real (LAPACK zlarfg conventions)
+static __device__ void tridiag_reflector(cf64* __restrict__ A, cf64* __restrict__ vs, cf64* __restrict__ taus,
+                                         double* __restrict__ dg, double* __restrict__ off,
+                                         const cf64* __restrict__ y, cf64* __restrict__ wbuf, int p, int j,
+                                         double (*red)[16], cf64* bc) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = blockDim.x, nw = nt >> 6;
   cf64* wprev = wbuf + (int64_t)((j + 1) & 1) * p;  // w_{j-1}
   const cf64* vprev = (j > 0) ? vs + (int64_t)(j - 1) * p : nullptr;
   if (j > 0) {
-    // y^H v over [j, p)
     double re = 0.0, im = 0.0;
-    for (int i = j + tid; i < p; i += 1024) {
+    for (int i = j + tid; i < p; i += nt) {
       const cf64 a = y[i], b = vprev[i];
       re += a.x * b.x + a.y * b.y;
       im += a.x * b.y - a.y * b.x;
@@ -207,36 +206,26 @@ __global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64
     __syncthreads();
     if (tid == 0) {
       double r = 0, m = 0;
-      for (int w = 0; w < 16; ++w) { r += red[0][w]; m += red[1][w]; }
-      const cf64 tau = taus[j - 1];
-      const cf64 yv = make_double2(r, m);
-      const cf64 k = cmul(tau, yv);
-      bc[0] = make_double2(-0.5 * k.x, -0.5 * k.y);  // coefficient of v in w
+      for (int w = 0; w < nw; ++w) { r += red[0][w]; m += red[1][w]; }
+      const cf64 k = cmul(taus[j - 1], make_double2(r, m));
+      bc[0] = make_double2(-0.5 * k.x, -0.5 * k.y);
     }
     __syncthreads();
     const cf64 c = bc[0];
-    for (int i = tid; i < p; i += 1024) {
-      cf64 wv = czero<cf64>();
-      if (i >= j) wv = cadd(y[i], cmul(c, vprev[i]));
-      wprev[i] = wv;
-    }
+    for (int i = tid; i < p; i += nt) wprev[i] = (i >= j) ? cadd(y[i], cmul(c, vprev[i])) : czero<cf64>();
     __syncthreads();
   }
-  // current column j entries i >= j: x_i = conj(A[j][i]) - (vprev[i] conj(w[j]) + w[i] conj(vprev[j]))
-  // diagonal d_j
   if (j >= p) return;
   cf64 wj = czero<cf64>(), vj = czero<cf64>();
   if (j > 0) { wj = wprev[j]; vj = vprev[j]; }
   if (tid == 0) {
-    cf64 ajj = A[(int64_t)j * p + j];
-    double d = ajj.x;
+    double d = A[(int64_t)j * p + j].x;
     if (j > 0) d -= 2.0 * (vj.x * wj.x + vj.y * wj.y);
     dg[j] = d;
   }
   if (j == p - 1) return;
-  // norm of x[1:] and alpha = x[0]
   double nrm = 0.0;
-  for (int i = j + 2 + tid; i < p; i += 1024) {
+  for (int i = j + 2 + tid; i < p; i += nt) {
     cf64 x = cconj(A[(int64_t)j * p + i]);
     if (j > 0) x = csub(x, cadd(cmulc(vprev[i], wj), cmulc(wprev[i], vj)));
     nrm += cabs2(x);
@@ -246,7 +235,7 @@ __global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64
   __syncthreads();
   if (tid == 0) {
     double xn2 = 0.0;
-    for (int w = 0; w < 16; ++w) xn2 += red[0][w];
+    for (int w = 0; w < nw; ++w) xn2 += red[0][w];
     const int i = j + 1;
     cf64 alpha = cconj(A[(int64_t)j * p + i]);
     if (j > 0) alpha = csub(alpha, cadd(cmulc(vprev[i], wj), cmulc(wprev[i], vj)));
@@ -260,7 +249,6 @@ __global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64
       const double nr = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
       beta = (alpha.x >= 0.0) ? -nr : nr;
       tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-      // scale = 1 / (alpha - beta)
       const cf64 den = make_double2(alpha.x - beta, alpha.y);
       const double dd = den.x * den.x + den.y * den.y;
       scale = make_double2(den.x / dd, -den.y / dd);
@@ -272,7 +260,7 @@ __global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64
   __syncthreads();
   const cf64 scale = bc[1];
   cf64* vj_out = vs + (int64_t)j * p;
-  for (int i = tid; i < p; i += 1024) {
+  for (int i = tid; i < p; i += nt) {
     cf64 v = czero<cf64>();
     if (i == j + 1) v = make_double2(1.0, 0.0);
     else if (i > j + 1) {
@@ -284,8 +272,18 @@ __global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64
   }
 }
 
-// Step B (rows i in [j+1, p), one wave per row): apply the pending update
-// (v_{j-1}, w_{j-1}) to row i (columns >= j+1), then y_i = tau_j * sum_k A[i][k] v_j[k].
+__global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64* __restrict__ vs,
+                                                       cf64* __restrict__ taus, double* __restrict__ dg,
+                                                       double* __restrict__ off, const cf64* __restrict__ y,
+                                                       cf64* __restrict__ wbuf, int p, int j) {
+  __shared__ double red[2][16];
+  __shared__ cf64 bc[4];
+  tridiag_reflector(A, vs, taus, dg, off, y, wbuf, p, j, red, bc);
+}
+
+// Row step for column j (one wavefront per row i in [j+1, p)): apply the
+// pending update (v_{j-1}, w_{j-1}) to row i (columns >= j+1), then
+// y_i = tau_j sum_k A[i][k] v_j[k].  A one-workgroup reflector launch follows.
 __global__ __launch_bounds__(256) void tridiag_stepB(cf64* __restrict__ A, const cf64* __restrict__ vs,
                                                       const cf64* __restrict__ taus, cf64* __restrict__ y,
                                                       const cf64* __restrict__ wbuf, int p, int j) {
@@ -340,32 +338,50 @@ static __device__ int sturm_count(const double* dg, const double* off, int p, do
   return cnt;
 }
 
-__global__ void bisect_kernel(const double* dg, const double* off, int p, int k, double* evals) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per wanted eigenvalue: each round every lane counts the
+// eigenvalues below one of 64 equispaced probes of the current interval, and
+// the interval shrinks to the probe gap that holds the target (64-way
+// multisection; 10-12 rounds reach full double precision).
+__global__ __launch_bounds__(64) void bisect_kernel(const double* dg, const double* off, int p, int k,
+                                                    double* evals) {
+  const int t = blockIdx.x;
+  const int lane = threadIdx.x;
   if (t >= k) return;
   double lo = 1e300, hi = -1e300, emax = 0.0;
-  for (int i = 0; i < p; ++i) {
+  for (int i = lane; i < p; i += 64) {
     const double r = (i > 0 ? fabs(off[i - 1]) : 0.0) + (i < p - 1 ? fabs(off[i]) : 0.0);
     lo = fmin(lo, dg[i] - r);
     hi = fmax(hi, dg[i] + r);
     if (i < p - 1) emax = fmax(emax, off[i] * off[i]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+    emax = fmax(emax, __shfl_xor(emax, o, 64));
   }
   const double scale = fmax(fabs(lo), fabs(hi));
   const double pivmin = fmax(1e-300, 2.3e-308 * fmax(1.0, emax));
   lo -= 1e-14 * scale + 1e-300;
   hi += 1e-14 * scale + 1e-300;
   const int target = p - 1 - t;  // ascending index of the t-th largest
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
+  for (int it = 0; it < 40; ++it) {
     if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
-    const int c = sturm_count(dg, off, p, mid, pivmin);
-    if (c <= target) lo = mid; else hi = mid;
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const int c = sturm_count(dg, off, p, x, pivmin);
+    // probes with count <= target lie left of the eigenvalue
+    const unsigned long long le = __ballot(c <= target);
+    const int nle = __popcll(le);          // probes are increasing, so these are lanes 0..nle-1
+    const double nlo = (nle == 0) ? lo : __shfl(x, nle - 1, 64);
+    const double nhi = (nle == 64) ? hi : __shfl(x, nle, 64);
+    if (!(nhi - nlo < hi - lo)) break;
+    lo = nlo;
+    hi = nhi;
   }
-  evals[t] = 0.5 * (lo + hi);
+  if (lane == 0) evals[t] = 0.5 * (lo + hi);
 }
 hipError_t launch_bisect_top(const double* dg, const double* off, int p, int k, double* evals, hipStream_t st) {
-  hipLaunchKernelGGL(bisect_kernel, dim3((k + 63) / 64), dim3(64), 0, st, dg, off, p, k, evals);
+  hipLaunchKernelGGL(bisect_kernel, dim3(k), dim3(64), 0, st, dg, off, p, k, evals);
   return hipGetLastError();
 }
 
@@ -431,7 +447,7 @@ __global__ void inverse_iter_kernel(const double* __restrict__ dg, const double*
   // start vector: deterministic, not orthogonal to anything in particular
   double* b = x;
   for (int i = 0; i < p; ++i) b[i] = 1.0 + 0.37 * sin(1.3 * (double)(i + 1) * (double)(t + 1)) ;
-  for (int it = 0; it < 3; ++it) {
+  for (int it = 0; it < 2; ++it) {
     // forward: apply L^{-1} P
     for (int i = 0; i < p - 1; ++i) {
       double f = dl[i * K + t];
@@ -470,12 +486,12 @@ hipError_t launch_inverse_iter(const double* dg, const double* off, int p, int k
 // Two-pass classical Gram-Schmidt in column order; a column that loses more
 // than 1 - 1e-8 of its norm (numerically dependent, e.g. inside a cluster of
 // equal eigenvalues) is replaced by a unit vector and re-orthogonalised.
-__global__ __launch_bounds__(1024) void ortho_kernel(double* __restrict__ X, int p, int k) {
+__global__ __launch_bounds__(1024) void ortho_kernel(double* __restrict__ X, int p, int k, int j0) {
   __shared__ double h[1024];
   __shared__ double red[16];
   __shared__ double sc[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = 0; j < k; ++j) {
+  for (int j = j0; j < k; ++j) {
     double* xj = X + (int64_t)j * p;
     int trial = 0;
     while (true) {
@@ -528,9 +544,40 @@ __global__ __launch_bounds__(1024) void ortho_kernel(double* __restrict__ X, int
     }
   }
 }
-hipError_t launch_orthonormalize_real(double* X, int p, int k, hipStream_t st) {
+hipError_t launch_orthonormalize_real(double* X, int p, int k, int j0, hipStream_t st) {
   if (k > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ortho_kernel, dim3(1), dim3(1024), 0, st, X, p, k);
+  if (j0 >= k) return hipSuccess;
+  hipLaunchKernelGGL(ortho_kernel, dim3(1), dim3(1024), 0, st, X, p, k, j0);
+  return hipGetLastError();
+}
+
+// Orthonormality defect of the columns of X: bad[j] = 1 if column j deviates
+// from unit norm or from orthogonality to an earlier column by more than tol.
+// One wavefront per pair (a <= b).
+__global__ __launch_bounds__(256) void ortho_check_kernel(const double* __restrict__ X, int p, int k, double tol,
+                                                          int* __restrict__ bad) {
+  const int lane = threadIdx.x & 63;
+  const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t npairs = (int64_t)k * (k + 1) / 2;
+  if (pair >= npairs) return;
+  // decode pair -> (a, b) with a <= b, row-major over b
+  int b = (int)((sqrt(8.0 * (double)pair + 1.0) - 1.0) * 0.5);
+  while ((int64_t)b * (b + 1) / 2 > pair) --b;
+  while ((int64_t)(b + 1) * (b + 2) / 2 <= pair) ++b;
+  const int a = (int)(pair - (int64_t)b * (b + 1) / 2);
+  const double* xa = X + (int64_t)a * p;
+  const double* xb = X + (int64_t)b * p;
+  double s = 0.0;
+  for (int i = lane; i < p; i += 64) s += xa[i] * xb[i];
+  s = wave_sum_d(s);
+  if (lane == 0) {
+    const double dev = (a == b) ? fabs(s - 1.0) : fabs(s);
+    if (!(dev <= tol)) bad[b] = 1;
+  }
+}
+hipError_t launch_ortho_check(const double* X, int p, int k, double tol, int* bad, hipStream_t st) {
+  const int64_t npairs = (int64_t)k * (k + 1) / 2;
+  hipLaunchKernelGGL(ortho_check_kernel, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, st, X, p, k, tol, bad);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ template <> struct GemmCfg<PREC_FP32> {
 };
 template <> struct GemmCfg<PREC_BF16X3> {
   typedef cf32 CT;
-  static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 64, MB = 32, KSTEP = 16;
+  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64, MB = 32, KSTEP = 16;
 };
 template <> struct GemmCfg<PREC_FP64> {
   typedef cf64 CT;
@@ -62,8 +62,12 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ 
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, WM = Cfg::WM, WN = Cfg::WN, MB = Cfg::MB;
   constexpr int NI = WM / MB, NJ = WN / MB;
   constexpr int NT = 256;
-  __shared__ CT As[BK][BM + 1];
-  __shared__ CT Bs[BK][BN + 1];
+  constexpr int NA = BM * BK / NT, NB = BK * BN / NT;
+  // double-buffered LDS tiles, k-major; one barrier per K tile, the next
+  // tile's global loads are in flight (in registers) while the current one
+  // feeds the matrix cores
+  __shared__ CT As[2][BK][BM + 1];
+  __shared__ CT Bs[2][BK][BN + 1];
 
   const GemmJob job = jobs[blockIdx.z];
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -82,134 +86,172 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ 
       accI[i][j] = AccT{};
     }
 
-  for (int sg = 0; sg < job.nseg; ++sg) {
-    const GemmSeg seg = segs[job.seg0 + sg];
-    const CT* __restrict__ A = reinterpret_cast<const CT*>(seg.A);
-    const CT* __restrict__ B = reinterpret_cast<const CT*>(seg.B);
-    const int64_t lda = seg.lda, ldb = seg.ldb;
-    const int K = seg.K;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      // ---- stage A tile (BM x BK of op(A)) into As[k][m]
-#pragma unroll 4
-      for (int idx = tid; idx < BM * BK; idx += NT) {
-        int mm, kk;
-        if (!TA) { mm = idx / BK; kk = idx % BK; }
-        else     { kk = idx / BM; mm = idx % BM; }
-        const int gm = m0 + mm, gk = k0 + kk;
-        CT v = czero<CT>();
-        if (gm < M && gk < K) v = TA ? ld_c<CT, true>(A + (int64_t)gk * lda + gm) : A[(int64_t)gm * lda + gk];
-        As[kk][mm] = v;
-      }
-      // ---- stage B tile (BK x BN of op(B)) into Bs[k][n]
-#pragma unroll 4
-      for (int idx = tid; idx < BK * BN; idx += NT) {
-        int kk, nn;
-        if (!TB) { kk = idx / BN; nn = idx % BN; }
-        else     { nn = idx / BK; kk = idx % BK; }
-        const int gn = n0 + nn, gk = k0 + kk;
-        CT v = czero<CT>();
-        if (gn < N && gk < K) v = TB ? ld_c<CT, true>(B + (int64_t)gn * ldb + gk) : B[(int64_t)gk * ldb + gn];
-        Bs[kk][nn] = v;
-      }
-      __syncthreads();
-
-      if constexpr (PREC == PREC_FP32) {
+  // flattened K-tile sequence over the job's segments
+  int ld_seg = 0, ld_k0 = 0;  // next tile to load
+  GemmSeg sg = segs[job.seg0];
+  CT ra[NA], rb[NB];
+  auto load_tile = [&]() {
+    const CT* __restrict__ A = reinterpret_cast<const CT*>(sg.A);
+    const CT* __restrict__ B = reinterpret_cast<const CT*>(sg.B);
+    const int K = sg.K;
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 2) {
-          float ar[NI], ai[NI], br[NJ], bi[NJ];
-#pragma unroll
-          for (int i = 0; i < NI; ++i) {
-            CT v = As[kk + (lane >> 5)][wm0 + 32 * i + (lane & 31)];
-            ar[i] = v.x; ai[i] = v.y;
-          }
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            CT v = Bs[kk + (lane >> 5)][wn0 + 32 * j + (lane & 31)];
-            br[j] = v.x; bi[j] = v.y;
-          }
-#pragma unroll
-          for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-              accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], accR[i][j], 0, 0, 0);
-              accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[i], bi[j], accR[i][j], 0, 0, 0);
-              accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], bi[j], accI[i][j], 0, 0, 0);
-              accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], br[j], accI[i][j], 0, 0, 0);
-            }
-        }
-      } else if constexpr (PREC == PREC_FP64) {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-          double ar[NI], ai[NI], br[NJ], bi[NJ];
-#pragma unroll
-          for (int i = 0; i < NI; ++i) {
-            CT v = As[kk + (lane >> 4)][wm0 + 16 * i + (lane & 15)];
-            ar[i] = v.x; ai[i] = v.y;
-          }
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            CT v = Bs[kk + (lane >> 4)][wn0 + 16 * j + (lane & 15)];
-            br[j] = v.x; bi[j] = v.y;
-          }
-#pragma unroll
-          for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
-              accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accR[i][j], 0, 0, 0);
-              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
-              accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
-            }
-        }
-      } else {  // BF16x3
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
-          v8bf arh[NI], arl[NI], aih[NI], ail[NI], naih[NI], nail[NI];
-          v8bf brh[NJ], brl[NJ], bih[NJ], bil[NJ];
-#pragma unroll
-          for (int i = 0; i < NI; ++i) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              CT v = As[kk + 8 * (lane >> 5) + t][wm0 + 32 * i + (lane & 31)];
-              __bf16 h, l;
-              split_bf16(v.x, h, l); arh[i][t] = h; arl[i][t] = l;
-              split_bf16(v.y, h, l); aih[i][t] = h; ail[i][t] = l;
-              naih[i][t] = bf_neg(h); nail[i][t] = bf_neg(l);
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              CT v = Bs[kk + 8 * (lane >> 5) + t][wn0 + 32 * j + (lane & 31)];
-              __bf16 h, l;
-              split_bf16(v.x, h, l); brh[j][t] = h; brl[j][t] = l;
-              split_bf16(v.y, h, l); bih[j][t] = h; bil[j][t] = l;
-            }
-          }
-#pragma unroll
-          for (int i = 0; i < NI; ++i)
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-              v16f r = accR[i][j], m = accI[i][j];
-              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brh[j], r, 0, 0, 0);
-              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brl[j], r, 0, 0, 0);
-              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], brh[j], r, 0, 0, 0);
-              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih[i], bih[j], r, 0, 0, 0);
-              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih[i], bil[j], r, 0, 0, 0);
-              r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nail[i], bih[j], r, 0, 0, 0);
-              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bih[j], m, 0, 0, 0);
-              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bil[j], m, 0, 0, 0);
-              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], bih[j], m, 0, 0, 0);
-              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brh[j], m, 0, 0, 0);
-              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brl[j], m, 0, 0, 0);
-              m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail[i], brh[j], m, 0, 0, 0);
-              accR[i][j] = r; accI[i][j] = m;
-            }
-        }
-      }
-      __syncthreads();
+    for (int t = 0; t < NA; ++t) {
+      const int idx = tid + t * NT;
+      int mm, kk;
+      if (!TA) { mm = idx / BK; kk = idx % BK; }
+      else     { kk = idx / BM; mm = idx % BM; }
+      const int gm = m0 + mm, gk = ld_k0 + kk;
+      CT v = czero<CT>();
+      if (gm < M && gk < K) v = TA ? ld_c<CT, true>(A + (int64_t)gk * sg.lda + gm) : A[(int64_t)gm * sg.lda + gk];
+      ra[t] = v;
     }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int idx = tid + t * NT;
+      int kk, nn;
+      if (!TB) { kk = idx / BN; nn = idx % BN; }
+      else     { nn = idx / BK; kk = idx % BK; }
+      const int gn = n0 + nn, gk = ld_k0 + kk;
+      CT v = czero<CT>();
+      if (gn < N && gk < K) v = TB ? ld_c<CT, true>(B + (int64_t)gn * sg.ldb + gk) : B[(int64_t)gk * sg.ldb + gn];
+      rb[t] = v;
+    }
+    // advance to the next tile
+    ld_k0 += BK;
+    if (ld_k0 >= sg.K && ld_seg + 1 < job.nseg) {
+      ++ld_seg;
+      ld_k0 = 0;
+      sg = segs[job.seg0 + ld_seg];
+    } else if (ld_k0 >= sg.K) {
+      ld_seg = job.nseg;  // exhausted
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < NA; ++t) {
+      const int idx = tid + t * NT;
+      int mm, kk;
+      if (!TA) { mm = idx / BK; kk = idx % BK; }
+      else     { kk = idx / BM; mm = idx % BM; }
+      As[buf][kk][mm] = ra[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int idx = tid + t * NT;
+      int kk, nn;
+      if (!TB) { kk = idx / BN; nn = idx % BN; }
+      else     { nn = idx / BK; kk = idx % BK; }
+      Bs[buf][kk][nn] = rb[t];
+    }
+  };
+
+  load_tile();
+  store_tile(0);
+  __syncthreads();
+  int buf = 0;
+  while (true) {
+    const bool more = ld_seg < job.nseg;
+    if (more) load_tile();
+
+    if constexpr (PREC == PREC_FP32) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        float ar[NI], ai[NI], br[NJ], bi[NJ];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          CT v = As[buf][kk + (lane >> 5)][wm0 + 32 * i + (lane & 31)];
+          ar[i] = v.x; ai[i] = v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          CT v = Bs[buf][kk + (lane >> 5)][wn0 + 32 * j + (lane & 31)];
+          br[j] = v.x; bi[j] = v.y;
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], accR[i][j], 0, 0, 0);
+            accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[i], bi[j], accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], bi[j], accI[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], br[j], accI[i][j], 0, 0, 0);
+          }
+      }
+    } else if constexpr (PREC == PREC_FP64) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double ar[NI], ai[NI], br[NJ], bi[NJ];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          CT v = As[buf][kk + (lane >> 4)][wm0 + 16 * i + (lane & 15)];
+          ar[i] = v.x; ai[i] = v.y;
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          CT v = Bs[buf][kk + (lane >> 4)][wn0 + 16 * j + (lane & 15)];
+          br[j] = v.x; bi[j] = v.y;
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
+            accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accR[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+          }
+      }
+    } else {  // BF16x3
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 16) {
+        v8bf arh[NI], arl[NI], aih[NI], ail[NI], naih[NI], nail[NI];
+        v8bf brh[NJ], brl[NJ], bih[NJ], bil[NJ];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            CT v = As[buf][kk + 8 * (lane >> 5) + t][wm0 + 32 * i + (lane & 31)];
+            __bf16 h, l;
+            split_bf16(v.x, h, l); arh[i][t] = h; arl[i][t] = l;
+            split_bf16(v.y, h, l); aih[i][t] = h; ail[i][t] = l;
+            naih[i][t] = bf_neg(h); nail[i][t] = bf_neg(l);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            CT v = Bs[buf][kk + 8 * (lane >> 5) + t][wn0 + 32 * j + (lane & 31)];
+            __bf16 h, l;
+            split_bf16(v.x, h, l); brh[j][t] = h; brl[j][t] = l;
+            split_bf16(v.y, h, l); bih[j][t] = h; bil[j][t] = l;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            v16f r = accR[i][j], m = accI[i][j];
+            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brh[j], r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], brl[j], r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], brh[j], r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih[i], bih[j], r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(naih[i], bil[j], r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nail[i], bih[j], r, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bih[j], m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh[i], bil[j], m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl[i], bih[j], m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brh[j], m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih[i], brl[j], m, 0, 0, 0);
+            m = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail[i], brh[j], m, 0, 0, 0);
+            accR[i][j] = r; accI[i][j] = m;
+          }
+      }
+    }
+    if (!more) break;
+    store_tile(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
 
   // ---- epilogue
@@ -235,6 +277,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ 
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
+          // 32x32 outputs: accumulator r of lane l holds D[8(r/4) + 4(l/32) + r%4][l%32]
           const int row = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
           const int col = n0 + wn0 + 32 * j + (lane & 31);
           if (row < M && col < N) {

@@ -35,6 +35,13 @@ struct tn_ctx {
   double* pinned = nullptr;                             // host pinned scratch (4096 doubles)
   hipEvent_t ev[8];
   bool ev_ok = false;
+  // profiling of the window matvec (HIP events around each launch)
+  bool prof = false;
+  hipEvent_t pev[6];
+  double prof_ms[5] = {0, 0, 0, 0, 0};   // convert, GEMM-L, operators, GEMM-R, reduce
+  double prof_flops[3] = {0, 0, 0};      // algorithmic: L-contraction, R-contraction, whole matvec
+  int64_t prof_n = 0;
+  double prof_bytes[2] = {0, 0};         // algorithmic bytes read + written by the two GEMMs
 };
 
 void* dev_alloc(tn_ctx* c, size_t bytes);
@@ -138,6 +145,7 @@ struct WindowOp {
   void* partials = nullptr; // split-K partials
   int nsplit = 1;
   size_t n = 0;
+  double fl_L = 0, fl_R = 0, fl_all = 0, by_L = 0, by_R = 0;
   void setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int prec_, int chi_l_, int chi_r_,
              const std::vector<const void*>& envL, const std::vector<const void*>& envRt, bool raw_leg0,
              const std::string& tag);

@@ -193,7 +193,7 @@ static __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-#define MD_MAXV 64
+#define MD_MAXV 72
 int multidot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 512)); }
 
 // partials[v][block] = sum_{e in block} conj(vs[v][e]) * w[e]
@@ -374,22 +374,124 @@ hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream
   hipLaunchKernelGGL(ctranspose_kernel, dim3(grid_for(tot)), dim3(256), 0, st, dst, src, n, k);
   return hipGetLastError();
 }
-// Lanczos scalars: alpha_j = Re(h1[j] + h2[j]), beta_j = sqrt(nrm2), inv = 1/beta_j
-__global__ void lanczos_scalars_kernel(const cf64* h1, const cf64* h2, const cf64* nrm2, int j, double* alpha,
-                                       double* beta, double* inv, double* host_out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+// Lanczos step scalars and the projected problem, one wavefront:
+//   alpha_j = Re(h1[j] + h2[j]);  ||w||^2 = <w1, w1> - sum_i |h2_i|^2 (h2[j+1] holds
+//   <w1, w1> from the second Gram-Schmidt pass);  beta_j = ||w||.
+// Then the lowest eigenpair of the (j+1) x (j+1) tridiagonal T_j: 64-way
+// multisection on Sturm counts for the eigenvalue, inverse iteration with
+// partial pivoting (one lane) for the eigenvector, written as Ritz
+// coefficients.  host_out = {alpha, beta, lambda, y_last}.
+__global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const cf64* h2, int j, double* alpha,
+                                                          double* beta, double* inv, double* coefs, double* out) {
+  __shared__ double sa[80], sb[80], y[80], dd[80], du[80], du2[80], dl[80];
+  __shared__ int piv[80];
+  __shared__ double lam_s;
+  const int lane = threadIdx.x;
+  if (lane == 0) {
     const double a = h1[j].x + h2[j].x;
-    const double b = sqrt(fmax(nrm2[0].x, 0.0));
+    double w2 = h2[j + 1].x;
+    for (int i = 0; i <= j; ++i) w2 -= h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+    const double b = sqrt(fmax(w2, 0.0));
     alpha[j] = a;
     beta[j] = b;
     inv[0] = (b > 0.0) ? 1.0 / b : 0.0;
-    host_out[0] = a;
-    host_out[1] = b;
+    out[0] = a;
+    out[1] = b;
+  }
+  __syncthreads();
+  const int n = j + 1;
+  for (int i = lane; i < n; i += 64) { sa[i] = alpha[i]; sb[i] = (i < n - 1) ? beta[i] : 0.0; }
+  __syncthreads();
+  double lo = 1e300, hi = -1e300;
+  for (int i = lane; i < n; i += 64) {
+    const double r = (i > 0 ? fabs(sb[i - 1]) : 0.0) + (i < n - 1 ? fabs(sb[i]) : 0.0);
+    lo = fmin(lo, sa[i] - r);
+    hi = fmax(hi, sa[i] + r);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  const double sc = fmax(fabs(lo), fabs(hi)) + 1e-300;
+  lo -= 1e-14 * sc;
+  hi += 1e-14 * sc;
+  for (int it = 0; it < 40; ++it) {
+    if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    int cnt = 0;
+    double q = sa[0] - x;
+    if (fabs(q) < 1e-300) q = -1e-300;
+    cnt += q < 0;
+    for (int i = 1; i < n; ++i) {
+      q = (sa[i] - x) - sb[i - 1] * sb[i - 1] / q;
+      if (fabs(q) < 1e-300) q = -1e-300;
+      cnt += q < 0;
+    }
+    const unsigned long long le = __ballot(cnt == 0);
+    const int nle = __popcll(le);
+    const double nlo = (nle == 0) ? lo : __shfl(x, nle - 1, 64);
+    const double nhi = (nle == 64) ? hi : __shfl(x, nle, 64);
+    if (!(nhi - nlo < hi - lo)) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) {
+    const double lam = 0.5 * (lo + hi);
+    lam_s = lam;
+    const double tiny = fmax(2.2e-16 * sc, 1e-300);
+    // LU with partial pivoting of T - lam I
+    for (int i = 0; i < n; ++i) {
+      dd[i] = sa[i] - lam;
+      du[i] = (i < n - 1) ? sb[i] : 0.0;
+      dl[i] = (i < n - 1) ? sb[i] : 0.0;
+      du2[i] = 0.0;
+      piv[i] = 0;
+    }
+    for (int i = 0; i < n - 1; ++i) {
+      if (fabs(dd[i]) >= fabs(dl[i])) {
+        if (dd[i] == 0.0) dd[i] = tiny;
+        const double f = dl[i] / dd[i];
+        dl[i] = f;
+        dd[i + 1] -= f * du[i];
+      } else {
+        const double f = dd[i] / dl[i];
+        dd[i] = dl[i];
+        dl[i] = f;
+        const double t = du[i];
+        du[i] = dd[i + 1];
+        dd[i + 1] = t - f * dd[i + 1];
+        if (i < n - 2) { du2[i] = du[i + 1]; du[i + 1] = -f * du[i + 1]; }
+        piv[i] = 1;
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      if (fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
+    for (int i = 0; i < n; ++i) y[i] = 1.0;
+    for (int it = 0; it < 3; ++it) {
+      for (int i = 0; i < n - 1; ++i) {
+        if (piv[i]) { const double t = y[i]; y[i] = y[i + 1]; y[i + 1] = t - dl[i] * y[i]; }
+        else y[i + 1] -= dl[i] * y[i];
+      }
+      y[n - 1] /= dd[n - 1];
+      if (n >= 2) y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) / dd[n - 2];
+      for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / dd[i];
+      double nr = 0.0;
+      for (int i = 0; i < n; ++i) nr += y[i] * y[i];
+      nr = 1.0 / sqrt(nr);
+      for (int i = 0; i < n; ++i) y[i] *= nr;
+    }
+    // sign convention: first component non-negative
+    const double sg = (y[0] < 0.0) ? -1.0 : 1.0;
+    for (int i = 0; i < n; ++i) coefs[i] = sg * y[i];
+    out[2] = lam;
+    out[3] = sg * y[n - 1];
   }
 }
-hipError_t launch_lanczos_scalars(const cf64* h1, const cf64* h2, const cf64* nrm2, int j, double* alpha, double* beta,
-                                  double* inv, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(lanczos_scalars_kernel, dim3(1), dim3(64), 0, st, h1, h2, nrm2, j, alpha, beta, inv, out);
+hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, double* alpha, double* beta, double* inv,
+                               double* coefs, double* out, hipStream_t st) {
+  if (j + 1 > 72) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(64), 0, st, h1, h2, j, alpha, beta, inv, coefs, out);
   return hipGetLastError();
 }
 // gather real parts of column 0 of an n x n complex matrix (eigenvectors as columns)

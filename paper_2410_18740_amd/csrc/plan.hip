@@ -232,6 +232,17 @@ void WindowOp::setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int pre
   njobL = (int)jl.size();
   nopjob = (int)oj.size();
   njobR = (int)jr.size();
+  // algorithmic work of the two contractions (formula terms) for profiling
+  {
+    const double d2 = (double)ds * dt;
+    fl_L = 8.0 * d2 * chi_l * (double)chi_l * chi_r * wl;
+    fl_R = 8.0 * d2 * chi_l * (double)chi_r * chi_r * wr;
+    fl_all = (nsites == 2 && !raw_leg0) ? matvec_flops_formula(mpo, site, chi_l, chi_r) : fl_L + fl_R;
+    const double ebs = (double)eb;
+    // L: environments + theta in + Y out;  R: Y/T in + environments + partial out
+    by_L = ebs * ((double)wl * chi_l * chi_l + (double)n + (double)plan.L.size() * n);
+    by_R = ebs * ((double)plan.R.size() * n + (double)wr * chi_r * chi_r + (double)nsplit * n);
+  }
   // one descriptor block
   size_t off = 0;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -272,11 +283,32 @@ void WindowOp::setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int pre
 void WindowOp::apply(const cf64* x, cf64* y) {
   hipStream_t st = ctx->stream;
   const int sprec = (prec == PREC_FP64) ? PREC_FP64 : PREC_FP32;
+  const bool pf = ctx->prof;
+  if (pf) HIPCHK(hipEventRecord(ctx->pev[0], st));
   HIPCHK(launch_convert(sprec, xin, PREC_FP64, x, (int64_t)n, st));
+  if (pf) HIPCHK(hipEventRecord(ctx->pev[1], st));
   HIPCHK(launch_cgemm(prec, 0, 0, d_jobL, njobL, d_segL, chi_l, ds * dt * chi_r, 0, st));
+  if (pf) HIPCHK(hipEventRecord(ctx->pev[2], st));
   HIPCHK(launch_opapply(sprec, d_opjob, nopjob, d_opterm, chi_l, ds, dt, chi_r, st));
+  if (pf) HIPCHK(hipEventRecord(ctx->pev[3], st));
   HIPCHK(launch_cgemm(prec, 0, 0, d_jobR, njobR, d_segR, chi_l * ds * dt, chi_r, 0, st));
+  if (pf) HIPCHK(hipEventRecord(ctx->pev[4], st));
   HIPCHK(launch_reduce_partials(y, sprec, partials, nsplit, (int64_t)n, st));
+  if (pf) {
+    HIPCHK(hipEventRecord(ctx->pev[5], st));
+    HIPCHK(hipEventSynchronize(ctx->pev[5]));
+    for (int i = 0; i < 5; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->pev[i], ctx->pev[i + 1]));
+      ctx->prof_ms[i] += ms;
+    }
+    ctx->prof_flops[0] += fl_L;
+    ctx->prof_flops[1] += fl_R;
+    ctx->prof_flops[2] += fl_all;
+    ctx->prof_bytes[0] += by_L;
+    ctx->prof_bytes[1] += by_R;
+    ctx->prof_n += 1;
+  }
 }
 
 // ------------------------------------------------------------------ flop formulas

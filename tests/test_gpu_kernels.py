@@ -239,7 +239,9 @@ def test_truncate(ctx, m, n, chi, decay, rank, direction):
     # the product is the renormalised best rank-k approximation
     approx = left @ right
     best = (U * S) @ Vh
-    assert np.linalg.norm(approx - best) < 1e-10
+    # directions with sigma < ~sqrt(eps) are not resolved by the Gram matrix
+    tol = 1e-10 if S_ref[k - 1] > 1e-6 else 5e-8
+    assert np.linalg.norm(approx - best) < tol
     if direction > 0:
         assert np.abs(left.conj().T @ left - np.eye(k)).max() < 1e-12
     else:
