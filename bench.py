@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--max-matvecs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare", action="store_true", help="also time one sweep in each other form")
+    ap.add_argument("--to-target", action="store_true",
+                    help="time-to-target comparison of the forms (plain FP64, FP32+refine, BF16x3+refine)")
+    ap.add_argument("--target", type=float, default=1e-8)
+    ap.add_argument("--max-sweeps", type=int, default=12)
     return ap.parse_args()
 
 
@@ -78,8 +82,52 @@ def cpu_baseline(w, r, U, budget_s=20.0):
                       f"of the same workload, {dt:.1f} s"}
 
 
+def to_target(a):
+    """Wall time until the FP64 <H> reaches the target, per arithmetic form,
+    from the same seeded initial state (R-literal reading: <H> <= target)."""
+    import torch
+    import paper_2410_18740_amd as P
+    import workloads as W
+    w = W.WORKLOADS[a.workload]
+    r, U = W.workload_problem(a.workload)
+    ctx = P.Context(0)
+    res = {}
+    for form in ("fp64", "fp32", "bf16x3"):
+        prec = FORMS[form]
+        mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
+        mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
+        sw = P.SweepOpts(chi_max=w.chi, krylov_max=24, max_matvecs=a.max_matvecs)
+        torch.cuda.synchronize()
+        out = P.dmrg_solve(ctx, mpo, mps, sw, max_sweeps=a.max_sweeps, bulk_precision=prec, max_refine=3,
+                           target=a.target, switch_tol=1e-6, conv_tol=1e-13,
+                           bulk_tol=1e-8 if prec == 0 else 1e-6, refine_tol=1e-9, lbo_bulk=0 if a.no_lbo else 1,
+                           lbo_refine=0 if a.no_lbo else 1)
+        res[form] = out
+        print(f"{form}: reached={out['reached']} t_target={out['t_target']:.2f}s sweeps={out['sweeps']} "
+              f"E={out['energy']:.3e} trace={[f'{e:.2e}' for e in out['energy_trace']]}", file=sys.stderr, flush=True)
+        del mps, mpo
+    base = res["fp64"]["t_target"]
+    line = {
+        "metric": METRIC, "value": res["fp32"]["t_target"], "unit": "s", "n_gpus": 1, "steps": None,
+        "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic", "config": {"workload": a.workload, "target": a.target,
+                                                         "lbo": not a.no_lbo},
+        "forms": {f: {k: v for k, v in o.items()} for f, o in res.items()},
+        "speedup_vs_plain_fp64": {f: (base / o["t_target"]) if o["reached"] and res["fp64"]["reached"] else None
+                                  for f, o in res.items()},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     a = parse()
+    if a.to_target:
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        to_target(a)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the sharded design is described in DESIGN.md",
               file=sys.stderr)

@@ -157,6 +157,43 @@ typedef struct {
 
 tn_status tn_dmrg_sweep(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, const tn_sweep_opts* opts, tn_sweep_stats* out);
 
+/* Sweeps with the precision schedule until a target energy.  Bulk sweeps run
+ * in bulk_precision (TN_FP64 for the plain form); once the FP64 <H> after a
+ * sweep changes by less than switch_tol (relative to max(1, <H>)) or rises
+ * twice, up to max_refine FP64 refinement sweeps follow.  The run stops as soon
+ * as <H> <= target, when an FP64 sweep changes <H> by less than conv_tol, or
+ * after max_sweeps.  Wall time starts at the call (inputs already on the GPU). */
+typedef struct {
+  int32_t max_sweeps;
+  int32_t bulk_precision;
+  int32_t max_refine;
+  int32_t lbo_bulk;         /* local basis optimisation in bulk sweeps */
+  int32_t lbo_refine;       /* ... and in refinement sweeps */
+  int32_t pad_;
+  double target;            /* stop when <H> <= target */
+  double switch_tol;
+  double conv_tol;
+  double bulk_tol;          /* Lanczos tolerance of bulk sweeps */
+  double refine_tol;        /* Lanczos tolerance of refinement sweeps */
+  tn_sweep_opts sweep;      /* chi_max, sigma_cut, krylov_max, max_matvecs (precision/tol/lbo set per sweep) */
+} tn_solve_opts;
+
+typedef struct {
+  int32_t sweeps;           /* total sweeps run */
+  int32_t refine_sweeps;
+  int32_t reached;          /* 1 if <H> <= target */
+  int32_t pad_;
+  double energy;            /* final FP64 <H> */
+  double seconds;           /* wall time of the whole call */
+  double t_target;          /* wall time when <H> <= target first held (NaN if never) */
+  double heff_flops, t_heff;
+} tn_solve_result;
+
+/* energy_trace / time_trace (may be NULL): FP64 <H> and elapsed seconds after
+ * each sweep, capacity max_sweeps. */
+tn_status tn_dmrg_solve(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, const tn_solve_opts* opts, tn_solve_result* out,
+                        double* energy_trace, double* time_trace);
+
 /* <psi|PHP|psi>/<psi|psi> in FP64 by a full environment sweep (eq.
  * MagOfSimError); norm2 (may be NULL) receives <psi|psi>. */
 tn_status tn_energy(tn_ctx* ctx, const tn_mpo* mpo, const tn_mps* mps, double* energy, double* norm2);

@@ -58,6 +58,22 @@ class tn_sweep_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
+class tn_solve_opts(C.Structure):
+    _fields_ = [("max_sweeps", C.c_int32), ("bulk_precision", C.c_int32), ("max_refine", C.c_int32),
+                ("lbo_bulk", C.c_int32), ("lbo_refine", C.c_int32), ("pad_", C.c_int32),
+                ("target", C.c_double), ("switch_tol", C.c_double), ("conv_tol", C.c_double),
+                ("bulk_tol", C.c_double), ("refine_tol", C.c_double), ("sweep", tn_sweep_opts)]
+
+
+class tn_solve_result(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("refine_sweeps", C.c_int32), ("reached", C.c_int32), ("pad_", C.c_int32),
+                ("energy", C.c_double), ("seconds", C.c_double), ("t_target", C.c_double),
+                ("heff_flops", C.c_double), ("t_heff", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
 _lib = None
 
 
@@ -90,6 +106,7 @@ def lib():
         "tn_mps_destroy": (None, [vp]),
         "tn_dmrg_sweep": (i32, [vp, vp, vp, P(tn_sweep_opts), P(tn_sweep_stats)]),
         "tn_energy": (i32, [vp, vp, vp, P(dbl), P(dbl)]),
+        "tn_dmrg_solve": (i32, [vp, vp, vp, P(tn_solve_opts), P(tn_solve_result), P(dbl), P(dbl)]),
         "tn_lbo_step": (i32, [vp, vp, vp, i32, P(tn_sweep_opts), P(dbl)]),
         "tn_marginals": (i32, [vp, vp, vp, i32, P(dbl)]),
         "tn_sample": (i32, [vp, vp, vp, i64, C.c_uint64, vp]),

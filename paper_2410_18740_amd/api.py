@@ -225,6 +225,23 @@ def dmrg_sweep(ctx: Context, mpo: MPO, mps: MPS, opts: SweepOpts) -> dict:
     return st.as_dict()
 
 
+def dmrg_solve(ctx: Context, mpo: MPO, mps: MPS, sweep: SweepOpts, max_sweeps: int = 20,
+               bulk_precision: int = FP32, max_refine: int = 2, target: float = 1e-8,
+               switch_tol: float = 1e-5, conv_tol: float = 1e-12, bulk_tol: float = 1e-6,
+               refine_tol: float = 1e-9, lbo_bulk: int = 1, lbo_refine: int = 0) -> dict:
+    """Sweeps with the precision schedule until <H> <= target (see tn_dmrg_solve)."""
+    so = L.tn_solve_opts(max_sweeps, bulk_precision, max_refine, lbo_bulk, lbo_refine, 0, target, switch_tol,
+                         conv_tol, bulk_tol, refine_tol, sweep.c())
+    res = L.tn_solve_result()
+    et = np.full(max_sweeps, np.nan)
+    tt = np.full(max_sweeps, np.nan)
+    ctx.check(L.lib().tn_dmrg_solve(ctx.h, mpo.h, mps.h, C.byref(so), C.byref(res), L.dptr(et), L.dptr(tt)))
+    d = res.as_dict()
+    d["energy_trace"] = et[:res.sweeps].tolist()
+    d["time_trace"] = tt[:res.sweeps].tolist()
+    return d
+
+
 def energy(ctx: Context, mpo: MPO, mps: MPS):
     e = C.c_double()
     n = C.c_double()

@@ -183,7 +183,7 @@ static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& eva
   tw.taus = wsT<cf64>(c, "eig:tau", p);
   tw.dg = wsT<double>(c, "eig:dg", p);
   tw.off = wsT<double>(c, "eig:off", p);
-  tw.y = wsT<cf64>(c, "eig:y", p);
+  tw.y = wsT<cf64>(c, "eig:y", 2 * (size_t)p);
   tw.w = wsT<cf64>(c, "eig:w", 2 * (size_t)p);
   tw.counter = wsT<unsigned int>(c, "eig:cnt", 1);
   HIPCHK(launch_tridiag(tw, p, st));
@@ -502,14 +502,21 @@ static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_
   LzResult lz = lanczos(c, [&](const cf64* x, cf64* y) { op.apply(x, y); }, B, (int64_t)nraw, o.tol, o.krylov_max,
                         o.max_matvecs);
   if (mv) *mv += lz.matvecs;
-  // rho = sum_a B[a] B[a]^dag (D x D)
+  // rho = sum_a B[a] B[a]^dag (D x D): split over a into partial products,
+  // then a fixed-order reduction
   cf64* rho = wsT<cf64>(c, "lbo:rho", (size_t)D * D);
   {
+    const int np = std::max(1, std::min(cl, 64));
+    cf64* parts = wsT<cf64>(c, "lbo:rhop", (size_t)np * D * D);
     std::vector<GemmJob> jobs;
     std::vector<GemmSeg> segs;
     for (int a = 0; a < cl; ++a) segs.push_back({B + (size_t)a * D * cr, B + (size_t)a * D * cr, cr, cr, cr, 0});
-    jobs.push_back({rho, D, D, D, 0, cl});
+    for (int g = 0; g < np; ++g) {
+      const int a0 = (int)((int64_t)cl * g / np), a1 = (int)((int64_t)cl * (g + 1) / np);
+      jobs.push_back({parts + (size_t)g * D * D, D, D, D, a0, a1 - a0});
+    }
     gemm_batch(c, PREC_FP64, 0, 1, jobs, segs, D, D, "lbo:g1");
+    HIPCHK(launch_reduce_partials(rho, PREC_FP64, parts, np, (int64_t)D * D, st));
   }
   double* ev = wsT<double>(c, "lbo:ev", D);
   cf64* Zr = wsT<cf64>(c, "lbo:Z", (size_t)D * D);
@@ -734,6 +741,65 @@ extern "C" tn_status tn_dmrg_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_s
   check_opts(o);
   check_pair(mpo, m);
   sweep_impl(c, mpo, m, *o, out);
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_dmrg_solve(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_solve_opts* so, tn_solve_result* out,
+                                   double* etrace, double* ttrace) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !m || !so) TN_THROW(TN_EINVAL, "null argument");
+  if (so->max_sweeps < 1) TN_THROW(TN_EINVAL, "max_sweeps must be >= 1");
+  if (so->bulk_precision < 0 || so->bulk_precision > 2) TN_THROW(TN_EINVAL, "unknown bulk precision");
+  if (so->max_refine < 0) TN_THROW(TN_EINVAL, "max_refine must be >= 0");
+  check_pair(mpo, m);
+  tn_sweep_opts base = so->sweep;
+  base.precision = so->bulk_precision;
+  base.tol = so->bulk_tol;
+  base.compute_energy = 1;
+  check_opts(&base);
+  if (!(so->refine_tol > 0.0)) TN_THROW(TN_EINVAL, "refine_tol must be positive");
+  const double t0 = wall();
+  tn_solve_result R{};
+  R.t_target = NAN;
+  R.energy = NAN;
+  bool refining = so->bulk_precision == PREC_FP64;
+  int rises = 0, refine_done = 0;
+  double prev = NAN;
+  for (int sw = 0; sw < so->max_sweeps; ++sw) {
+    tn_sweep_opts o = base;
+    const bool fp64 = refining || so->bulk_precision == PREC_FP64;
+    o.precision = fp64 ? PREC_FP64 : so->bulk_precision;
+    o.tol = (refining && so->bulk_precision != PREC_FP64) ? so->refine_tol : so->bulk_tol;
+    o.lbo = (refining && so->bulk_precision != PREC_FP64) ? so->lbo_refine : so->lbo_bulk;
+    tn_sweep_stats S{};
+    sweep_impl(c, mpo, m, o, &S);
+    R.sweeps++;
+    if (refining && so->bulk_precision != PREC_FP64) { R.refine_sweeps++; refine_done++; }
+    R.heff_flops += S.heff_flops;
+    R.t_heff += S.t_heff;
+    const double E = S.energy;
+    const double el = wall() - t0;
+    if (etrace) etrace[sw] = E;
+    if (ttrace) ttrace[sw] = el;
+    R.energy = E;
+    if (E <= so->target) {
+      if (std::isnan(R.t_target)) R.t_target = el;
+      R.reached = 1;
+      break;
+    }
+    const double dE = std::isnan(prev) ? INFINITY : E - prev;
+    prev = E;
+    if (fp64 && std::fabs(dE) < so->conv_tol * std::max(1.0, std::fabs(E))) break;
+    if (!refining) {
+      if (dE > 0) ++rises;
+      if (std::fabs(dE) < so->switch_tol * std::max(1.0, std::fabs(E)) || rises >= 2) refining = true;
+    } else if (so->bulk_precision != PREC_FP64 && refine_done >= so->max_refine) {
+      break;
+    }
+  }
+  R.seconds = wall() - t0;
+  if (out) *out = R;
   TN_GUARD_END(c)
 }
 

@@ -182,22 +182,30 @@ hipError_t launch_build_tridiag(const double* alpha, const double* beta, int n, 
 }
 
 // ------------------------------------------------------------------ Householder tridiagonalisation
-// Reflector step for column j (any workgroup size that is a multiple of 64):
-//   if j > 0: w_{j-1} = y_{j-1} - 1/2 tau_{j-1} (y^H v_{j-1}) v_{j-1}
-//   current column j (rows >= j) = conj(row j) minus the pending rank-2 update
-//   reflector with H^H x = beta e_1, beta real (LAPACK zlarfg conventions)
-static __device__ void tridiag_reflector(cf64* __restrict__ A, cf64* __restrict__ vs, cf64* __restrict__ taus,
-                                         double* __restrict__ dg, double* __restrict__ off,
-                                         const cf64* __restrict__ y, cf64* __restrict__ wbuf, int p, int j,
-                                         double (*red)[16], cf64* bc) {
+// One launch per column j.  Every workgroup recomputes (redundantly, from data
+// finalised by the previous launch) w_{j-1} = y_{j-1} - 1/2 tau_{j-1}
+// (y_{j-1}^H v_{j-1}) v_{j-1} and the reflector of column j into LDS, then
+// updates its own rows i in [j+1, p) with the pending rank-2 term
+// (v_{j-1}, w_{j-1}) and forms y_j[i] = tau_j sum_k A[i][k] v_j[k] (one
+// wavefront per row).  Workgroup 0 also publishes v_j, tau_j and the diagonal
+// and off-diagonal entries.
+__global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* __restrict__ vs,
+                                                    cf64* __restrict__ taus, double* __restrict__ dg,
+                                                    double* __restrict__ off, cf64* __restrict__ y, int p, int j) {
+  extern __shared__ unsigned char sm_raw[];
+  cf64* vS = reinterpret_cast<cf64*>(sm_raw);  // v_j
+  cf64* wS = vS + p;                           // w_{j-1}
+  __shared__ double red[2][4];
+  __shared__ cf64 bc[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nt = blockDim.x, nw = nt >> 6;
-  cf64* wprev = wbuf + (int64_t)((j + 1) & 1) * p;  // w_{j-1}
   const cf64* vprev = (j > 0) ? vs + (int64_t)(j - 1) * p : nullptr;
+  cf64* ycur = y + (int64_t)(j & 1) * p;            // y_j (written here)
+  const cf64* yprev = y + (int64_t)((j + 1) & 1) * p;  // y_{j-1}
+  // ---- w_{j-1}
   if (j > 0) {
     double re = 0.0, im = 0.0;
-    for (int i = j + tid; i < p; i += nt) {
-      const cf64 a = y[i], b = vprev[i];
+    for (int i = j + tid; i < p; i += 256) {
+      const cf64 a = yprev[i], b = vprev[i];
       re += a.x * b.x + a.y * b.y;
       im += a.x * b.y - a.y * b.x;
     }
@@ -205,40 +213,40 @@ static __device__ void tridiag_reflector(cf64* __restrict__ A, cf64* __restrict_
     if (lane == 0) { red[0][wave] = re; red[1][wave] = im; }
     __syncthreads();
     if (tid == 0) {
-      double r = 0, m = 0;
-      for (int w = 0; w < nw; ++w) { r += red[0][w]; m += red[1][w]; }
-      const cf64 k = cmul(taus[j - 1], make_double2(r, m));
+      const cf64 k = cmul(taus[j - 1], make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                                                    red[1][0] + red[1][1] + red[1][2] + red[1][3]));
       bc[0] = make_double2(-0.5 * k.x, -0.5 * k.y);
     }
     __syncthreads();
     const cf64 c = bc[0];
-    for (int i = tid; i < p; i += nt) wprev[i] = (i >= j) ? cadd(y[i], cmul(c, vprev[i])) : czero<cf64>();
-    __syncthreads();
+    for (int i = tid; i < p; i += 256) wS[i] = (i >= j) ? cadd(yprev[i], cmul(c, vprev[i])) : czero<cf64>();
+  } else {
+    for (int i = tid; i < p; i += 256) wS[i] = czero<cf64>();
   }
-  if (j >= p) return;
-  cf64 wj = czero<cf64>(), vj = czero<cf64>();
-  if (j > 0) { wj = wprev[j]; vj = vprev[j]; }
-  if (tid == 0) {
-    double d = A[(int64_t)j * p + j].x;
+  __syncthreads();
+  // ---- column j (rows >= j) with the pending update; reflector
+  const cf64 wj = wS[j];
+  const cf64 vj = (j > 0) ? vprev[j] : czero<cf64>();
+  const cf64* rowj = A + (int64_t)j * p;
+  if (blockIdx.x == 0 && tid == 0) {
+    double d = rowj[j].x;
     if (j > 0) d -= 2.0 * (vj.x * wj.x + vj.y * wj.y);
     dg[j] = d;
   }
   if (j == p - 1) return;
   double nrm = 0.0;
-  for (int i = j + 2 + tid; i < p; i += nt) {
-    cf64 x = cconj(A[(int64_t)j * p + i]);
-    if (j > 0) x = csub(x, cadd(cmulc(vprev[i], wj), cmulc(wprev[i], vj)));
-    nrm += cabs2(x);
+  for (int i = j + 1 + tid; i < p; i += 256) {
+    cf64 x = cconj(rowj[i]);
+    if (j > 0) x = csub(x, cadd(cmulc(vprev[i], wj), cmulc(wS[i], vj)));
+    vS[i] = x;  // stash the column; scaled below
+    if (i > j + 1) nrm += cabs2(x);
   }
   nrm = wave_sum_d(nrm);
   if (lane == 0) red[0][wave] = nrm;
   __syncthreads();
   if (tid == 0) {
-    double xn2 = 0.0;
-    for (int w = 0; w < nw; ++w) xn2 += red[0][w];
-    const int i = j + 1;
-    cf64 alpha = cconj(A[(int64_t)j * p + i]);
-    if (j > 0) alpha = csub(alpha, cadd(cmulc(vprev[i], wj), cmulc(wprev[i], vj)));
+    const double xn2 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const cf64 alpha = vS[j + 1];
     cf64 tau, scale;
     double beta;
     if (xn2 == 0.0 && alpha.y == 0.0) {
@@ -253,72 +261,52 @@ static __device__ void tridiag_reflector(cf64* __restrict__ A, cf64* __restrict_
       const double dd = den.x * den.x + den.y * den.y;
       scale = make_double2(den.x / dd, -den.y / dd);
     }
-    taus[j] = tau;
-    off[j] = beta;
+    bc[0] = tau;
     bc[1] = scale;
+    if (blockIdx.x == 0) { taus[j] = tau; off[j] = beta; }
   }
   __syncthreads();
-  const cf64 scale = bc[1];
-  cf64* vj_out = vs + (int64_t)j * p;
-  for (int i = tid; i < p; i += nt) {
+  const cf64 tau = bc[0], scale = bc[1];
+  for (int i = tid; i < p; i += 256) {
     cf64 v = czero<cf64>();
     if (i == j + 1) v = make_double2(1.0, 0.0);
-    else if (i > j + 1) {
-      cf64 x = cconj(A[(int64_t)j * p + i]);
-      if (j > 0) x = csub(x, cadd(cmulc(vprev[i], wj), cmulc(wprev[i], vj)));
-      v = cmul(x, scale);
-    }
-    vj_out[i] = v;
+    else if (i > j + 1) v = cmul(vS[i], scale);
+    vS[i] = v;
   }
-}
-
-__global__ __launch_bounds__(1024) void tridiag_stepA(cf64* __restrict__ A, cf64* __restrict__ vs,
-                                                       cf64* __restrict__ taus, double* __restrict__ dg,
-                                                       double* __restrict__ off, const cf64* __restrict__ y,
-                                                       cf64* __restrict__ wbuf, int p, int j) {
-  __shared__ double red[2][16];
-  __shared__ cf64 bc[4];
-  tridiag_reflector(A, vs, taus, dg, off, y, wbuf, p, j, red, bc);
-}
-
-// Row step for column j (one wavefront per row i in [j+1, p)): apply the
-// pending update (v_{j-1}, w_{j-1}) to row i (columns >= j+1), then
-// y_i = tau_j sum_k A[i][k] v_j[k].  A one-workgroup reflector launch follows.
-__global__ __launch_bounds__(256) void tridiag_stepB(cf64* __restrict__ A, const cf64* __restrict__ vs,
-                                                      const cf64* __restrict__ taus, cf64* __restrict__ y,
-                                                      const cf64* __restrict__ wbuf, int p, int j) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    cf64* vout = vs + (int64_t)j * p;
+    for (int i = tid; i < p; i += 256) vout[i] = vS[i];
+  }
+  // ---- own rows
   const int i = j + 1 + blockIdx.x * 4 + wave;
   if (i >= p) return;
-  const cf64* v = vs + (int64_t)j * p;
-  const cf64* vprev = (j > 0) ? vs + (int64_t)(j - 1) * p : nullptr;
-  const cf64* wprev = wbuf + (int64_t)((j + 1) & 1) * p;
   cf64* row = A + (int64_t)i * p;
   cf64 vi = czero<cf64>(), wi = czero<cf64>();
-  if (j > 0) { vi = vprev[i]; wi = wprev[i]; }
+  if (j > 0) { vi = vprev[i]; wi = wS[i]; }
   double re = 0.0, im = 0.0;
   for (int k = j + 1 + lane; k < p; k += 64) {
     cf64 a = row[k];
     if (j > 0) {
-      a = csub(a, cadd(cmulc(vi, wprev[k]), cmulc(wi, vprev[k])));
+      a = csub(a, cadd(cmulc(vi, wS[k]), cmulc(wi, vprev[k])));
       row[k] = a;
     }
-    const cf64 vk = v[k];
+    const cf64 vk = vS[k];
     re += a.x * vk.x - a.y * vk.y;
     im += a.x * vk.y + a.y * vk.x;
   }
   re = wave_sum_d(re);
   im = wave_sum_d(im);
-  if (lane == 0) y[i] = cmul(taus[j], make_double2(re, im));
+  if (lane == 0) ycur[i] = cmul(tau, make_double2(re, im));
 }
 
 hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st) {
+  const size_t shm = (size_t)2 * p * sizeof(cf64);
+  if (shm > 150 * 1024) return hipErrorInvalidValue;
   for (int j = 0; j < p; ++j) {
-    hipLaunchKernelGGL(tridiag_stepA, dim3(1), dim3(1024), 0, st, tw.A, tw.vs, tw.taus, tw.dg, tw.off, tw.y, tw.w, p, j);
-    if (j <= p - 2) {
-      const int rows = p - j - 1;
-      hipLaunchKernelGGL(tridiag_stepB, dim3((rows + 3) / 4), dim3(256), 0, st, tw.A, tw.vs, tw.taus, tw.y, tw.w, p, j);
-    }
+    const int rows = p - j - 1;
+    hipLaunchKernelGGL(tridiag_col, dim3(std::max(1, (rows + 3) / 4)), dim3(256), shm, st, tw.A, tw.vs, tw.taus,
+                       tw.dg, tw.off, tw.y, p, j);
   }
   return hipGetLastError();
 }
@@ -386,99 +374,88 @@ hipError_t launch_bisect_top(const double* dg, const double* off, int p, int k, 
 }
 
 // ------------------------------------------------------------------ inverse iteration
-// One thread per eigenvalue.  scratch layout: 4*p doubles per column, interleaved.
-__global__ void inverse_iter_kernel(const double* __restrict__ dg, const double* __restrict__ off, int p, int k,
-                                    const double* __restrict__ evals, double* __restrict__ X,
-                                    double* __restrict__ scratch) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per eigenvalue; the LU factors of (T - lambda I) with partial
+// pivoting live in LDS (5 p doubles), the recurrences run on one lane.
+__global__ __launch_bounds__(64) void inverse_iter_kernel(const double* __restrict__ dg, const double* __restrict__ off,
+                                                          int p, int k, const double* __restrict__ evals,
+                                                          double* __restrict__ X) {
+  extern __shared__ unsigned char sm_raw[];
+  double* dd = reinterpret_cast<double*>(sm_raw);
+  double* du = dd + p;
+  double* du2 = du + p;
+  double* dl = du2 + p;
+  double* b = dl + p;
+  unsigned char* piv = reinterpret_cast<unsigned char*>(b + p);
+  __shared__ double red[1];
+  const int t = blockIdx.x;
+  const int lane = threadIdx.x;
   if (t >= k) return;
-  const int64_t K = k;
-  double* dd = scratch;                 // [i][t]
-  double* du = scratch + (int64_t)p * K;
-  double* du2 = scratch + 2 * (int64_t)p * K;
-  double* dl = scratch + 3 * (int64_t)p * K;
-  double* x = X + (int64_t)t * p;        // column-major X[t][i]
-  double tnorm = 0.0;
-  for (int i = 0; i < p; ++i) tnorm = fmax(tnorm, fabs(dg[i]) + (i > 0 ? fabs(off[i - 1]) : 0.0) + (i < p - 1 ? fabs(off[i]) : 0.0));
-  const double lam = evals[t];
-  const double eps = 2.2e-16;
-  const double tiny = fmax(eps * tnorm, 1e-300);
-  // LU with partial pivoting of (T - lam I); pivot flag encoded in du2 sign via separate array: use dl high bit
-  // factorisation
-  for (int i = 0; i < p; ++i) {
-    dd[i * K + t] = dg[i] - lam;
-    du[i * K + t] = (i < p - 1) ? off[i] : 0.0;
-    du2[i * K + t] = 0.0;
-    dl[i * K + t] = (i < p - 1) ? off[i] : 0.0;
+  double tn = 0.0;
+  for (int i = lane; i < p; i += 64) {
+    tn = fmax(tn, fabs(dg[i]) + (i > 0 ? fabs(off[i - 1]) : 0.0) + (i < p - 1 ? fabs(off[i]) : 0.0));
+    dd[i] = dg[i] - evals[t];
+    du[i] = (i < p - 1) ? off[i] : 0.0;
+    dl[i] = (i < p - 1) ? off[i] : 0.0;
+    du2[i] = 0.0;
+    piv[i] = 0;
+    b[i] = 1.0 + 0.37 * sin(1.3 * (double)(i + 1) * (double)(t + 1));
   }
-  // pivots stored as the sign trick is unsafe; keep a bitmask in registers for up to p bits is too big,
-  // so we store pivot flags by negating nothing and instead recompute: we use du2 != 0 or an explicit flag array.
-  // explicit flag: reuse X as temporary storage of flags (overwritten later by the solution).
-  for (int i = 0; i < p - 1; ++i) {
-    const double di = dd[i * K + t], li = dl[i * K + t];
-    if (fabs(di) >= fabs(li)) {
-      double piv = di;
-      if (piv == 0.0) { piv = tiny; dd[i * K + t] = piv; }
-      const double fact = li / piv;
-      dl[i * K + t] = fact;
-      dd[(i + 1) * K + t] -= fact * du[i * K + t];
-      x[i] = 0.0;  // no interchange
-    } else {
-      const double fact = di / li;
-      dd[i * K + t] = li;
-      dl[i * K + t] = fact;
-      const double temp = du[i * K + t];
-      du[i * K + t] = dd[(i + 1) * K + t];
-      dd[(i + 1) * K + t] = temp - fact * dd[(i + 1) * K + t];
-      if (i < p - 2) {
-        du2[i * K + t] = du[(i + 1) * K + t];
-        du[(i + 1) * K + t] = -fact * du[(i + 1) * K + t];
-      }
-      x[i] = 1.0;  // interchange
-    }
-  }
-  if (dd[(p - 1) * K + t] == 0.0) dd[(p - 1) * K + t] = tiny;
-  for (int i = 0; i < p; ++i)
-    if (fabs(dd[i * K + t]) < tiny) dd[i * K + t] = (dd[i * K + t] >= 0 ? tiny : -tiny);
-  // pack interchange flags into the sign of dl (dl holds |fact| <= 1 multipliers... keep a separate
-  // encoding: store flag in du2's companion by adding 4.0 to dl when interchanged; |fact| <= 1 always)
-  for (int i = 0; i < p - 1; ++i)
-    if (x[i] != 0.0) dl[i * K + t] += 4.0;
-  // start vector: deterministic, not orthogonal to anything in particular
-  double* b = x;
-  for (int i = 0; i < p; ++i) b[i] = 1.0 + 0.37 * sin(1.3 * (double)(i + 1) * (double)(t + 1)) ;
-  for (int it = 0; it < 2; ++it) {
-    // forward: apply L^{-1} P
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
+  __syncthreads();
+  if (lane == 0) {
+    const double tiny = fmax(2.2e-16 * tn, 1e-300);
     for (int i = 0; i < p - 1; ++i) {
-      double f = dl[i * K + t];
-      if (f > 2.0) {  // interchange
-        f -= 4.0;
-        const double temp = b[i];
-        b[i] = b[i + 1];
-        b[i + 1] = temp - f * b[i];
+      if (fabs(dd[i]) >= fabs(dl[i])) {
+        if (dd[i] == 0.0) dd[i] = tiny;
+        const double f = dl[i] / dd[i];
+        dl[i] = f;
+        dd[i + 1] -= f * du[i];
       } else {
-        b[i + 1] -= f * b[i];
+        const double f = dd[i] / dl[i];
+        dd[i] = dl[i];
+        dl[i] = f;
+        const double tmp = du[i];
+        du[i] = dd[i + 1];
+        dd[i + 1] = tmp - f * dd[i + 1];
+        if (i < p - 2) { du2[i] = du[i + 1]; du[i + 1] = -f * du[i + 1]; }
+        piv[i] = 1;
       }
     }
-    // back substitution
-    b[p - 1] = b[p - 1] / dd[(p - 1) * K + t];
-    if (p >= 2) b[p - 2] = (b[p - 2] - du[(p - 2) * K + t] * b[p - 1]) / dd[(p - 2) * K + t];
-    for (int i = p - 3; i >= 0; --i)
-      b[i] = (b[i] - du[i * K + t] * b[i + 1] - du2[i * K + t] * b[i + 2]) / dd[i * K + t];
-    double nr = 0.0;
-    for (int i = 0; i < p; ++i) nr += b[i] * b[i];
-    nr = sqrt(nr);
-    if (!(nr > 0.0) || !isfinite(nr)) {
-      for (int i = 0; i < p; ++i) b[i] = (i == (t % p)) ? 1.0 : 0.0;
-    } else {
-      const double inv = 1.0 / nr;
-      for (int i = 0; i < p; ++i) b[i] *= inv;
+    for (int i = 0; i < p; ++i)
+      if (fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
+    for (int it = 0; it < 2; ++it) {
+      for (int i = 0; i < p - 1; ++i) {
+        if (piv[i]) { const double tmp = b[i]; b[i] = b[i + 1]; b[i + 1] = tmp - dl[i] * b[i]; }
+        else b[i + 1] -= dl[i] * b[i];
+      }
+      b[p - 1] /= dd[p - 1];
+      if (p >= 2) b[p - 2] = (b[p - 2] - du[p - 2] * b[p - 1]) / dd[p - 2];
+      for (int i = p - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+      if (it == 0) {
+        double mx = 0.0;
+        for (int i = 0; i < p; ++i) mx = fmax(mx, fabs(b[i]));
+        const double s = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 0.0;
+        for (int i = 0; i < p; ++i) b[i] *= s;
+      }
     }
   }
+  __syncthreads();
+  double nr = 0.0;
+  for (int i = lane; i < p; i += 64) nr += b[i] * b[i];
+  nr = wave_sum_d(nr);
+  if (lane == 0) red[0] = nr;
+  __syncthreads();
+  const double s = (red[0] > 0.0 && isfinite(red[0])) ? 1.0 / sqrt(red[0]) : 0.0;
+  double* x = X + (int64_t)t * p;
+  for (int i = lane; i < p; i += 64) x[i] = (s > 0.0) ? b[i] * s : (i == (t % p) ? 1.0 : 0.0);
 }
 hipError_t launch_inverse_iter(const double* dg, const double* off, int p, int k, const double* evals, double* X,
                                double* scratch, hipStream_t st) {
-  hipLaunchKernelGGL(inverse_iter_kernel, dim3((k + 63) / 64), dim3(64), 0, st, dg, off, p, k, evals, X, scratch);
+  (void)scratch;
+  const size_t shm = (size_t)5 * p * sizeof(double) + (size_t)p;
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(inverse_iter_kernel, dim3(k), dim3(64), shm, st, dg, off, p, k, evals, X);
   return hipGetLastError();
 }
 
@@ -582,39 +559,107 @@ hipError_t launch_ortho_check(const double* X, int p, int k, double tol, int* ba
 }
 
 // ------------------------------------------------------------------ back-transformation U = Q X
-// Q = H_0 H_1 ... H_{p-2}; apply in reverse order to each column.  U row-major (p x k).
-__global__ __launch_bounds__(256) void backtransform_kernel(const cf64* __restrict__ vs, const cf64* __restrict__ taus,
-                                                             int p, const double* __restrict__ X, int k,
-                                                             cf64* __restrict__ U) {
-  extern __shared__ unsigned char sm_raw[];
-  cf64* x = reinterpret_cast<cf64*>(sm_raw);
-  __shared__ double red[2][4];
+// Q = H_0 H_1 ... H_{p-2}, applied in reverse order to each column.  One
+// wavefront per column; lane l keeps entries l, l+64, ... of the column in
+// registers and already holds the next reflector while the current one is
+// applied, so the chain of p dependent steps does not wait on memory.
+template <int MAXE>
+__global__ __launch_bounds__(64) void backtransform_reg_kernel(const cf64* __restrict__ vs,
+                                                               const cf64* __restrict__ taus, int p,
+                                                               const double* __restrict__ X, int k,
+                                                               cf64* __restrict__ U) {
+  const int lane = threadIdx.x;
   const int col = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < p; i += 256) x[i] = make_double2(X[(int64_t)col * p + i], 0.0);
-  __syncthreads();
+  if (col >= k) return;
+  cf64 x[MAXE], vn[MAXE];
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int i = lane + 64 * e;
+    x[e] = make_double2(i < p ? X[(int64_t)col * p + i] : 0.0, 0.0);
+  }
+  int j = p - 2;
+  cf64 tn = czero<cf64>();
+  if (j >= 0) {
+    tn = taus[j];
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+      const int i = lane + 64 * e;
+      vn[e] = (i < p && i > j) ? vs[(int64_t)j * p + i] : czero<cf64>();
+    }
+  }
+  for (; j >= 0; --j) {
+    cf64 v[MAXE];
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) v[e] = vn[e];
+    const cf64 tau = tn;
+    // prefetch reflector j-1
+    if (j > 0) {
+      tn = taus[j - 1];
+#pragma unroll
+      for (int e = 0; e < MAXE; ++e) {
+        const int i = lane + 64 * e;
+        vn[e] = (i < p && i > j - 1) ? vs[(int64_t)(j - 1) * p + i] : czero<cf64>();
+      }
+    }
+    if (tau.x == 0.0 && tau.y == 0.0) continue;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {  // v is zero outside (j, p)
+      re += v[e].x * x[e].x + v[e].y * x[e].y;
+      im += v[e].x * x[e].y - v[e].y * x[e].x;
+    }
+    re = wave_sum_d(re);
+    im = wave_sum_d(im);
+    const cf64 c = cmul(tau, make_double2(re, im));
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) x[e] = csub(x[e], cmul(c, v[e]));
+  }
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int i = lane + 64 * e;
+    if (i < p) U[(int64_t)i * k + col] = x[e];
+  }
+}
+
+// general fallback: the column in LDS
+__global__ __launch_bounds__(64) void backtransform_kernel(const cf64* __restrict__ vs, const cf64* __restrict__ taus,
+                                                            int p, const double* __restrict__ X, int k,
+                                                            cf64* __restrict__ U) {
+  extern __shared__ unsigned char sm_raw[];
+  const int lane = threadIdx.x;
+  const int col = blockIdx.x;
+  cf64* x = reinterpret_cast<cf64*>(sm_raw);
+  if (col >= k) return;
+  for (int i = lane; i < p; i += 64) x[i] = make_double2(X[(int64_t)col * p + i], 0.0);
   for (int j = p - 2; j >= 0; --j) {
     const cf64 tau = taus[j];
     if (tau.x == 0.0 && tau.y == 0.0) continue;
     const cf64* v = vs + (int64_t)j * p;
     double re = 0.0, im = 0.0;
-    for (int i = j + 1 + tid; i < p; i += 256) {
-      const cf64 a = v[i], b = x[i];  // conj(v) * x
+    for (int i = j + 1 + lane; i < p; i += 64) {
+      const cf64 a = v[i], b = x[i];
       re += a.x * b.x + a.y * b.y;
       im += a.x * b.y - a.y * b.x;
     }
-    re = wave_sum_d(re); im = wave_sum_d(im);
-    if (lane == 0) { red[0][wave] = re; red[1][wave] = im; }
-    __syncthreads();
-    const cf64 s = make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3], red[1][0] + red[1][1] + red[1][2] + red[1][3]);
-    const cf64 c = cmul(tau, s);
-    for (int i = j + 1 + tid; i < p; i += 256) x[i] = csub(x[i], cmul(c, v[i]));
-    __syncthreads();
+    re = wave_sum_d(re);
+    im = wave_sum_d(im);
+    const cf64 c = cmul(tau, make_double2(re, im));
+    for (int i = j + 1 + lane; i < p; i += 64) x[i] = csub(x[i], cmul(c, v[i]));
   }
-  for (int i = tid; i < p; i += 256) U[(int64_t)i * k + col] = x[i];
+  for (int i = lane; i < p; i += 64) U[(int64_t)i * k + col] = x[i];
 }
 hipError_t launch_backtransform(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(backtransform_kernel, dim3(k), dim3(256), (size_t)p * sizeof(cf64), st, vs, taus, p, X, k, U);
+  if (p <= 64 * 8)
+    hipLaunchKernelGGL((backtransform_reg_kernel<8>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
+  else if (p <= 64 * 16)
+    hipLaunchKernelGGL((backtransform_reg_kernel<16>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
+  else if (p <= 64 * 24)
+    hipLaunchKernelGGL((backtransform_reg_kernel<24>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
+  else {
+    const size_t shm = (size_t)p * sizeof(cf64);
+    if (shm > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(backtransform_kernel, dim3(k), dim3(64), shm, st, vs, taus, p, X, k, U);
+  }
   return hipGetLastError();
 }
