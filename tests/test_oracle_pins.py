@@ -382,3 +382,110 @@ def test_sampler_statistics_match_exact_marginals():
     H /= n
     sig = np.sqrt(P * (1 - P) / n) + 1e-12
     assert np.all(np.abs(H - P) <= 5 * sig + 1e-3)
+
+
+# --------------------------------------------------------------- local basis
+def test_gaussian_reduced_state_spectrum():
+    """Sec. III.A.1: the spectrum of rho_i of a Gaussian state is
+    nbar^k / (nbar+1)^(k+1); checked on rho_i from the exact amplitudes of a
+    3-mode state (large box), and the truncation bounds N eps >= eps_D >= eps
+    of eq. SpecWfromSDsums at a small cutoff."""
+    from oracle import lbo
+    r, U = _small_problem()
+    Db = 22
+    psi = gbs.exact_amplitudes(r, U, Db)
+    V = gbs.covariance(r, U)
+    for i in range(3):
+        rho = lbo.rdm_from_dense(psi, i)
+        ev = np.sort(np.linalg.eigvalsh(rho))[::-1][:6]
+        ref = lbo.gaussian_rdm_spectrum(V, i, 6)
+        # the box [0, 22)^3 holds all but ~1e-7 of the state
+        assert np.abs(ev - ref).max() < 2 * (1 - float(np.vdot(psi, psi).real)) + 1e-12
+    # bounds at cutoff D = 4 in the optimal local basis, with eps from the spectra
+    d = 4
+    eps = 1 - np.mean([lbo.gaussian_rdm_spectrum(V, i, d).sum() for i in range(3)])
+    # eps_D of the optimal-basis truncation: project each mode on its top-d eigenvectors
+    proj = psi
+    for i in range(3):
+        rho = lbo.rdm_from_dense(psi, i)
+        w, Z = np.linalg.eigh(rho)
+        Pi = Z[:, -d:] @ Z[:, -d:].conj().T
+        proj = np.moveaxis(np.tensordot(Pi, proj, axes=([1], [i])), 0, i)
+    epsD = 1 - float(np.vdot(psi, proj).real) / float(np.vdot(psi, psi).real)
+    assert 3 * eps >= epsD - 1e-12 and epsD >= eps - 1e-12
+
+
+def test_lbo_step_finds_product_state_basis():
+    """U = identity: the state is a product of single-mode squeezed vacua, so
+    one local basis vector per site (d = 1) suffices; after LBO + DMRG the
+    energy is that of the cutoff-D single-mode problems and the basis vector is
+    the single-mode ground state."""
+    from oracle import lbo
+    N, D, d = 3, 10, 1
+    r = np.array([0.3, 0.5, 0.4])
+    U = np.eye(N, dtype=complex)
+    al, be, ga, raw = lbo.local_ops(r, U, D)
+    iso = [np.eye(D)[:, :d].astype(complex) for _ in range(N)]
+    mps_ = [np.ones((1, d, 1), dtype=complex) for _ in range(N)]
+    for s in range(N):
+        cores = lbo.cores_in_basis(al, be, ga, raw, iso)
+        raw_cores = mpo.cores(al, be, ga, raw)
+        # centre at s: with chi = 1 every tensor is a normalised scalar
+        Wn, A, disc, lam = lbo.lbo_site(mps_, cores, raw_cores[s], iso[s], s)
+        iso[s] = Wn
+        mps_[s] = A
+    cores = lbo.cores_in_basis(al, be, ga, raw, iso)
+    E = dmrg.energy(mps_, cores)
+    E_single = sum(np.linalg.eigvalsh(raw[s][2])[0] for s in range(N))
+    assert abs(E - E_single) < 1e-10
+    for s in range(N):
+        gs = np.linalg.eigh(raw[s][2])[1][:, 0]
+        assert abs(abs(np.vdot(gs, iso[s][:, 0])) - 1.0) < 1e-8
+
+
+# --------------------------------------------------------------- learned warm start
+def test_mlp_gradients_match_finite_differences():
+    """Backward pass == central finite differences of the MSE (FP64)."""
+    from oracle import mlp
+    rng = np.random.default_rng(0)
+    params = mlp.init_params(rng, in_dim=7, hidden=9, out_dim=3)
+    X = rng.standard_normal((5, 7))
+    T = rng.standard_normal((5, 3))
+    L, grads = mlp.loss_and_grads(params, X, T)
+    p0, g0 = mlp.flatten(params), mlp.flatten(grads)
+    h = 1e-6
+    idx = rng.choice(len(p0), 40, replace=False)
+    for i in idx:
+        pp, pm = p0.copy(), p0.copy()
+        pp[i] += h
+        pm[i] -= h
+        Lp, _ = mlp.loss_and_grads(mlp.unflatten(pp, 7, 9, 3), X, T)
+        Lm, _ = mlp.loss_and_grads(mlp.unflatten(pm, 7, 9, 3), X, T)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g0[i]) <= 1e-6 * max(1e-3, abs(g0[i])) + 1e-9
+
+
+def test_squeezed_basis_closed_form_and_targets():
+    """The squeezed basis is an isometry whose first column is the squeezed
+    vacuum (closed form); a single-mode squeezed state's moments give back its
+    squeezing parameter and nbar = 0 (eq. diagReducedGaussianDM with one term)."""
+    from oracle import mlp
+    zeta = 0.4 * np.exp(0.7j)
+    Wb = mlp.squeezed_basis(zeta, 30, 6)
+    assert np.abs(Wb.conj().T @ Wb - np.eye(6)).max() < 1e-12
+    t, e = np.tanh(0.4), np.exp(0.7j)
+    for q in range(5):
+        ref = (-e * t) ** q * math.sqrt(math.factorial(2 * q)) / (2 ** q * math.factorial(q)) / math.sqrt(np.cosh(0.4))
+        assert abs(Wb[2 * q, 0] - ref) < 1e-9
+    rho = np.outer(Wb[:, 0], Wb[:, 0].conj())
+    n, m = mlp.moments(rho)
+    tg = mlp.targets_from_moments(n, m)
+    assert abs(tg[0] + 1j * tg[1] - zeta) < 1e-8
+    assert abs(tg[2]) < 1e-8
+    # the basis spans the eigenvectors of a squeezed thermal state
+    nbar = 0.3
+    lam = np.array([nbar ** k / (nbar + 1) ** (k + 1) for k in range(40)])
+    Wbig = mlp.squeezed_basis(zeta, 60, 40)
+    rho = (Wbig * lam) @ Wbig.conj().T
+    tg = mlp.targets_from_moments(*mlp.moments(rho))
+    assert abs(tg[0] + 1j * tg[1] - zeta) < 1e-6 and abs(tg[2] - math.log1p(nbar)) < 1e-6
