@@ -89,3 +89,25 @@ def marginals(mps, isometries=None) -> np.ndarray:
         rho = np.einsum("ab,asc,btd,cd->st", left[j], A.conj(), A, right[j + 1])
         out[j] = np.real(np.diag(rho)) / nrm
     return out
+
+
+def reduced_density_matrices(mps, isometries=None) -> np.ndarray:
+    """rho_j[n, n'] = <n|rho_j|n'> = sum over the other modes of psi_n conj(psi_n')
+    / <psi|psi> (eq. ReducedDensityMatrix), in the raw Fock basis, shape
+    (N, D_raw, D_raw)."""
+    F = fock_tensors(mps, isometries)
+    N = len(F)
+    left = [np.ones((1, 1), dtype=np.complex128)]
+    for A in F:
+        # left[x, y] = sum over left modes of psi_x conj(psi_y)
+        left.append(np.einsum("ab,asc,bsd->cd", left[-1], A, A.conj()))
+    right = [np.ones((1, 1), dtype=np.complex128)]
+    for A in reversed(F):
+        right.append(np.einsum("cd,asc,bsd->ab", right[-1], A, A.conj()))
+    right = right[::-1]
+    nrm = left[-1][0, 0].real
+    D = F[0].shape[1]
+    out = np.zeros((N, D, D), dtype=np.complex128)
+    for j, A in enumerate(F):
+        out[j] = np.einsum("ab,asc,btd,cd->st", left[j], A, A.conj(), right[j + 1]) / nrm
+    return out

@@ -489,3 +489,33 @@ def test_squeezed_basis_closed_form_and_targets():
     rho = (Wbig * lam) @ Wbig.conj().T
     tg = mlp.targets_from_moments(*mlp.moments(rho))
     assert abs(tg[0] + 1j * tg[1] - zeta) < 1e-6 and abs(tg[2] - math.log1p(nbar)) < 1e-6
+
+
+def test_squeezed_basis_matches_matrix_exponential():
+    """Columns of the squeezed basis equal S(zeta)|k> with S(zeta) =
+    exp(1/2 (zeta* a^2 - zeta a^dag^2)) taken by scipy's expm on a large box."""
+    import scipy.linalg
+    from oracle import mlp
+    zeta = 0.55 * np.exp(-1.1j)
+    Db = 240
+    a = np.diag(np.sqrt(np.arange(1, Db)), 1).astype(complex)
+    S = scipy.linalg.expm(0.5 * (np.conj(zeta) * a @ a - zeta * a.T @ a.T))
+    Wb = mlp.squeezed_basis(zeta, 110, 8)   # tails beyond row 110 are below 1e-13
+    assert np.abs(Wb - S[:110, :8]).max() < 1e-10
+
+
+def test_reduced_density_matrices_match_dense_partial_trace():
+    """rho_j from the MPS contraction == brute-force partial trace of the dense
+    state; Hermitian, unit trace, diagonal == the marginals."""
+    from oracle import lbo
+    m = W.random_mps(4, 3, 5, 21)
+    psi = M.to_dense(m).reshape((3,) * 4)
+    psi = psi / np.linalg.norm(psi)
+    rho = M.reduced_density_matrices(m)
+    marg = M.marginals(m)
+    for j in range(4):
+        ref = lbo.rdm_from_dense(psi, j)
+        assert np.abs(rho[j] - ref).max() < 1e-13
+        assert abs(np.trace(rho[j]) - 1) < 1e-13
+        assert np.abs(rho[j] - rho[j].conj().T).max() < 1e-14
+        assert np.abs(np.real(np.diag(rho[j])) - marg[j]).max() < 1e-13
