@@ -221,6 +221,40 @@ tn_status tn_marginals(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int32_
 tn_status tn_sample(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
                     int32_t* out);
 
+/* Single-site reduced density matrices rho_j[n][n'] = <n|rho_j|n'> (eq.
+ * ReducedDensityMatrix) in the raw Fock basis, FP64, for j < n_modes.  out:
+ * host [n_modes][D_raw][D_raw] complex.  Same centre requirement as
+ * tn_marginals. */
+tn_status tn_rdm(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int32_t n_modes, double* out);
+
+/* ------------------------------------------------------------------ learned warm start
+ * A 3-layer perceptron in FP32 (tanh, tanh, linear), trained with a
+ * mean-squared error and Adam by the library's own kernels.  It maps the
+ * per-site features of an instance to the parameters of a squeezed local
+ * basis (tn_squeezed_basis) and the local thermal occupation; the learned
+ * basis and a product-state initial MPS warm-start the DMRG, and <H> after the
+ * first sweep decides whether the start is kept (plain start as fallback).
+ * x, y, t below are device float arrays, row-major [batch][dim]. */
+tn_status tn_mlp_create(tn_ctx* ctx, int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed, tn_mlp** out);
+void tn_mlp_destroy(tn_mlp* mlp);
+int64_t tn_mlp_num_params(const tn_mlp* mlp);
+/* get (host, may be NULL) receives all parameters [W1 b1 W2 b2 W3 b3]
+ * (W_l row-major out x in); set (host, may be NULL) replaces them and resets
+ * the optimiser state. */
+tn_status tn_mlp_params(tn_ctx* ctx, tn_mlp* mlp, float* get, const float* set);
+tn_status tn_mlp_forward(tn_ctx* ctx, tn_mlp* mlp, const float* x, int32_t batch, float* y);
+/* gradients of mean((y - t)^2) into grads (host, may be NULL); loss to host */
+tn_status tn_mlp_grad(tn_ctx* ctx, tn_mlp* mlp, const float* x, const float* t, int32_t batch, float* grads,
+                      float* loss);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean-squared error */
+tn_status tn_mlp_train_step(tn_ctx* ctx, tn_mlp* mlp, const float* x, const float* t, int32_t batch, float lr,
+                            float* loss);
+/* Squeezed local basis: out (host, D x d complex) = first d columns of
+ * <n|S(zeta)|k>, S(zeta) = exp(1/2 (zeta* a^2 - zeta a^dag^2)), the optimal
+ * local basis of a squeezed thermal reduced state (Sec. III.A.1), built on a
+ * (D + margin) box, cut to D rows and orthonormalised. */
+tn_status tn_squeezed_basis(double zeta_re, double zeta_im, int32_t D, int32_t d, int32_t margin, double* out);
+
 /* ------------------------------------------------------------------ step entry points
  * Building blocks of the sweep, on caller-owned device buffers (FP64 complex):
  *   theta: [chi_l][d][d][chi_r] for the window (site, site+1);

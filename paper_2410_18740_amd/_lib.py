@@ -118,6 +118,15 @@ def lib():
         "tn_philox4x32_10": (i32, [vp, P(C.c_uint32), P(C.c_uint32), P(C.c_uint32), i32]),
         "tn_matvec_flops": (dbl, [vp, i32, i32, i32]),
         "tn_env_flops": (dbl, [vp, i32, i32, i32]),
+        "tn_rdm": (i32, [vp, vp, vp, i32, P(dbl)]),
+        "tn_mlp_create": (i32, [vp, i32, i32, i32, C.c_uint64, P(vp)]),
+        "tn_mlp_destroy": (None, [vp]),
+        "tn_mlp_num_params": (i64, [vp]),
+        "tn_mlp_params": (i32, [vp, vp, P(C.c_float), P(C.c_float)]),
+        "tn_mlp_forward": (i32, [vp, vp, vp, i32, vp]),
+        "tn_mlp_grad": (i32, [vp, vp, vp, vp, i32, P(C.c_float), P(C.c_float)]),
+        "tn_mlp_train_step": (i32, [vp, vp, vp, vp, i32, C.c_float, P(C.c_float)]),
+        "tn_squeezed_basis": (i32, [dbl, dbl, i32, i32, i32, P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -342,3 +342,83 @@ def matvec_flops(mpo: MPO, site: int, chi_l: int, chi_r: int) -> float:
 
 def env_flops(mpo: MPO, site: int, chi_l: int, chi_r: int) -> float:
     return L.lib().tn_env_flops(mpo.h, site, chi_l, chi_r)
+
+
+def rdm(ctx: Context, mps: MPS, mpo: MPO, n_modes: int | None = None):
+    """Single-site reduced density matrices [n_modes][D_raw][D_raw] (FP64)."""
+    n = mps.N if n_modes is None else n_modes
+    out = np.zeros((n, mpo.D_raw, mpo.D_raw), dtype=np.complex128)
+    ctx.check(L.lib().tn_rdm(ctx.h, mps.h, mpo.h, n, L.dptr(out.view(np.float64))))
+    return out
+
+
+def squeezed_basis(zeta: complex, D: int, d: int, margin: int = 64):
+    out = np.zeros((D, d), dtype=np.complex128)
+    st = L.lib().tn_squeezed_basis(float(np.real(zeta)), float(np.imag(zeta)), D, d, margin,
+                                   L.dptr(out.view(np.float64)))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_squeezed_basis: bad arguments")
+    return out
+
+
+def _fdev(x):
+    torch = _torch()
+    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+    return C.c_void_p(x.data_ptr())
+
+
+class MLP:
+    """3-layer FP32 perceptron trained by the library's kernels (tn_mlp_*)."""
+
+    def __init__(self, ctx: Context, in_dim: int, hidden: int, out_dim: int, seed: int = 0):
+        self.ctx = ctx
+        self.in_dim, self.hidden, self.out_dim = in_dim, hidden, out_dim
+        h = C.c_void_p()
+        ctx.check(L.lib().tn_mlp_create(ctx.h, in_dim, hidden, out_dim, C.c_uint64(seed), C.byref(h)))
+        self.h = h
+        ctx._children.add(self)
+
+    @property
+    def num_params(self) -> int:
+        return int(L.lib().tn_mlp_num_params(self.h))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, dtype=np.float32)
+        self.ctx.check(L.lib().tn_mlp_params(self.ctx.h, self.h, L.dptr(out, C.c_float), None))
+        return out
+
+    def set_params(self, flat) -> None:
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        if flat.size != self.num_params:
+            raise ValueError("parameter vector has the wrong length")
+        self.ctx.check(L.lib().tn_mlp_params(self.ctx.h, self.h, None, L.dptr(flat, C.c_float)))
+
+    def forward(self, X):
+        torch = _torch()
+        Y = torch.empty((X.shape[0], self.out_dim), dtype=torch.float32, device=X.device)
+        self.ctx.check(L.lib().tn_mlp_forward(self.ctx.h, self.h, _fdev(X), int(X.shape[0]), _fdev(Y)))
+        return Y
+
+    def grad(self, X, T):
+        g = np.zeros(self.num_params, dtype=np.float32)
+        loss = C.c_float()
+        self.ctx.check(L.lib().tn_mlp_grad(self.ctx.h, self.h, _fdev(X), _fdev(T), int(X.shape[0]),
+                                           L.dptr(g, C.c_float), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, T, lr: float) -> float:
+        loss = C.c_float()
+        self.ctx.check(L.lib().tn_mlp_train_step(self.ctx.h, self.h, _fdev(X), _fdev(T), int(X.shape[0]),
+                                                 C.c_float(lr), C.byref(loss)))
+        return loss.value
+
+    def _release(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            L.lib().tn_mlp_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self._release()
+        except Exception:
+            pass
