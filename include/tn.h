@@ -255,6 +255,25 @@ tn_status tn_mlp_train_step(tn_ctx* ctx, tn_mlp* mlp, const float* x, const floa
  * (D + margin) box, cut to D rows and orthonormalised. */
 tn_status tn_squeezed_basis(double zeta_re, double zeta_im, int32_t D, int32_t d, int32_t margin, double* out);
 
+/* Host helpers of the warm start (no GPU work).
+ * tn_ws_features: out (host float [N][66]) = per output mode j: j/N, N/64, then
+ * for the 16 largest |U_jk| (ties by k) the tuple (r_k, |U_jk|, cos 2 arg U_jk,
+ * sin 2 arg U_jk), zero-padded; U host complex N x N row-major.
+ * tn_ws_targets: out (host float [n_modes][3]) = (Re zeta, Im zeta,
+ * log(1 + nbar)) of the squeezed thermal state with the same <a^dag a> and
+ * <a^2> as rho_j (host complex [n_modes][D][D], as from tn_rdm); the
+ * diagonal form of a Gaussian reduced state (Sec. III.A.1) motivates it.
+ * tn_ws_initial_state: from outputs y (host float [N][3]) writes iso (host
+ * complex [N][D][d], squeezed bases) and a product-state MPS with thermal
+ * amplitudes in bond channel (0, 0) plus seeded complex Gaussian noise of
+ * scale `noise`; dims (N + 1) receives min(chi, d^s, d^(N-s)); tensors (host,
+ * `cap` doubles) receives the site tensors (chi_s, d, chi_s+1) back to back,
+ * complex interleaved; with tensors NULL only *need is set. */
+tn_status tn_ws_features(int32_t N, const double* r, const double* U, float* out);
+tn_status tn_ws_targets(int32_t n_modes, int32_t D, const double* rho, float* out);
+tn_status tn_ws_initial_state(int32_t N, int32_t D, int32_t d, int32_t chi, const float* y, uint64_t seed,
+                              double noise, double* iso, int32_t* dims, double* tensors, size_t cap, size_t* need);
+
 /* ------------------------------------------------------------------ step entry points
  * Building blocks of the sweep, on caller-owned device buffers (FP64 complex):
  *   theta: [chi_l][d][d][chi_r] for the window (site, site+1);

@@ -5,8 +5,10 @@ squeezed Fock basis, eq. OLB / eq. diagReducedGaussianDM).
 
 Reading taken here:
 * features of output mode j of an instance (r, U): [j/N, N/64] and, for the 16
-  largest |U_jk|, (r_k, |U_jk|, cos arg U_jk, sin arg U_jk) in descending
-  order of |U_jk|, zero-padded (66 numbers);
+  largest |U_jk|, (r_k, |U_jk|, cos 2 arg U_jk, sin 2 arg U_jk) in descending
+  order of |U_jk|, zero-padded (66 numbers).  The doubled angle: a squeezed
+  vacuum is unchanged by a_k -> -a_k, so the reduced state of mode j of the
+  Gaussian state depends on U_jk only through |U_jk| and U_jk^2;
 * targets from a converged state's single-mode reduced density matrix rho_j:
   n = <a^dag a>, m = <a^2>; the state is S(zeta) tau S(zeta)^dag with tau
   thermal, S(zeta) = exp(1/2 (zeta* a^2 - zeta a^dag^2)), which gives
@@ -36,8 +38,8 @@ def features(r, U, j):
     for k in order:
         z = row[k]
         a = abs(z)
-        f += [float(r[k]), a, math.cos(math.atan2(z.imag, z.real)) if a > 0 else 1.0,
-              math.sin(math.atan2(z.imag, z.real)) if a > 0 else 0.0]
+        th = math.atan2(z.imag, z.real)
+        f += [float(r[k]), a, math.cos(2 * th) if a > 0 else 1.0, math.sin(2 * th) if a > 0 else 0.0]
     f += [0.0] * (IN_DIM - len(f))
     return np.array(f)
 
@@ -93,6 +95,21 @@ def squeezed_basis(zeta, D, d, margin=64):
             Wm[:, j] -= np.vdot(Wm[:, i], Wm[:, j]) * Wm[:, i]
         Wm[:, j] /= np.linalg.norm(Wm[:, j])
     return Wm
+
+
+def initial_product_state(y, D, d):
+    """Warm-start state from outputs y[j] = (Re zeta, Im zeta, log(1 + nbar)):
+    the squeezed basis of zeta_j and thermal amplitudes sqrt(lambda_m),
+    lambda_m = nbar^m / (nbar + 1)^(m + 1) renormalised over m < d (the
+    eigenvalues of a thermal state, eq. diagReducedGaussianDM)."""
+    isos, amps = [], []
+    for yj in y:
+        zeta = complex(yj[0], yj[1])
+        nbar = max(math.expm1(float(yj[2])), 0.0)
+        lam = np.array([nbar ** m / (nbar + 1.0) ** (m + 1) for m in range(d)])
+        isos.append(squeezed_basis(zeta, D, d))
+        amps.append(np.sqrt(lam / lam.sum()))
+    return isos, amps
 
 
 # ------------------------------------------------------------------ network

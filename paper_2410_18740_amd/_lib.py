@@ -127,6 +127,10 @@ def lib():
         "tn_mlp_grad": (i32, [vp, vp, vp, vp, i32, P(C.c_float), P(C.c_float)]),
         "tn_mlp_train_step": (i32, [vp, vp, vp, vp, i32, C.c_float, P(C.c_float)]),
         "tn_squeezed_basis": (i32, [dbl, dbl, i32, i32, i32, P(dbl)]),
+        "tn_ws_features": (i32, [i32, P(dbl), P(dbl), P(C.c_float)]),
+        "tn_ws_targets": (i32, [i32, i32, P(dbl), P(C.c_float)]),
+        "tn_ws_initial_state": (i32, [i32, i32, i32, i32, P(C.c_float), C.c_uint64, dbl, P(dbl), P(i32), P(dbl),
+                                      szt, P(szt)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

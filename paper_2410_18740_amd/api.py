@@ -422,3 +422,51 @@ class MLP:
             self._release()
         except Exception:
             pass
+
+
+def ws_features(r, U):
+    """Network inputs [N][66] of every output mode (tn_ws_features)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    Uf = np.ascontiguousarray(U, dtype=np.complex128).view(np.float64)
+    out = np.zeros((len(r), 66), dtype=np.float32)
+    st = L.lib().tn_ws_features(len(r), L.dptr(r), L.dptr(Uf), L.dptr(out, C.c_float))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_ws_features: bad arguments")
+    return out
+
+
+def ws_targets(rho):
+    """Training targets [n][3] from reduced density matrices [n][D][D]."""
+    rho = np.ascontiguousarray(rho, dtype=np.complex128)
+    out = np.zeros((rho.shape[0], 3), dtype=np.float32)
+    st = L.lib().tn_ws_targets(rho.shape[0], rho.shape[1], L.dptr(rho.view(np.float64)), L.dptr(out, C.c_float))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_ws_targets: bad arguments")
+    return out
+
+
+def ws_initial_state(y, D: int, d: int, chi: int, seed: int, noise: float = 1e-3):
+    """(isometries [N][D][d], site tensors) of the learned warm start."""
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    N = y.shape[0]
+    dims = np.zeros(N + 1, dtype=np.int32)
+    need = C.c_size_t()
+    iso = np.zeros((N, D, d), dtype=np.complex128)
+    lib = L.lib()
+    st = lib.tn_ws_initial_state(N, D, d, chi, L.dptr(y, C.c_float), C.c_uint64(seed), noise,
+                                 L.dptr(iso.view(np.float64)), L.dptr(dims, C.c_int32), None, 0, C.byref(need))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_ws_initial_state: bad arguments")
+    buf = np.zeros(need.value, dtype=np.float64)
+    st = lib.tn_ws_initial_state(N, D, d, chi, L.dptr(y, C.c_float), C.c_uint64(seed), noise,
+                                 L.dptr(iso.view(np.float64)), L.dptr(dims, C.c_int32), L.dptr(buf), need.value,
+                                 C.byref(need))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_ws_initial_state: bad outputs")
+    z = buf.view(np.complex128)
+    out, off = [], 0
+    for s in range(N):
+        n = int(dims[s]) * d * int(dims[s + 1])
+        out.append(z[off:off + n].reshape(int(dims[s]), d, int(dims[s + 1])).copy())
+        off += n
+    return iso, out

@@ -451,3 +451,121 @@ extern "C" tn_status tn_rdm(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int32
   }
   TN_GUARD_END(c)
 }
+
+// ------------------------------------------------------------------ warm-start host helpers
+// Network input of output mode j: [j/N, N/64] then, for the 16 largest |U_jk|
+// (ties by k), (r_k, |U_jk|, cos 2 arg U_jk, sin 2 arg U_jk), zero-padded.  The
+// reduced state of mode j of a squeezed Gaussian state depends on U_jk only
+// through |U_jk| and U_jk^2 (a squeezed vacuum is even under a_k -> -a_k).
+static constexpr int WS_KTOP = 16;
+static constexpr int WS_IN = 2 + 4 * WS_KTOP;
+
+extern "C" tn_status tn_ws_features(int32_t N, const double* r, const double* U, float* out) {
+  if (N < 1 || N > 4096 || !r || !U || !out) return TN_EINVAL;
+  std::vector<int> idx(N);
+  for (int j = 0; j < N; ++j) {
+    const double* row = U + (size_t)2 * N * j;
+    for (int k = 0; k < N; ++k) idx[k] = k;
+    auto mag = [&](int k) { return std::hypot(row[2 * k], row[2 * k + 1]); };
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return mag(a) > mag(b); });
+    float* f = out + (size_t)WS_IN * j;
+    for (int q = 0; q < WS_IN; ++q) f[q] = 0.f;
+    f[0] = (float)((double)j / N);
+    f[1] = (float)(N / 64.0);
+    for (int q = 0; q < std::min(N, WS_KTOP); ++q) {
+      const int k = idx[q];
+      const double a = mag(k);
+      if (!std::isfinite(a) || !std::isfinite(r[k])) return TN_EINVAL;
+      f[2 + 4 * q] = (float)r[k];
+      f[3 + 4 * q] = (float)a;
+      // cos 2t = (re^2 - im^2) / a^2, sin 2t = 2 re im / a^2
+      const double re = row[2 * k], im = row[2 * k + 1];
+      f[4 + 4 * q] = (float)(a > 0 ? (re * re - im * im) / (a * a) : 1.0);
+      f[5 + 4 * q] = (float)(a > 0 ? 2.0 * re * im / (a * a) : 0.0);
+    }
+  }
+  return TN_OK;
+}
+
+// Targets from a single-mode state rho[n][n'] = <n|rho|n'>: with n = <a^dag a>
+// and m = <a^2>, a squeezed thermal state S(zeta) tau S(zeta)^dag has
+// (2 nbar + 1)^2 = (2n + 1)^2 - 4|m|^2, tanh(2|zeta|) = 2|m| / (2n + 1) and
+// zeta / |zeta| = -m / |m|.  out[j] = (Re zeta, Im zeta, log(1 + nbar)).
+extern "C" tn_status tn_ws_targets(int32_t n_modes, int32_t D, const double* rho, float* out) {
+  if (n_modes < 1 || D < 1 || !rho || !out) return TN_EINVAL;
+  for (int j = 0; j < n_modes; ++j) {
+    const double* R = rho + (size_t)2 * D * D * j;
+    double n = 0.0;
+    cd m = 0.0;
+    for (int k = 0; k < D; ++k) n += k * R[2 * ((size_t)k * D + k)];
+    for (int k = 2; k < D; ++k) {
+      const size_t e = (size_t)k * D + (k - 2);
+      m += cd(R[2 * e], R[2 * e + 1]) * std::sqrt((double)k * (k - 1));
+    }
+    if (!std::isfinite(n) || !std::isfinite(std::abs(m))) return TN_ENUMERIC;
+    const double s = 2 * n + 1, am = std::abs(m);
+    const double nu2 = std::max(s * s - 4 * am * am, 1.0);
+    const double nbar = 0.5 * (std::sqrt(nu2) - 1.0);
+    const double rr = am > 0 ? 0.5 * std::atanh(std::min(2 * am / s, 1 - 1e-15)) : 0.0;
+    const cd ph = am > 0 ? -m / am : cd(1.0, 0.0);
+    out[3 * j + 0] = (float)(rr * ph.real());
+    out[3 * j + 1] = (float)(rr * ph.imag());
+    out[3 * j + 2] = (float)std::log1p(std::max(nbar, 0.0));
+  }
+  return TN_OK;
+}
+
+// Warm-start state from network outputs y[j] = (Re zeta, Im zeta, log(1 + nbar)):
+// iso[j] = squeezed basis of zeta_j (D x d), and a product MPS whose site j
+// holds the thermal amplitudes sqrt(lambda_m), lambda_m ~ nbar^m / (nbar + 1)^(m + 1)
+// (normalised over m < d), in bond channel (0, 0), plus complex Gaussian noise of
+// scale `noise` on every entry (splitmix64 + Box-Muller, seeded).  Bond
+// dimensions min(chi, d^s, d^(N-s)) go to dims (N + 1); tensors (chi_s, d,
+// chi_s+1) are written back to back, complex interleaved; when tensors is NULL
+// only *need (doubles) is set.
+extern "C" tn_status tn_ws_initial_state(int32_t N, int32_t D, int32_t d, int32_t chi, const float* y, uint64_t seed,
+                                         double noise, double* iso, int32_t* dims, double* tensors, size_t cap,
+                                         size_t* need) {
+  if (N < 1 || D < 1 || d < 1 || d > D || chi < 1 || !y || !dims || !need || !(noise >= 0)) return TN_EINVAL;
+  for (int s = 0; s <= N; ++s) {
+    double l = std::pow((double)d, std::min(s, 40)), rr = std::pow((double)d, std::min(N - s, 40));
+    dims[s] = (int32_t)std::min({(double)chi, l, rr});
+  }
+  size_t tot = 0;
+  for (int s = 0; s < N; ++s) tot += (size_t)dims[s] * d * dims[s + 1] * 2;
+  *need = tot;
+  if (!tensors) return TN_OK;
+  if (cap < tot || !iso) return TN_EINVAL;
+  uint64_t st = seed;
+  auto normal = [&]() {
+    const double u1 = ((splitmix(st) >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+  };
+  size_t off = 0;
+  for (int s = 0; s < N; ++s) {
+    const double zr = y[3 * s], zi = y[3 * s + 1], ln = y[3 * s + 2];
+    if (!std::isfinite(zr) || !std::isfinite(zi) || !std::isfinite(ln)) return TN_ENUMERIC;
+    const tn_status b = tn_squeezed_basis(zr, zi, D, d, 64, iso + (size_t)2 * D * d * s);
+    if (b != TN_OK) return b;
+    const double nbar = std::max(std::expm1((double)ln), 0.0);
+    std::vector<double> lam(d);
+    double tl = 0.0;
+    for (int m = 0; m < d; ++m) {
+      lam[m] = std::pow(nbar / (nbar + 1.0), m) / (nbar + 1.0);
+      tl += lam[m];
+    }
+    const int cl = dims[s], cr = dims[s + 1];
+    for (int a = 0; a < cl; ++a)
+      for (int m = 0; m < d; ++m)
+        for (int q = 0; q < cr; ++q) {
+          double re = noise * normal(), im = noise * normal();
+          if (a == 0 && q == 0) re += std::sqrt(lam[m] / tl);
+          const size_t e = off + 2 * (((size_t)a * d + m) * cr + q);
+          tensors[e] = re;
+          tensors[e + 1] = im;
+        }
+    off += (size_t)cl * d * cr * 2;
+  }
+  return TN_OK;
+}

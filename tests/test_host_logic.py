@@ -23,3 +23,54 @@ def test_squeezed_basis_rejects_bad_arguments():
     for args in [(0.1, 4, 5), (0.1, 0, 1), (np.nan, 4, 2), (30.0, 4, 2)]:
         with pytest.raises(P.TnError):
             P.squeezed_basis(*args)
+
+
+@pytest.mark.parametrize("N", [5, 20])
+def test_ws_features_match_oracle(N):
+    import paper_2410_18740_amd as P
+    import workloads as W
+    r, U = W.make_problem(N, 31 + N, (0.3, 1.2))
+    got = P.ws_features(r, U)
+    ref = np.stack([omlp.features(r, U, j) for j in range(N)])
+    assert got.shape == (N, omlp.IN_DIM)
+    assert np.abs(got - ref).max() < 1e-6
+
+
+def test_ws_targets_match_oracle():
+    import paper_2410_18740_amd as P
+    rng = np.random.default_rng(4)
+    rhos = []
+    for k in range(6):
+        A = rng.standard_normal((10, 10)) + 1j * rng.standard_normal((10, 10))
+        A *= np.exp(-0.4 * np.arange(10))[:, None]
+        rho = A @ A.conj().T
+        rhos.append(rho / np.trace(rho))
+    zeta, nbar = 0.35 * np.exp(1.9j), 0.2
+    Wb = omlp.squeezed_basis(zeta, 48, 30)
+    lam = np.array([nbar ** k / (nbar + 1) ** (k + 1) for k in range(30)])
+    rhos.append(((Wb * lam) @ Wb.conj().T)[:10, :10])
+    rhos = np.array(rhos)
+    got = P.ws_targets(rhos)
+    ref = np.stack([omlp.targets_from_moments(*omlp.moments(r_)) for r_ in rhos])
+    assert np.abs(got - ref).max() < 1e-6 * max(1.0, np.abs(ref).max())
+
+
+def test_ws_initial_state_matches_oracle():
+    import paper_2410_18740_amd as P
+    y = np.array([[0.3, -0.1, 0.4], [0.0, 0.0, 0.0], [-0.5, 0.2, 1.1], [0.1, 0.6, 0.05]], dtype=np.float32)
+    D, d, chi = 12, 5, 7
+    iso, A = P.ws_initial_state(y, D, d, chi, seed=3, noise=0.0)
+    iso_r, amps = omlp.initial_product_state(y.astype(np.float64), D, d)
+    dims = [1, 5, 7, 5, 1]
+    for s in range(4):
+        assert A[s].shape == (dims[s], d, dims[s + 1])
+        assert np.abs(iso[s] - iso_r[s]).max() < 1e-9
+        assert np.abs(A[s][0, :, 0] - amps[s]).max() < 1e-7
+        rest = A[s].copy()
+        rest[0, :, 0] = 0
+        assert np.abs(rest).max() == 0.0
+    _, An = P.ws_initial_state(y, D, d, chi, seed=3, noise=1e-3)
+    _, An2 = P.ws_initial_state(y, D, d, chi, seed=3, noise=1e-3)
+    noise = np.concatenate([(a - b).reshape(-1) for a, b in zip(An, A)])
+    assert all(np.array_equal(a, b) for a, b in zip(An, An2))
+    assert abs(np.std(noise.real) - 1e-3) < 2e-4 and abs(np.mean(noise.real)) < 2e-4

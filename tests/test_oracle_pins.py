@@ -519,3 +519,16 @@ def test_reduced_density_matrices_match_dense_partial_trace():
         assert abs(np.trace(rho[j]) - 1) < 1e-13
         assert np.abs(rho[j] - rho[j].conj().T).max() < 1e-14
         assert np.abs(np.real(np.diag(rho[j])) - marg[j]).max() < 1e-13
+
+
+def test_reduced_state_depends_on_doubled_angle_only():
+    """The learned start's features use 2 arg U_jk: flipping the sign of any
+    input mode (U -> U diag(+-1), an even squeezed vacuum is unchanged) leaves
+    the Gaussian covariance, hence every reduced state, and the features alike."""
+    from oracle import mlp
+    r, U = W.make_problem(7, 5, (0.3, 1.2))
+    s = np.array([1, -1, -1, 1, -1, 1, 1])
+    U2 = U * s[None, :]
+    assert np.abs(gbs.covariance(r, U) - gbs.covariance(r, U2)).max() < 1e-13
+    for j in range(7):
+        assert np.abs(mlp.features(r, U, j) - mlp.features(r, U2, j)).max() < 1e-13
