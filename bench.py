@@ -195,7 +195,12 @@ def warmstart_eval(a):
             traces[form] = tr
             row.update({f"{form}_E": tr.energies, f"{form}_s": tr.seconds, f"{form}_init_s": tr.init_seconds,
                         f"{form}_used": used, f"{form}_first_E": e1})
-        e_ref = min(traces[f].final for f in ("plain", "learned", "learned_basis"))
+        traces["learned_hybrid"] = WS.solve_hybrid(ctx, net, r, U, D, d, chi, seed, init, 2, a.max_sweeps,
+                                                   conv_tol=1e-10)
+        row.update({"learned_hybrid_E": traces["learned_hybrid"].energies,
+                    "learned_hybrid_s": traces["learned_hybrid"].seconds,
+                    "learned_hybrid_used": True, "learned_hybrid_first_E": traces["learned_hybrid"].energies[0]})
+        e_ref = min(traces[f].final for f in ("plain", "learned", "learned_basis", "learned_hybrid"))
         for name, rel in (("1e-2", 1e-2), ("1e-3", 1e-3), ("1e-4", 1e-4)):
             for form, tr in traces.items():
                 row[f"{form}_{name}"] = tr.time_to(e_ref * (1 + rel))
@@ -212,7 +217,7 @@ def warmstart_eval(a):
         v = [r_[key][idx] for r_ in rows if r_[key][0] is not None]
         return (float(np.median(v)) if v else None), len(v)
 
-    forms = ("plain", "learned", "learned_basis", "learned_nolbo")
+    forms = ("plain", "learned", "learned_basis", "learned_nolbo", "learned_hybrid")
     summary = {}
     for name in ("1e-2", "1e-3", "1e-4"):
         for form in forms:
@@ -223,7 +228,7 @@ def warmstart_eval(a):
                                                          for k, v in fam.items()}, "train_instances": a.train_instances, "train_rows": int(X.shape[0]),
             "data_s": t_data, "train_s": t_train, "epochs": a.epochs, "final_train_loss": losses[-1],
             "val_loss": vloss, "eval_instances": a.eval_instances,
-            "kept": {f: sum(r_[f + "_used"] for r_ in rows) for f in forms[1:]},
+            "kept": {f: sum(r_[f + "_used"] for r_ in rows) for f in forms[1:-1]},
             "first_sweep_E_median": {f: float(np.median([r_[f + "_first_E"] if f != "plain" else r_["plain_E"][0]
                                                          for r_ in rows])) for f in forms},
             "final_E_median": {f: float(np.median([r_[f + "_E"][-1] for r_ in rows]))

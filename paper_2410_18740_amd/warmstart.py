@@ -165,3 +165,21 @@ def solve_with_fallback(ctx, net, r, U, D: int, d: int, chi: int, seed: int, pla
     tr = run_sweeps(ctx, mpo, mps, sweep_opts(chi), max_sweeps, conv_tol, stop_at,
                     init_seconds=lost + time.perf_counter() - t1)
     return tr, False, e1
+
+
+def solve_hybrid(ctx, net, r, U, D: int, d: int, chi: int, seed: int, plain_tensors, bulk_sweeps: int,
+                 max_sweeps: int, conv_tol: float = 1e-9, stop_at: float | None = None):
+    """Learned local bases held fixed for bulk_sweeps sweeps (no local basis
+    optimisation, about half the cost of a joint sweep), then joint DMRG + LBO
+    sweeps.  No fallback.  Returns the trace."""
+    import torch
+    t0 = time.perf_counter()
+    mpo, mps = learned_start(ctx, net, r, U, D, d, chi, seed, tensors=plain_tensors)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    a = run_sweeps(ctx, mpo, mps, sweep_opts(chi, lbo=False), bulk_sweeps, init_seconds=t_init)
+    b = run_sweeps(ctx, mpo, mps, sweep_opts(chi), max_sweeps - bulk_sweeps, conv_tol, stop_at)
+    es = a.energies + b.energies
+    ts = a.seconds + [a.seconds[-1] + x for x in b.seconds]
+    ph = {k: a.phases.get(k, 0.0) + b.phases.get(k, 0.0) for k in a.phases}
+    return RunTrace(es, ts, t_init, ph)
