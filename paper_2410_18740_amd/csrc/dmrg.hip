@@ -177,6 +177,7 @@ static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& eva
     ldz = p;
     return;
   }
+  if (p > 3200) TN_THROW(TN_EINVAL, "eigensolver size " + std::to_string(p) + " exceeds 3200 (LDS-staged reflectors)");
   TridiagWork tw;
   tw.A = G;
   tw.vs = wsT<cf64>(c, "eig:vs", (size_t)p * p);

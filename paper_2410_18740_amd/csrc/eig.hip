@@ -186,60 +186,90 @@ hipError_t launch_build_tridiag(const double* alpha, const double* beta, int n, 
 // finalised by the previous launch) w_{j-1} = y_{j-1} - 1/2 tau_{j-1}
 // (y_{j-1}^H v_{j-1}) v_{j-1} and the reflector of column j into LDS, then
 // updates its own rows i in [j+1, p) with the pending rank-2 term
-// (v_{j-1}, w_{j-1}) and forms y_j[i] = tau_j sum_k A[i][k] v_j[k] (one
-// wavefront per row).  Workgroup 0 also publishes v_j, tau_j and the diagonal
-// and off-diagonal entries.
+// (v_{j-1}, w_{j-1}) and forms y_j[i] = tau_j sum_k A[i][k] v_j[k].  A
+// workgroup owns TRI_ROWS rows; each row is split over two wavefronts.  The
+// step is bound by latency, not bandwidth, so every global load the step needs
+// is issued in one round at the start: the first TRI_UNROLL row elements of
+// each lane, and y_{j-1}, v_{j-1} and row j (staged in LDS).  Workgroup 0 also
+// publishes v_j, tau_j and the diagonal and off-diagonal entries.
+static constexpr int TRI_ROWS = 2;    // rows per workgroup (two wavefronts each)
+static constexpr int TRI_UNROLL = 8;  // row loads in flight per lane
+
 __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* __restrict__ vs,
                                                     cf64* __restrict__ taus, double* __restrict__ dg,
                                                     double* __restrict__ off, cf64* __restrict__ y, int p, int j) {
   extern __shared__ unsigned char sm_raw[];
-  cf64* vS = reinterpret_cast<cf64*>(sm_raw);  // v_j
-  cf64* wS = vS + p;                           // w_{j-1}
+  cf64* vS = reinterpret_cast<cf64*>(sm_raw);  // row j, then v_j
+  cf64* wS = vS + p;                           // y_{j-1}, then w_{j-1}
+  cf64* pS = wS + p;                           // v_{j-1}
   __shared__ double red[2][4];
   __shared__ cf64 bc[2];
+  __shared__ double part[TRI_ROWS][2][2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cf64* vprev = (j > 0) ? vs + (int64_t)(j - 1) * p : nullptr;
   cf64* ycur = y + (int64_t)(j & 1) * p;            // y_j (written here)
   const cf64* yprev = y + (int64_t)((j + 1) & 1) * p;  // y_{j-1}
-  // ---- w_{j-1}
-  if (j > 0) {
-    double re = 0.0, im = 0.0;
-    for (int i = j + tid; i < p; i += 256) {
-      const cf64 a = yprev[i], b = vprev[i];
-      re += a.x * b.x + a.y * b.y;
-      im += a.x * b.y - a.y * b.x;
+  const cf64* rowj = A + (int64_t)j * p;
+  // ---- one round of global loads
+  // rows are dealt to workgroups so that row i always lands on the same XCD
+  // (workgroup b runs on XCD b % 8): XCD x owns the rows i = x (mod 8), in
+  // groups of TRI_ROWS, and keeps them in its L2 from one column to the next
+  const int rl = wave >> 1, half = wave & 1, tl = half * 64 + lane;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int i0 = j + 1 + ((xcd - (j + 1)) % 8 + 8) % 8;  // first row >= j+1 with i = xcd (mod 8)
+  const int i = i0 + 8 * (slot * TRI_ROWS + rl);
+  const bool own = (j < p - 1) && (i < p);
+  cf64* row = A + (int64_t)(own ? i : 0) * p;
+  cf64 a0[TRI_UNROLL];
+#pragma unroll
+  for (int u = 0; u < TRI_UNROLL; ++u) {
+    const int k = j + 1 + tl + 128 * u;
+    a0[u] = (own && k < p) ? row[k] : czero<cf64>();
+  }
+  const cf64 tprev = (j > 0) ? taus[j - 1] : czero<cf64>();
+  double re = 0.0, im = 0.0;
+  for (int q = j + tid; q < p; q += 256) {
+    const cf64 r = rowj[q];
+    vS[q] = cconj(r);
+    if (j > 0) {
+      const cf64 yy = yprev[q], vv = vprev[q];
+      wS[q] = yy;
+      pS[q] = vv;
+      re += yy.x * vv.x + yy.y * vv.y;
+      im += yy.x * vv.y - yy.y * vv.x;
     }
-    re = wave_sum_d(re); im = wave_sum_d(im);
+  }
+  // ---- w_{j-1} = y_{j-1} - 1/2 tau_{j-1} (y_{j-1}^H v_{j-1}) v_{j-1}
+  if (j > 0) {
+    re = wave_sum_d(re);
+    im = wave_sum_d(im);
     if (lane == 0) { red[0][wave] = re; red[1][wave] = im; }
     __syncthreads();
     if (tid == 0) {
-      const cf64 k = cmul(taus[j - 1], make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
-                                                    red[1][0] + red[1][1] + red[1][2] + red[1][3]));
+      const cf64 k = cmul(tprev, make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                                              red[1][0] + red[1][1] + red[1][2] + red[1][3]));
       bc[0] = make_double2(-0.5 * k.x, -0.5 * k.y);
     }
     __syncthreads();
     const cf64 c = bc[0];
-    for (int i = tid; i < p; i += 256) wS[i] = (i >= j) ? cadd(yprev[i], cmul(c, vprev[i])) : czero<cf64>();
-  } else {
-    for (int i = tid; i < p; i += 256) wS[i] = czero<cf64>();
+    for (int q = j + tid; q < p; q += 256) wS[q] = cadd(wS[q], cmul(c, pS[q]));
   }
   __syncthreads();
   // ---- column j (rows >= j) with the pending update; reflector
-  const cf64 wj = wS[j];
-  const cf64 vj = (j > 0) ? vprev[j] : czero<cf64>();
-  const cf64* rowj = A + (int64_t)j * p;
+  const cf64 wj = (j > 0) ? wS[j] : czero<cf64>();
+  const cf64 vj = (j > 0) ? pS[j] : czero<cf64>();
   if (blockIdx.x == 0 && tid == 0) {
-    double d = rowj[j].x;
+    double d = vS[j].x;
     if (j > 0) d -= 2.0 * (vj.x * wj.x + vj.y * wj.y);
     dg[j] = d;
   }
   if (j == p - 1) return;
   double nrm = 0.0;
-  for (int i = j + 1 + tid; i < p; i += 256) {
-    cf64 x = cconj(rowj[i]);
-    if (j > 0) x = csub(x, cadd(cmulc(vprev[i], wj), cmulc(wS[i], vj)));
-    vS[i] = x;  // stash the column; scaled below
-    if (i > j + 1) nrm += cabs2(x);
+  for (int q = j + 1 + tid; q < p; q += 256) {
+    cf64 x = vS[q];
+    if (j > 0) x = csub(x, cadd(cmulc(pS[q], wj), cmulc(wS[q], vj)));
+    vS[q] = x;  // the column; scaled below
+    if (q > j + 1) nrm += cabs2(x);
   }
   nrm = wave_sum_d(nrm);
   if (lane == 0) red[0][wave] = nrm;
@@ -267,46 +297,72 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   }
   __syncthreads();
   const cf64 tau = bc[0], scale = bc[1];
-  for (int i = tid; i < p; i += 256) {
+  for (int q = tid; q < p; q += 256) {
     cf64 v = czero<cf64>();
-    if (i == j + 1) v = make_double2(1.0, 0.0);
-    else if (i > j + 1) v = cmul(vS[i], scale);
-    vS[i] = v;
+    if (q == j + 1) v = make_double2(1.0, 0.0);
+    else if (q > j + 1) v = cmul(vS[q], scale);
+    vS[q] = v;
   }
   __syncthreads();
   if (blockIdx.x == 0) {
     cf64* vout = vs + (int64_t)j * p;
-    for (int i = tid; i < p; i += 256) vout[i] = vS[i];
+    for (int q = tid; q < p; q += 256) vout[q] = vS[q];
   }
-  // ---- own rows
-  const int i = j + 1 + blockIdx.x * 4 + wave;
-  if (i >= p) return;
-  cf64* row = A + (int64_t)i * p;
-  cf64 vi = czero<cf64>(), wi = czero<cf64>();
-  if (j > 0) { vi = vprev[i]; wi = wS[i]; }
-  double re = 0.0, im = 0.0;
-  for (int k = j + 1 + lane; k < p; k += 64) {
-    cf64 a = row[k];
-    if (j > 0) {
-      a = csub(a, cadd(cmulc(vi, wS[k]), cmulc(wi, vprev[k])));
-      row[k] = a;
+  // ---- own rows: wavefronts (2r, 2r+1) share row i, interleaved by 128 columns
+  re = 0.0;
+  im = 0.0;
+  if (own) {
+    cf64 vi = czero<cf64>(), wi = czero<cf64>();
+    if (j > 0) { vi = pS[i]; wi = wS[i]; }
+    for (int k0 = j + 1; k0 < p; k0 += 128 * TRI_UNROLL) {
+      cf64 a[TRI_UNROLL];
+      if (k0 == j + 1) {
+#pragma unroll
+        for (int u = 0; u < TRI_UNROLL; ++u) a[u] = a0[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < TRI_UNROLL; ++u) {
+          const int k = k0 + tl + 128 * u;
+          a[u] = (k < p) ? row[k] : czero<cf64>();
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TRI_UNROLL; ++u) {
+        const int k = k0 + tl + 128 * u;
+        if (k < p) {
+          cf64 x = a[u];
+          if (j > 0) {
+            x = csub(x, cadd(cmulc(vi, wS[k]), cmulc(wi, pS[k])));
+            row[k] = x;
+          }
+          const cf64 vk = vS[k];
+          re += x.x * vk.x - x.y * vk.y;
+          im += x.x * vk.y + x.y * vk.x;
+        }
+      }
     }
-    const cf64 vk = vS[k];
-    re += a.x * vk.x - a.y * vk.y;
-    im += a.x * vk.y + a.y * vk.x;
   }
   re = wave_sum_d(re);
   im = wave_sum_d(im);
-  if (lane == 0) ycur[i] = cmul(tau, make_double2(re, im));
+  if (lane == 0) { part[rl][half][0] = re; part[rl][half][1] = im; }
+  __syncthreads();
+  if (tid < TRI_ROWS) {
+    const int ii = i0 + 8 * (slot * TRI_ROWS + tid);
+    if (j < p - 1 && ii < p)
+      ycur[ii] = cmul(tau, make_double2(part[tid][0][0] + part[tid][1][0], part[tid][0][1] + part[tid][1][1]));
+  }
 }
 
 hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st) {
-  const size_t shm = (size_t)2 * p * sizeof(cf64);
+  const size_t shm = (size_t)3 * p * sizeof(cf64);
   if (shm > 150 * 1024) return hipErrorInvalidValue;
   for (int j = 0; j < p; ++j) {
     const int rows = p - j - 1;
-    hipLaunchKernelGGL(tridiag_col, dim3(std::max(1, (rows + 3) / 4)), dim3(256), shm, st, tw.A, tw.vs, tw.taus,
-                       tw.dg, tw.off, tw.y, p, j);
+    // 8 XCDs x enough slots of TRI_ROWS rows for the largest residue class
+    const int per_xcd = (rows + 7) / 8;
+    const int slots = std::max(1, (per_xcd + TRI_ROWS - 1) / TRI_ROWS);
+    hipLaunchKernelGGL(tridiag_col, dim3(8 * slots), dim3(256), shm, st, tw.A,
+                       tw.vs, tw.taus, tw.dg, tw.off, tw.y, p, j);
   }
   return hipGetLastError();
 }
