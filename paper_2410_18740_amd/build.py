@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libtn.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["gemm.hip", "ops.hip", "eig.hip", "plan.hip", "api.hip", "dmrg.hip", "sample.hip", "mlp.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-         # packed FP32 instructions stay off (see the design notes on gfx950)
+         # no packed FP32 (v_pk_*_f32) code generation
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
 

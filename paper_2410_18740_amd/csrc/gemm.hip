@@ -1,6 +1,8 @@
 // Complex GEMM on CDNA4 matrix cores (gfx950), three arithmetic forms:
 //   FP64   : v_mfma_f64_16x16x4f64,  real-block complex product (4 real MFMAs)
-//   FP32   : v_mfma_f32_32x32x2f32,  real-block complex product (4 real MFMAs)
+//   FP32   : v_mfma_f32_32x32x2f32,  three real products per complex block
+//            (P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); Re = P1 - P2,
+//            Im = P3 - P1 - P2: the 3M method, 3 MFMAs instead of 4)
 //   BF16x3 : v_mfma_f32_32x32x16_bf16, each FP32 operand split into bf16 hi + lo,
 //            product ~ hi*hi + hi*lo + lo*hi with FP32 accumulation (12 MFMAs
 //            per complex block product).
@@ -77,13 +79,15 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ 
   const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
 
   typedef typename std::conditional<PREC == PREC_FP64, v4d, v16f>::type AccT;
-  AccT accR[NI][NJ], accI[NI][NJ];
+  // FP32 (3M): accR = P1, accX = P2, accI = P3; other forms: accR = Re, accI = Im
+  AccT accR[NI][NJ], accI[NI][NJ], accX[NI][NJ];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       accR[i][j] = AccT{};
       accI[i][j] = AccT{};
+      accX[i][j] = AccT{};
     }
 
   // flattened K-tile sequence over the job's segments
@@ -156,25 +160,24 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ 
     if constexpr (PREC == PREC_FP32) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 2) {
-        float ar[NI], ai[NI], br[NJ], bi[NJ];
+        float ar[NI], ai[NI], sa[NI], br[NJ], bi[NJ], sb[NJ];
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
           CT v = As[buf][kk + (lane >> 5)][wm0 + 32 * i + (lane & 31)];
-          ar[i] = v.x; ai[i] = v.y;
+          ar[i] = v.x; ai[i] = v.y; sa[i] = v.x + v.y;
         }
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
           CT v = Bs[buf][kk + (lane >> 5)][wn0 + 32 * j + (lane & 31)];
-          br[j] = v.x; bi[j] = v.y;
+          br[j] = v.x; bi[j] = v.y; sb[j] = v.x + v.y;
         }
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
           for (int j = 0; j < NJ; ++j) {
             accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], accR[i][j], 0, 0, 0);
-            accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[i], bi[j], accR[i][j], 0, 0, 0);
-            accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], bi[j], accI[i][j], 0, 0, 0);
-            accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], br[j], accI[i][j], 0, 0, 0);
+            accX[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], accX[i][j], 0, 0, 0);
+            accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[i], sb[j], accI[i][j], 0, 0, 0);
           }
       }
     } else if constexpr (PREC == PREC_FP64) {
@@ -281,7 +284,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ 
           const int row = m0 + wm0 + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
           const int col = n0 + wn0 + 32 * j + (lane & 31);
           if (row < M && col < N) {
-            CT v = cmk(accR[i][j][r], accI[i][j][r]);
+            CT v;
+            if constexpr (PREC == PREC_FP32) {
+              const float p1 = accR[i][j][r], p2 = accX[i][j][r];
+              v = cmk(p1 - p2, accI[i][j][r] - p1 - p2);
+            } else {
+              v = cmk(accR[i][j][r], accI[i][j][r]);
+            }
             CT* p = C + (int64_t)row * ldc + col;
             if (accumulate) v = cadd(v, *p);
             *p = v;
