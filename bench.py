@@ -41,6 +41,8 @@ def parse():
                     help="time-to-target comparison of the forms (plain FP64, FP32+refine, BF16x3+refine)")
     ap.add_argument("--target", type=float, default=1e-8)
     ap.add_argument("--max-sweeps", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB copy before the timed sweeps (PMC counter scaling)")
     ap.add_argument("--warmstart", action="store_true",
                     help="learned warm start: generate data with plain DMRG+LBO, train the MLP, evaluate vs plain")
     ap.add_argument("--train-instances", type=int, default=200)
@@ -90,6 +92,42 @@ def cpu_baseline(w, r, U, budget_s=20.0):
     return {"value": fl * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} FP64 NumPy two-site matvecs of the middle window (site {site}, chi {cl}x{cr}, d {d}) "
                       f"of the same workload, {dt:.1f} s"}
+
+
+def copy_calibration(nbytes: int = 256 << 20, reps: int = 4):
+    """A plain copy of known size (torch's elementwise negation: nbytes read,
+    nbytes written) for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cgemm_fp32_gbs_n32_chi128_traffic.md")
+
+
+def gemm_traffic(form, workload):
+    """HBM bytes per launch of the matvec GEMM from the committed rocprofv3
+    --pmc summary, or None when it does not cover this form and workload or the
+    GEMM source has changed since the counters were taken."""
+    import hashlib
+    if form != "fp32" or workload != "gbs_n32_d16to8_chi128" or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line and line.startswith("- `"):
+            k, v = line[3:].split("`", 1)
+            vals[k] = v.split(":", 1)[1].strip().strip("`")
+    src = os.path.join(ROOT, "paper_2410_18740_amd", "csrc", "gemm.hip")
+    if vals.get("gemm_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def to_target(a):
@@ -281,7 +319,12 @@ def main():
         log.append(("warmup", s["energy"], s["t_total"]))
         print(f"warmup sweep {i}: <H> = {s['energy']:.6e}, {s['t_total']:.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    if a.copy_calibration:
+        copy_calibration()
     stats = []
+    # HIP events around every matvec launch on the context's stream, over the timed sweeps
+    ctx.profile(1)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
         s = P.dmrg_sweep(ctx, mpo, mps, opts)
@@ -289,18 +332,17 @@ def main():
         print(f"timed sweep {i}: <H> = {s['energy']:.6e}, {s['t_total']:.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    heff = sum(s["heff_flops"] for s in stats)
-    value = heff / wall / 1e12
-    # roofline of the dominant kernel (the MFMA GEMM) from HIP events over one more sweep
-    ctx.profile(1)
-    sp = P.dmrg_sweep(ctx, mpo, mps, opts)
     pr = ctx.profile(-1)
     ctx.profile(0)
+    heff = sum(s["heff_flops"] for s in stats)
+    value = heff / wall / 1e12
+    # roofline of the dominant kernel: the FP32 MFMA GEMM of the matvec contractions
     gemm_ms = pr["ms_gemm_l"] + pr["ms_gemm_r"]
     launches = 2 * pr["matvecs"]
     achieved = (pr["flops_l"] + pr["flops_r"]) / (gemm_ms * 1e-3) / 1e12
     peak = PEAKS[a.form]
     matvec_ms = sum(pr[k] for k in ("ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce"))
+    traffic = gemm_traffic(a.form, a.workload)
     extra = {
         "sweep_s": wall / a.steps,
         "energy": stats[-1]["energy"],
@@ -308,7 +350,10 @@ def main():
         "phase_s": {k: sum(s[k] for s in stats) / a.steps for k in
                     ("t_heff", "t_lanczos", "t_svd", "t_env", "t_lbo", "t_energy")},
         "matvecs_per_sweep": sum(s["matvecs"] for s in stats) / a.steps,
+        "gemm_launches": launches,
         "gemm_launch_avg_ms": gemm_ms / max(1, launches),
+        "gemm_flops_per_launch": (pr["flops_l"] + pr["flops_r"]) / max(1, launches),
+        "gemm_algorithmic_bytes_per_launch": (pr["bytes_l"] + pr["bytes_r"]) / max(1, launches),
         "matvec_phase_ms": {k: pr[k] / max(1, pr["matvecs"]) for k in
                             ("ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce")},
     }
@@ -336,7 +381,7 @@ def main():
         "config": {"workload": a.workload, "N": w.N, "D_raw": w.D_raw, "d": w.d, "chi": w.chi,
                    "form": a.form + ("" if a.no_lbo else "+lbo"), "lanczos_tol": tol},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": "cgemm_kernel (left and right environment contractions of the matvec)"},
         "extra": extra,
     }
