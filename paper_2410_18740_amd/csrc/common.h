@@ -57,6 +57,46 @@ struct GemmJob {
   int32_t seg0, nseg;
 };
 
+// ------------------------------------------------------------------ wavefront reduction (DPP)
+// Sum over the 64 lanes of a wavefront with data-parallel-primitive moves
+// (register crossbar, no LDS traffic): quad xor 1 and 2, half-row and row
+// mirrors give every lane its row-of-16 sum; row_bcast:15 and row_bcast:31
+// fold rows 0..3 into row 3; lane 63 then broadcasts the total.  The
+// summation order is fixed, so results are reproducible.
+template <int CTRL, int ROWMASK = 0xf>
+static __device__ __forceinline__ double dpp_src_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int ROWMASK = 0xf>
+static __device__ __forceinline__ float dpp_src_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xf, false));
+}
+static __device__ __forceinline__ double wave_reduce_sum(double v) {
+  v += dpp_src_d<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_src_d<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_src_d<0x141>(v);       // row_half_mirror
+  v += dpp_src_d<0x140>(v);       // row_mirror
+  v += dpp_src_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_src_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+static __device__ __forceinline__ float wave_reduce_sum(float v) {
+  v += dpp_src_f<0xB1>(v);
+  v += dpp_src_f<0x4E>(v);
+  v += dpp_src_f<0x141>(v);
+  v += dpp_src_f<0x140>(v);
+  v += dpp_src_f<0x142, 0xA>(v);
+  v += dpp_src_f<0x143, 0xC>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+
 // Launch a batch of jobs.  All jobs share precision and transposition flags.
 // d_jobs / d_segs are device arrays.  Max M/N over jobs sets the grid.
 hipError_t launch_cgemm(int prec, int trans_a, int trans_b, const GemmJob* d_jobs, int njobs,
@@ -129,7 +169,7 @@ hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st);
 hipError_t launch_bisect_top(const double* dg, const double* off, int p, int k, double* evals, hipStream_t st);
 hipError_t launch_inverse_iter(const double* dg, const double* off, int p, int k, const double* evals, double* X,
                                double* scratch, hipStream_t st);
-hipError_t launch_orthonormalize_real(double* X, int p, int k, int j0, hipStream_t st);
+hipError_t launch_orthonormalize_real(double* X, int p, int k, int j0, double* H /* k x 16 */, hipStream_t st);
 hipError_t launch_ortho_check(const double* X, int p, int k, double tol, int* bad, hipStream_t st);
 hipError_t launch_backtransform(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
                                 hipStream_t st);

@@ -203,7 +203,7 @@ static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& eva
   int j0 = kk;
   for (int j = 0; j < kk; ++j)
     if (hb[j]) { j0 = j; break; }
-  HIPCHK(launch_orthonormalize_real(X, p, kk, j0, st));
+  HIPCHK(launch_orthonormalize_real(X, p, kk, j0, wsT<double>(c, "eig:H", (size_t)kk * 16), st));
   Z = wsT<cf64>(c, "eig:Z", (size_t)p * kk);
   HIPCHK(launch_backtransform(tw.vs, tw.taus, p, X, kk, Z, st));
   evals.resize(kk);

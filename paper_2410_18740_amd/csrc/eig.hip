@@ -13,11 +13,7 @@
 #define JAC_N 64
 #define HIPCHK_DEV(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
-static __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+static __device__ __forceinline__ double wave_sum_d(double v) { return wave_reduce_sum(v); }
 
 // round-robin pairing (circle method) over n2 (even) indices
 static __device__ __forceinline__ void rr_pair(int r, int k, int n2, int& p, int& q) {
@@ -516,19 +512,49 @@ hipError_t launch_inverse_iter(const double* dg, const double* off, int p, int k
 }
 
 // ------------------------------------------------------------------ orthonormalisation of X (k columns of length p)
-// Two-pass classical Gram-Schmidt in column order; a column that loses more
-// than 1 - 1e-8 of its norm (numerically dependent, e.g. inside a cluster of
-// equal eigenvalues) is replaced by a unit vector and re-orthogonalised.
-__global__ __launch_bounds__(1024) void ortho_kernel(double* __restrict__ X, int p, int k, int j0) {
+// Columns [j0, k) are re-orthonormalised in blocks of OB columns, in column
+// order (the result is that of classical Gram-Schmidt done twice):
+//   1. the block is projected twice against all earlier columns (dot products
+//      one wavefront per pair, update one thread per entry: many workgroups);
+//   2. one workgroup orthonormalises the block's columns among themselves
+//      (two passes); a column that loses more than 1 - 1e-8 of its norm
+//      (numerically dependent, e.g. inside a cluster of equal eigenvalues) is
+//      replaced by a unit vector and re-orthogonalised against every earlier
+//      column.
+static constexpr int OB = 16;
+
+__global__ __launch_bounds__(256) void ortho_dot_kernel(const double* __restrict__ X, int p, int c0, int nb,
+                                                        double* __restrict__ H) {
+  const int lane = threadIdx.x & 63;
+  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pair >= c0 * nb) return;
+  const int l = pair / nb, c = pair % nb;
+  const double* xl = X + (int64_t)l * p;
+  const double* xc = X + (int64_t)(c0 + c) * p;
+  double s = 0.0;
+  for (int i = lane; i < p; i += 64) s += xl[i] * xc[i];
+  s = wave_sum_d(s);
+  if (lane == 0) H[l * OB + c] = s;
+}
+__global__ __launch_bounds__(256) void ortho_upd_kernel(double* __restrict__ X, int p, int c0, int nb,
+                                                        const double* __restrict__ H) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= p || c >= nb) return;
+  double v = X[(int64_t)(c0 + c) * p + i];
+  for (int l = 0; l < c0; ++l) v -= H[l * OB + c] * X[(int64_t)l * p + i];
+  X[(int64_t)(c0 + c) * p + i] = v;
+}
+__global__ __launch_bounds__(1024) void ortho_block_kernel(double* __restrict__ X, int p, int c0, int c1) {
   __shared__ double h[1024];
   __shared__ double red[16];
   __shared__ double sc[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = j0; j < k; ++j) {
+  for (int j = c0; j < c1; ++j) {
     double* xj = X + (int64_t)j * p;
     int trial = 0;
+    int lo = c0;  // earlier columns to project against: the block's, or all after a replacement
     while (true) {
-      // norm before
       double nb = 0.0;
       for (int i = tid; i < p; i += 1024) nb += xj[i] * xj[i];
       nb = wave_sum_d(nb);
@@ -538,8 +564,7 @@ __global__ __launch_bounds__(1024) void ortho_kernel(double* __restrict__ X, int
       __syncthreads();
       const double norm0 = sqrt(sc[0]);
       for (int pass = 0; pass < 2; ++pass) {
-        // h_l = <x_l, x_j> for l < j: one wave per l (strided)
-        for (int l = wave; l < j; l += 16) {
+        for (int l = lo + wave; l < j; l += 16) {
           const double* xl = X + (int64_t)l * p;
           double s = 0.0;
           for (int i = lane; i < p; i += 64) s += xl[i] * xj[i];
@@ -549,7 +574,7 @@ __global__ __launch_bounds__(1024) void ortho_kernel(double* __restrict__ X, int
         __syncthreads();
         for (int i = tid; i < p; i += 1024) {
           double v = xj[i];
-          for (int l = 0; l < j; ++l) v -= h[l] * X[(int64_t)l * p + i];
+          for (int l = lo; l < j; ++l) v -= h[l] * X[(int64_t)l * p + i];
           xj[i] = v;
         }
         __syncthreads();
@@ -568,19 +593,28 @@ __global__ __launch_bounds__(1024) void ortho_kernel(double* __restrict__ X, int
         __syncthreads();
         break;
       }
-      // replace by a unit vector and retry
+      // replace by a unit vector and orthogonalise it against every earlier column
       const int pos = (j + 7 * trial) % p;
       for (int i = tid; i < p; i += 1024) xj[i] = (i == pos) ? 1.0 : 0.0;
       __syncthreads();
+      lo = 0;
       ++trial;
       if (trial > p + 2) break;
     }
   }
 }
-hipError_t launch_orthonormalize_real(double* X, int p, int k, int j0, hipStream_t st) {
+hipError_t launch_orthonormalize_real(double* X, int p, int k, int j0, double* H, hipStream_t st) {
   if (k > 1024) return hipErrorInvalidValue;
-  if (j0 >= k) return hipSuccess;
-  hipLaunchKernelGGL(ortho_kernel, dim3(1), dim3(1024), 0, st, X, p, k, j0);
+  for (int c0 = j0; c0 < k; c0 += OB) {
+    const int nb = std::min(OB, k - c0);
+    if (c0 > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(ortho_dot_kernel, dim3((c0 * nb + 3) / 4), dim3(256), 0, st, X, p, c0, nb, H);
+        hipLaunchKernelGGL(ortho_upd_kernel, dim3((p + 255) / 256, nb), dim3(256), 0, st, X, p, c0, nb, H);
+      }
+    }
+    hipLaunchKernelGGL(ortho_block_kernel, dim3(1), dim3(1024), 0, st, X, p, c0, c0 + nb);
+  }
   return hipGetLastError();
 }
 
@@ -617,9 +651,10 @@ hipError_t launch_ortho_check(const double* X, int p, int k, double tol, int* ba
 // ------------------------------------------------------------------ back-transformation U = Q X
 // Q = H_0 H_1 ... H_{p-2}, applied in reverse order to each column.  One
 // wavefront per column; lane l keeps entries l, l+64, ... of the column in
-// registers and already holds the next reflector while the current one is
-// applied, so the chain of p dependent steps does not wait on memory.
-template <int MAXE>
+// registers, and the next DEPTH reflectors are loaded while the current ones
+// are applied (DEPTH = 1 measured fastest: the chain of p dependent steps is
+// bound by the reduction of each step, not by the loads).
+template <int MAXE, int DEPTH>
 __global__ __launch_bounds__(64) void backtransform_reg_kernel(const cf64* __restrict__ vs,
                                                                const cf64* __restrict__ taus, int p,
                                                                const double* __restrict__ X, int k,
@@ -627,37 +662,22 @@ __global__ __launch_bounds__(64) void backtransform_reg_kernel(const cf64* __res
   const int lane = threadIdx.x;
   const int col = blockIdx.x;
   if (col >= k) return;
-  cf64 x[MAXE], vn[MAXE];
+  cf64 x[MAXE];
 #pragma unroll
   for (int e = 0; e < MAXE; ++e) {
     const int i = lane + 64 * e;
     x[e] = make_double2(i < p ? X[(int64_t)col * p + i] : 0.0, 0.0);
   }
-  int j = p - 2;
-  cf64 tn = czero<cf64>();
-  if (j >= 0) {
-    tn = taus[j];
+  // reflector j (zero for j < 0, so that applying it is the identity)
+  auto load = [&](int j, cf64 (&r)[MAXE], cf64& t) {
+    t = (j >= 0) ? taus[j] : czero<cf64>();
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) {
       const int i = lane + 64 * e;
-      vn[e] = (i < p && i > j) ? vs[(int64_t)j * p + i] : czero<cf64>();
+      r[e] = (j >= 0 && i < p && i > j) ? vs[(int64_t)j * p + i] : czero<cf64>();
     }
-  }
-  for (; j >= 0; --j) {
-    cf64 v[MAXE];
-#pragma unroll
-    for (int e = 0; e < MAXE; ++e) v[e] = vn[e];
-    const cf64 tau = tn;
-    // prefetch reflector j-1
-    if (j > 0) {
-      tn = taus[j - 1];
-#pragma unroll
-      for (int e = 0; e < MAXE; ++e) {
-        const int i = lane + 64 * e;
-        vn[e] = (i < p && i > j - 1) ? vs[(int64_t)(j - 1) * p + i] : czero<cf64>();
-      }
-    }
-    if (tau.x == 0.0 && tau.y == 0.0) continue;
+  };
+  auto apply = [&](const cf64 (&v)[MAXE], cf64 tau) {
     double re = 0.0, im = 0.0;
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) {  // v is zero outside (j, p)
@@ -669,6 +689,17 @@ __global__ __launch_bounds__(64) void backtransform_reg_kernel(const cf64* __res
     const cf64 c = cmul(tau, make_double2(re, im));
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) x[e] = csub(x[e], cmul(c, v[e]));
+  };
+  cf64 r[DEPTH][MAXE];
+  cf64 t[DEPTH];
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) load(p - 2 - d, r[d], t[d]);
+  for (int j = p - 2; j >= 0; j -= DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      apply(r[d], t[d]);
+      load(j - DEPTH - d, r[d], t[d]);
+    }
   }
 #pragma unroll
   for (int e = 0; e < MAXE; ++e) {
@@ -707,11 +738,11 @@ __global__ __launch_bounds__(64) void backtransform_kernel(const cf64* __restric
 hipError_t launch_backtransform(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
                                 hipStream_t st) {
   if (p <= 64 * 8)
-    hipLaunchKernelGGL((backtransform_reg_kernel<8>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
+    hipLaunchKernelGGL((backtransform_reg_kernel<8, 1>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
   else if (p <= 64 * 16)
-    hipLaunchKernelGGL((backtransform_reg_kernel<16>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
+    hipLaunchKernelGGL((backtransform_reg_kernel<16, 1>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
   else if (p <= 64 * 24)
-    hipLaunchKernelGGL((backtransform_reg_kernel<24>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
+    hipLaunchKernelGGL((backtransform_reg_kernel<24, 1>), dim3(k), dim3(64), 0, st, vs, taus, p, X, k, U);
   else {
     const size_t shm = (size_t)p * sizeof(cf64);
     if (shm > 160 * 1024) return hipErrorInvalidValue;

@@ -100,8 +100,7 @@ __global__ __launch_bounds__(256) void mse_kernel(const float* Y, const float* T
     dY[e] = 2.f * d * scale;
     s += (double)d * d;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  s = wave_reduce_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];

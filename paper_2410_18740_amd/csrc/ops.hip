@@ -187,11 +187,7 @@ hipError_t launch_reduce_partials(cf64* out, int prec, const void* partials, int
 
 // ------------------------------------------------------------------ Krylov vector kernels (FP64)
 // wavefront-level tree reduction (fixed order) followed by a workgroup stage
-static __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+static __device__ __forceinline__ double wave_sum(double v) { return wave_reduce_sum(v); }
 
 #define MD_MAXV 72
 int multidot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 512)); }

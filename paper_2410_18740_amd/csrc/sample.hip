@@ -77,8 +77,7 @@ __global__ __launch_bounds__(256) void sample_step_kernel(const cf64* __restrict
   for (int n = 0; n < D; ++n) {
     double s = 0.0;
     for (int j = lane; j < cr; j += 64) s += cabs2(row[(size_t)n * cr + j]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    s = wave_reduce_sum(s);
     if (lane == 0) p[wave][n] = s;
   }
   __builtin_amdgcn_wave_barrier();
@@ -118,8 +117,7 @@ __global__ __launch_bounds__(256) void marg_kernel(const cf64* __restrict__ A, c
     const cf64 x = A[idx], y = Y[idx];
     s += x.x * y.x + x.y * y.y;
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  s = wave_reduce_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) out[n] = red[0] + red[1] + red[2] + red[3];
