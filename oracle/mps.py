@@ -70,24 +70,41 @@ def fock_tensors(mps, isometries):
     return [np.einsum("nm,amb->anb", W, A) for W, A in zip(isometries, mps)]
 
 
-def marginals(mps, isometries=None) -> np.ndarray:
+def _env_left(L, A):
+    """L'[c, d] = sum_{a,b,s} L[a, b] conj(A[a, s, c]) A[b, s, d]."""
+    T = np.tensordot(L, A, axes=([1], [0]))              # (a, s, d)
+    return np.tensordot(A.conj(), T, axes=([0, 1], [0, 1]))
+
+
+def _env_right(R, A):
+    """R'[a, b] = sum_{c,d,s} conj(A[a, s, c]) A[b, s, d] R[c, d]."""
+    T = np.tensordot(A, R.T, axes=([2], [0]))            # (b, s, c)
+    return np.tensordot(A.conj(), T, axes=([1, 2], [1, 2]))
+
+
+def marginals(mps, isometries=None, n_modes=None) -> np.ndarray:
     """Single-mode photon-number marginals P_j(n) by contracting the reduced
-    density matrix rho_j (eq. ReducedDensityMatrix), shape (N, D_raw)."""
+    density matrix rho_j (eq. ReducedDensityMatrix), shape (n_modes, D_raw)."""
     F = fock_tensors(mps, isometries)
     N = len(F)
+    n_modes = N if n_modes is None else n_modes
     left = [np.ones((1, 1), dtype=np.complex128)]
-    for A in F:
-        left.append(np.einsum("ab,asc,bsd->cd", left[-1], A.conj(), A))
+    for A in F[:n_modes]:
+        left.append(_env_left(left[-1], A))
     right = [np.ones((1, 1), dtype=np.complex128)]
     for A in reversed(F):
-        right.append(np.einsum("cd,asc,bsd->ab", right[-1], A.conj(), A))
+        right.append(_env_right(right[-1], A))
     right = right[::-1]
-    nrm = left[-1][0, 0].real
+    # <psi|psi> from the full right environment of site 0
+    nrm = right[0][0, 0].real
     D = F[0].shape[1]
-    out = np.zeros((N, D))
-    for j, A in enumerate(F):
-        rho = np.einsum("ab,asc,btd,cd->st", left[j], A.conj(), A, right[j + 1])
-        out[j] = np.real(np.diag(rho)) / nrm
+    out = np.zeros((n_modes, D))
+    for j in range(n_modes):
+        A = F[j]
+        # rho_j[s, s] = sum L[a, b] conj(A[a, s, c]) A[b, s, d] R[c, d]
+        T = np.tensordot(left[j], A, axes=([1], [0]))    # (a, s, d)
+        T = np.tensordot(T, right[j + 1], axes=([2], [1]))  # (a, s, c)
+        out[j] = np.real(np.einsum("asc,asc->s", A.conj(), T)) / nrm
     return out
 
 
