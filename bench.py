@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--to-target", action="store_true",
                     help="time-to-target comparison of the forms (plain FP64, FP32+refine, BF16x3+refine)")
     ap.add_argument("--target", type=float, default=1e-8)
+    ap.add_argument("--relative", action="store_true",
+                    help="with --to-target: E* = the plain FP64 form's energy after --max-sweeps sweeps (or sweep "
+                         "change < 1e-12); report each form's time to E* + 1e-8 and to E* (1 + 1e-4), (1 + 1e-2)")
     ap.add_argument("--max-sweeps", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB copy before the timed sweeps (PMC counter scaling)")
@@ -279,6 +282,56 @@ def warmstart_eval(a):
     ctx.close()
 
 
+def to_target_relative(a):
+    """Relative reading of the target on a workload where <H> <= 1e-8 cannot
+    be reached: every form runs its schedule from the same seeded state; the
+    plain FP64 form's final energy is E*; the first wall time at which each
+    form's FP64 <H> crosses E* + 1e-8, E* (1 + 1e-4) and E* (1 + 1e-2) is
+    reported (timers include every sweep and every <H> evaluation)."""
+    import torch
+    import paper_2410_18740_amd as P
+    import workloads as W
+    w = W.WORKLOADS[a.workload]
+    r, U = W.workload_problem(a.workload)
+    ctx = P.Context(0)
+    res = {}
+    for form in ("fp64", "fp32", "bf16x3"):
+        prec = FORMS[form]
+        mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
+        mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
+        sw = P.SweepOpts(chi_max=w.chi, krylov_max=24, max_matvecs=a.max_matvecs)
+        torch.cuda.synchronize()
+        out = P.dmrg_solve(ctx, mpo, mps, sw, max_sweeps=a.max_sweeps, bulk_precision=prec, max_refine=4,
+                           target=-1.0, switch_tol=1e-6, conv_tol=1e-12,
+                           bulk_tol=1e-8 if prec == 0 else 1e-6, refine_tol=1e-9, lbo_bulk=0 if a.no_lbo else 1,
+                           lbo_refine=0 if a.no_lbo else 1)
+        res[form] = out
+        print(f"{form}: sweeps={out['sweeps']} (refine {out['refine_sweeps']}) {out['seconds']:.2f}s "
+              f"E={out['energy']:.10e}", file=sys.stderr, flush=True)
+        del mps, mpo
+    e_star = res["fp64"]["energy"]
+    crit = {"E*+1e-8": e_star + 1e-8, "E*(1+1e-4)": e_star * (1 + 1e-4), "E*(1+1e-2)": e_star * (1 + 1e-2)}
+
+    def first(o, tgt):
+        for e, t in zip(o["energy_trace"], o["time_trace"]):
+            if e <= tgt:
+                return t
+        return None
+    times = {f: {k: first(o, v) for k, v in crit.items()} for f, o in res.items()}
+    line = {
+        "metric": METRIC, "value": times["fp32"]["E*+1e-8"], "unit": "s", "n_gpus": 1, "steps": None,
+        "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic", "config": {"workload": a.workload, "reading": "relative",
+                                                         "E_star": e_star, "lbo": not a.no_lbo},
+        "time_to": times,
+        "speedup_vs_plain_fp64": {f: {k: (times["fp64"][k] / t) if (t and times["fp64"][k]) else None
+                                      for k, t in tt.items()} for f, tt in times.items()},
+        "forms": {f: {k: v for k, v in o.items()} for f, o in res.items()},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     a = parse()
     if a.warmstart:
@@ -291,7 +344,10 @@ def main():
         if a.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        to_target(a)
+        if a.relative:
+            to_target_relative(a)
+        else:
+            to_target(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}): the path is built and measured on one "

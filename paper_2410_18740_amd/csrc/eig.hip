@@ -364,14 +364,15 @@ hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ bisection (top-k)
-static __device__ int sturm_count(const double* dg, const double* off, int p, double x, double pivmin) {
-  // number of eigenvalues < x
+static __device__ int sturm_count(const double* dS, const double* e2S, int p, double x, double pivmin) {
+  // number of eigenvalues < x; dS, e2S: diagonal and squared off-diagonal in LDS
   int cnt = 0;
-  double q = dg[0] - x;
+  double q = dS[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0) ++cnt;
+#pragma unroll 4
   for (int i = 1; i < p; ++i) {
-    q = (dg[i] - x) - off[i - 1] * off[i - 1] / q;
+    q = (dS[i] - x) - e2S[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0) ++cnt;
   }
@@ -384,9 +385,17 @@ static __device__ int sturm_count(const double* dg, const double* off, int p, do
 // multisection; 10-12 rounds reach full double precision).
 __global__ __launch_bounds__(64) void bisect_kernel(const double* dg, const double* off, int p, int k,
                                                     double* evals) {
+  extern __shared__ unsigned char sm_raw[];
+  double* dS = reinterpret_cast<double*>(sm_raw);
+  double* e2S = dS + p;
   const int t = blockIdx.x;
   const int lane = threadIdx.x;
   if (t >= k) return;
+  for (int i = lane; i < p; i += 64) {
+    dS[i] = dg[i];
+    e2S[i] = (i < p - 1) ? off[i] * off[i] : 0.0;
+  }
+  __syncthreads();
   double lo = 1e300, hi = -1e300, emax = 0.0;
   for (int i = lane; i < p; i += 64) {
     const double r = (i > 0 ? fabs(off[i - 1]) : 0.0) + (i < p - 1 ? fabs(off[i]) : 0.0);
@@ -408,7 +417,7 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* dg, const doub
   for (int it = 0; it < 40; ++it) {
     if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
     const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-    const int c = sturm_count(dg, off, p, x, pivmin);
+    const int c = sturm_count(dS, e2S, p, x, pivmin);
     // probes with count <= target lie left of the eigenvalue
     const unsigned long long le = __ballot(c <= target);
     const int nle = __popcll(le);          // probes are increasing, so these are lanes 0..nle-1
@@ -421,7 +430,9 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* dg, const doub
   if (lane == 0) evals[t] = 0.5 * (lo + hi);
 }
 hipError_t launch_bisect_top(const double* dg, const double* off, int p, int k, double* evals, hipStream_t st) {
-  hipLaunchKernelGGL(bisect_kernel, dim3(k), dim3(64), 0, st, dg, off, p, k, evals);
+  const size_t shm = (size_t)2 * p * sizeof(double);
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bisect_kernel, dim3(k), dim3(64), shm, st, dg, off, p, k, evals);
   return hipGetLastError();
 }
 
@@ -455,41 +466,71 @@ __global__ __launch_bounds__(64) void inverse_iter_kernel(const double* __restri
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
   __syncthreads();
+  const double tiny = fmax(2.2e-16 * tn, 1e-300);
   if (lane == 0) {
-    const double tiny = fmax(2.2e-16 * tn, 1e-300);
+    // LU with partial pivoting of the tridiagonal T - lambda I; the running
+    // diagonal and super-diagonal entries are carried in registers
+    double cdd = dd[0], cdu = du[0];
     for (int i = 0; i < p - 1; ++i) {
-      if (fabs(dd[i]) >= fabs(dl[i])) {
-        if (dd[i] == 0.0) dd[i] = tiny;
-        const double f = dl[i] / dd[i];
+      const double l = dl[i], ndd = dd[i + 1], ndu = du[i + 1];
+      if (fabs(cdd) >= fabs(l)) {
+        if (cdd == 0.0) cdd = tiny;
+        const double f = l / cdd;
+        dd[i] = cdd;
         dl[i] = f;
-        dd[i + 1] -= f * du[i];
+        du[i] = cdu;
+        cdd = ndd - f * cdu;
+        cdu = ndu;
       } else {
-        const double f = dd[i] / dl[i];
-        dd[i] = dl[i];
+        const double f = cdd / l;
+        dd[i] = l;
         dl[i] = f;
-        const double tmp = du[i];
-        du[i] = dd[i + 1];
-        dd[i + 1] = tmp - f * dd[i + 1];
-        if (i < p - 2) { du2[i] = du[i + 1]; du[i + 1] = -f * du[i + 1]; }
+        du[i] = ndd;
         piv[i] = 1;
+        cdd = cdu - f * ndd;
+        if (i < p - 2) { du2[i] = ndu; cdu = -f * ndu; }
+        else cdu = ndu;
       }
     }
-    for (int i = 0; i < p; ++i)
-      if (fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
-    for (int it = 0; it < 2; ++it) {
+    dd[p - 1] = cdd;
+  }
+  __syncthreads();
+  for (int i = lane; i < p; i += 64)
+    if (fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
+  __syncthreads();
+  for (int it = 0; it < 2; ++it) {
+    if (lane == 0) {
+      double cb = b[0];
       for (int i = 0; i < p - 1; ++i) {
-        if (piv[i]) { const double tmp = b[i]; b[i] = b[i + 1]; b[i + 1] = tmp - dl[i] * b[i]; }
-        else b[i + 1] -= dl[i] * b[i];
+        const double nb = b[i + 1], l = dl[i];
+        if (piv[i]) { b[i] = nb; cb = cb - l * nb; }
+        else { b[i] = cb; cb = nb - l * cb; }
       }
-      b[p - 1] /= dd[p - 1];
-      if (p >= 2) b[p - 2] = (b[p - 2] - du[p - 2] * b[p - 1]) / dd[p - 2];
-      for (int i = p - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
-      if (it == 0) {
-        double mx = 0.0;
-        for (int i = 0; i < p; ++i) mx = fmax(mx, fabs(b[i]));
-        const double s = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 0.0;
-        for (int i = 0; i < p; ++i) b[i] *= s;
+      double x1 = cb / dd[p - 1];
+      b[p - 1] = x1;
+      double x2 = 0.0;
+      if (p >= 2) {
+        const double x0 = (b[p - 2] - du[p - 2] * x1) / dd[p - 2];
+        b[p - 2] = x0;
+        x2 = x1;
+        x1 = x0;
       }
+      for (int i = p - 3; i >= 0; --i) {
+        const double x0 = (b[i] - du[i] * x1 - du2[i] * x2) / dd[i];
+        b[i] = x0;
+        x2 = x1;
+        x1 = x0;
+      }
+    }
+    __syncthreads();
+    if (it == 0) {
+      double mx = 0.0;
+      for (int i = lane; i < p; i += 64) mx = fmax(mx, fabs(b[i]));
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+      const double sc = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 0.0;
+      for (int i = lane; i < p; i += 64) b[i] *= sc;
+      __syncthreads();
     }
   }
   __syncthreads();
