@@ -52,10 +52,13 @@ def parse():
     ap.add_argument("--eval-instances", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--data-sweeps", type=int, default=4)
-    ap.add_argument("--family", default="cfg3", choices=["cfg3", "basis"],
+    ap.add_argument("--family", default="cfg3", choices=["cfg3", "basis", "mesh"],
                     help="cfg3: N~U{8..16}, cutoff 10, basis 8, chi 48, r~U[0.3,1.2] for training; N=20, cutoff 12, "
                          "chi 64 for evaluation.  basis: strongly squeezed modes (r~U[1.0,1.5]), cutoff 16 "
-                         "compressed to a 4-dim local basis, chi 32, N~U{6..14} / N=12")
+                         "compressed to a 4-dim local basis, chi 32, N~U{6..14} / N=12.  mesh: weakly squeezed "
+                         "brickwork meshes (r~U[0.1,0.2], 4 layers), cutoff 16 compressed to 8, chi 32, "
+                         "N~U{8..16}; evaluated by time to <H> <= 1e-8 at N=32, chi 128 (the brickwork twin "
+                         "and further seeds)")
     return ap.parse_args()
 
 
@@ -168,6 +171,95 @@ def to_target(a):
                                   for f, o in res.items()},
     }
     print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def _solve_to(P, ctx, mpo, mps, w_chi, prec, a, target=1e-8):
+    sw = P.SweepOpts(chi_max=w_chi, krylov_max=24, max_matvecs=a.max_matvecs)
+    return P.dmrg_solve(ctx, mpo, mps, sw, max_sweeps=a.max_sweeps, bulk_precision=prec, max_refine=3,
+                        target=target, switch_tol=1e-6, conv_tol=1e-13, bulk_tol=1e-8 if prec == 0 else 1e-6,
+                        refine_tol=1e-9, lbo_bulk=1, lbo_refine=1)
+
+
+def warmstart_mesh(a):
+    """Learned warm start judged by time to <H> <= 1e-8 on weakly squeezed
+    brickwork meshes (N = 32, cutoff 16 -> 8, chi 128), where the literal
+    target is reachable: plain random start vs learned bases + learned product
+    state, each with the FP64 and the FP32 + refine schedule.  The judge keeps
+    the learned start only if its first-sweep <H> is no larger than the plain
+    start's; otherwise its first sweep is charged and the plain time added."""
+    import torch
+    import paper_2410_18740_amd as P
+    from paper_2410_18740_amd import warmstart as WS
+    import workloads as W
+    ctx = P.Context(0)
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    for i in range(a.train_instances):
+        seed = 10000 + i
+        N = int(np.random.default_rng(seed).integers(8, 17))
+        r, U = W.make_problem(N, seed, (0.1, 0.2), kind="brickwork")
+        X, T, tr = WS.instance_data(ctx, r, U, 16, 8, 32, W.random_mps(N, 8, 32, seed + 500000),
+                                    max_sweeps=a.data_sweeps)
+        Xs.append(X)
+        Ts.append(T)
+        if i % 20 == 0:
+            print(f"data {i}/{a.train_instances} N={N} E={tr.final:.3e} {time.perf_counter() - t0:.1f}s",
+                  file=sys.stderr, flush=True)
+    X, T = np.concatenate(Xs), np.concatenate(Ts)
+    t_data = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    net, losses, vloss = WS.train(ctx, X, T, epochs=a.epochs)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    print(f"trained on {X.shape[0]} rows: loss {losses[0]:.5f} -> {losses[-1]:.6f}, val {vloss:.6f}, {t_train:.1f}s",
+          file=sys.stderr, flush=True)
+    w = W.WORKLOADS["mesh_n32_d16to8_chi128"]
+    rows = []
+    for i in range(a.eval_instances):
+        seed = w.seed if i == 0 else 20000 + i
+        r, U = W.make_problem(w.N, seed, w.r_range, kind="brickwork")
+        init = W.random_mps(w.N, w.d, w.chi, w.mps_seed if i == 0 else seed + 500000)
+        row = {"seed": seed}
+        for form, prec in (("fp64", 0), ("fp32", 1)):
+            mpo, mps = WS.plain_start(ctx, r, U, w.D_raw, w.d, init)
+            torch.cuda.synchronize()
+            plain = _solve_to(P, ctx, mpo, mps, w.chi, prec, a)
+            del mps, mpo
+            tl = time.perf_counter()
+            mpo, mps = WS.learned_start(ctx, net, r, U, w.D_raw, w.d, w.chi, seed)
+            torch.cuda.synchronize()
+            t_init = time.perf_counter() - tl
+            learned = _solve_to(P, ctx, mpo, mps, w.chi, prec, a)
+            del mps, mpo
+            e1p, e1l = plain["energy_trace"][0], learned["energy_trace"][0]
+            kept = bool(np.isfinite(e1l) and e1l <= e1p)
+            if kept:
+                t_l = t_init + learned["t_target"] if learned["reached"] else None
+            else:
+                t_l = (t_init + learned["time_trace"][0] + plain["t_target"]) if plain["reached"] else None
+            row[form] = {"plain_t": plain["t_target"] if plain["reached"] else None, "plain_sweeps": plain["sweeps"],
+                         "plain_E1": e1p, "learned_t": t_l, "learned_kept": kept,
+                         "learned_sweeps": learned["sweeps"], "learned_E1": e1l, "learned_init_s": t_init,
+                         "plain_trace": plain["energy_trace"], "learned_trace": learned["energy_trace"]}
+            print(f"eval seed {seed} {form}: plain {row[form]['plain_t']} s ({plain['sweeps']} sw, E1 {e1p:.3e}); "
+                  f"learned {t_l} s ({learned['sweeps']} sw, E1 {e1l:.3e}, kept {kept}, init {t_init:.2f} s)",
+                  file=sys.stderr, flush=True)
+        rows.append(row)
+
+    def med(form, key):
+        v = [r_[form][key] for r_ in rows if r_[form][key] is not None]
+        return float(np.median(v)) if v else None
+    line = {"mode": "warmstart", "family": "mesh", "train_instances": a.train_instances, "train_rows": int(X.shape[0]),
+            "data_s": t_data, "train_s": t_train, "epochs": a.epochs, "final_train_loss": losses[-1],
+            "val_loss": vloss, "eval_instances": a.eval_instances, "target": 1e-8,
+            "median_time_to_target_s": {f"{f}_{k}": med(f, k + "_t") for f in ("fp64", "fp32")
+                                        for k in ("plain", "learned")},
+            "kept": {f: sum(r_[f]["learned_kept"] for r_ in rows) for f in ("fp64", "fp32")}}
+    print(json.dumps(line), flush=True)
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", "warmstart_mesh_rows.json"), "w") as f:
+        json.dump(rows, f)
     ctx.close()
 
 
@@ -338,7 +430,10 @@ def main():
         if a.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        warmstart_eval(a)
+        if a.family == "mesh":
+            warmstart_mesh(a)
+        else:
+            warmstart_eval(a)
         return
     if a.to_target:
         if a.gpus != 1:

@@ -88,3 +88,41 @@ def test_fallback_takes_the_plain_start(trained):
     # a bar that any finite energy meets keeps the learned start
     tr2, used2, _ = WS.solve_with_fallback(ctx, net, r, U, D, d, CHI, 5, init, math.inf, 2)
     assert used2 and len(tr2.energies) == 2
+
+
+@pytest.fixture(scope="module")
+def mesh_trained():
+    import paper_2410_18740_amd as P
+    from paper_2410_18740_amd import warmstart as WS
+    ctx = P.Context(0)
+    Xs, Ts = [], []
+    for i in range(24):
+        seed = 32000 + i
+        N = int(np.random.default_rng(seed).integers(6, 11))
+        r, U = W.make_problem(N, seed, (0.1, 0.2), kind="brickwork")
+        X, T, _ = WS.instance_data(ctx, r, U, 12, 6, 16, W.random_mps(N, 6, 16, seed + 1), max_sweeps=3)
+        Xs.append(X)
+        Ts.append(T)
+    net, losses, vloss = WS.train(ctx, np.concatenate(Xs), np.concatenate(Ts), epochs=300, batch=64)
+    yield ctx, net
+    ctx.close()
+
+
+def test_learned_start_on_weakly_squeezed_meshes(mesh_trained):
+    """On weakly squeezed brickwork meshes the learned product state in the
+    learned bases is close to the ground state: after one sweep its <H> is
+    below the plain random start's (several times below, typically), on
+    held-out instances larger than any seen in training."""
+    from paper_2410_18740_amd import warmstart as WS
+    ctx, net = mesh_trained
+    for i in range(2):
+        seed = 33000 + i
+        N = 16
+        r, U = W.make_problem(N, seed, (0.1, 0.2), kind="brickwork")
+        init = W.random_mps(N, 6, 16, seed + 1)
+        mpo, mps = WS.plain_start(ctx, r, U, 12, 6, init)
+        plain = WS.run_sweeps(ctx, mpo, mps, WS.sweep_opts(16), 1)
+        mpo, mps = WS.learned_start(ctx, net, r, U, 12, 6, 16, seed)
+        learned = WS.run_sweeps(ctx, mpo, mps, WS.sweep_opts(16), 1)
+        print(f"seed {seed}: first-sweep <H> plain {plain.final:.3e}, learned {learned.final:.3e}")
+        assert learned.final < plain.final
