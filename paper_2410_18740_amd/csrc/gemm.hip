@@ -20,15 +20,18 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 template <int PREC> struct GemmCfg;
 template <> struct GemmCfg<PREC_FP32> {
   typedef cf32 CT;
-  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64, MB = 32, KSTEP = 2;
+  // 128 x 64 tiles at three workgroups per CU (168 VGPRs): measured faster
+  // than 128 x 128 at one, since other waves' MFMAs cover each wave's LDS
+  // reads, barriers and epilogue
+  static constexpr int BM = 128, BN = 64, BK = 16, WM = 64, WN = 32, MB = 32, KSTEP = 2, MINB = 3;
 };
 template <> struct GemmCfg<PREC_BF16X3> {
   typedef cf32 CT;
-  static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64, MB = 32, KSTEP = 16;
+  static constexpr int BM = 128, BN = 64, BK = 16, WM = 64, WN = 32, MB = 32, KSTEP = 16, MINB = 2;
 };
 template <> struct GemmCfg<PREC_FP64> {
   typedef cf64 CT;
-  static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MB = 16, KSTEP = 4;
+  static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MB = 16, KSTEP = 4, MINB = 1;
 };
 
 static __device__ __forceinline__ __bf16 bf_from_bits(uint32_t b) {
@@ -57,7 +60,7 @@ static __device__ __forceinline__ CT ld_c(const CT* p) {
 }
 
 template <int PREC, bool TA, bool TB>
-__global__ __launch_bounds__(256) void cgemm_kernel(const GemmJob* __restrict__ jobs,
+__global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const GemmJob* __restrict__ jobs,
                                                     const GemmSeg* __restrict__ segs, int accumulate) {
   using Cfg = GemmCfg<PREC>;
   using CT = typename Cfg::CT;
