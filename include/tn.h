@@ -70,12 +70,16 @@ void tn_ctx_destroy(tn_ctx* ctx);
 const char* tn_last_error(const tn_ctx* ctx);
 /* Kernel timing of the window matvec.  When profiling is on, every matvec
  * records HIP events around its launches on the context stream and waits for
- * them (so it serialises the host).  out (may be NULL, 11 doubles) receives the
+ * them (so it serialises the host).  out (may be NULL, 14 doubles) receives the
  * accumulated milliseconds of [convert, left contraction GEMM, operator kernel,
  * right contraction GEMM, split-K reduction], the matvec count, the
  * algorithmic flops of the left contraction, of the right contraction and of
- * the whole matvec (the integer formula), and the algorithmic bytes of the two
- * GEMMs.  mode: -1 read only, 0 stop and reset, 1 start (after reset). */
+ * the whole matvec (the integer formula), the algorithmic bytes of the two
+ * GEMMs, and for the truncation's Householder tridiagonalisation (one event
+ * pair around each sequence of column launches) the milliseconds, the launch
+ * count and the algorithmic bytes (32 (p - j - 1)^2 for column j: the
+ * trailing block read and written once).
+ * mode: -1 read only, 0 stop and reset, 1 start (after reset). */
 tn_status tn_profile(tn_ctx* ctx, int32_t mode, double* out);
 
 /* ------------------------------------------------------------------ problem / MPO

@@ -107,6 +107,7 @@ extern "C" void tn_ctx_destroy(tn_ctx* c) {
   if (c->ev_ok) {
     for (int i = 0; i < 8; ++i) (void)hipEventDestroy(c->ev[i]);
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(c->pev[i]);
+    for (auto e : c->tri_ev) (void)hipEventDestroy(e);
   }
   delete c;
 }
@@ -121,6 +122,9 @@ extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
     for (int i = 0; i < 3; ++i) out[6 + i] = c->prof_flops[i];
     out[9] = c->prof_bytes[0];
     out[10] = c->prof_bytes[1];
+    out[11] = c->prof_tri_ms;
+    out[12] = (double)c->prof_tri_n;
+    out[13] = c->prof_tri_bytes;
   }
   if (mode >= 0) {
     c->prof = mode > 0;
@@ -128,6 +132,8 @@ extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
     for (int i = 0; i < 3; ++i) c->prof_flops[i] = 0.0;
     c->prof_bytes[0] = c->prof_bytes[1] = 0.0;
     c->prof_n = 0;
+    c->prof_tri_ms = c->prof_tri_bytes = 0.0;
+    c->prof_tri_n = 0;
   }
   return TN_OK;
 }

@@ -187,7 +187,18 @@ static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& eva
   tw.y = wsT<cf64>(c, "eig:y", 2 * (size_t)p);
   tw.w = wsT<cf64>(c, "eig:w", 2 * (size_t)p);
   tw.counter = wsT<unsigned int>(c, "eig:cnt", 1);
+  // profiling: one event pair around the whole sequence of column launches
+  const bool pf = c->prof;
+  if (pf) {
+    while (c->tri_ev.size() < 2) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      c->tri_ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(c->tri_ev[0], st));
+  }
   HIPCHK(launch_tridiag(tw, p, st));
+  if (pf) HIPCHK(hipEventRecord(c->tri_ev[1], st));
   double* ev = wsT<double>(c, "eig:ev", kk);
   HIPCHK(launch_bisect_top(tw.dg, tw.off, p, kk, ev, st));
   double* X = wsT<double>(c, "eig:X", (size_t)kk * p);
@@ -200,6 +211,14 @@ static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& eva
   HIPCHK(launch_ortho_check(X, p, kk, 1e-13, bad, st));
   std::vector<int> hb(kk);
   download(c, hb.data(), bad, kk * sizeof(int));
+  if (pf) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->tri_ev[0], c->tri_ev[1]) == hipSuccess) {
+      c->prof_tri_ms += ms;
+      c->prof_tri_n += p;
+      for (int j = 0; j < p; ++j) c->prof_tri_bytes += 32.0 * (double)(p - j - 1) * (double)(p - j - 1);
+    }
+  }
   int j0 = kk;
   for (int j = 0; j < kk; ++j)
     if (hb[j]) { j0 = j; break; }

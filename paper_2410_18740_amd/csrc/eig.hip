@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   cf64* wS = vS + p;                           // y_{j-1}, then w_{j-1}
   cf64* pS = wS + p;                           // v_{j-1}
   __shared__ double red[2][4];
-  __shared__ cf64 bc[2];
+  __shared__ double red2[4];
   __shared__ double part[TRI_ROWS][2][2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cf64* vprev = (j > 0) ? vs + (int64_t)(j - 1) * p : nullptr;
@@ -223,7 +223,12 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
     a0[u] = (own && k < p) ? row[k] : czero<cf64>();
   }
   const cf64 tprev = (j > 0) ? taus[j - 1] : czero<cf64>();
+  // entries j of y_{j-1} and v_{j-1}: every thread forms w_{j-1}[j] itself
+  const cf64 yj = (j > 0) ? yprev[j] : czero<cf64>();
+  const cf64 pj = (j > 0) ? vprev[j] : czero<cf64>();
   double re = 0.0, im = 0.0;
+  // each thread owns the entries q = j + tid (mod 256) of the LDS vectors up to
+  // the reflector, so only the two reductions need workgroup barriers
   for (int q = j + tid; q < p; q += 256) {
     const cf64 r = rowj[q];
     vS[q] = cconj(r);
@@ -236,24 +241,20 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
     }
   }
   // ---- w_{j-1} = y_{j-1} - 1/2 tau_{j-1} (y_{j-1}^H v_{j-1}) v_{j-1}
+  cf64 c = czero<cf64>();
   if (j > 0) {
     re = wave_sum_d(re);
     im = wave_sum_d(im);
     if (lane == 0) { red[0][wave] = re; red[1][wave] = im; }
     __syncthreads();
-    if (tid == 0) {
-      const cf64 k = cmul(tprev, make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
-                                              red[1][0] + red[1][1] + red[1][2] + red[1][3]));
-      bc[0] = make_double2(-0.5 * k.x, -0.5 * k.y);
-    }
-    __syncthreads();
-    const cf64 c = bc[0];
+    const cf64 k = cmul(tprev, make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                                            red[1][0] + red[1][1] + red[1][2] + red[1][3]));
+    c = make_double2(-0.5 * k.x, -0.5 * k.y);
     for (int q = j + tid; q < p; q += 256) wS[q] = cadd(wS[q], cmul(c, pS[q]));
   }
-  __syncthreads();
   // ---- column j (rows >= j) with the pending update; reflector
-  const cf64 wj = (j > 0) ? wS[j] : czero<cf64>();
-  const cf64 vj = (j > 0) ? pS[j] : czero<cf64>();
+  const cf64 wj = (j > 0) ? cadd(yj, cmul(c, pj)) : czero<cf64>();
+  const cf64 vj = pj;
   if (blockIdx.x == 0 && tid == 0) {
     double d = vS[j].x;
     if (j > 0) d -= 2.0 * (vj.x * wj.x + vj.y * wj.y);
@@ -261,19 +262,20 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   }
   if (j == p - 1) return;
   double nrm = 0.0;
-  for (int q = j + 1 + tid; q < p; q += 256) {
+  for (int q = j + tid; q < p; q += 256) {
+    if (q == j) continue;
     cf64 x = vS[q];
     if (j > 0) x = csub(x, cadd(cmulc(pS[q], wj), cmulc(wS[q], vj)));
-    vS[q] = x;  // the column; scaled below
+    vS[q] = x;  // the column; the reflector is v = (q == j + 1 ? 1 : x scale)
     if (q > j + 1) nrm += cabs2(x);
   }
   nrm = wave_sum_d(nrm);
-  if (lane == 0) red[0][wave] = nrm;
+  if (lane == 0) red2[wave] = nrm;
   __syncthreads();
-  if (tid == 0) {
-    const double xn2 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  cf64 tau, scale;
+  {
+    const double xn2 = red2[0] + red2[1] + red2[2] + red2[3];
     const cf64 alpha = vS[j + 1];
-    cf64 tau, scale;
     double beta;
     if (xn2 == 0.0 && alpha.y == 0.0) {
       tau = czero<cf64>();
@@ -287,22 +289,16 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
       const double dd = den.x * den.x + den.y * den.y;
       scale = make_double2(den.x / dd, -den.y / dd);
     }
-    bc[0] = tau;
-    bc[1] = scale;
-    if (blockIdx.x == 0) { taus[j] = tau; off[j] = beta; }
+    if (blockIdx.x == 0 && tid == 0) { taus[j] = tau; off[j] = beta; }
   }
-  __syncthreads();
-  const cf64 tau = bc[0], scale = bc[1];
-  for (int q = tid; q < p; q += 256) {
-    cf64 v = czero<cf64>();
-    if (q == j + 1) v = make_double2(1.0, 0.0);
-    else if (q > j + 1) v = cmul(vS[q], scale);
-    vS[q] = v;
-  }
-  __syncthreads();
   if (blockIdx.x == 0) {
     cf64* vout = vs + (int64_t)j * p;
-    for (int q = tid; q < p; q += 256) vout[q] = vS[q];
+    for (int q = tid; q < p; q += 256) {
+      cf64 v = czero<cf64>();
+      if (q == j + 1) v = make_double2(1.0, 0.0);
+      else if (q > j + 1) v = cmul(vS[q], scale);
+      vout[q] = v;
+    }
   }
   // ---- own rows: wavefronts (2r, 2r+1) share row i, interleaved by 128 columns
   re = 0.0;
@@ -331,7 +327,7 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
             x = csub(x, cadd(cmulc(vi, wS[k]), cmulc(wi, pS[k])));
             row[k] = x;
           }
-          const cf64 vk = vS[k];
+          const cf64 vk = (k == j + 1) ? make_double2(1.0, 0.0) : cmul(vS[k], scale);
           re += x.x * vk.x - x.y * vk.y;
           im += x.x * vk.y + x.y * vk.x;
         }

@@ -42,6 +42,10 @@ struct tn_ctx {
   double prof_flops[3] = {0, 0, 0};      // algorithmic: L-contraction, R-contraction, whole matvec
   int64_t prof_n = 0;
   double prof_bytes[2] = {0, 0};         // algorithmic bytes read + written by the two GEMMs
+  // sampled tridiagonalisation columns (every TRI_SAMPLE-th launch): ms, count, algorithmic bytes
+  std::vector<hipEvent_t> tri_ev;
+  double prof_tri_ms = 0.0, prof_tri_bytes = 0.0;
+  int64_t prof_tri_n = 0;
 };
 
 void* dev_alloc(tn_ctx* c, size_t bytes);
