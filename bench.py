@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-lbo", action="store_true")
     ap.add_argument("--max-matvecs", type=int, default=16)
+    ap.add_argument("--lbo-matvecs", type=int, default=0, help="matvec cap of each LBO solve (0: --max-matvecs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare", action="store_true", help="also time one sweep in each other form")
     ap.add_argument("--to-target", action="store_true",
@@ -486,7 +487,7 @@ def main():
     mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
     mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
     opts = P.SweepOpts(chi_max=w.chi, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec,
-                       lbo=0 if a.no_lbo else 1, compute_energy=1)
+                       lbo=0 if a.no_lbo else 1, compute_energy=1, lbo_matvecs=a.lbo_matvecs)
     log = []
     for i in range(a.warmup):
         s = P.dmrg_sweep(ctx, mpo, mps, opts)

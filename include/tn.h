@@ -144,6 +144,7 @@ typedef struct {
   int32_t precision;       /* TN_FP64 / TN_FP32 / TN_BF16X3 */
   int32_t lbo;             /* 0 / 1 */
   int32_t compute_energy;  /* 0 / 1: FP64 <H> after the sweep */
+  int32_t lbo_matvecs;     /* per LBO raw single-site solve; 0 = max_matvecs */
 } tn_sweep_opts;
 
 typedef struct {

@@ -41,7 +41,7 @@ class tn_problem(C.Structure):
 class tn_sweep_opts(C.Structure):
     _fields_ = [("chi_max", C.c_int32), ("sigma_cut", C.c_double), ("tol", C.c_double),
                 ("krylov_max", C.c_int32), ("max_matvecs", C.c_int32), ("precision", C.c_int32),
-                ("lbo", C.c_int32), ("compute_energy", C.c_int32)]
+                ("lbo", C.c_int32), ("compute_energy", C.c_int32), ("lbo_matvecs", C.c_int32)]
 
 
 class tn_sweep_stats(C.Structure):

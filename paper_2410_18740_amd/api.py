@@ -213,10 +213,11 @@ class SweepOpts:
     precision: int = FP64
     lbo: int = 0
     compute_energy: int = 1
+    lbo_matvecs: int = 0
 
     def c(self):
         return L.tn_sweep_opts(self.chi_max, self.sigma_cut, self.tol, self.krylov_max,
-                               self.max_matvecs, self.precision, self.lbo, self.compute_energy)
+                               self.max_matvecs, self.precision, self.lbo, self.compute_energy, self.lbo_matvecs)
 
 
 def dmrg_sweep(ctx: Context, mpo: MPO, mps: MPS, opts: SweepOpts) -> dict:

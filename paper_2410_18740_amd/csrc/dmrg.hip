@@ -520,7 +520,7 @@ static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_
   op.setup(c, mpo, s, 1, prec, cl, cr, env_ptrs(m, mpo, true, s, prec), env_ptrs(m, mpo, false, s + 1, prec), true,
            "lbo");
   LzResult lz = lanczos(c, [&](const cf64* x, cf64* y) { op.apply(x, y); }, B, (int64_t)nraw, o.tol, o.krylov_max,
-                        o.max_matvecs);
+                        o.lbo_matvecs > 0 ? o.lbo_matvecs : o.max_matvecs);
   if (mv) *mv += lz.matvecs;
   // rho = sum_a B[a] B[a]^dag (D x D): split over a into partial products,
   // then a fixed-order reduction
@@ -701,6 +701,7 @@ static void check_opts(const tn_sweep_opts* o) {
   if (!(o->tol > 0.0)) TN_THROW(TN_EINVAL, "tol must be positive");
   if (o->krylov_max < 2 || o->krylov_max > 64) TN_THROW(TN_EINVAL, "krylov_max must be in [2, 64]");
   if (o->max_matvecs < 1) TN_THROW(TN_EINVAL, "max_matvecs must be >= 1");
+  if (o->lbo_matvecs < 0) TN_THROW(TN_EINVAL, "lbo_matvecs must be >= 0");
   if (o->precision < 0 || o->precision > 2) TN_THROW(TN_EINVAL, "unknown precision");
   if (!(o->sigma_cut >= 0.0) || o->sigma_cut >= 1.0) TN_THROW(TN_EINVAL, "sigma_cut must be in [0, 1)");
 }
