@@ -383,16 +383,21 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
   __shared__ int piv[80];
   __shared__ double lam_s;
   const int lane = threadIdx.x;
-  if (lane == 0) {
-    const double a = h1[j].x + h2[j].x;
-    double w2 = h2[j + 1].x;
-    for (int i = 0; i <= j; ++i) w2 -= h2[i].x * h2[i].x + h2[i].y * h2[i].y;
-    const double b = sqrt(fmax(w2, 0.0));
-    alpha[j] = a;
-    beta[j] = b;
-    inv[0] = (b > 0.0) ? 1.0 / b : 0.0;
-    out[0] = a;
-    out[1] = b;
+  {
+    // ||w||^2 after the second pass = <w, w> - sum_i |h2_i|^2 (lanes in parallel)
+    double part = 0.0;
+    for (int i = lane; i <= j; i += 64) part += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+    const double sum = wave_sum(part);
+    if (lane == 0) {
+      const double a = h1[j].x + h2[j].x;
+      const double w2 = h2[j + 1].x - sum;
+      const double b = sqrt(fmax(w2, 0.0));
+      alpha[j] = a;
+      beta[j] = b;
+      inv[0] = (b > 0.0) ? 1.0 / b : 0.0;
+      out[0] = a;
+      out[1] = b;
+    }
   }
   __syncthreads();
   const int n = j + 1;
@@ -436,7 +441,7 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
     const double lam = 0.5 * (lo + hi);
     lam_s = lam;
     const double tiny = fmax(2.2e-16 * sc, 1e-300);
-    // LU with partial pivoting of T - lam I
+    // LU with partial pivoting of T - lam I, the running entries in registers
     for (int i = 0; i < n; ++i) {
       dd[i] = sa[i] - lam;
       du[i] = (i < n - 1) ? sb[i] : 0.0;
@@ -444,34 +449,56 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
       du2[i] = 0.0;
       piv[i] = 0;
     }
-    for (int i = 0; i < n - 1; ++i) {
-      if (fabs(dd[i]) >= fabs(dl[i])) {
-        if (dd[i] == 0.0) dd[i] = tiny;
-        const double f = dl[i] / dd[i];
-        dl[i] = f;
-        dd[i + 1] -= f * du[i];
-      } else {
-        const double f = dd[i] / dl[i];
-        dd[i] = dl[i];
-        dl[i] = f;
-        const double t = du[i];
-        du[i] = dd[i + 1];
-        dd[i + 1] = t - f * dd[i + 1];
-        if (i < n - 2) { du2[i] = du[i + 1]; du[i + 1] = -f * du[i + 1]; }
-        piv[i] = 1;
+    {
+      double cdd = dd[0], cdu = du[0];
+      for (int i = 0; i < n - 1; ++i) {
+        const double l = dl[i], ndd = dd[i + 1], ndu = du[i + 1];
+        if (fabs(cdd) >= fabs(l)) {
+          if (cdd == 0.0) cdd = tiny;
+          const double f = l / cdd;
+          dd[i] = cdd;
+          dl[i] = f;
+          du[i] = cdu;
+          cdd = ndd - f * cdu;
+          cdu = ndu;
+        } else {
+          const double f = cdd / l;
+          dd[i] = l;
+          dl[i] = f;
+          du[i] = ndd;
+          piv[i] = 1;
+          cdd = cdu - f * ndd;
+          if (i < n - 2) { du2[i] = ndu; cdu = -f * ndu; }
+          else cdu = ndu;
+        }
       }
+      dd[n - 1] = cdd;
     }
     for (int i = 0; i < n; ++i)
       if (fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
     for (int i = 0; i < n; ++i) y[i] = 1.0;
     for (int it = 0; it < 3; ++it) {
+      double cb = y[0];
       for (int i = 0; i < n - 1; ++i) {
-        if (piv[i]) { const double t = y[i]; y[i] = y[i + 1]; y[i + 1] = t - dl[i] * y[i]; }
-        else y[i + 1] -= dl[i] * y[i];
+        const double nb = y[i + 1], l = dl[i];
+        if (piv[i]) { y[i] = nb; cb = cb - l * nb; }
+        else { y[i] = cb; cb = nb - l * cb; }
       }
-      y[n - 1] /= dd[n - 1];
-      if (n >= 2) y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) / dd[n - 2];
-      for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / dd[i];
+      double x1 = cb / dd[n - 1];
+      y[n - 1] = x1;
+      double x2 = 0.0;
+      if (n >= 2) {
+        const double x0 = (y[n - 2] - du[n - 2] * x1) / dd[n - 2];
+        y[n - 2] = x0;
+        x2 = x1;
+        x1 = x0;
+      }
+      for (int i = n - 3; i >= 0; --i) {
+        const double x0 = (y[i] - du[i] * x1 - du2[i] * x2) / dd[i];
+        y[i] = x0;
+        x2 = x1;
+        x1 = x0;
+      }
       double nr = 0.0;
       for (int i = 0; i < n; ++i) nr += y[i] * y[i];
       nr = 1.0 / sqrt(nr);
