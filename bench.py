@@ -63,7 +63,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, r, U, budget_s=20.0):
+def cpu_baseline(w, r, U, budget_s=15.0):
     """The FP64 oracle's two-site matvec on the middle window of the same
     workload, timed on the host cores."""
     from oracle import gbs, operators, mpo as omp, dmrg as odmrg, flops as oflops
@@ -93,7 +93,7 @@ def cpu_baseline(w, r, U, budget_s=20.0):
     while True:
         odmrg.heff_matvec(Le, Ws[site], Ws[site + 1], Re, th)
         n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 8:
+        if time.perf_counter() - t0 > budget_s or n >= 40:
             break
     dt = time.perf_counter() - t0
     return {"value": fl * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
