@@ -141,6 +141,10 @@ hipError_t launch_multidot_finish(const cf64* partials, int nv, int nblocks, cf6
 hipError_t launch_multiaxpy(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, double sign, int64_t n,
                             hipStream_t st);
 hipError_t launch_scale(cf64* dst, const cf64* src, const double* inv_norm_dev, int64_t n, hipStream_t st);
+hipError_t launch_axpy_dot(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, int64_t n, cf64* partials,
+                           int nblocks, hipStream_t st);
+hipError_t launch_axpy_scale(cf64* dst, const cf64* w, const cf64* const* vs, int nv, const cf64* coefs,
+                             const double* inv, int64_t n, hipStream_t st);
 hipError_t launch_lincomb(cf64* dst, const cf64* const* vs, int nv, const double* coefs_dev, int64_t n,
                           hipStream_t st);
 int multidot_blocks(int64_t n);

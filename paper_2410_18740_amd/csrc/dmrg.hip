@@ -82,9 +82,8 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
   const int nb = multidot_blocks(n);
   cf64* V = wsT<cf64>(c, "lz:V", (size_t)(kmax + 1) * n);
   cf64* W = wsT<cf64>(c, "lz:W", (size_t)n);
-  // pointer tables: ptrs = [V_0..V_kmax]; tabW[j] = [V_0..V_j, W]
+  // pointer table ptrs = [V_0..V_kmax]
   const cf64** ptrs = wsT<const cf64*>(c, "lz:ptr", kmax + 1);
-  const cf64** tabW = wsT<const cf64*>(c, "lz:tabW", (size_t)kmax * (kmax + 2));
   cf64* part = wsT<cf64>(c, "lz:part", (size_t)nb * (kmax + 2));
   cf64* h1 = wsT<cf64>(c, "lz:h1", kmax + 2);
   cf64* h2 = wsT<cf64>(c, "lz:h2", kmax + 2);
@@ -96,13 +95,7 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
   {
     std::vector<const cf64*> hp(kmax + 1);
     for (int i = 0; i <= kmax; ++i) hp[i] = V + (size_t)i * n;
-    std::vector<const cf64*> ht((size_t)kmax * (kmax + 2));
-    for (int j = 0; j < kmax; ++j) {
-      for (int i = 0; i <= j; ++i) ht[(size_t)j * (kmax + 2) + i] = V + (size_t)i * n;
-      ht[(size_t)j * (kmax + 2) + j + 1] = W;
-    }
     HIPCHK(hipMemcpyAsync(ptrs, hp.data(), hp.size() * sizeof(cf64*), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(tabW, ht.data(), ht.size() * sizeof(cf64*), hipMemcpyHostToDevice, st));
   }
   double nx = dev_norm2(c, x, n);
   if (!(nx > 0.0) || !std::isfinite(nx)) TN_THROW(TN_ENUMERIC, "Lanczos start vector is zero or non-finite");
@@ -122,11 +115,9 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
       // also returns <w, w>, from which ||w|| after the pass follows
       HIPCHK(launch_multidot(ptrs, j + 1, W, n, part, nb, st));
       HIPCHK(launch_multidot_finish(part, j + 1, nb, h1, st));
-      HIPCHK(launch_multiaxpy(W, ptrs, j + 1, h1, 1.0, n, st));
-      const cf64* const* tw = tabW + (size_t)j * (kmax + 2);
-      HIPCHK(launch_multidot(tw, j + 2, W, n, part, nb, st));
+      // first update fused with the second pass's dot products and <w, w>
+      HIPCHK(launch_axpy_dot(W, ptrs, j + 1, h1, n, part, nb, st));
       HIPCHK(launch_multidot_finish(part, j + 2, nb, h2, st));
-      HIPCHK(launch_multiaxpy(W, ptrs, j + 1, h2, 1.0, n, st));
       HIPCHK(launch_lanczos_step(h1, h2, j, alpha, beta, inv, coefs, sc, st));
       HIPCHK(hipMemcpyAsync(hout, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -141,7 +132,8 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
       const double bscale = std::max(1.0, std::fabs(lam));
       if (res <= tol || b <= 1e-14 * bscale) { R.converged = true; stop = true; break; }
       if (R.matvecs >= max_mv) { stop = true; break; }
-      if (j + 1 < kmax) HIPCHK(launch_scale(V + (size_t)(j + 1) * n, W, inv, n, st));
+      // second update fused with the normalisation: V_{j+1} = (w - sum h2 V) / beta
+      if (j + 1 < kmax) HIPCHK(launch_axpy_scale(V + (size_t)(j + 1) * n, W, ptrs, j + 1, h2, inv, n, st));
     }
     // Ritz vector x = sum_i y_i V_i
     HIPCHK(launch_lincomb(x, ptrs, jlast + 1, coefs, n, st));

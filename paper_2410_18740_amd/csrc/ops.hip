@@ -267,6 +267,106 @@ hipError_t launch_multiaxpy(cf64* w, const cf64* const* vs, int nv, const cf64* 
   return hipGetLastError();
 }
 
+// Fused first update and second-pass dot products of classical Gram-Schmidt:
+//   w <- w - sum_v coefs[v] vs[v];  partials[v][block] = <vs[v], w> (v < nv),
+//   partials[nv][block] = <w, w>.
+// Each chunk of 256 elements is updated (one element per thread), staged in
+// LDS, and then dotted with every vs[v] by the wavefront that owns v (v = wave
+// mod 4): the vs[v] reads of the dot pass hit the cache lines the update just
+// brought in, so the basis makes one trip from memory instead of two.
+#define AD_MAXV 72
+#define AD_PER_WAVE (AD_MAXV / 4)
+__global__ __launch_bounds__(256) void axpy_dot_kernel(cf64* __restrict__ w, const cf64* const* __restrict__ vs, int nv,
+                                                       const cf64* __restrict__ coefs, int64_t n,
+                                                       cf64* __restrict__ partials, int nblocks) {
+  __shared__ cf64 cS[AD_MAXV];
+  __shared__ cf64 accS[256];
+  __shared__ double redw[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int v = tid; v < nv; v += 256) cS[v] = coefs[v];
+  const int64_t per = (n + nblocks - 1) / nblocks;
+  const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min(n, e0 + per);
+  double pr[AD_PER_WAVE], pi[AD_PER_WAVE];
+#pragma unroll
+  for (int q = 0; q < AD_PER_WAVE; ++q) { pr[q] = 0.0; pi[q] = 0.0; }
+  double ww = 0.0;
+  __syncthreads();
+  for (int64_t c0 = e0; c0 < e1; c0 += 256) {
+    const int64_t e = c0 + tid;
+    cf64 acc = czero<cf64>();
+    if (e < e1) {
+      acc = w[e];
+      for (int v = 0; v < nv; ++v) {
+        const cf64 cc = cS[v];
+        const cf64 x = vs[v][e];
+        acc.x -= cc.x * x.x - cc.y * x.y;
+        acc.y -= cc.x * x.y + cc.y * x.x;
+      }
+      w[e] = acc;
+      ww += acc.x * acc.x + acc.y * acc.y;
+    }
+    accS[tid] = acc;
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(256, e1 - c0);
+#pragma unroll
+    for (int q = 0; q < AD_PER_WAVE; ++q) {
+      const int v = wave + 4 * q;
+      if (v < nv) {
+        const cf64* x = vs[v] + c0;
+        for (int t = lane; t < cnt; t += 64) {
+          const cf64 a = x[t], b = accS[t];
+          pr[q] += a.x * b.x + a.y * b.y;
+          pi[q] += a.x * b.y - a.y * b.x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < AD_PER_WAVE; ++q) {
+    const int v = wave + 4 * q;
+    if (v < nv) {
+      const double r = wave_sum(pr[q]), m = wave_sum(pi[q]);
+      if (lane == 0) partials[(int64_t)v * nblocks + blockIdx.x] = make_double2(r, m);
+    }
+  }
+  ww = wave_sum(ww);
+  if (lane == 0) redw[0][wave] = ww;
+  __syncthreads();
+  if (tid == 0)
+    partials[(int64_t)nv * nblocks + blockIdx.x] = make_double2(redw[0][0] + redw[0][1] + redw[0][2] + redw[0][3], 0.0);
+}
+hipError_t launch_axpy_dot(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, int64_t n, cf64* partials,
+                           int nblocks, hipStream_t st) {
+  if (nv < 0 || nv > AD_MAXV || n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(axpy_dot_kernel, dim3(nblocks), dim3(256), 0, st, w, vs, nv, coefs, n, partials, nblocks);
+  return hipGetLastError();
+}
+
+// dst = (w - sum_v coefs[v] vs[v]) * inv[0]: the second update fused with the
+// normalisation into the next Krylov vector
+__global__ void axpy_scale_kernel(cf64* __restrict__ dst, const cf64* __restrict__ w,
+                                  const cf64* const* __restrict__ vs, int nv, const cf64* __restrict__ coefs,
+                                  const double* __restrict__ inv, int64_t n) {
+  const double f = inv[0];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    cf64 acc = w[e];
+    for (int v = 0; v < nv; ++v) {
+      const cf64 c = coefs[v];
+      const cf64 x = vs[v][e];
+      acc.x -= c.x * x.x - c.y * x.y;
+      acc.y -= c.x * x.y + c.y * x.x;
+    }
+    dst[e] = make_double2(acc.x * f, acc.y * f);
+  }
+}
+hipError_t launch_axpy_scale(cf64* dst, const cf64* w, const cf64* const* vs, int nv, const cf64* coefs,
+                             const double* inv, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_scale_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, w, vs, nv, coefs, inv, n);
+  return hipGetLastError();
+}
+
 // dst = src * inv_norm[0]
 __global__ void scale_kernel(cf64* dst, const cf64* src, const double* s, int64_t n) {
   const double f = s[0];
