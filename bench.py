@@ -140,11 +140,12 @@ def gemm_traffic(form, workload):
 TRIDIAG_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "tridiag_col_gbs_n32_chi128_traffic.md")
 
 
-def tridiag_traffic():
+def tridiag_traffic(form, workload):
     """HBM bytes per launch of tridiag_col from the committed --pmc summary, or
-    None when absent or when eig.hip has changed since the counters were taken."""
+    None when it does not cover this form and workload, or when eig.hip has
+    changed since the counters were taken."""
     import hashlib
-    if not os.path.exists(TRIDIAG_TRAFFIC_SUMMARY):
+    if form != "fp32" or workload != "gbs_n32_d16to8_chi128" or not os.path.exists(TRIDIAG_TRAFFIC_SUMMARY):
         return None
     vals = {}
     for line in open(TRIDIAG_TRAFFIC_SUMMARY):
@@ -531,7 +532,7 @@ def main():
     # dispatch gaps included in the per-launch average)
     tri_total_ms = pr["ms_tridiag"]
     roof_tri = {"bound": "hbm", "achieved": tri_gbs, "peak": 8000.0, "unit": "GB/s", "frac": tri_gbs / 8000.0,
-                "traffic": tridiag_traffic(), "kernel": "tridiag_col (one Householder column of the truncation's "
+                "traffic": tridiag_traffic(a.form, a.workload), "kernel": "tridiag_col (one Householder column of the truncation's "
                 "Gram matrix, one launch per column: bound by launch latency)",
                 "avg_launch_us": tri_avg_s * 1e6, "algorithmic_bytes_per_launch": tri_bytes,
                 "launches": int(pr["tridiag_launches"]), "total_ms": tri_total_ms}
