@@ -53,8 +53,8 @@ def parse():
     ap.add_argument("--eval-instances", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--data-sweeps", type=int, default=4)
-    ap.add_argument("--family", default="cfg3", choices=["cfg3", "basis", "mesh"],
-                    help="cfg3: N~U{8..16}, cutoff 10, basis 8, chi 48, r~U[0.3,1.2] for training; N=20, cutoff 12, "
+    ap.add_argument("--family", default="haar", choices=["haar", "basis", "mesh"],
+                    help="haar: N~U{8..16}, cutoff 10, basis 8, chi 48, r~U[0.3,1.2] for training; N=20, cutoff 12, "
                          "chi 64 for evaluation.  basis: strongly squeezed modes (r~U[1.0,1.5]), cutoff 16 "
                          "compressed to a 4-dim local basis, chi 32, N~U{6..14} / N=12.  mesh: weakly squeezed "
                          "brickwork meshes (r~U[0.1,0.2], 4 layers), cutoff 16 compressed to 8, chi 32, "
@@ -298,7 +298,7 @@ def warmstart_eval(a):
     import paper_2410_18740_amd as P
     from paper_2410_18740_amd import warmstart as WS
     import workloads as W
-    fam = {"cfg3": dict(n_lo=8, n_hi=16, D=10, d=8, chi=48, r=(0.3, 1.2), eN=20, eD=12, ed=8, echi=64),
+    fam = {"haar": dict(n_lo=8, n_hi=16, D=10, d=8, chi=48, r=(0.3, 1.2), eN=20, eD=12, ed=8, echi=64),
            "basis": dict(n_lo=6, n_hi=14, D=16, d=4, chi=32, r=(1.0, 1.5), eN=12, eD=16, ed=4, echi=32)}[a.family]
     ctx = P.Context(0)
     t0 = time.perf_counter()

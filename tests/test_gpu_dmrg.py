@@ -20,7 +20,7 @@ def ctx():
 
 
 @pytest.fixture(scope="module")
-def cfg0():
+def four_mode():
     w, r, U = problem("gbs_n4_d6_chi16")
     Ws = oracle_cores(r, U, 6)
     m0 = W.random_mps(4, 6, 16, w.mps_seed)
@@ -43,58 +43,58 @@ def _run(ctx, cfg, chi, sweeps, prec_schedule, tol=1e-12):
     return m, mp, stats
 
 
-def test_dmrg_fp64_matches_oracle(ctx, cfg0):
-    m, mp, stats = _run(ctx, cfg0, 16, 6, lambda s: 0)
+def test_dmrg_fp64_matches_oracle(ctx, four_mode):
+    m, mp, stats = _run(ctx, four_mode, 16, 6, lambda s: 0)
     E = stats[-1]["energy"]
-    print("GPU E", E, "oracle E", cfg0["st"][-1]["energy"], "ED", cfg0["E_ed"])
-    assert abs(E - cfg0["st"][-1]["energy"]) < 1e-10
-    assert E >= cfg0["E_ed"] - 1e-12
+    print("GPU E", E, "oracle E", four_mode["st"][-1]["energy"], "ED", four_mode["E_ed"])
+    assert abs(E - four_mode["st"][-1]["energy"]) < 1e-10
+    assert E >= four_mode["E_ed"] - 1e-12
     assert stats[-1]["unconverged_steps"] == 0
     t = mp.export()
     P_gpu = omps.probabilities(t)
-    P_ref = omps.probabilities(cfg0["ref"])
+    P_ref = omps.probabilities(four_mode["ref"])
     assert np.abs(P_gpu - P_ref).max() < 1e-8
-    assert abs(stats[-1]["max_discarded"] - cfg0["st"][-1]["max_discarded"]) < 1e-10
+    assert abs(stats[-1]["max_discarded"] - four_mode["st"][-1]["max_discarded"]) < 1e-10
 
 
-def test_dmrg_full_rank_matches_ed(ctx, cfg0):
-    m, mp, stats = _run(ctx, cfg0, 36, 3, lambda s: 0)
-    assert abs(stats[-1]["energy"] - cfg0["E_ed"]) < 1e-10
+def test_dmrg_full_rank_matches_ed(ctx, four_mode):
+    m, mp, stats = _run(ctx, four_mode, 36, 3, lambda s: 0)
+    assert abs(stats[-1]["energy"] - four_mode["E_ed"]) < 1e-10
     P_gpu = omps.probabilities(mp.export())
-    assert np.abs(P_gpu - np.abs(cfg0["gs"]) ** 2).max() < 1e-8
+    assert np.abs(P_gpu - np.abs(four_mode["gs"]) ** 2).max() < 1e-8
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-def test_fast_form_then_fp64_refine(ctx, cfg0, prec):
+def test_fast_form_then_fp64_refine(ctx, four_mode, prec):
     """Bulk sweeps in FP32 / BF16x3, then FP64 refinement sweeps reach the FP64
     result to 1e-10."""
-    m, mp, stats = _run(ctx, cfg0, 16, 6, lambda s: prec if s < 3 else 0)
-    assert abs(stats[-1]["energy"] - cfg0["st"][-1]["energy"]) < 1e-10
+    m, mp, stats = _run(ctx, four_mode, 16, 6, lambda s: prec if s < 3 else 0)
+    assert abs(stats[-1]["energy"] - four_mode["st"][-1]["energy"]) < 1e-10
 
 
-def test_marginals_match_oracle(ctx, cfg0):
+def test_marginals_match_oracle(ctx, four_mode):
     import paper_2410_18740_amd as P
-    m, mp, stats = _run(ctx, cfg0, 16, 6, lambda s: 0)
+    m, mp, stats = _run(ctx, four_mode, 16, 6, lambda s: 0)
     marg = P.marginals(ctx, mp, m)
     ref = omps.marginals(mp.export())
     assert np.abs(marg - ref).max() < 1e-12
-    ref2 = omps.marginals(cfg0["ref"])
+    ref2 = omps.marginals(four_mode["ref"])
     assert np.abs(marg - ref2).max() < 1e-8
 
 
-def test_energy_entry_point_matches_sweep(ctx, cfg0):
+def test_energy_entry_point_matches_sweep(ctx, four_mode):
     import paper_2410_18740_amd as P
-    m, mp, stats = _run(ctx, cfg0, 16, 2, lambda s: 0)
+    m, mp, stats = _run(ctx, four_mode, 16, 2, lambda s: 0)
     e, n = P.energy(ctx, m, mp)
     assert abs(e - stats[-1]["energy"]) < 1e-13
     assert abs(n - 1.0) < 1e-12
-    assert abs(e - odmrg.energy(mp.export(), cfg0["Ws"])) < 1e-12
+    assert abs(e - odmrg.energy(mp.export(), four_mode["Ws"])) < 1e-12
 
 
-def test_sampler_matches_oracle_stream(ctx, cfg0):
+def test_sampler_matches_oracle_stream(ctx, four_mode):
     import paper_2410_18740_amd as P
     from oracle import sampler
-    m, mp, stats = _run(ctx, cfg0, 16, 4, lambda s: 0)
+    m, mp, stats = _run(ctx, four_mode, 16, 4, lambda s: 0)
     t = mp.export()
     smp = P.sample(ctx, mp, m, 400, 2004).cpu().numpy()
     ref = sampler.sample(t, 400, 2004)
