@@ -64,6 +64,19 @@ def targets_from_moments(n, m):
     return np.array([zeta.real, zeta.imag, math.log1p(max(nbar, 0.0))])
 
 
+def gaussian_params(V, j):
+    """(Re zeta, Im zeta, log(1 + nbar)) of output mode j read off the reduced
+    covariance V_j (2 x 2 block of V in xxpp order): <a^dag a> =
+    (Vxx + Vpp)/2 - 1/2 and <a^2> = (Vxx - Vpp + 2i Vxp)/2 for a = (X + iP)/sqrt 2;
+    the reduced state is exactly the squeezed thermal state with these moments
+    (eq. diagReducedGaussianDM, eq. OLB)."""
+    N = V.shape[0] // 2
+    vxx, vpp, vxp = V[j, j], V[N + j, N + j], V[j, N + j]
+    n = 0.5 * (vxx + vpp) - 0.5
+    m = 0.5 * (vxx - vpp) + 1j * vxp
+    return targets_from_moments(n, m)
+
+
 def squeezed_basis(zeta, D, d, margin=64):
     """W (D x d): first d columns of <n|S(zeta)|k>, built on a (D + margin) box,
     cut to D rows, orthonormalised column by column."""

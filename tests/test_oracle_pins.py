@@ -532,3 +532,24 @@ def test_reduced_state_depends_on_doubled_angle_only():
     assert np.abs(gbs.covariance(r, U) - gbs.covariance(r, U2)).max() < 1e-13
     for j in range(7):
         assert np.abs(mlp.features(r, U, j) - mlp.features(r, U2, j)).max() < 1e-13
+
+
+def test_gaussian_params_reproduce_the_exact_reduced_state():
+    """The squeezed thermal state built from a mode's reduced covariance equals
+    that mode's reduced density matrix of the exact GBS state (dense, large
+    cutoff), and its spectrum is the Williamson one (eq. diagReducedGaussianDM)."""
+    from oracle import mlp, lbo
+    r, U = W.make_problem(3, 8, (0.3, 0.6))
+    V = gbs.covariance(r, U)
+    D = 16
+    psi = gbs.exact_amplitudes(r, U, D)
+    psi = psi / np.linalg.norm(psi)
+    for j in range(3):
+        y = mlp.gaussian_params(V, j)
+        zeta, nbar = y[0] + 1j * y[1], math.expm1(y[2])
+        Wb = mlp.squeezed_basis(zeta, 60, 40)
+        lam = np.array([nbar ** k / (nbar + 1) ** (k + 1) for k in range(40)])
+        rho_model = ((Wb * lam) @ Wb.conj().T)[:D, :D]
+        rho = lbo.rdm_from_dense(psi, j)
+        assert np.abs(rho - rho_model).max() < 1e-6
+        assert np.abs(lam[:6] - lbo.gaussian_rdm_spectrum(V, j, 6)).max() < 1e-12
