@@ -276,6 +276,12 @@ tn_status tn_squeezed_basis(double zeta_re, double zeta_im, int32_t D, int32_t d
  * complex interleaved; with tensors NULL only *need is set. */
 tn_status tn_ws_features(int32_t N, const double* r, const double* U, float* out);
 tn_status tn_ws_targets(int32_t n_modes, int32_t D, const double* rho, float* out);
+/* The same (Re zeta, Im zeta, log(1 + nbar)) read off each output mode's
+ * reduced covariance (the 2 x 2 block of V = 1/2 O D^2 O^T, Sec. II.C.1): for
+ * a Gaussian state the reduced state is exactly squeezed thermal, so these are
+ * the optimal local basis (eq. OLB, eq. WilliamsonDecomposition) and the
+ * network's ceiling.  out: host float [N][3]; U as in tn_ws_features. */
+tn_status tn_ws_gaussian_params(int32_t N, const double* r, const double* U, float* out);
 tn_status tn_ws_initial_state(int32_t N, int32_t D, int32_t d, int32_t chi, const float* y, uint64_t seed,
                               double noise, double* iso, int32_t* dims, double* tensors, size_t cap, size_t* need);
 

@@ -447,6 +447,17 @@ def ws_targets(rho):
     return out
 
 
+def ws_gaussian_params(r, U):
+    """Analytic local-basis parameters [N][3] from each mode's reduced covariance."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    Uf = np.ascontiguousarray(U, dtype=np.complex128).view(np.float64)
+    out = np.zeros((len(r), 3), dtype=np.float32)
+    st = L.lib().tn_ws_gaussian_params(len(r), L.dptr(r), L.dptr(Uf), L.dptr(out, C.c_float))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_ws_gaussian_params: bad arguments")
+    return out
+
+
 def ws_initial_state(y, D: int, d: int, chi: int, seed: int, noise: float = 1e-3):
     """(isometries [N][D][d], site tensors) of the learned warm start."""
     y = np.ascontiguousarray(y, dtype=np.float32)

@@ -490,6 +490,17 @@ extern "C" tn_status tn_ws_features(int32_t N, const double* r, const double* U,
 // and m = <a^2>, a squeezed thermal state S(zeta) tau S(zeta)^dag has
 // (2 nbar + 1)^2 = (2n + 1)^2 - 4|m|^2, tanh(2|zeta|) = 2|m| / (2n + 1) and
 // zeta / |zeta| = -m / |m|.  out[j] = (Re zeta, Im zeta, log(1 + nbar)).
+static void moments_to_params(double n, cd m, float* out) {
+  const double s = 2 * n + 1, am = std::abs(m);
+  const double nu2 = std::max(s * s - 4 * am * am, 1.0);
+  const double nbar = 0.5 * (std::sqrt(nu2) - 1.0);
+  const double rr = am > 0 ? 0.5 * std::atanh(std::min(2 * am / s, 1 - 1e-15)) : 0.0;
+  const cd ph = am > 0 ? -m / am : cd(1.0, 0.0);
+  out[0] = (float)(rr * ph.real());
+  out[1] = (float)(rr * ph.imag());
+  out[2] = (float)std::log1p(std::max(nbar, 0.0));
+}
+
 extern "C" tn_status tn_ws_targets(int32_t n_modes, int32_t D, const double* rho, float* out) {
   if (n_modes < 1 || D < 1 || !rho || !out) return TN_EINVAL;
   for (int j = 0; j < n_modes; ++j) {
@@ -502,14 +513,34 @@ extern "C" tn_status tn_ws_targets(int32_t n_modes, int32_t D, const double* rho
       m += cd(R[2 * e], R[2 * e + 1]) * std::sqrt((double)k * (k - 1));
     }
     if (!std::isfinite(n) || !std::isfinite(std::abs(m))) return TN_ENUMERIC;
-    const double s = 2 * n + 1, am = std::abs(m);
-    const double nu2 = std::max(s * s - 4 * am * am, 1.0);
-    const double nbar = 0.5 * (std::sqrt(nu2) - 1.0);
-    const double rr = am > 0 ? 0.5 * std::atanh(std::min(2 * am / s, 1 - 1e-15)) : 0.0;
-    const cd ph = am > 0 ? -m / am : cd(1.0, 0.0);
-    out[3 * j + 0] = (float)(rr * ph.real());
-    out[3 * j + 1] = (float)(rr * ph.imag());
-    out[3 * j + 2] = (float)std::log1p(std::max(nbar, 0.0));
+    moments_to_params(n, m, out + 3 * j);
+  }
+  return TN_OK;
+}
+
+// Analytic parameters of each output mode's reduced Gaussian state: the 2 x 2
+// block of V = 1/2 O D^2 O^T (Sec. II.C.1) for mode j,
+//   Vxx = 1/2 sum_k (Re U_jk^2 e^{-2 r_k} + Im U_jk^2 e^{2 r_k}),
+//   Vpp = 1/2 sum_k (Im U_jk^2 e^{-2 r_k} + Re U_jk^2 e^{2 r_k}),
+//   Vxp = 1/2 sum_k Re U_jk Im U_jk (e^{-2 r_k} - e^{2 r_k}),
+// gives <a^dag a> = (Vxx + Vpp)/2 - 1/2 and <a^2> = (Vxx - Vpp)/2 + i Vxp; the
+// reduced state is exactly the squeezed thermal state with these moments, so
+// its squeezed basis is the optimal local basis (eq. OLB).
+extern "C" tn_status tn_ws_gaussian_params(int32_t N, const double* r, const double* U, float* out) {
+  if (N < 1 || N > 4096 || !r || !U || !out) return TN_EINVAL;
+  for (int k = 0; k < N; ++k)
+    if (!std::isfinite(r[k])) return TN_EINVAL;
+  for (int j = 0; j < N; ++j) {
+    double vxx = 0.0, vpp = 0.0, vxp = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double re = U[2 * ((size_t)j * N + k)], im = U[2 * ((size_t)j * N + k) + 1];
+      if (!std::isfinite(re) || !std::isfinite(im)) return TN_EINVAL;
+      const double em = std::exp(-2.0 * r[k]), ep = std::exp(2.0 * r[k]);
+      vxx += 0.5 * (re * re * em + im * im * ep);
+      vpp += 0.5 * (im * im * em + re * re * ep);
+      vxp += 0.5 * re * im * (em - ep);
+    }
+    moments_to_params(0.5 * (vxx + vpp) - 0.5, cd(0.5 * (vxx - vpp), vxp), out + 3 * j);
   }
   return TN_OK;
 }

@@ -74,3 +74,15 @@ def test_ws_initial_state_matches_oracle():
     noise = np.concatenate([(a - b).reshape(-1) for a, b in zip(An, A)])
     assert all(np.array_equal(a, b) for a, b in zip(An, An2))
     assert abs(np.std(noise.real) - 1e-3) < 2e-4 and abs(np.mean(noise.real)) < 2e-4
+
+
+def test_ws_gaussian_params_match_oracle():
+    import paper_2410_18740_amd as P
+    import workloads as W
+    from oracle import gbs
+    for N, seed, kind, rr in ((6, 3, "haar", (0.3, 1.2)), (20, 4, "brickwork", (0.1, 0.2))):
+        r, U = W.make_problem(N, seed, rr, kind=kind)
+        got = P.ws_gaussian_params(r, U)
+        V = gbs.covariance(r, U)
+        ref = np.stack([omlp.gaussian_params(V, j) for j in range(N)])
+        assert np.abs(got - ref).max() < 1e-6
