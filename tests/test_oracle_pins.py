@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import gbs, operators, dense, mpo, mps as M, dmrg, flops
+from oracle import gbs, operators, dense, mpo, mps as M, dmrg, flops, lbo
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -553,3 +553,67 @@ def test_gaussian_params_reproduce_the_exact_reduced_state():
         rho = lbo.rdm_from_dense(psi, j)
         assert np.abs(rho - rho_model).max() < 1e-6
         assert np.abs(lam[:6] - lbo.gaussian_rdm_spectrum(V, j, 6)).max() < 1e-12
+
+
+def test_two_mode_cutoff_error_equals_the_discarded_weight():
+    """A pure two-mode Gaussian state is, in the two optimal local bases, a
+    Schmidt sum over |k>|k> with weights sigma_k^2 (Sec. III.A.1), so keeping d
+    states per mode gives eps_D = eps exactly (the lower bound of eq.
+    SpecWfromSDsums met).  eps_D here is computed by brute force: exact
+    amplitudes on a 40-photon box, each mode's top-d reduced eigenvectors,
+    1 - |projection|^2."""
+    from oracle import cutoff
+    for seed in (1, 2, 3):
+        r, U = W.make_problem(2, seed, (0.4, 0.8))
+        V = gbs.covariance(r, U)
+        psi = gbs.exact_amplitudes(r, U, 40)
+        box_loss = 1.0 - np.linalg.norm(psi) ** 2
+        assert box_loss < 1e-10
+        for d in (2, 4):
+            Ws = []
+            for i in range(2):
+                _, v = np.linalg.eigh(lbo.rdm_from_dense(psi, i))
+                Ws.append(v[:, ::-1][:, :d])
+            eps_D = 1.0 - np.linalg.norm(Ws[0].conj().T @ psi @ Ws[1].conj()) ** 2
+            tails, eps, (lo, hi) = cutoff.eps_bounds(V, d)
+            assert abs(eps_D - eps) < 1e-10 and abs(tails[0] - tails[1]) < 1e-12
+            assert lo == eps and abs(hi - 2 * eps) < 1e-15
+
+
+def test_cutoff_error_bounds_hold_for_three_modes():
+    """eps <= eps_D <= N eps (eq. SpecWfromSDsums) with eps_D by brute force on
+    a 22-photon box for three-mode Haar instances; the ratio eps / eps_D lies
+    strictly inside [1/N, 1] for these generic states, as in Fig. 2."""
+    from oracle import cutoff
+    for seed in (4, 5, 6):
+        r, U = W.make_problem(3, seed, (0.3, 0.6))
+        V = gbs.covariance(r, U)
+        psi = gbs.exact_amplitudes(r, U, 22)
+        assert 1.0 - np.linalg.norm(psi) ** 2 < 1e-8       # far below eps_D (1e-4 .. 1e-2 here)
+        Ws = []
+        for i in range(3):
+            _, v = np.linalg.eigh(lbo.rdm_from_dense(psi, i))
+            Ws.append(v[:, ::-1][:, :3])
+        proj = np.einsum("am,bn,co,abc->mno", Ws[0].conj(), Ws[1].conj(), Ws[2].conj(), psi)
+        eps_D = 1.0 - np.linalg.norm(proj) ** 2
+        _, eps, (lo, hi) = cutoff.eps_bounds(V, 3)
+        assert lo < eps_D < hi
+        assert 1 / 3 < eps / eps_D < 1
+
+
+def test_effective_cutoff_of_the_squeezed_vacuum_closed_form():
+    """With one kept vector the isometry defect at cutoff D is the squeezed
+    vacuum's weight beyond D, sum_{2q >= D} tanh(r)^{2q} (2q)! / (4^q q!^2) /
+    cosh r; the effective cutoff is the first D where that tail is within tol.
+    With r = 0 the squeezed basis is the Fock basis: the effective cutoff is
+    d itself."""
+    from oracle import cutoff
+    for r, tol in ((0.6, 1e-12), (1.1, 1e-10)):
+        t = math.tanh(r)
+        w = [t ** (2 * q) * math.comb(2 * q, q) / 4 ** q / math.cosh(r) for q in range(400)]
+        tail = lambda D: 1.0 - sum(w[q] for q in range(400) if 2 * q < D)
+        D_ref = next(D for D in range(1, 600) if tail(D) <= tol)
+        zeta = r * np.exp(0.7j)
+        assert cutoff.effective_cutoff(zeta, 1, 300, tol) == D_ref
+    for d in (1, 3, 8):
+        assert cutoff.effective_cutoff(0.0, d, 40, 1e-14) == d
