@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--max-sweeps", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB copy before the timed sweeps (PMC counter scaling)")
+    ap.add_argument("--cutoff-report", action="store_true",
+                    help="cutoff errors of the Gaussian optimal basis for every named workload (host only)")
     ap.add_argument("--warmstart", action="store_true",
                     help="learned warm start: generate data with plain DMRG+LBO, train the MLP, evaluate vs plain")
     ap.add_argument("--train-instances", type=int, default=200)
@@ -194,6 +196,7 @@ def to_target(a):
         "forms": {f: {k: v for k, v in o.items()} for f, o in res.items()},
         "speedup_vs_plain_fp64": {f: (base / o["t_target"]) if o["reached"] and res["fp64"]["reached"] else None
                                   for f, o in res.items()},
+        "cutoff": cutoff_summary(r, U, w.d, w.D_raw),
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -257,6 +260,12 @@ def warmstart_mesh(a):
             t_init = time.perf_counter() - tl
             learned = _solve_to(P, ctx, mpo, mps, w.chi, prec, a)
             del mps, mpo
+            tl = time.perf_counter()
+            mpo, mps = WS.analytic_start(ctx, r, U, w.D_raw, w.d, w.chi, seed)
+            torch.cuda.synchronize()
+            t_an = time.perf_counter() - tl
+            analytic = _solve_to(P, ctx, mpo, mps, w.chi, prec, a)
+            del mps, mpo
             e1p, e1l = plain["energy_trace"][0], learned["energy_trace"][0]
             kept = bool(np.isfinite(e1l) and e1l <= e1p)
             if kept:
@@ -266,10 +275,14 @@ def warmstart_mesh(a):
             row[form] = {"plain_t": plain["t_target"] if plain["reached"] else None, "plain_sweeps": plain["sweeps"],
                          "plain_E1": e1p, "learned_t": t_l, "learned_kept": kept,
                          "learned_sweeps": learned["sweeps"], "learned_E1": e1l, "learned_init_s": t_init,
-                         "plain_trace": plain["energy_trace"], "learned_trace": learned["energy_trace"]}
+                         "plain_trace": plain["energy_trace"], "learned_trace": learned["energy_trace"],
+                         "analytic_t": t_an + analytic["t_target"] if analytic["reached"] else None,
+                         "analytic_sweeps": analytic["sweeps"], "analytic_E1": analytic["energy_trace"][0],
+                         "analytic_trace": analytic["energy_trace"]}
             print(f"eval seed {seed} {form}: plain {row[form]['plain_t']} s ({plain['sweeps']} sw, E1 {e1p:.3e}); "
-                  f"learned {t_l} s ({learned['sweeps']} sw, E1 {e1l:.3e}, kept {kept}, init {t_init:.2f} s)",
-                  file=sys.stderr, flush=True)
+                  f"learned {t_l} s ({learned['sweeps']} sw, E1 {e1l:.3e}, kept {kept}, init {t_init:.2f} s); "
+                  f"analytic {row[form]['analytic_t']} s ({analytic['sweeps']} sw, "
+                  f"E1 {row[form]['analytic_E1']:.3e})", file=sys.stderr, flush=True)
         rows.append(row)
 
     def med(form, key):
@@ -279,7 +292,9 @@ def warmstart_mesh(a):
             "data_s": t_data, "train_s": t_train, "epochs": a.epochs, "final_train_loss": losses[-1],
             "val_loss": vloss, "eval_instances": a.eval_instances, "target": 1e-8,
             "median_time_to_target_s": {f"{f}_{k}": med(f, k + "_t") for f in ("fp64", "fp32")
-                                        for k in ("plain", "learned")},
+                                        for k in ("plain", "learned", "analytic")},
+            "median_first_sweep_E": {f"{f}_{k}": float(np.median([r_[f][k + "_E1"] for r_ in rows]))
+                                     for f in ("fp64", "fp32") for k in ("plain", "learned", "analytic")},
             "kept": {f: sum(r_[f]["learned_kept"] for r_ in rows) for f in ("fp64", "fp32")}}
     print(json.dumps(line), flush=True)
     os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
@@ -358,7 +373,16 @@ def warmstart_eval(a):
         row.update({"learned_hybrid_E": traces["learned_hybrid"].energies,
                     "learned_hybrid_s": traces["learned_hybrid"].seconds,
                     "learned_hybrid_used": True, "learned_hybrid_first_E": traces["learned_hybrid"].energies[0]})
-        e_ref = min(traces[f].final for f in ("plain", "learned", "learned_basis", "learned_hybrid"))
+        # the network's ceiling: the same start with the exact Gaussian parameters
+        tp = time.perf_counter()
+        mpo, mps = WS.analytic_start(ctx, r, U, D, d, chi, seed)
+        torch.cuda.synchronize()
+        traces["analytic"] = WS.run_sweeps(ctx, mpo, mps, WS.sweep_opts(chi), a.max_sweeps, conv_tol=1e-10,
+                                           init_seconds=time.perf_counter() - tp)
+        del mps, mpo
+        row.update({"analytic_E": traces["analytic"].energies, "analytic_s": traces["analytic"].seconds,
+                    "analytic_used": True, "analytic_first_E": traces["analytic"].energies[0]})
+        e_ref = min(traces[f].final for f in ("plain", "learned", "learned_basis", "learned_hybrid", "analytic"))
         for name, rel in (("1e-2", 1e-2), ("1e-3", 1e-3), ("1e-4", 1e-4)):
             for form, tr in traces.items():
                 row[f"{form}_{name}"] = tr.time_to(e_ref * (1 + rel))
@@ -366,7 +390,8 @@ def warmstart_eval(a):
         print(f"eval {seed}: E1 plain {plain.energies[0]:.4e} fock-nolbo {traces['fock_nolbo'].energies[0]:.4e} "
               f"learned {row['learned_first_E']:.4e} (kept {row['learned_used']}) learned-basis "
               f"{row['learned_basis_first_E']:.4e} (kept {row['learned_basis_used']}) learned-nolbo "
-              f"{row['learned_nolbo_first_E']:.4e} (kept {row['learned_nolbo_used']}); final "
+              f"{row['learned_nolbo_first_E']:.4e} (kept {row['learned_nolbo_used']}) analytic "
+              f"{row['analytic_first_E']:.4e}; final "
               + " / ".join(f"{k} {t.final:.6e} ({len(t.energies)} sw, {t.init_seconds + t.seconds[-1]:.2f} s)"
                            for k, t in traces.items())
               + f"; to 1e-3: " + " ".join(f"{k} {row[k + '_1e-3']}" for k in traces), file=sys.stderr, flush=True)
@@ -375,7 +400,7 @@ def warmstart_eval(a):
         v = [r_[key][idx] for r_ in rows if r_[key][0] is not None]
         return (float(np.median(v)) if v else None), len(v)
 
-    forms = ("plain", "learned", "learned_basis", "learned_nolbo", "learned_hybrid")
+    forms = ("plain", "learned", "learned_basis", "learned_nolbo", "learned_hybrid", "analytic")
     summary = {}
     for name in ("1e-2", "1e-3", "1e-4"):
         for form in forms:
@@ -386,7 +411,7 @@ def warmstart_eval(a):
                                                          for k, v in fam.items()}, "train_instances": a.train_instances, "train_rows": int(X.shape[0]),
             "data_s": t_data, "train_s": t_train, "epochs": a.epochs, "final_train_loss": losses[-1],
             "val_loss": vloss, "eval_instances": a.eval_instances,
-            "kept": {f: sum(r_[f + "_used"] for r_ in rows) for f in forms[1:-1]},
+            "kept": {f: sum(r_[f + "_used"] for r_ in rows) for f in forms[1:-2]},
             "first_sweep_E_median": {f: float(np.median([r_[f + "_first_E"] if f != "plain" else r_["plain_E"][0]
                                                          for r_ in rows])) for f in forms},
             "final_E_median": {f: float(np.median([r_[f + "_E"][-1] for r_ in rows]))
@@ -449,8 +474,32 @@ def to_target_relative(a):
     ctx.close()
 
 
+def cutoff_summary(r, U, d: int, D_raw: int, tol: float = 1e-12):
+    """eps, its eps_D bounds and the effective cutoffs of the Gaussian optimal
+    basis with d kept states per mode (library host code)."""
+    import paper_2410_18740_amd as P
+    rep = P.cutoff_report(r, U, d, D_max=max(256, 4 * D_raw), tol=tol)
+    de = rep["D_eff"]
+    return {"d": d, "eps": rep["eps"], "eps_D_lower": rep["eps_D_bounds"][0], "eps_D_upper": rep["eps_D_bounds"][1],
+            "eps_mode_max": float(rep["eps_mode"].max()), "tol": tol,
+            "D_eff_min": int(de.min()), "D_eff_median": float(np.median(de)), "D_eff_max": int(de.max()),
+            "modes_within_D_raw": int((de <= D_raw).sum()), "D_raw": D_raw}
+
+
+def cutoff_report_all():
+    import workloads as W
+    out = {}
+    for name, w in W.WORKLOADS.items():
+        r, U = W.workload_problem(name)
+        out[name] = cutoff_summary(r, U, w.d, w.D_raw)
+    print(json.dumps({"mode": "cutoff_report", "basis": "Gaussian optimal (analytic)", "workloads": out}), flush=True)
+
+
 def main():
     a = parse()
+    if a.cutoff_report:
+        cutoff_report_all()
+        return
     if a.warmstart:
         if a.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)

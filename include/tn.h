@@ -282,6 +282,21 @@ tn_status tn_ws_targets(int32_t n_modes, int32_t D, const double* rho, float* ou
  * the optimal local basis (eq. OLB, eq. WilliamsonDecomposition) and the
  * network's ceiling.  out: host float [N][3]; U as in tn_ws_features. */
 tn_status tn_ws_gaussian_params(int32_t N, const double* r, const double* U, float* out);
+/* Cutoff errors of the Gaussian optimal local basis with d kept states per
+ * mode (Sec. II.E.1 eq. epsilonD, Sec. III.A.2 eq. SpecWfromSDsums and eq.
+ * Effectivecutoff).  Host only, no GPU work.  For output mode j of (r, U):
+ *   eps_mode[j] = (nbar_j / (nbar_j + 1))^d, the thermal weight beyond the d
+ *                 kept states, nbar_j = sqrt(det V_j) - 1/2;
+ *   D_eff[j]    = the smallest Fock cutoff D <= D_max at which the first d
+ *                 squeezed basis vectors, cut to D rows, are orthonormal
+ *                 within tol (max |V^dag V - 1|), or -1 if none is;
+ *   bounds[0]   = eps = mean_j eps_mode[j], bounds[1] = N eps: the bounds
+ *                 eps <= eps_D <= N eps on eps_D = 1 - <psi|P|psi>.
+ * Outputs are host arrays of N (eps_mode, D_eff) and 2 (bounds) entries.
+ * TN_EINVAL on N or D_max outside [1, 4096], d > D_max, tol <= 0, NULL
+ * pointers or non-finite inputs. */
+tn_status tn_cutoff_report(int32_t N, const double* r, const double* U, int32_t d, int32_t D_max, double tol,
+                           double* eps_mode, int32_t* D_eff, double* bounds);
 tn_status tn_ws_initial_state(int32_t N, int32_t D, int32_t d, int32_t chi, const float* y, uint64_t seed,
                               double noise, double* iso, int32_t* dims, double* tensors, size_t cap, size_t* need);
 

@@ -130,6 +130,7 @@ def lib():
         "tn_ws_features": (i32, [i32, P(dbl), P(dbl), P(C.c_float)]),
         "tn_ws_targets": (i32, [i32, i32, P(dbl), P(C.c_float)]),
         "tn_ws_gaussian_params": (i32, [i32, P(dbl), P(dbl), P(C.c_float)]),
+        "tn_cutoff_report": (i32, [i32, P(dbl), P(dbl), i32, i32, dbl, P(dbl), P(i32), P(dbl)]),
         "tn_ws_initial_state": (i32, [i32, i32, i32, i32, P(C.c_float), C.c_uint64, dbl, P(dbl), P(i32), P(dbl),
                                       szt, P(szt)]),
     }

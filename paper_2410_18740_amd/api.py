@@ -458,6 +458,22 @@ def ws_gaussian_params(r, U):
     return out
 
 
+def cutoff_report(r, U, d: int, D_max: int = 256, tol: float = 1e-12):
+    """Cutoff errors of the Gaussian optimal basis with d kept states per mode:
+    {"eps_mode": [N], "eps": eps, "eps_D_bounds": (eps, N eps), "D_eff": [N]}."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    Uf = np.ascontiguousarray(U, dtype=np.complex128).view(np.float64)
+    N = len(r)
+    eps = np.zeros(N)
+    deff = np.zeros(N, dtype=np.int32)
+    b = np.zeros(2)
+    st = L.lib().tn_cutoff_report(N, L.dptr(r), L.dptr(Uf), d, D_max, tol, L.dptr(eps), L.dptr(deff, C.c_int32),
+                                  L.dptr(b))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_cutoff_report: bad arguments")
+    return {"eps_mode": eps, "eps": float(b[0]), "eps_D_bounds": (float(b[0]), float(b[1])), "D_eff": deff}
+
+
 def ws_initial_state(y, D: int, d: int, chi: int, seed: int, noise: float = 1e-3):
     """(isometries [N][D][d], site tensors) of the learned warm start."""
     y = np.ascontiguousarray(y, dtype=np.float32)

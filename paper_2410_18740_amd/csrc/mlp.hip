@@ -322,14 +322,11 @@ extern "C" tn_status tn_mlp_train_step(tn_ctx* c, tn_mlp* M, const float* X, con
 // S(zeta) = exp(1/2 (zeta* a^2 - zeta a^dag^2)), built on a (D + margin) box
 // from the squeezed vacuum and S|k> = (a^dag cosh r + e^{-i phi} sinh r a) S|k-1> / sqrt(k),
 // cut to D rows and orthonormalised column by column.
-extern "C" tn_status tn_squeezed_basis(double zeta_re, double zeta_im, int32_t D, int32_t d, int32_t margin,
-                                       double* out) {
-  if (!out || D < 1 || d < 1 || d > D || margin < 0 || D + margin > 4096) return TN_EINVAL;
-  if (!std::isfinite(zeta_re) || !std::isfinite(zeta_im)) return TN_EINVAL;
-  const int Db = D + margin;
-  const double r = std::hypot(zeta_re, zeta_im);
-  if (r > 20.0) return TN_EINVAL;
-  const cd e = r > 0 ? cd(zeta_re / r, zeta_im / r) : cd(1.0, 0.0);
+// Columns k < d of <n|S(zeta)|k> on a box of Db rows; row i of column k is
+// exact for i < Db - k (each ladder step reads one row further down).
+static std::vector<std::vector<cd>> squeezed_columns(cd zeta, int Db, int d) {
+  const double r = std::abs(zeta);
+  const cd e = r > 0 ? zeta / r : cd(1.0, 0.0);
   const double t = std::tanh(r), ch = std::cosh(r), sh = std::sinh(r);
   std::vector<cd> v(Db, 0.0);
   // squeezed vacuum via the ratio recursion c_{2q+2} / c_{2q} = -e t sqrt((2q+1)/(2q+2))
@@ -347,6 +344,15 @@ extern "C" tn_status tn_squeezed_basis(double zeta_re, double zeta_im, int32_t D
     }
     cols.push_back(nx);
   }
+  return cols;
+}
+
+extern "C" tn_status tn_squeezed_basis(double zeta_re, double zeta_im, int32_t D, int32_t d, int32_t margin,
+                                       double* out) {
+  if (!out || D < 1 || d < 1 || d > D || margin < 0 || D + margin > 4096) return TN_EINVAL;
+  if (!std::isfinite(zeta_re) || !std::isfinite(zeta_im)) return TN_EINVAL;
+  if (std::hypot(zeta_re, zeta_im) > 20.0) return TN_EINVAL;
+  const std::vector<std::vector<cd>> cols = squeezed_columns(cd(zeta_re, zeta_im), D + margin, d);
   std::vector<cd> Wm((size_t)D * d);
   for (int j = 0; j < d; ++j)
     for (int i = 0; i < D; ++i) Wm[(size_t)i * d + j] = cols[j][i];
@@ -526,22 +532,72 @@ extern "C" tn_status tn_ws_targets(int32_t n_modes, int32_t D, const double* rho
 // gives <a^dag a> = (Vxx + Vpp)/2 - 1/2 and <a^2> = (Vxx - Vpp)/2 + i Vxp; the
 // reduced state is exactly the squeezed thermal state with these moments, so
 // its squeezed basis is the optimal local basis (eq. OLB).
+static bool reduced_covariance(int N, const double* r, const double* U, int j, double& vxx, double& vpp,
+                               double& vxp) {
+  vxx = vpp = vxp = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double re = U[2 * ((size_t)j * N + k)], im = U[2 * ((size_t)j * N + k) + 1];
+    if (!std::isfinite(re) || !std::isfinite(im) || !std::isfinite(r[k])) return false;
+    const double em = std::exp(-2.0 * r[k]), ep = std::exp(2.0 * r[k]);
+    vxx += 0.5 * (re * re * em + im * im * ep);
+    vpp += 0.5 * (im * im * em + re * re * ep);
+    vxp += 0.5 * re * im * (em - ep);
+  }
+  return std::isfinite(vxx) && std::isfinite(vpp) && std::isfinite(vxp);
+}
+
 extern "C" tn_status tn_ws_gaussian_params(int32_t N, const double* r, const double* U, float* out) {
   if (N < 1 || N > 4096 || !r || !U || !out) return TN_EINVAL;
-  for (int k = 0; k < N; ++k)
-    if (!std::isfinite(r[k])) return TN_EINVAL;
   for (int j = 0; j < N; ++j) {
-    double vxx = 0.0, vpp = 0.0, vxp = 0.0;
-    for (int k = 0; k < N; ++k) {
-      const double re = U[2 * ((size_t)j * N + k)], im = U[2 * ((size_t)j * N + k) + 1];
-      if (!std::isfinite(re) || !std::isfinite(im)) return TN_EINVAL;
-      const double em = std::exp(-2.0 * r[k]), ep = std::exp(2.0 * r[k]);
-      vxx += 0.5 * (re * re * em + im * im * ep);
-      vpp += 0.5 * (im * im * em + re * re * ep);
-      vxp += 0.5 * re * im * (em - ep);
-    }
+    double vxx, vpp, vxp;
+    if (!reduced_covariance(N, r, U, j, vxx, vpp, vxp)) return TN_EINVAL;
     moments_to_params(0.5 * (vxx + vpp) - 0.5, cd(0.5 * (vxx - vpp), vxp), out + 3 * j);
   }
+  return TN_OK;
+}
+
+// Cutoff errors of the Gaussian optimal basis with d kept states per mode.
+// nbar_j = sqrt(det V_j) - 1/2 (eq. WilliamsonDecomposition); the thermal
+// spectrum nbar^k / (nbar + 1)^(k+1) (eq. diagReducedGaussianDM) discards
+// (nbar / (nbar + 1))^d beyond the first d states; eps is the mean of those and
+// eps <= eps_D <= N eps (eq. SpecWfromSDsums).  The effective cutoff (eq.
+// Effectivecutoff) scans D upward, adding row D - 1 of the first d squeezed
+// basis vectors to their Gram matrix, until max |G - 1| <= tol.
+extern "C" tn_status tn_cutoff_report(int32_t N, const double* r, const double* U, int32_t d, int32_t D_max, double tol,
+                                      double* eps_mode, int32_t* D_eff, double* bounds) {
+  if (N < 1 || N > 4096 || d < 1 || D_max < d || D_max > 4096 || !(tol > 0) || !r || !U || !eps_mode || !D_eff ||
+      !bounds)
+    return TN_EINVAL;
+  double sum = 0.0;
+  for (int j = 0; j < N; ++j) {
+    double vxx, vpp, vxp;
+    if (!reduced_covariance(N, r, U, j, vxx, vpp, vxp)) return TN_EINVAL;
+    const double nbar = std::max(std::sqrt(std::max(vxx * vpp - vxp * vxp, 0.0)) - 0.5, 0.0);
+    eps_mode[j] = std::pow(nbar / (nbar + 1.0), d);
+    sum += eps_mode[j];
+    // |zeta_j| of the squeezed basis; its phase does not change |V^dag V - 1|
+    const double s2 = vxx + vpp, am = 0.5 * std::hypot(vxx - vpp, 2.0 * vxp);
+    const double rj = am > 0 ? 0.5 * std::atanh(std::min(2.0 * am / s2, 1.0 - 1e-15)) : 0.0;
+    if (rj > 20.0) return TN_EINVAL;
+    const auto cols = squeezed_columns(cd(rj, 0.0), D_max + d, d);
+    std::vector<cd> G((size_t)d * d, 0.0);
+    D_eff[j] = -1;
+    for (int D = 1; D <= D_max; ++D) {
+      const int i = D - 1;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) G[(size_t)a * d + b] += std::conj(cols[a][i]) * cols[b][i];
+      if (D < d) continue;
+      double dev = 0.0;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) dev = std::max(dev, std::abs(G[(size_t)a * d + b] - (a == b ? 1.0 : 0.0)));
+      if (dev <= tol) {
+        D_eff[j] = D;
+        break;
+      }
+    }
+  }
+  bounds[0] = sum / N;
+  bounds[1] = sum;
   return TN_OK;
 }
 

@@ -89,6 +89,19 @@ def learned_start(ctx, net: api.MLP, r, U, D: int, d: int, chi: int, seed: int, 
     import torch
     X = torch.from_numpy(api.ws_features(r, U)).cuda()
     y = net.forward(X).cpu().numpy()
+    return start_from_params(ctx, y, r, U, D, d, chi, seed, noise, tensors)
+
+
+def analytic_start(ctx, r, U, D: int, d: int, chi: int, seed: int, noise: float = 1e-3, tensors=None):
+    """The same start with the parameters read off each mode's reduced
+    covariance (tn_ws_gaussian_params) instead of the network: exact for a
+    Gaussian state, so the ceiling of what the network can learn."""
+    return start_from_params(ctx, api.ws_gaussian_params(r, U), r, U, D, d, chi, seed, noise, tensors)
+
+
+def start_from_params(ctx, y, r, U, D: int, d: int, chi: int, seed: int, noise: float = 1e-3, tensors=None):
+    """MPO in the squeezed bases given by y [N][3] and the product state of
+    their thermal weights (or `tensors`)."""
     iso, prod = api.ws_initial_state(y, D, d, chi, seed, noise)
     return api.MPO(ctx, r, U, D, d, iso=iso), api.MPS(ctx, prod if tensors is None else tensors)
 

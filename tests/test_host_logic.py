@@ -86,3 +86,29 @@ def test_ws_gaussian_params_match_oracle():
         V = gbs.covariance(r, U)
         ref = np.stack([omlp.gaussian_params(V, j) for j in range(N)])
         assert np.abs(got - ref).max() < 1e-6
+
+
+def test_cutoff_report_matches_oracle():
+    import paper_2410_18740_amd as P
+    import workloads as W
+    from oracle import gbs, cutoff
+    for N, seed, kind, rr, d in ((3, 4, "haar", (0.3, 0.6), 3), (12, 9, "haar", (0.5, 1.2), 6),
+                                 (16, 5, "brickwork", (0.1, 0.2), 4)):
+        r, U = W.make_problem(N, seed, rr, kind=kind)
+        rep = P.cutoff_report(r, U, d, D_max=200, tol=1e-10)
+        tails, eps, (lo, hi) = cutoff.eps_bounds(gbs.covariance(r, U), d)
+        assert np.allclose(rep["eps_mode"], tails, rtol=1e-9, atol=1e-15)
+        assert abs(rep["eps"] - eps) <= 1e-9 * eps + 1e-16 and abs(rep["eps_D_bounds"][1] - hi) <= 1e-9 * hi + 1e-15
+        for j in range(N):
+            zeta = complex(*omlp.gaussian_params(gbs.covariance(r, U), j)[:2])
+            assert rep["D_eff"][j] == cutoff.effective_cutoff(zeta, d, 200, 1e-10), (N, seed, j)
+
+
+def test_cutoff_report_rejects_bad_arguments():
+    import paper_2410_18740_amd as P
+    r, U = np.array([0.3, 0.4]), np.eye(2, dtype=complex)
+    for kw in (dict(d=0), dict(d=5, D_max=4), dict(d=2, tol=0.0), dict(d=2, D_max=5000)):
+        with pytest.raises(P.TnError):
+            P.cutoff_report(r, U, **kw)
+    with pytest.raises(P.TnError):
+        P.cutoff_report(np.array([0.3, np.nan]), U, 2)
