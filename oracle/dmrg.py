@@ -63,6 +63,32 @@ def energy(mps, Ws) -> float:
     return float(L[0, 0, 0].real) / mpsmod.norm2(mps)
 
 
+def env2_left_update(L, A, W):
+    """Two-layer left environment of <psi|H H|psi>:
+    L'[b,u',v',b'] = sum conj(A[a,n,b]) W[u,u',n,m] W[v,v',m,k] A[a',k,b'] L[a,u,v,a']."""
+    T = np.tensordot(L, A, axes=([3], [0]))                  # a u v k b'
+    T = np.tensordot(T, W, axes=([2, 3], [0, 3]))            # a u b' v' m
+    T = np.tensordot(T, W, axes=([1, 4], [0, 3]))            # a b' v' u' n
+    T = np.tensordot(A.conj(), T, axes=([0, 1], [0, 4]))     # b b' v' u'
+    return np.ascontiguousarray(T.transpose(0, 3, 2, 1))
+
+
+def energy_variance(mps, Ws, iso=None):
+    """(<H>, <H^2>, sigma_H^2) of the normalised state for the MPO Ws of PHP in
+    the raw Fock box (Sec. II.E.2: sigma_H^2 = <(PHP)^2> - <PHP>^2).  With
+    isometries iso[s] (D x d) the physical state has site tensors W_s A_s, so
+    (PHP)^2 is taken in the raw box, not in the kept basis."""
+    if iso is not None:
+        mps = [np.einsum("im,amb->aib", W, A) for W, A in zip(iso, mps)]
+    L = np.ones((1, 1, 1, 1), dtype=np.complex128)
+    for A, W in zip(mps, Ws):
+        L = env2_left_update(L, A, W)
+    n2 = mpsmod.norm2(mps)
+    e = energy(mps, Ws)
+    h2 = float(L[0, 0, 0, 0].real) / n2
+    return e, h2, h2 - e * e
+
+
 def energy_bogoliubov(mps, r, U, D) -> float:
     """<H> = sum_k ||b_k psi||^2 / <psi|psi> (eq. CentralEquation read as a sum
     of squares), evaluated on the dense state with b_k restricted to the box

@@ -617,3 +617,56 @@ def test_effective_cutoff_of_the_squeezed_vacuum_closed_form():
         assert cutoff.effective_cutoff(zeta, 1, 300, tol) == D_ref
     for d in (1, 3, 8):
         assert cutoff.effective_cutoff(0.0, d, 40, 1e-14) == d
+
+
+def _split_dense(psi, d, N):
+    """Exact MPS of a dense state by successive SVDs (no truncation)."""
+    out, rest, cl = [], psi.reshape(1, -1), 1
+    for s in range(N - 1):
+        Uu, S, Vh = np.linalg.svd(rest.reshape(cl * d, -1), full_matrices=False)
+        out.append(Uu.reshape(cl, d, -1))
+        cl = len(S)
+        rest = S[:, None] * Vh
+    out.append(rest.reshape(cl, d, 1))
+    return out
+
+
+def test_energy_variance_against_dense_states():
+    """<H^2> of the two-layer MPO contraction equals ||H psi||^2 with H the dense
+    quadrature-form PHP (a separate construction), on random MPS, also with
+    isometries where (PHP)^2 acts in the raw box; an eigenvector of PHP has
+    sigma_H = 0 (Sec. II.E.2)."""
+    for N, D, seed in ((3, 4, 1), (4, 3, 2)):
+        r, U = W.make_problem(N, seed, (0.4, 0.8))
+        al, be, ga = gbs.coefficients(r, U)
+        ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+        Ws = mpo.cores(al, be, ga, ops)
+        H = dense.php_quadrature(al, be, ga, D)
+        state = W.random_mps(N, D, 4, seed + 10)
+        psi = M.to_dense(state).reshape(-1)
+        n2 = np.vdot(psi, psi).real
+        e_ref = np.vdot(psi, H @ psi).real / n2
+        h2_ref = np.linalg.norm(H @ psi) ** 2 / n2
+        e, h2, var = dmrg.energy_variance(state, Ws)
+        assert abs(e - e_ref) < 1e-10 * max(1, abs(e_ref)) and abs(h2 - h2_ref) < 1e-10 * h2_ref
+        assert var > 1e-3
+        # an eigenvector of PHP as an exact MPS
+        w, v = np.linalg.eigh(H)
+        e0, h20, var0 = dmrg.energy_variance(_split_dense(v[:, 0], D, N), Ws)
+        assert abs(e0 - w[0]) < 1e-10 and abs(var0) < 1e-10
+    # isometries: the physical state lives in the raw box, D = 5 -> d = 3
+    N, D, d = 3, 5, 3
+    r, U = W.make_problem(N, 7, (0.4, 0.8))
+    al, be, ga = gbs.coefficients(r, U)
+    ops = [operators.local_operators(D, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+    Ws = mpo.cores(al, be, ga, ops)
+    H = dense.php_quadrature(al, be, ga, D)
+    rng = np.random.default_rng(3)
+    iso = [np.linalg.qr(rng.normal(size=(D, d)) + 1j * rng.normal(size=(D, d)))[0] for _ in range(N)]
+    state = W.random_mps(N, d, 4, 17)
+    Psi = M.to_dense([np.einsum("im,amb->aib", Wi, A) for Wi, A in zip(iso, state)]).reshape(-1)
+    n2 = np.vdot(Psi, Psi).real
+    e_ref = np.vdot(Psi, H @ Psi).real / n2
+    h2_ref = np.linalg.norm(H @ Psi) ** 2 / n2
+    e, h2, var = dmrg.energy_variance(state, Ws, iso)
+    assert abs(e - e_ref) < 1e-10 * max(1, abs(e_ref)) and abs(h2 - h2_ref) < 1e-10 * h2_ref
