@@ -184,7 +184,11 @@ def to_target(a):
                            bulk_tol=1e-8 if prec == 0 else 1e-6, refine_tol=1e-9, lbo_bulk=0 if a.no_lbo else 1,
                            lbo_refine=0 if a.no_lbo else 1)
         res[form] = out
+        # sigma_H^2 of the final state (Sec. II.E.2), outside the timed solve
+        e_v, h2_v, var_v = P.energy_variance(ctx, mpo, mps)
+        out["variance"] = var_v
         print(f"{form}: reached={out['reached']} t_target={out['t_target']:.2f}s sweeps={out['sweeps']} "
+              f"sigma_H^2={var_v:.3e} "
               f"E={out['energy']:.3e} trace={[f'{e:.2e}' for e in out['energy_trace']]}", file=sys.stderr, flush=True)
         del mps, mpo
     base = res["fp64"]["t_target"]

@@ -203,6 +203,20 @@ tn_status tn_dmrg_solve(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, const tn_solve_op
  * MagOfSimError); norm2 (may be NULL) receives <psi|psi>. */
 tn_status tn_energy(tn_ctx* ctx, const tn_mpo* mpo, const tn_mps* mps, double* energy, double* norm2);
 
+/* Energy variance sigma_H^2 = <(PHP)^2> - <PHP>^2 of the normalised state
+ * (Sec. II.E.2), in FP64: ~0 when the state is an eigenstate, so it separates
+ * the bond-dimension error from the cutoff error.  <(PHP)^2> comes from a
+ * two-layer environment contraction with the product operators taken in the
+ * raw Fock box (with a local basis W the physical state is W A, and W W^dag is
+ * not inserted between the two copies of PHP).  Outputs are host doubles;
+ * h2 (may be NULL) receives <(PHP)^2>.  The variance is returned as computed
+ * (it may be slightly negative from rounding).  Workspace: two environments of
+ * w^2 chi^2 complex doubles at the widest bond, plus GEMM buffers up to 8 GiB.
+ * TN_EINVAL on NULL handles or outputs, TN_ESTATE on an MPS/MPO mismatch,
+ * TN_ENUMERIC on a non-finite result. */
+tn_status tn_energy_variance(tn_ctx* ctx, const tn_mpo* mpo, const tn_mps* mps, double* energy, double* h2,
+                             double* variance);
+
 /* Local basis optimisation.  site >= 0: re-optimise W_site (the orthogonality
  * centre must be at `site`, else TN_ESTATE); site == -1: one joint LBO + DMRG
  * sweep.  discarded (may be NULL) receives the local discarded weight

@@ -3,12 +3,12 @@ sampling (arXiv 2410.18740), as a thin Python layer over the HIP library
 libtn.so.  Torch provides device memory and the stream; all arithmetic of the
 method runs in the library's kernels.
 """
-from .api import (Context, MPO, MPS, SweepOpts, dmrg_sweep, dmrg_solve, energy, lbo_step, marginals, sample,
+from .api import (Context, MPO, MPS, SweepOpts, dmrg_sweep, dmrg_solve, energy, energy_variance, lbo_step, marginals, sample,
                   heff_apply, env_update, truncate, cgemm, philox4x32_10, matvec_flops, env_flops, rdm,
                   squeezed_basis, MLP, ws_features, ws_targets, ws_initial_state, ws_gaussian_params, cutoff_report,
                   FP64, FP32, BF16X3)
 from ._lib import TnError, LIB_PATH
 
-__all__ = ["Context", "MPO", "MPS", "SweepOpts", "dmrg_sweep", "dmrg_solve", "energy", "lbo_step", "marginals",
+__all__ = ["Context", "MPO", "MPS", "SweepOpts", "dmrg_sweep", "dmrg_solve", "energy", "energy_variance", "lbo_step", "marginals",
            "sample", "heff_apply", "env_update", "truncate", "cgemm", "philox4x32_10", "matvec_flops",
            "env_flops", "rdm", "squeezed_basis", "MLP", "ws_features", "ws_targets", "ws_initial_state", "ws_gaussian_params", "cutoff_report", "FP64", "FP32", "BF16X3", "TnError", "LIB_PATH"]

@@ -106,6 +106,7 @@ def lib():
         "tn_mps_destroy": (None, [vp]),
         "tn_dmrg_sweep": (i32, [vp, vp, vp, P(tn_sweep_opts), P(tn_sweep_stats)]),
         "tn_energy": (i32, [vp, vp, vp, P(dbl), P(dbl)]),
+        "tn_energy_variance": (i32, [vp, vp, vp, P(dbl), P(dbl), P(dbl)]),
         "tn_dmrg_solve": (i32, [vp, vp, vp, P(tn_solve_opts), P(tn_solve_result), P(dbl), P(dbl)]),
         "tn_lbo_step": (i32, [vp, vp, vp, i32, P(tn_sweep_opts), P(dbl)]),
         "tn_marginals": (i32, [vp, vp, vp, i32, P(dbl)]),

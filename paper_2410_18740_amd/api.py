@@ -251,6 +251,13 @@ def energy(ctx: Context, mpo: MPO, mps: MPS):
     return e.value, n.value
 
 
+def energy_variance(ctx: Context, mpo: MPO, mps: MPS):
+    """(<H>, <H^2>, sigma_H^2) of the normalised state, FP64."""
+    e, h2, v = C.c_double(), C.c_double(), C.c_double()
+    ctx.check(L.lib().tn_energy_variance(ctx.h, mpo.h, mps.h, C.byref(e), C.byref(h2), C.byref(v)))
+    return e.value, h2.value, v.value
+
+
 def lbo_step(ctx: Context, mpo: MPO, mps: MPS, site: int, opts: SweepOpts) -> float:
     disc = C.c_double()
     o = opts.c()

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include "internal.h"
 
 #define TN_GUARD_BEGIN try {
@@ -294,16 +295,22 @@ static void mixed_envs(tn_ctx* c, int prec, const std::vector<PlanL>& Ls, const 
   HIPCHK(hipStreamSynchronize(c->stream));
 }
 
-static void run_ops(tn_ctx* c, int sprec, const tn_mpo* mpo, int site, bool raw, const Plan& P, char* Y, char* T,
-                    size_t nel, int chi_l, int ds, int chi_r, const std::string& tag) {
+// device operators of one site by index; entry 0 (the identity) is never read
+using OpTable = std::vector<const void*>;
+static OpTable site_ops(const tn_mpo* mpo, int sprec, int site) {
+  return {nullptr, mpo->op_ptr(sprec, site, 1, false), mpo->op_ptr(sprec, site, 2, false),
+          mpo->op_ptr(sprec, site, 3, false)};
+}
+
+static void run_ops(tn_ctx* c, int sprec, const OpTable& ops, const Plan& P, char* Y, char* T, size_t nel, int chi_l,
+                    int ds, int chi_r, const std::string& tag) {
   if (P.T.empty()) return;
   const size_t eb = elem_bytes(sprec);
   std::vector<OpJob> oj;
   std::vector<OpTerm> ot;
   for (size_t j = 0; j < P.T.size(); ++j) {
     oj.push_back({T + j * nel * eb, (int)ot.size(), (int)P.T[j].terms.size(), 0, 0});
-    for (auto& t : P.T[j].terms)
-      ot.push_back({Y + (size_t)t.ych * nel * eb, t.a ? mpo->op_ptr(sprec, site, t.a, raw) : nullptr, nullptr, t.c});
+    for (auto& t : P.T[j].terms) ot.push_back({Y + (size_t)t.ych * nel * eb, t.a ? ops.at(t.a) : nullptr, nullptr, t.c});
   }
   const size_t bj = (oj.size() * sizeof(OpJob) + 255) & ~size_t(255);
   char* d = (char*)ws_get(c, tag + ":opd", bj + ot.size() * sizeof(OpTerm));
@@ -334,29 +341,29 @@ static const void* stage_A(tn_ctx* c, int prec, const cf64* A, size_t n, const s
   return p;
 }
 
-// left update across `site`: Lout[w_{s+1}][chi_r][chi_r] from Lin[w_s][chi_l][chi_l]
-static void env_left(tn_ctx* c, const tn_mpo* mpo, int site, int prec, int chi_l, int chi_r,
-                     const std::vector<const void*>& Lin, const cf64* A, void* Lout) {
+// left update across one site for a single-site term list: Lout[wo][chi_r][chi_r]
+// from Lin[.][chi_l][chi_l]; output channels that no term reaches are zeroed when
+// zero_rest, and marked in `covered` (size wo) either way
+static void env_left_terms(tn_ctx* c, int prec, const Plan& P, int wo, int d, const OpTable& ops, int chi_l,
+                           int chi_r, const std::vector<const void*>& Lin, const cf64* A, void* Lout, bool zero_rest,
+                           std::vector<bool>& cov, const std::string& tag) {
   const int sprec = prec == PREC_FP64 ? PREC_FP64 : PREC_FP32;
   const size_t eb = elem_bytes(sprec);
-  const int d = mpo->d, wo = mpo->w[site + 1];
   const size_t nel = (size_t)chi_l * d * chi_r;
-  const void* AP = stage_A(c, prec, A, nel, "envL:A");
-  Plan P = build_plan(window_terms(mpo, site, 1), mpo->w[site], wo, false);
+  const void* AP = stage_A(c, prec, A, nel, tag + ":A");
   std::vector<const void*> Lp;
-  mixed_envs(c, sprec, P.L, Lin, (int64_t)chi_l * chi_l, Lp, "envL");
-  char* Y = (char*)ws_get(c, "envL:Y", std::max<size_t>(1, P.L.size()) * nel * eb);
-  char* T = (char*)ws_get(c, "envL:T", std::max<size_t>(1, P.T.size()) * nel * eb);
+  mixed_envs(c, sprec, P.L, Lin, (int64_t)chi_l * chi_l, Lp, tag);
+  char* Y = (char*)ws_get(c, tag + ":Y", std::max<size_t>(1, P.L.size()) * nel * eb);
+  char* T = (char*)ws_get(c, tag + ":T", std::max<size_t>(1, P.T.size()) * nel * eb);
   std::vector<GemmJob> jobs;
   std::vector<GemmSeg> segs;
   for (size_t i = 0; i < P.L.size(); ++i) {
     segs.push_back({Lp[i], AP, chi_l, (int64_t)d * chi_r, chi_l, 0});
     jobs.push_back({Y + i * nel * eb, (int64_t)d * chi_r, chi_l, d * chi_r, (int)segs.size() - 1, 1});
   }
-  gemm_batch(c, prec, 0, 0, jobs, segs, chi_l, d * chi_r, "envL:g1");
-  run_ops(c, sprec, mpo, site, false, P, Y, T, nel, chi_l, d, chi_r, "envL");
+  gemm_batch(c, prec, 0, 0, jobs, segs, chi_l, d * chi_r, tag + ":g1");
+  run_ops(c, sprec, ops, P, Y, T, nel, chi_l, d, chi_r, tag);
   jobs.clear(); segs.clear();
-  std::vector<bool> cov(wo, false);
   for (auto& R : P.R) {
     const int ch = R.env[0].first;
     cov[ch] = true;
@@ -364,8 +371,18 @@ static void env_left(tn_ctx* c, const tn_mpo* mpo, int site, int prec, int chi_l
     segs.push_back({AP, src, chi_r, chi_r, chi_l * d, 0});
     jobs.push_back({(char*)Lout + (size_t)ch * chi_r * chi_r * eb, chi_r, chi_r, chi_r, (int)segs.size() - 1, 1});
   }
-  gemm_batch(c, prec, 1, 0, jobs, segs, chi_r, chi_r, "envL:g2");
-  zero_channels(c, sprec, Lout, wo, (int64_t)chi_r * chi_r, cov);
+  gemm_batch(c, prec, 1, 0, jobs, segs, chi_r, chi_r, tag + ":g2");
+  if (zero_rest) zero_channels(c, sprec, Lout, wo, (int64_t)chi_r * chi_r, cov);
+}
+
+// left update across `site`: Lout[w_{s+1}][chi_r][chi_r] from Lin[w_s][chi_l][chi_l]
+static void env_left(tn_ctx* c, const tn_mpo* mpo, int site, int prec, int chi_l, int chi_r,
+                     const std::vector<const void*>& Lin, const cf64* A, void* Lout) {
+  const int sprec = prec == PREC_FP64 ? PREC_FP64 : PREC_FP32;
+  const int wo = mpo->w[site + 1];
+  const Plan P = build_plan(window_terms(mpo, site, 1), mpo->w[site], wo, false);
+  std::vector<bool> cov(wo, false);
+  env_left_terms(c, prec, P, wo, mpo->d, site_ops(mpo, sprec, site), chi_l, chi_r, Lin, A, Lout, true, cov, "envL");
 }
 
 // right update across `site`: Rout[w_s][chi_l][chi_l] (transposed) from Rin[w_{s+1}][chi_r][chi_r] (transposed)
@@ -390,7 +407,7 @@ static void env_right(tn_ctx* c, const tn_mpo* mpo, int site, int prec, int chi_
     jobs.push_back({Z + i * nel * eb, chi_r, chi_l * d, chi_r, (int)segs.size() - 1, 1});
   }
   gemm_batch(c, prec, 0, 0, jobs, segs, chi_l * d, chi_r, "envR:g1");
-  run_ops(c, sprec, mpo, site, false, P, Z, T, nel, chi_l, d, chi_r, "envR");
+  run_ops(c, sprec, site_ops(mpo, sprec, site), P, Z, T, nel, chi_l, d, chi_r, "envR");
   jobs.clear(); segs.clear();
   std::vector<bool> cov(wo, false);
   for (auto& R : P.R) {
@@ -686,6 +703,109 @@ static double energy_fp64(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double*
   return e.x / nn.x;
 }
 
+// ------------------------------------------------------------------ <(PHP)^2> (FP64)
+// Two-layer left environments L[(u, v)][chi][chi], u and v the bond channels of
+// the two copies of the MPO.  Each pair of core entries (u -> u', op_a) and
+// (v -> v', op_b) of a site is one single-site term (u, v) -> (u', v') whose
+// operator is the product Q_ab = W^dag R_a R_b W of the raw-box operators
+// (R_0 = 1): (PHP)^2 is taken in the raw box, so with a local basis the
+// projector W W^dag is not inserted between the two copies.  The term lists go
+// through the same planner and batched GEMMs as the one-layer update; output
+// channels are processed in groups of first-layer channels sized to a
+// workspace budget.
+static void product_ops(const tn_mpo* mpo, int s, std::vector<cd>& Q) {
+  const int D = mpo->D_raw, d = mpo->d;
+  const auto& raw = mpo->raw_ops[s];
+  const auto& W = mpo->iso[s];
+  auto R = [&](int a, int i, int j) -> cd {
+    if (a == 0) return i == j ? cd(1.0) : cd(0.0);
+    return raw[(size_t)(a - 1) * D * D + (size_t)i * D + j];
+  };
+  Q.assign((size_t)16 * d * d, 0.0);
+  std::vector<cd> RW((size_t)D * d), RRW((size_t)D * d);
+  for (int b = 0; b < 4; ++b) {
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < d; ++j) {
+        cd t = 0.0;
+        for (int k = 0; k < D; ++k) t += R(b, i, k) * W[(size_t)k * d + j];
+        RW[(size_t)i * d + j] = t;
+      }
+    for (int a = 0; a < 4; ++a) {
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < d; ++j) {
+          cd t = 0.0;
+          for (int k = 0; k < D; ++k) t += R(a, i, k) * RW[(size_t)k * d + j];
+          RRW[(size_t)i * d + j] = t;
+        }
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          cd t = 0.0;
+          for (int k = 0; k < D; ++k) t += std::conj(W[(size_t)k * d + i]) * RRW[(size_t)k * d + j];
+          Q[((size_t)(a * 4 + b) * d + i) * d + j] = t;
+        }
+    }
+  }
+}
+
+static double h2_fp64(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m) {
+  const int N = m->N, d = m->d;
+  hipStream_t st = c->stream;
+  size_t maxw = 1;
+  for (int t = 0; t <= N; ++t) maxw = std::max(maxw, (size_t)mpo->w[t] * mpo->w[t] * m->dims[t] * m->dims[t]);
+  cf64* La = wsT<cf64>(c, "h2:La", maxw);
+  cf64* Lb = wsT<cf64>(c, "h2:Lb", maxw);
+  cf64* Qd = wsT<cf64>(c, "h2:Q", (size_t)16 * d * d);
+  HIPCHK(launch_set_one(La, PREC_FP64, st));
+  const size_t budget = (size_t)8 << 30;  // Y + T buffers per group
+  std::vector<cd> Q;
+  std::vector<cf64> Qh((size_t)16 * d * d);
+  for (int s = 0; s < N; ++s) {
+    const int cl = m->dims[s], cr = m->dims[s + 1];
+    const int wi = mpo->w[s], wo = mpo->w[s + 1];
+    product_ops(mpo, s, Q);
+    for (size_t i = 0; i < Q.size(); ++i) Qh[i] = make_double2(Q[i].real(), Q[i].imag());
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(Qd, Qh.data(), Qh.size() * sizeof(cf64), hipMemcpyHostToDevice));
+    OpTable ops(16, nullptr);
+    for (int k = 1; k < 16; ++k) ops[k] = Qd + (size_t)k * d * d;
+    // terms grouped by the first layer's output channel
+    std::vector<std::vector<Term2>> by_u(wo);
+    for (const auto& e1 : mpo->entries[s])
+      for (const auto& e2 : mpo->entries[s])
+        for (int a = 0; a < 4; ++a) {
+          if (e1.c[a] == 0.0) continue;
+          for (int b = 0; b < 4; ++b) {
+            if (e2.c[b] == 0.0) continue;
+            by_u[e1.col].push_back({e1.row * wi + e2.row, e1.col * wo + e2.col, a * 4 + b, 0, e1.c[a] * e2.c[b]});
+          }
+        }
+    std::vector<const void*> lin((size_t)wi * wi);
+    for (size_t i = 0; i < lin.size(); ++i) lin[i] = La + i * cl * cl;
+    std::vector<bool> cov((size_t)wo * wo, false);
+    const size_t nel_b = (size_t)cl * d * cr * sizeof(cf64);
+    // first-layer output channels [u0, u1) in one plan, halved while its buffers exceed the budget
+    std::function<void(int, int)> run = [&](int u0, int u1) {
+      std::vector<Term2> terms;
+      for (int u = u0; u < u1; ++u) terms.insert(terms.end(), by_u[u].begin(), by_u[u].end());
+      if (terms.empty()) return;
+      Plan P = build_plan(terms, wi * wi, wo * wo, false);
+      if (u1 - u0 > 1 && (P.L.size() + P.T.size()) * nel_b > budget) {
+        run(u0, (u0 + u1) / 2);
+        run((u0 + u1) / 2, u1);
+        return;
+      }
+      env_left_terms(c, PREC_FP64, P, wo * wo, d, ops, cl, cr, lin, m->A[s], Lb, false, cov, "h2");
+    };
+    run(0, wo);
+    zero_channels(c, PREC_FP64, Lb, wo * wo, (int64_t)cr * cr, cov);
+    std::swap(La, Lb);
+  }
+  cf64 h;
+  download(c, &h, La, sizeof(cf64));
+  if (!std::isfinite(h.x)) TN_THROW(TN_ENUMERIC, "non-finite <H^2>");
+  return h.x;
+}
+
 // ------------------------------------------------------------------ ABI
 static void check_opts(const tn_sweep_opts* o) {
   if (!o) TN_THROW(TN_EINVAL, "null options");
@@ -830,6 +950,21 @@ extern "C" tn_status tn_energy(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, do
   if (!mpo || !m || !energy) TN_THROW(TN_EINVAL, "null argument");
   check_pair(mpo, m);
   *energy = energy_fp64(c, mpo, m, norm2);
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_energy_variance(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double* energy,
+                                        double* h2, double* variance) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !m || !energy || !variance) TN_THROW(TN_EINVAL, "null argument");
+  check_pair(mpo, m);
+  double n2 = 0.0;
+  const double e = energy_fp64(c, mpo, m, &n2);
+  const double q = h2_fp64(c, mpo, m) / n2;
+  *energy = e;
+  if (h2) *h2 = q;
+  *variance = q - e * e;
   TN_GUARD_END(c)
 }
 
