@@ -4,6 +4,7 @@
 // vector kernels (multi-dot with fixed-order two-stage reduction, multi-axpy,
 // scaling, linear combination).  All reductions are deterministic: block
 // partials are combined in a fixed order, never with atomics.
+#include <algorithm>
 #include "common.h"
 
 // ------------------------------------------------------------------ op apply
@@ -82,6 +83,149 @@ __global__ __launch_bounds__(256) void opapply_kernel(const OpJob* __restrict__ 
   }
 }
 
+// Register-blocked form for legs of at most MD states.  One-leg tensors (dt = 1):
+// thread (a, bb) owns dst[a][0..ds)[b0 + bb] in registers, loads its column
+// src[a][0..ds)[b] per term and applies the s-leg operator in registers.  Two
+// legs (ds = dt): block = one (a, b-chunk), thread (t, bb) owns
+// dst[a][0..ds)[t][b] in registers; a t-leg operator is applied first with
+// thread (s, bb) owning src[a][s][0..dt)[b], and its result crosses to the
+// (t, bb) owner through LDS.  Operators are staged in LDS and read as
+// wave-uniform broadcasts, so LDS carries one write and one read per element
+// and term instead of one read per multiply.
+template <typename CT, int MD, bool TWO>
+__global__ __launch_bounds__(256) void opapply_reg_kernel(const OpJob* __restrict__ jobs,
+                                                           const OpTerm* __restrict__ terms, int chi_l, int ds,
+                                                           int dt, int chi_r, int bw) {
+  using RT = typename real_of<CT>::type;
+  extern __shared__ unsigned char smem_raw[];
+  CT* opa = reinterpret_cast<CT*>(smem_raw);  // ds * ds
+  CT* opb = opa + MD * MD;                    // dt * dt
+  CT* tmp = opb + MD * MD;                    // [ds][dt][bw] (two legs)
+  const int nb = (chi_r + bw - 1) / bw;
+  const int tid = threadIdx.x;
+  const int bb = tid % bw, row = tid / bw;
+  const int b0 = (blockIdx.x % nb) * bw;
+  const int b = b0 + bb;
+  int a, t;
+  if (TWO) {
+    a = blockIdx.x / nb;
+    t = row;  // < dt: the block has dt * bw threads
+  } else {
+    a = (blockIdx.x / nb) * (blockDim.x / bw) + row;
+    t = 0;
+  }
+  const bool live = b < chi_r && a < chi_l;
+  const OpJob job = jobs[blockIdx.y];
+  CT* dst = reinterpret_cast<CT*>(job.dst);
+  const int64_t sstride = (int64_t)dt * chi_r;                 // s -> s + 1
+  const int64_t col = ((int64_t)a * ds * dt + t) * chi_r + b;  // [a][0][t][b]
+  CT acc[MD];
+#pragma unroll
+  for (int s = 0; s < MD; ++s) acc[s] = czero<CT>();
+  if (job.accumulate && live) {
+#pragma unroll
+    for (int s = 0; s < MD; ++s)
+      if (s < ds) acc[s] = dst[col + s * sstride];
+  }
+  for (int k = 0; k < job.nterms; ++k) {
+    const OpTerm term = terms[job.t0 + k];
+    const CT* src = reinterpret_cast<const CT*>(term.src);
+    const CT* oA = reinterpret_cast<const CT*>(term.opA);
+    const CT* oB = reinterpret_cast<const CT*>(term.opB);
+    __syncthreads();  // the previous term is done with opa, opb and tmp
+    for (int e = tid; e < ds * ds; e += blockDim.x) opa[e] = oA ? oA[e] : czero<CT>();
+    if (TWO)
+      for (int e = tid; e < dt * dt; e += blockDim.x) opb[e] = oB ? oB[e] : czero<CT>();
+    CT z[MD];
+    if (TWO && oB) {
+      // thread (s = row, bb): y[t'] = sum_t opB[t'][t] src[a][s][t][b]
+      CT x[MD];
+      const int sr = row;
+      const int64_t c1 = ((int64_t)a * ds + sr) * dt * chi_r + b;
+#pragma unroll
+      for (int q = 0; q < MD; ++q) x[q] = (live && q < dt) ? src[c1 + q * chi_r] : czero<CT>();
+      __syncthreads();  // opb staged
+#pragma unroll
+      for (int tp = 0; tp < MD; ++tp) {
+        if (tp < dt) {
+          CT v = czero<CT>();
+#pragma unroll
+          for (int q = 0; q < MD; ++q)
+            if (q < dt) {
+              const CT o = opb[tp * dt + q];
+              v.x += o.x * x[q].x - o.y * x[q].y;
+              v.y += o.x * x[q].y + o.y * x[q].x;
+            }
+          tmp[(sr * dt + tp) * bw + bb] = v;
+        }
+      }
+      __syncthreads();  // tmp complete
+#pragma unroll
+      for (int s = 0; s < MD; ++s) z[s] = (s < ds) ? tmp[(s * dt + t) * bw + bb] : czero<CT>();
+    } else {
+#pragma unroll
+      for (int s = 0; s < MD; ++s) z[s] = (live && s < ds) ? src[col + s * sstride] : czero<CT>();
+      __syncthreads();  // opa staged
+    }
+    const RT c = (RT)term.coef;
+    if (oA) {
+#pragma unroll
+      for (int sp = 0; sp < MD; ++sp) {
+        if (sp < ds) {
+          CT v = czero<CT>();
+#pragma unroll
+          for (int s = 0; s < MD; ++s)
+            if (s < ds) {
+              const CT o = opa[sp * ds + s];
+              v.x += o.x * z[s].x - o.y * z[s].y;
+              v.y += o.x * z[s].y + o.y * z[s].x;
+            }
+          acc[sp].x += c * v.x;
+          acc[sp].y += c * v.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < MD; ++s) {
+        acc[s].x += c * z[s].x;
+        acc[s].y += c * z[s].y;
+      }
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int s = 0; s < MD; ++s)
+      if (s < ds) dst[col + s * sstride] = acc[s];
+  }
+}
+
+template <typename CT, int MD>
+static void launch_opapply_reg(const OpJob* d_jobs, int njobs, const OpTerm* d_terms, int chi_l, int ds, int dt,
+                               int chi_r, hipStream_t st) {
+  const bool two = dt > 1;
+  int cap = 1;
+  while (cap < chi_r) cap <<= 1;
+  int bw = 64;
+  if (two) {
+    while (bw > 1 && dt * bw > 256) bw >>= 1;
+  }
+  bw = std::min(bw, cap);
+  const int nb = (chi_r + bw - 1) / bw;
+  const size_t eb = sizeof(CT);
+  if (two) {
+    const size_t shm = (2 * MD * MD + (size_t)ds * dt * bw) * eb;
+    dim3 grid(chi_l * nb, njobs);
+    hipLaunchKernelGGL((opapply_reg_kernel<CT, MD, true>), grid, dim3(dt * bw), shm, st, d_jobs, d_terms, chi_l, ds,
+                       dt, chi_r, bw);
+  } else {
+    const int rows = 256 / bw;
+    const size_t shm = 2 * MD * MD * eb;
+    dim3 grid(((chi_l + rows - 1) / rows) * nb, njobs);
+    hipLaunchKernelGGL((opapply_reg_kernel<CT, MD, false>), grid, dim3(rows * bw), shm, st, d_jobs, d_terms, chi_l,
+                       ds, dt, chi_r, bw);
+  }
+}
+
 static int pick_bw(int elem_bytes, int dsdt, int ds, int dt, int chi_r) {
   const int budget = 96 * 1024;
   int bw = 64;
@@ -96,6 +240,17 @@ static int pick_bw(int elem_bytes, int dsdt, int ds, int dt, int chi_r) {
 hipError_t launch_opapply(int prec, const OpJob* d_jobs, int njobs, const OpTerm* d_terms, int chi_l, int ds, int dt,
                           int chi_r, hipStream_t st) {
   if (njobs <= 0) return hipSuccess;
+  if ((dt == 1 || dt == ds) && ds <= 16) {
+    const bool f64 = prec == PREC_FP64;
+    if (ds <= 8) {
+      if (f64) launch_opapply_reg<cf64, 8>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
+      else launch_opapply_reg<cf32, 8>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
+    } else {
+      if (f64) launch_opapply_reg<cf64, 16>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
+      else launch_opapply_reg<cf32, 16>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
+    }
+    return hipGetLastError();
+  }
   const int eb = (prec == PREC_FP64) ? 16 : 8;
   const int bw = pick_bw(eb, ds * dt, ds, dt, chi_r);
   const int nb_chunks = (chi_r + bw - 1) / bw;
