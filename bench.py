@@ -598,6 +598,8 @@ def main():
         "phase_s": {k: sum(s[k] for s in stats) / a.steps for k in
                     ("t_heff", "t_lanczos", "t_svd", "t_env", "t_lbo", "t_energy")},
         "matvecs_per_sweep": sum(s["matvecs"] for s in stats) / a.steps,
+        "lanczos_iters_per_sweep": pr["lanczos_iters"] / a.steps,
+        "lanczos_full_passes_per_sweep": pr["lanczos_full_passes"] / a.steps,
         "gemm_launches": launches,
         "gemm_launch_avg_ms": gemm_ms / max(1, launches),
         "gemm_flops_per_launch": (pr["flops_l"] + pr["flops_r"]) / max(1, launches),

@@ -70,7 +70,7 @@ void tn_ctx_destroy(tn_ctx* ctx);
 const char* tn_last_error(const tn_ctx* ctx);
 /* Kernel timing of the window matvec.  When profiling is on, every matvec
  * records HIP events around its launches on the context stream and waits for
- * them (so it serialises the host).  out (may be NULL, 14 doubles) receives the
+ * them (so it serialises the host).  out (may be NULL, 16 doubles) receives the
  * accumulated milliseconds of [convert, left contraction GEMM, operator kernel,
  * right contraction GEMM, split-K reduction], the matvec count, the
  * algorithmic flops of the left contraction, of the right contraction and of
@@ -78,7 +78,9 @@ const char* tn_last_error(const tn_ctx* ctx);
  * GEMMs, and for the truncation's Householder tridiagonalisation (one event
  * pair around each sequence of column launches) the milliseconds, the launch
  * count and the algorithmic bytes (32 (p - j - 1)^2 for column j: the
- * trailing block read and written once).
+ * trailing block read and written once), then the Lanczos iterations and how
+ * many of them orthogonalised against the whole Krylov basis (these two are
+ * counted whether or not profiling is on). 
  * mode: -1 read only, 0 stop and reset, 1 start (after reset). */
 tn_status tn_profile(tn_ctx* ctx, int32_t mode, double* out);
 

@@ -80,11 +80,11 @@ class Context:
 
     def profile(self, mode: int = -1) -> dict:
         """mode -1 read, 0 stop+reset, 1 start (reset first)."""
-        out = np.zeros(14)
+        out = np.zeros(16)
         self.check(L.lib().tn_profile(self.h, mode, L.dptr(out)))
         keys = ["ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce", "matvecs",
                 "flops_l", "flops_r", "flops_matvec", "bytes_l", "bytes_r",
-                "ms_tridiag", "tridiag_launches", "bytes_tridiag"]
+                "ms_tridiag", "tridiag_launches", "bytes_tridiag", "lanczos_iters", "lanczos_full_passes"]
         return dict(zip(keys, out.tolist()))
 
     @property

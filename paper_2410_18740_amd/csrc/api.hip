@@ -125,6 +125,8 @@ extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
     out[11] = c->prof_tri_ms;
     out[12] = (double)c->prof_tri_n;
     out[13] = c->prof_tri_bytes;
+    out[14] = (double)c->lz_iters;
+    out[15] = (double)c->lz_full;
   }
   if (mode >= 0) {
     c->prof = mode > 0;
@@ -134,6 +136,7 @@ extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
     c->prof_n = 0;
     c->prof_tri_ms = c->prof_tri_bytes = 0.0;
     c->prof_tri_n = 0;
+    c->lz_iters = c->lz_full = 0;
   }
   return TN_OK;
 }

@@ -182,8 +182,9 @@ hipError_t launch_transpose_from64(int prec, void* dst, const cf64* src, int bat
 hipError_t launch_transpose_to64(int prec, cf64* dst, const void* src, int batch, int rows, int cols, hipStream_t st);
 hipError_t launch_scale_host(cf64* dst, const cf64* src, double s, int64_t n, hipStream_t st);
 hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream_t st);
-hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, double* alpha, double* beta, double* inv,
-                               double* coefs, double* out, hipStream_t st);
+hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta,
+                               double* inv, double* coefs, double* out, hipStream_t st);
+hipError_t launch_inv_norm(const cf64* h, int nv, double* inv, hipStream_t st);
 hipError_t launch_ritz_coefs(const cf64* V, int n, double* out, double* last, hipStream_t st);
 hipError_t launch_finite_check(const cf64* x, int64_t n, int* flag, hipStream_t st);
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);

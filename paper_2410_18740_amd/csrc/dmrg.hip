@@ -73,10 +73,22 @@ struct LzResult {
   int matvecs = 0;
   bool converged = false;
   double t_mv = 0.0;
+  int full_passes = 0;  // iterations orthogonalised against the whole basis
 };
 
+// Lowest eigenpair by Lanczos with partial reorthogonalisation (Simon, Math.
+// Comp. 42, 1984).  Each new vector is orthogonalised (two classical
+// Gram-Schmidt passes) against the two latest basis vectors only, while the
+// recurrence
+//   beta_j w_{j+1,k} = beta_k w_{j,k+1} + (alpha_k - alpha_j) w_{j,k}
+//                      + beta_{k-1} w_{j,k-1} - beta_{j-1} w_{j-1,k}
+// estimates its overlaps w_{j+1,k} with the older ones, each step adding a
+// rounding term of unit u (the matvec's relative accuracy).  When an estimate
+// exceeds sqrt(u) the vector is orthogonalised against the whole basis, and so
+// is the next one; the basis stays orthogonal to sqrt(u), which keeps the Ritz
+// values accurate to O(u ||H||).  Restarts every kmax vectors from the Ritz vector.
 template <class MV>
-static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, int kmax, int max_mv) {
+static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, int kmax, int max_mv, double u) {
   LzResult R;
   hipStream_t st = c->stream;
   kmax = std::max(2, std::min(kmax, 64));
@@ -98,28 +110,37 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
     for (int i = 0; i <= kmax; ++i) hp[i] = V + (size_t)i * n;
     HIPCHK(hipMemcpyAsync(ptrs, hp.data(), hp.size() * sizeof(cf64*), hipMemcpyHostToDevice, st));
   }
+  const double thresh = std::sqrt(u);
   double nx = dev_norm2(c, x, n);
   if (!(nx > 0.0) || !std::isfinite(nx)) TN_THROW(TN_ENUMERIC, "Lanczos start vector is zero or non-finite");
   HIPCHK(launch_scale_host(V, x, 1.0 / std::sqrt(nx), n, st));
   double* hout = c->pinned;
   hipEvent_t e0 = c->ev[0], e1 = c->ev[1];
+  // two classical Gram-Schmidt passes of W against V_i0..V_{i0+nv-1}; the second
+  // pass also returns <w, w>; h1, h2 receive the two passes' dots at offset i0
+  auto cgs2 = [&](int i0, int nv) {
+    HIPCHK(launch_multidot(ptrs + i0, nv, W, n, part, nb, st));
+    HIPCHK(launch_multidot_finish(part, nv, nb, h1 + i0, st));
+    HIPCHK(launch_axpy_dot(W, ptrs + i0, nv, h1 + i0, n, part, nb, st));
+    HIPCHK(launch_multidot_finish(part, nv + 1, nb, h2 + i0, st));
+  };
   while (true) {
     int jlast = -1;
     bool stop = false;
     double lam = 0.0;
+    std::vector<double> al, be, om_prev, om_cur{1.0}, om_next;  // om_cur[k] = w_{j,k}
+    double anorm = 0.0;
+    bool force_full = false;
     for (int j = 0; j < kmax; ++j) {
       HIPCHK(hipEventRecord(e0, st));
       matvec(V + (size_t)j * n, W);
       HIPCHK(hipEventRecord(e1, st));
       R.matvecs++;
-      // two passes of classical Gram-Schmidt against V_0..V_j; the second pass
-      // also returns <w, w>, from which ||w|| after the pass follows
-      HIPCHK(launch_multidot(ptrs, j + 1, W, n, part, nb, st));
-      HIPCHK(launch_multidot_finish(part, j + 1, nb, h1, st));
-      // first update fused with the second pass's dot products and <w, w>
-      HIPCHK(launch_axpy_dot(W, ptrs, j + 1, h1, n, part, nb, st));
-      HIPCHK(launch_multidot_finish(part, j + 2, nb, h2, st));
-      HIPCHK(launch_lanczos_step(h1, h2, j, alpha, beta, inv, coefs, sc, st));
+      const bool full = force_full;
+      const int i0 = full ? 0 : std::max(0, j - 1);
+      if (full) R.full_passes++;
+      cgs2(i0, j - i0 + 1);
+      HIPCHK(launch_lanczos_step(h1, h2, j, i0, alpha, beta, inv, coefs, sc, st));
       HIPCHK(hipMemcpyAsync(hout, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       float ms = 0.f;
@@ -133,8 +154,38 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
       const double bscale = std::max(1.0, std::fabs(lam));
       if (res <= tol || b <= 1e-14 * bscale) { R.converged = true; stop = true; break; }
       if (R.matvecs >= max_mv) { stop = true; break; }
-      // second update fused with the normalisation: V_{j+1} = (w - sum h2 V) / beta
-      if (j + 1 < kmax) HIPCHK(launch_axpy_scale(V + (size_t)(j + 1) * n, W, ptrs, j + 1, h2, inv, n, st));
+      if (j + 1 >= kmax) break;
+      al.push_back(a);
+      be.push_back(b);
+      anorm = std::max(anorm, std::fabs(a) + b + (j > 0 ? be[j - 1] : 0.0));
+      // overlap estimates of the new vector with V_0..V_{j-2} (V_{j-1}, V_j were projected out)
+      om_next.assign(j + 2, u);
+      om_next[j + 1] = 1.0;
+      double worst = 0.0;
+      if (!full) {
+        for (int k = 0; k + 1 < j; ++k) {
+          double t = be[k] * om_cur[k + 1] + (al[k] - a) * om_cur[k] + (k > 0 ? be[k - 1] * om_cur[k - 1] : 0.0) -
+                     (j > 0 ? be[j - 1] * om_prev[k] : 0.0);
+          t += (t >= 0.0 ? 1.0 : -1.0) * u * (anorm + be[k] + b);
+          om_next[k] = t / b;
+          worst = std::max(worst, std::fabs(om_next[k]));
+        }
+      }
+      if (worst > thresh) {
+        // the new vector against the whole basis, and the next one as well
+        cgs2(0, j + 1);
+        HIPCHK(launch_inv_norm(h2, j + 1, inv, st));
+        HIPCHK(launch_axpy_scale(V + (size_t)(j + 1) * n, W, ptrs, j + 1, h2, inv, n, st));
+        R.full_passes++;
+        for (int k = 0; k <= j; ++k) om_next[k] = u;
+        force_full = true;
+      } else {
+        // second update fused with the normalisation: V_{j+1} = (w - sum h2 V) / beta
+        HIPCHK(launch_axpy_scale(V + (size_t)(j + 1) * n, W, ptrs + i0, j - i0 + 1, h2 + i0, inv, n, st));
+        force_full = false;
+      }
+      om_prev.swap(om_cur);
+      om_cur.swap(om_next);
     }
     // Ritz vector x = sum_i y_i V_i
     HIPCHK(launch_lincomb(x, ptrs, jlast + 1, coefs, n, st));
@@ -147,6 +198,14 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
     }
     HIPCHK(launch_scale_host(V, x, 1.0 / std::sqrt(xn), n, st));
   }
+}
+
+// relative accuracy of a matvec in the given GEMM form (the unit of the
+// orthogonality estimates)
+static double matvec_unit(int prec) {
+  if (prec == PREC_FP64) return 2.2e-16;
+  if (prec == PREC_FP32) return 1e-6;
+  return 1e-5;
 }
 
 // ------------------------------------------------------------------ truncation
@@ -529,7 +588,9 @@ static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_
   op.setup(c, mpo, s, 1, prec, cl, cr, env_ptrs(m, mpo, true, s, prec), env_ptrs(m, mpo, false, s + 1, prec), true,
            "lbo");
   LzResult lz = lanczos(c, [&](const cf64* x, cf64* y) { op.apply(x, y); }, B, (int64_t)nraw, o.tol, o.krylov_max,
-                        o.lbo_matvecs > 0 ? o.lbo_matvecs : o.max_matvecs);
+                        o.lbo_matvecs > 0 ? o.lbo_matvecs : o.max_matvecs, matvec_unit(prec));
+  c->lz_iters += lz.matvecs;
+  c->lz_full += lz.full_passes;
   if (mv) *mv += lz.matvecs;
   // rho = sum_a B[a] B[a]^dag (D x D): split over a into partial products,
   // then a fixed-order reduction
@@ -629,7 +690,9 @@ static StepStats two_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, int dir, con
   op.setup(c, mpo, s, 2, prec, cl, cr, env_ptrs(m, mpo, true, s, prec), env_ptrs(m, mpo, false, s + 2, prec), false,
            "heff");
   LzResult lz = lanczos(c, [&](const cf64* x, cf64* y) { op.apply(x, y); }, th, (int64_t)nth, o.tol, o.krylov_max,
-                        o.max_matvecs);
+                        o.max_matvecs, matvec_unit(prec));
+  c->lz_iters += lz.matvecs;
+  c->lz_full += lz.full_passes;
   const double t1 = wall();
   S.mv = lz.matvecs;
   S.conv = lz.converged;

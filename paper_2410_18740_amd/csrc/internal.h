@@ -46,6 +46,7 @@ struct tn_ctx {
   std::vector<hipEvent_t> tri_ev;
   double prof_tri_ms = 0.0, prof_tri_bytes = 0.0;
   int64_t prof_tri_n = 0;
+  int64_t lz_iters = 0, lz_full = 0;  // Lanczos iterations, and those orthogonalised against the whole basis
 };
 
 void* dev_alloc(tn_ctx* c, size_t bytes);

@@ -632,8 +632,9 @@ hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream
 // multisection on Sturm counts for the eigenvalue, inverse iteration with
 // partial pivoting (one lane) for the eigenvector, written as Ritz
 // coefficients.  host_out = {alpha, beta, lambda, y_last}.
-__global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const cf64* h2, int j, double* alpha,
-                                                          double* beta, double* inv, double* coefs, double* out) {
+__global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const cf64* h2, int j, int i0,
+                                                          double* alpha, double* beta, double* inv, double* coefs,
+                                                          double* out) {
   __shared__ double sa[80], sb[80], y[80], dd[80], du[80], du2[80], dl[80];
   __shared__ int piv[80];
   __shared__ double lam_s;
@@ -641,7 +642,7 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
   {
     // ||w||^2 after the second pass = <w, w> - sum_i |h2_i|^2 (lanes in parallel)
     double part = 0.0;
-    for (int i = lane; i <= j; i += 64) part += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+    for (int i = i0 + lane; i <= j; i += 64) part += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
     const double sum = wave_sum(part);
     if (lane == 0) {
       const double a = h1[j].x + h2[j].x;
@@ -766,10 +767,27 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
     out[3] = sg * y[n - 1];
   }
 }
-hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, double* alpha, double* beta, double* inv,
-                               double* coefs, double* out, hipStream_t st) {
-  if (j + 1 > 72) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(64), 0, st, h1, h2, j, alpha, beta, inv, coefs, out);
+hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta,
+                               double* inv, double* coefs, double* out, hipStream_t st) {
+  if (j + 1 > 72 || i0 < 0 || i0 > j) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(64), 0, st, h1, h2, j, i0, alpha, beta, inv, coefs, out);
+  return hipGetLastError();
+}
+
+// inv[0] = 1 / sqrt(h[nv] - sum_{i < nv} |h_i|^2): the norm after a Gram-Schmidt
+// update whose second-pass dots are h[0..nv) and whose <w, w> before it is h[nv]
+__global__ __launch_bounds__(64) void inv_norm_kernel(const cf64* h, int nv, double* inv) {
+  const int lane = threadIdx.x;
+  double part = 0.0;
+  for (int i = lane; i < nv; i += 64) part += h[i].x * h[i].x + h[i].y * h[i].y;
+  const double sum = wave_sum(part);
+  if (lane == 0) {
+    const double w2 = h[nv].x - sum;
+    inv[0] = (w2 > 0.0) ? 1.0 / sqrt(w2) : 0.0;
+  }
+}
+hipError_t launch_inv_norm(const cf64* h, int nv, double* inv, hipStream_t st) {
+  hipLaunchKernelGGL(inv_norm_kernel, dim3(1), dim3(64), 0, st, h, nv, inv);
   return hipGetLastError();
 }
 // gather real parts of column 0 of an n x n complex matrix (eigenvectors as columns)
