@@ -177,6 +177,11 @@ hipError_t launch_orthonormalize_real(double* X, int p, int k, int j0, double* H
 hipError_t launch_ortho_check(const double* X, int p, int k, double tol, int* bad, hipStream_t st);
 hipError_t launch_backtransform(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
                                 hipStream_t st);
+// the same with the reflectors in blocks of 16 (compact WY); Tws holds
+// backtransform_wy_workspace(p) complex entries; sizes beyond 3072 use the above
+size_t backtransform_wy_workspace(int p);
+hipError_t launch_backtransform_wy(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
+                                   cf64* Tws, hipStream_t st);
 
 hipError_t launch_transpose_from64(int prec, void* dst, const cf64* src, int batch, int rows, int cols, hipStream_t st);
 hipError_t launch_transpose_to64(int prec, cf64* dst, const void* src, int batch, int rows, int cols, hipStream_t st);

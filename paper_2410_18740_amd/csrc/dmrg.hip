@@ -276,7 +276,8 @@ static void herm_top(tn_ctx* c, cf64* G, int p, int kk, std::vector<double>& eva
     if (hb[j]) { j0 = j; break; }
   HIPCHK(launch_orthonormalize_real(X, p, kk, j0, wsT<double>(c, "eig:H", (size_t)kk * 16), st));
   Z = wsT<cf64>(c, "eig:Z", (size_t)p * kk);
-  HIPCHK(launch_backtransform(tw.vs, tw.taus, p, X, kk, Z, st));
+  HIPCHK(launch_backtransform_wy(tw.vs, tw.taus, p, X, kk, Z, wsT<cf64>(c, "eig:T", backtransform_wy_workspace(p)),
+                                 st));
   evals.resize(kk);
   download(c, evals.data(), ev, kk * sizeof(double));
   ldz = kk;

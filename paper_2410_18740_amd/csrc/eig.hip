@@ -229,17 +229,36 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   double re = 0.0, im = 0.0;
   // each thread owns the entries q = j + tid (mod 256) of the LDS vectors up to
   // the reflector, so only the two reductions need workgroup barriers
-  for (int q = j + tid; q < p; q += 256) {
-    const cf64 r = rowj[q];
-    vS[q] = cconj(r);
-    if (j > 0) {
-      const cf64 yy = yprev[q], vv = vprev[q];
-      wS[q] = yy;
-      pS[q] = vv;
-      re += yy.x * vv.x + yy.y * vv.y;
-      im += yy.x * vv.y - yy.y * vv.x;
+  // loads of four entries at a time are issued together (clamped addresses,
+  // masked use) so that they share one round trip; the first group is outside
+  // any loop, so its loads are in flight together with the row loads above
+  auto fill = [&](int q0) {
+    cf64 rr[4], yy[4], vv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int qc = min(q0 + 256 * t, p - 1);
+      rr[t] = rowj[qc];
+      if (j > 0) {
+        yy[t] = yprev[qc];
+        vv[t] = vprev[qc];
+      }
     }
-  }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = q0 + 256 * t;
+      if (q < p) {
+        vS[q] = cconj(rr[t]);
+        if (j > 0) {
+          wS[q] = yy[t];
+          pS[q] = vv[t];
+          re += yy[t].x * vv[t].x + yy[t].y * vv[t].y;
+          im += yy[t].x * vv[t].y - yy[t].y * vv[t].x;
+        }
+      }
+    }
+  };
+  fill(j + tid);
+  for (int q0 = j + tid + 256 * 4; q0 < p; q0 += 256 * 4) fill(q0);
   // ---- w_{j-1} = y_{j-1} - 1/2 tau_{j-1} (y_{j-1}^H v_{j-1}) v_{j-1}
   cf64 c = czero<cf64>();
   if (j > 0) {
@@ -255,12 +274,13 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   // ---- column j (rows >= j) with the pending update; reflector
   const cf64 wj = (j > 0) ? cadd(yj, cmul(c, pj)) : czero<cf64>();
   const cf64 vj = pj;
-  if (blockIdx.x == 0 && tid == 0) {
-    double d = vS[j].x;
-    if (j > 0) d -= 2.0 * (vj.x * wj.x + vj.y * wj.y);
-    dg[j] = d;
+  // diagonal entry j (stored at the end: a store here would stall the row loads)
+  double dj = vS[j].x;
+  if (j > 0) dj -= 2.0 * (vj.x * wj.x + vj.y * wj.y);
+  if (j == p - 1) {
+    if (blockIdx.x == 0 && tid == 0) dg[j] = dj;
+    return;
   }
-  if (j == p - 1) return;
   double nrm = 0.0;
   for (int q = j + tid; q < p; q += 256) {
     if (q == j) continue;
@@ -273,6 +293,7 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   if (lane == 0) red2[wave] = nrm;
   __syncthreads();
   cf64 tau, scale;
+  double offj;
   {
     const double xn2 = red2[0] + red2[1] + red2[2] + red2[3];
     const cf64 alpha = vS[j + 1];
@@ -289,20 +310,15 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
       const double dd = den.x * den.x + den.y * den.y;
       scale = make_double2(den.x / dd, -den.y / dd);
     }
-    if (blockIdx.x == 0 && tid == 0) { taus[j] = tau; off[j] = beta; }
-  }
-  if (blockIdx.x == 0) {
-    cf64* vout = vs + (int64_t)j * p;
-    for (int q = tid; q < p; q += 256) {
-      cf64 v = czero<cf64>();
-      if (q == j + 1) v = make_double2(1.0, 0.0);
-      else if (q > j + 1) v = cmul(vS[q], scale);
-      vout[q] = v;
-    }
+    offj = beta;
   }
   // ---- own rows: wavefronts (2r, 2r+1) share row i, interleaved by 128 columns
   re = 0.0;
   im = 0.0;
+  // the last chunk's updated entries are stored after the final barrier: a
+  // barrier waits for the wave's outstanding stores
+  cf64 xs[TRI_UNROLL];
+  int klast = -1;
   if (own) {
     cf64 vi = czero<cf64>(), wi = czero<cf64>();
     if (j > 0) { vi = pS[i]; wi = wS[i]; }
@@ -318,18 +334,29 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
           a[u] = (k < p) ? row[k] : czero<cf64>();
         }
       }
+      // every update first, then all the stores: a store between two uses of
+      // loaded data would make the wave wait for the store's completion
+      // (loads and stores share one completion counter)
 #pragma unroll
       for (int u = 0; u < TRI_UNROLL; ++u) {
         const int k = k0 + tl + 128 * u;
+        xs[u] = czero<cf64>();
         if (k < p) {
           cf64 x = a[u];
-          if (j > 0) {
-            x = csub(x, cadd(cmulc(vi, wS[k]), cmulc(wi, pS[k])));
-            row[k] = x;
-          }
+          if (j > 0) x = csub(x, cadd(cmulc(vi, wS[k]), cmulc(wi, pS[k])));
+          xs[u] = x;
           const cf64 vk = (k == j + 1) ? make_double2(1.0, 0.0) : cmul(vS[k], scale);
           re += x.x * vk.x - x.y * vk.y;
           im += x.x * vk.y + x.y * vk.x;
+        }
+      }
+      if (k0 + 128 * TRI_UNROLL >= p) {
+        klast = k0;
+      } else if (j > 0) {
+#pragma unroll
+        for (int u = 0; u < TRI_UNROLL; ++u) {
+          const int k = k0 + tl + 128 * u;
+          if (k < p) row[k] = xs[u];
         }
       }
     }
@@ -338,10 +365,33 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   im = wave_sum_d(im);
   if (lane == 0) { part[rl][half][0] = re; part[rl][half][1] = im; }
   __syncthreads();
+  // every store from here on
   if (tid < TRI_ROWS) {
     const int ii = i0 + 8 * (slot * TRI_ROWS + tid);
     if (j < p - 1 && ii < p)
       ycur[ii] = cmul(tau, make_double2(part[tid][0][0] + part[tid][1][0], part[tid][0][1] + part[tid][1][1]));
+  }
+  if (klast >= 0 && j > 0) {
+#pragma unroll
+    for (int u = 0; u < TRI_UNROLL; ++u) {
+      const int k = klast + tl + 128 * u;
+      if (k < p) row[k] = xs[u];
+    }
+  }
+  // workgroup 0 stores the reflector, tau, and the tridiagonal entries j
+  if (blockIdx.x == 0) {
+    cf64* vout = vs + (int64_t)j * p;
+    for (int q = tid; q < p; q += 256) {
+      cf64 v = czero<cf64>();
+      if (q == j + 1) v = make_double2(1.0, 0.0);
+      else if (q > j + 1) v = cmul(vS[q], scale);
+      vout[q] = v;
+    }
+    if (tid == 0) {
+      taus[j] = tau;
+      off[j] = offj;
+      dg[j] = dj;
+    }
   }
 }
 
@@ -772,6 +822,165 @@ __global__ __launch_bounds__(64) void backtransform_kernel(const cf64* __restric
   }
   for (int i = lane; i < p; i += 64) U[(int64_t)i * k + col] = x[i];
 }
+// ------------------------------------------------------------------ blocked back-transform
+// The reflectors H_j = 1 - tau_j v_j v_j^H in blocks of WY_NB consecutive ones:
+// H_j0 ... H_{j0+m-1} = 1 - V T V^H with T upper triangular (the compact WY form
+// of Schreiber and Van Loan, SIAM J. Sci. Stat. Comput. 10, 1989): T_ii = tau_i,
+// T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i], S = V^H V.  One workgroup per block
+// builds T; the apply kernel then costs two passes over a block's reflectors and
+// one batch of reductions per block instead of a dependent chain per reflector.
+constexpr int WY_NB = 16;
+constexpr int WY_T = 512;
+
+__global__ __launch_bounds__(256) void wy_factor_kernel(const cf64* __restrict__ vs, const cf64* __restrict__ taus,
+                                                         int p, cf64* __restrict__ Tout) {
+  __shared__ cf64 S[WY_NB][WY_NB];
+  __shared__ cf64 T[WY_NB][WY_NB];
+  const int b = blockIdx.x, j0 = b * WY_NB;
+  const int m = min(WY_NB, p - 1 - j0);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // S[l][i] = v_l^H v_i for l < i, over rows r > j0 + i (v_i is zero above)
+  for (int q = wv; q < WY_NB * WY_NB; q += 4) {
+    const int l = q / WY_NB, i = q % WY_NB;
+    if (l >= i || i >= m) continue;
+    const cf64* vl = vs + (int64_t)(j0 + l) * p;
+    const cf64* vi = vs + (int64_t)(j0 + i) * p;
+    double re = 0.0, im = 0.0;
+    for (int r = j0 + i + 1 + lane; r < p; r += 64) {
+      const cf64 a = vl[r], c = vi[r];
+      re += a.x * c.x + a.y * c.y;
+      im += a.x * c.y - a.y * c.x;
+    }
+    re = wave_sum_d(re);
+    im = wave_sum_d(im);
+    if (lane == 0) S[l][i] = make_double2(re, im);
+  }
+  for (int q = tid; q < WY_NB * WY_NB; q += 256) T[q / WY_NB][q % WY_NB] = czero<cf64>();
+  __syncthreads();
+  for (int i = 0; i < m; ++i) {
+    const cf64 ti = taus[j0 + i];
+    cf64 v = czero<cf64>();
+    if (tid < i) {
+      for (int q = tid; q < i; ++q) v = cadd(v, cmul(T[tid][q], S[q][i]));
+    }
+    __syncthreads();
+    if (tid < i) T[tid][i] = cmul(make_double2(-ti.x, -ti.y), v);
+    if (tid == i) T[i][i] = ti;
+    __syncthreads();
+  }
+  cf64* out = Tout + (int64_t)b * WY_NB * WY_NB;
+  for (int q = tid; q < WY_NB * WY_NB; q += 256) out[q] = T[q / WY_NB][q % WY_NB];
+}
+
+// One workgroup of WY_T threads per eigenvector column; thread t keeps rows
+// t + WY_T e (e < MAXE).
+// Blocks are applied last to first: U = Q_0 Q_1 ... X with Q_b = 1 - V_b T_b V_b^H.
+template <int MAXE>
+__global__ __launch_bounds__(WY_T) void wy_apply_kernel(const cf64* __restrict__ vs, const cf64* __restrict__ Tw,
+                                                        int p, const double* __restrict__ X, int k,
+                                                        cf64* __restrict__ U) {
+  __shared__ double red[WY_T / 64][2 * WY_NB];
+  __shared__ cf64 w[WY_NB], w2[WY_NB];
+  __shared__ cf64 Ts[WY_NB * WY_NB];
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  cf64 x[MAXE];
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int r = tid + WY_T * e;
+    x[e] = make_double2(r < p ? X[(int64_t)col * p + r] : 0.0, 0.0);
+  }
+  const int nblk = (p - 1 + WY_NB - 1) / WY_NB;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int j0 = b * WY_NB;
+    const int m = min(WY_NB, p - 1 - j0);
+    // T_b to LDS (one entry per thread), in flight while the dots are formed
+    for (int q = tid; q < WY_NB * WY_NB; q += WY_T) Ts[q] = Tw[(int64_t)b * WY_NB * WY_NB + q];
+    // partial dots v_i^H x over this thread's rows (v_i is zero for r <= j0 + i)
+    double pr[WY_NB], pi[WY_NB];
+#pragma unroll
+    for (int i = 0; i < WY_NB; ++i) {
+      pr[i] = 0.0;
+      pi[i] = 0.0;
+      // the stored reflectors carry explicit zeros above their support, so the
+      // loads need no mask; rows past p are clamped and weighted by zero, and
+      // i >= m reads the block's last reflector (its dot is not used)
+      const cf64* vi = vs + (int64_t)(j0 + min(i, m - 1)) * p;
+#pragma unroll
+      for (int e = 0; e < MAXE; ++e) {
+        const int r = tid + WY_T * e;
+        const cf64 a = vi[min(r, p - 1)];
+        const double f = (r < p) ? 1.0 : 0.0;
+        pr[i] += f * (a.x * x[e].x + a.y * x[e].y);
+        pi[i] += f * (a.x * x[e].y - a.y * x[e].x);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WY_NB; ++i) {
+      const double sr = wave_sum_d(pr[i]);
+      const double si = wave_sum_d(pi[i]);
+      if (lane == 0) {
+        red[wv][2 * i] = sr;
+        red[wv][2 * i + 1] = si;
+      }
+    }
+    __syncthreads();
+    if (tid < WY_NB) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < WY_T / 64; ++q) {
+        sr += red[q][2 * tid];
+        si += red[q][2 * tid + 1];
+      }
+      w[tid] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (tid < m) {
+      cf64 v = czero<cf64>();
+#pragma unroll
+      for (int l = 0; l < WY_NB; ++l)
+        if (l >= tid && l < m) v = cadd(v, cmul(Ts[tid * WY_NB + l], w[l]));
+      w2[tid] = v;
+    }
+    __syncthreads();
+    // x -= V_b w2
+#pragma unroll
+    for (int i = 0; i < WY_NB; ++i) {
+      const cf64* vi = vs + (int64_t)(j0 + min(i, m - 1)) * p;
+      const cf64 c = (i < m) ? w2[i] : czero<cf64>();
+#pragma unroll
+      for (int e = 0; e < MAXE; ++e) {
+        const int r = tid + WY_T * e;
+        const cf64 a = vi[min(r, p - 1)];  // rows past p are never stored
+        x[e] = csub(x[e], cmul(c, a));
+      }
+    }
+    __syncthreads();  // w, w2 and red are rewritten by the next block
+  }
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int r = tid + WY_T * e;
+    if (r < p) U[(int64_t)r * k + col] = x[e];
+  }
+}
+
+size_t backtransform_wy_workspace(int p) { return (size_t)((p - 1 + WY_NB - 1) / WY_NB) * WY_NB * WY_NB; }
+
+hipError_t launch_backtransform_wy(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
+                                   cf64* Tws, hipStream_t st) {
+  if (p < 2 || k < 1) return hipErrorInvalidValue;
+  if (p > WY_T * 6) return launch_backtransform(vs, taus, p, X, k, U, st);
+  const int nblk = (p - 1 + WY_NB - 1) / WY_NB;
+  hipLaunchKernelGGL(wy_factor_kernel, dim3(nblk), dim3(256), 0, st, vs, taus, p, Tws);
+  if (p <= WY_T * 2)
+    hipLaunchKernelGGL((wy_apply_kernel<2>), dim3(k), dim3(WY_T), 0, st, vs, Tws, p, X, k, U);
+  else if (p <= WY_T * 4)
+    hipLaunchKernelGGL((wy_apply_kernel<4>), dim3(k), dim3(WY_T), 0, st, vs, Tws, p, X, k, U);
+  else
+    hipLaunchKernelGGL((wy_apply_kernel<6>), dim3(k), dim3(WY_T), 0, st, vs, Tws, p, X, k, U);
+  return hipGetLastError();
+}
+
 hipError_t launch_backtransform(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
                                 hipStream_t st) {
   if (p <= 64 * 8)
