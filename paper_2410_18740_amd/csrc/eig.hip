@@ -410,6 +410,15 @@ hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ bisection (top-k)
+// 1/q from the hardware reciprocal refined by two Newton steps
+// (r <- r + r (1 - q r)), each of which squares the relative error
+static __device__ __forceinline__ double recip_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
 static __device__ int sturm_count(const double* dS, const double* e2S, int p, double x, double pivmin) {
   // number of eigenvalues < x; dS, e2S: diagonal and squared off-diagonal in LDS
   int cnt = 0;
@@ -418,42 +427,52 @@ static __device__ int sturm_count(const double* dS, const double* e2S, int p, do
   if (q < 0) ++cnt;
 #pragma unroll 4
   for (int i = 1; i < p; ++i) {
-    q = (dS[i] - x) - e2S[i - 1] / q;
+    q = (dS[i] - x) - e2S[i - 1] * recip_nr(q);
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0) ++cnt;
   }
   return cnt;
 }
 
-// One wavefront per wanted eigenvalue: each round every lane counts the
-// eigenvalues below one of 64 equispaced probes of the current interval, and
-// the interval shrinks to the probe gap that holds the target (64-way
-// multisection; 10-12 rounds reach full double precision).
-__global__ __launch_bounds__(64) void bisect_kernel(const double* dg, const double* off, int p, int k,
-                                                    double* evals) {
+// One workgroup of BIS_T threads per wanted eigenvalue: each round every thread
+// counts the eigenvalues below one of BIS_T equispaced probes of the current
+// interval, and the interval shrinks to the probe gap that holds the target
+// (BIS_T-way multisection; seven or eight rounds reach full double precision).
+constexpr int BIS_T = 256;
+__global__ __launch_bounds__(BIS_T) void bisect_kernel(const double* dg, const double* off, int p, int k,
+                                                       double* evals) {
   extern __shared__ unsigned char sm_raw[];
   double* dS = reinterpret_cast<double*>(sm_raw);
   double* e2S = dS + p;
+  __shared__ double rlo[BIS_T / 64], rhi[BIS_T / 64], rem[BIS_T / 64];
+  __shared__ int nle_w[BIS_T / 64];
   const int t = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (t >= k) return;
-  for (int i = lane; i < p; i += 64) {
-    dS[i] = dg[i];
-    e2S[i] = (i < p - 1) ? off[i] * off[i] : 0.0;
-  }
-  __syncthreads();
   double lo = 1e300, hi = -1e300, emax = 0.0;
-  for (int i = lane; i < p; i += 64) {
-    const double r = (i > 0 ? fabs(off[i - 1]) : 0.0) + (i < p - 1 ? fabs(off[i]) : 0.0);
-    lo = fmin(lo, dg[i] - r);
-    hi = fmax(hi, dg[i] + r);
-    if (i < p - 1) emax = fmax(emax, off[i] * off[i]);
+  for (int i = tid; i < p; i += BIS_T) {
+    const double di = dg[i], oi = (i < p - 1) ? off[i] : 0.0, om = (i > 0) ? off[i - 1] : 0.0;
+    dS[i] = di;
+    e2S[i] = oi * oi;
+    const double r = fabs(om) + fabs(oi);
+    lo = fmin(lo, di - r);
+    hi = fmax(hi, di + r);
+    emax = fmax(emax, oi * oi);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, o, 64));
     hi = fmax(hi, __shfl_xor(hi, o, 64));
     emax = fmax(emax, __shfl_xor(emax, o, 64));
+  }
+  if (lane == 0) { rlo[wv] = lo; rhi[wv] = hi; rem[wv] = emax; }
+  __syncthreads();
+  lo = rlo[0]; hi = rhi[0]; emax = rem[0];
+#pragma unroll
+  for (int q = 1; q < BIS_T / 64; ++q) {
+    lo = fmin(lo, rlo[q]);
+    hi = fmax(hi, rhi[q]);
+    emax = fmax(emax, rem[q]);
   }
   const double scale = fmax(fabs(lo), fabs(hi));
   const double pivmin = fmax(1e-300, 2.3e-308 * fmax(1.0, emax));
@@ -462,23 +481,30 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* dg, const doub
   const int target = p - 1 - t;  // ascending index of the t-th largest
   for (int it = 0; it < 40; ++it) {
     if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
-    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const double w = (hi - lo) / (double)(BIS_T + 1);
+    const double x = lo + w * (double)(tid + 1);
     const int c = sturm_count(dS, e2S, p, x, pivmin);
-    // probes with count <= target lie left of the eigenvalue
+    // probes with count <= target lie left of the eigenvalue; probes increase
+    // with the thread index, so those are threads 0 .. nle - 1
     const unsigned long long le = __ballot(c <= target);
-    const int nle = __popcll(le);          // probes are increasing, so these are lanes 0..nle-1
-    const double nlo = (nle == 0) ? lo : __shfl(x, nle - 1, 64);
-    const double nhi = (nle == 64) ? hi : __shfl(x, nle, 64);
+    __syncthreads();  // the previous round's nle_w has been read
+    if (lane == 0) nle_w[wv] = __popcll(le);
+    __syncthreads();
+    int nle = 0;
+#pragma unroll
+    for (int q = 0; q < BIS_T / 64; ++q) nle += nle_w[q];
+    const double nlo = (nle == 0) ? lo : lo + w * (double)nle;
+    const double nhi = (nle == BIS_T) ? hi : lo + w * (double)(nle + 1);
     if (!(nhi - nlo < hi - lo)) break;
     lo = nlo;
     hi = nhi;
   }
-  if (lane == 0) evals[t] = 0.5 * (lo + hi);
+  if (tid == 0) evals[t] = 0.5 * (lo + hi);
 }
 hipError_t launch_bisect_top(const double* dg, const double* off, int p, int k, double* evals, hipStream_t st) {
   const size_t shm = (size_t)2 * p * sizeof(double);
-  if (shm > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(bisect_kernel, dim3(k), dim3(64), shm, st, dg, off, p, k, evals);
+  if (shm > 150 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(bisect_kernel, dim3(k), dim3(BIS_T), shm, st, dg, off, p, k, evals);
   return hipGetLastError();
 }
 
@@ -521,14 +547,14 @@ __global__ __launch_bounds__(64) void inverse_iter_kernel(const double* __restri
       const double l = dl[i], ndd = dd[i + 1], ndu = du[i + 1];
       if (fabs(cdd) >= fabs(l)) {
         if (cdd == 0.0) cdd = tiny;
-        const double f = l / cdd;
+        const double f = l * recip_nr(cdd);
         dd[i] = cdd;
         dl[i] = f;
         du[i] = cdu;
         cdd = ndd - f * cdu;
         cdu = ndu;
       } else {
-        const double f = cdd / l;
+        const double f = cdd * recip_nr(l);
         dd[i] = l;
         dl[i] = f;
         du[i] = ndd;
@@ -541,8 +567,13 @@ __global__ __launch_bounds__(64) void inverse_iter_kernel(const double* __restri
     dd[p - 1] = cdd;
   }
   __syncthreads();
-  for (int i = lane; i < p; i += 64)
-    if (fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
+  // the pivots are used only through their reciprocals (no division on the
+  // solves' dependent chains)
+  for (int i = lane; i < p; i += 64) {
+    double v = dd[i];
+    if (fabs(v) < tiny) v = v >= 0 ? tiny : -tiny;
+    dd[i] = 1.0 / v;
+  }
   __syncthreads();
   for (int it = 0; it < 2; ++it) {
     if (lane == 0) {
@@ -552,17 +583,17 @@ __global__ __launch_bounds__(64) void inverse_iter_kernel(const double* __restri
         if (piv[i]) { b[i] = nb; cb = cb - l * nb; }
         else { b[i] = cb; cb = nb - l * cb; }
       }
-      double x1 = cb / dd[p - 1];
+      double x1 = cb * dd[p - 1];
       b[p - 1] = x1;
       double x2 = 0.0;
       if (p >= 2) {
-        const double x0 = (b[p - 2] - du[p - 2] * x1) / dd[p - 2];
+        const double x0 = (b[p - 2] - du[p - 2] * x1) * dd[p - 2];
         b[p - 2] = x0;
         x2 = x1;
         x1 = x0;
       }
       for (int i = p - 3; i >= 0; --i) {
-        const double x0 = (b[i] - du[i] * x1 - du2[i] * x2) / dd[i];
+        const double x0 = (b[i] - du[i] * x1 - du2[i] * x2) * dd[i];
         b[i] = x0;
         x2 = x1;
         x1 = x0;

@@ -262,6 +262,27 @@ def test_truncate_full_size(ctx):
     assert np.abs(left.conj().T @ left - np.eye(128)).max() < 1e-12
 
 
+@pytest.mark.parametrize("m,n,direction", [(1300, 1100, 1), (300, 1300, -1), (2560, 300, 1)])
+def test_truncate_gram_beyond_1024(ctx, m, n, direction):
+    """Gram sizes 1300 and 2560 (the 48-mode middle step): Householder rows
+    longer than one 1024-entry chunk, and the wider back-transform forms."""
+    import paper_2410_18740_amd as P
+    rng = np.random.default_rng(m + 7 * n)
+    th = _spectrum_matrix(m, n, rng, 0.97)
+    th /= np.linalg.norm(th)
+    left, right, sv, disc = P.truncate(ctx, to_dev(th), 128, 0.0, direction)
+    S_ref = np.linalg.svd(th, compute_uv=False)
+    print(f"p={m if direction > 0 else n}: sv2 err {np.abs(sv ** 2 - S_ref[:128] ** 2).max():.2e}")
+    assert np.abs(sv ** 2 - S_ref[:128] ** 2).max() < 1e-14
+    assert abs(disc - np.sum(S_ref[128:] ** 2)) < 1e-12
+    left, right = from_dev(left), from_dev(right)
+    U, S, Vh = np.linalg.svd(th, full_matrices=False)
+    best = (U[:, :128] * S[:128]) @ Vh[:128]
+    assert np.linalg.norm(left @ right - best / np.linalg.norm(S[:128])) < 1e-10
+    iso = left.conj().T @ left if direction > 0 else right @ right.conj().T
+    assert np.abs(iso - np.eye(128)).max() < 1e-12
+
+
 # ---------------------------------------------------------------- energy, flops, philox
 def test_energy_matches_oracle(ctx):
     import paper_2410_18740_amd as P
