@@ -57,6 +57,15 @@ struct GemmJob {
   int32_t seg0, nseg;
 };
 
+// 1/q from the hardware reciprocal refined by two Newton steps
+// (r <- r + r (1 - q r)), each of which squares the relative error
+static __device__ __forceinline__ double recip_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
 // ------------------------------------------------------------------ wavefront reduction (DPP)
 // Sum over the 64 lanes of a wavefront with data-parallel-primitive moves
 // (register crossbar, no LDS traffic): quad xor 1 and 2, half-row and row

@@ -23,19 +23,20 @@ static __device__ __forceinline__ void rr_pair(int r, int k, int n2, int& p, int
   if (p > q) { int t = p; p = q; q = t; }
 }
 
-__global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ain, int64_t strideA, int n,
+template <int JT>
+__global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain, int64_t strideA, int n,
                                                       double* __restrict__ evals, cf64* __restrict__ Vout,
                                                       int64_t strideV, int descending) {
   __shared__ cf64 A[JAC_N][JAC_N];
   __shared__ cf64 V[JAC_N][JAC_N];
   __shared__ double rot[JAC_N / 2][4];  // cs, sn, cos(phi), sin(phi)
   __shared__ int pr[JAC_N / 2][2];
-  __shared__ double red[2][4];
+  __shared__ double red[2][JT / 64];
   __shared__ int done;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cf64* a_in = Ain + (int64_t)blockIdx.x * strideA;
   const int n2 = n + (n & 1);
-  for (int e = tid; e < n2 * n2; e += 256) {
+  for (int e = tid; e < n2 * n2; e += JT) {
     const int i = e / n2, j = e % n2;
     A[i][j] = (i < n && j < n) ? a_in[(int64_t)i * n + j] : czero<cf64>();
     V[i][j] = (i == j) ? make_double2(1.0, 0.0) : czero<cf64>();
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ai
   if (tid == 0) done = 0;
   __syncthreads();
   // symmetrise (Hermitian part) for robustness
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += JT) {
     const int i = e / n, j = e % n;
     if (i < j) {
       cf64 x = A[i][j], y = A[j][i];
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ai
       }
       __syncthreads();
       // column update: A <- A J, V <- V J with J = [[cs, sn], [-sn e^{-i phi}, cs e^{-i phi}]]
-      for (int e = tid; e < npairs * n2; e += 256) {
+      for (int e = tid; e < npairs * n2; e += JT) {
         const int k = e / n2, row = e % n2;
         const double cs = rot[k][0], sn = rot[k][1];
         if (sn == 0.0) continue;
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ai
       }
       __syncthreads();
       // row update: A <- J^H A, J^H = [[cs, -sn e^{i phi}], [sn, cs e^{i phi}]]
-      for (int e = tid; e < npairs * n2; e += 256) {
+      for (int e = tid; e < npairs * n2; e += JT) {
         const int k = e / n2, col = e % n2;
         const double cs = rot[k][0], sn = rot[k][1];
         if (sn == 0.0) continue;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ai
     }
     // convergence test
     double off = 0.0, dia = 0.0;
-    for (int e = tid; e < n * n; e += 256) {
+    for (int e = tid; e < n * n; e += JT) {
       const int i = e / n, j = e % n;
       const double v = cabs2(A[i][j]);
       if (i == j) dia += v; else off += v;
@@ -132,8 +133,11 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ai
     if (lane == 0) { red[0][wave] = off; red[1][wave] = dia; }
     __syncthreads();
     if (tid == 0) {
-      const double o = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-      const double d = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+      double o = 0.0, d = 0.0;
+      for (int w = 0; w < JT / 64; ++w) {
+        o += red[0][w];
+        d += red[1][w];
+      }
       done = (o <= 1e-31 * d) || (o < 1e-300);
     }
     __syncthreads();
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ai
   // sort (rank by value, ties by index) and write
   double* ev = evals + (int64_t)blockIdx.x * n;
   cf64* vo = Vout + (int64_t)blockIdx.x * strideV;
-  for (int p = tid; p < n; p += 256) {
+  for (int p = tid; p < n; p += JT) {
     const double lp = A[p][p].x;
     int rank = 0;
     for (int q = 0; q < n; ++q) {
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const cf64* __restrict__ Ai
 hipError_t launch_jacobi(const cf64* A, int64_t strideA, int n, int batch, double* evals, cf64* V, int64_t strideV,
                          int descending, hipStream_t st) {
   if (n < 1 || n > JAC_N || batch <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(batch), dim3(256), 0, st, A, strideA, n, evals, V, strideV, descending);
+  hipLaunchKernelGGL(jacobi_kernel<256>, dim3(batch), dim3(256), 0, st, A, strideA, n, evals, V, strideV, descending);
   return hipGetLastError();
 }
 
@@ -410,15 +414,6 @@ hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ bisection (top-k)
-// 1/q from the hardware reciprocal refined by two Newton steps
-// (r <- r + r (1 - q r)), each of which squares the relative error
-static __device__ __forceinline__ double recip_nr(double q) {
-  double r = __builtin_amdgcn_rcp(q);
-  r = fma(r, fma(-q, r, 1.0), r);
-  r = fma(r, fma(-q, r, 1.0), r);
-  return r;
-}
-
 static __device__ int sturm_count(const double* dS, const double* e2S, int p, double x, double pivmin) {
   // number of eigenvalues < x; dS, e2S: diagonal and squared off-diagonal in LDS
   int cnt = 0;

@@ -632,6 +632,100 @@ hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream
 // multisection on Sturm counts for the eigenvalue, inverse iteration with
 // partial pivoting (one lane) for the eigenvector, written as Ritz
 // coefficients.  host_out = {alpha, beta, lambda, y_last}.
+// Lowest eigenvector of the n x n tridiagonal (sa, sb) at the eigenvalue lam by
+// three steps of inverse iteration with an LU factorisation with partial
+// pivoting of T - lam I, all in registers (n <= MN): no LDS round trip on the
+// dependent chains.  Writes y (normalised, first component >= 0) to coefs and
+// returns its last component.
+template <int MN>
+static __device__ double tri_eigvec_reg(const double* sa, const double* sb, int n, double lam, double tiny,
+                                        double* coefs) {
+  double dd[MN], du[MN], du2[MN], dl[MN], y[MN];
+  unsigned long long piv = 0;
+#pragma unroll
+  for (int i = 0; i < MN; ++i) {
+    dd[i] = (i < n) ? sa[i] - lam : 1.0;
+    du[i] = (i < n - 1) ? sb[i] : 0.0;
+    dl[i] = du[i];
+    du2[i] = 0.0;
+  }
+  {
+    double cdd = dd[0], cdu = du[0];
+#pragma unroll
+    for (int i = 0; i < MN - 1; ++i) {
+      if (i < n - 1) {
+        const double l = dl[i], ndd = dd[i + 1], ndu = du[i + 1];
+        if (fabs(cdd) >= fabs(l)) {
+          if (cdd == 0.0) cdd = tiny;
+          const double f = l * recip_nr(cdd);
+          dd[i] = cdd;
+          dl[i] = f;
+          du[i] = cdu;
+          cdd = ndd - f * cdu;
+          cdu = ndu;
+        } else {
+          const double f = cdd * recip_nr(l);
+          dd[i] = l;
+          dl[i] = f;
+          du[i] = ndd;
+          piv |= 1ull << i;
+          cdd = cdu - f * ndd;
+          if (i < n - 2) { du2[i] = ndu; cdu = -f * ndu; }
+          else cdu = ndu;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MN; ++i)
+      if (i == n - 1) dd[i] = cdd;
+  }
+  // reciprocal pivots
+#pragma unroll
+  for (int i = 0; i < MN; ++i) {
+    double v = dd[i];
+    if (fabs(v) < tiny) v = v >= 0 ? tiny : -tiny;
+    dd[i] = 1.0 / v;
+    y[i] = 1.0;
+  }
+  for (int it = 0; it < 3; ++it) {
+    double cb = y[0];
+#pragma unroll
+    for (int i = 0; i < MN - 1; ++i) {
+      if (i < n - 1) {
+        const double nb = y[i + 1], l = dl[i];
+        if ((piv >> i) & 1ull) { y[i] = nb; cb = cb - l * nb; }
+        else { y[i] = cb; cb = nb - l * cb; }
+      }
+    }
+    double x1 = 0.0, x2 = 0.0;
+#pragma unroll
+    for (int i = MN - 1; i >= 0; --i) {
+      if (i < n) {
+        const double bi = (i == n - 1) ? cb : y[i];
+        const double x0 = (bi - du[i] * x1 - du2[i] * x2) * dd[i];  // du[n-1] = du2[n-2..] = 0
+        y[i] = x0;
+        x2 = x1;
+        x1 = x0;
+      }
+    }
+    double nr = 0.0;
+#pragma unroll
+    for (int i = 0; i < MN; ++i)
+      if (i < n) nr += y[i] * y[i];
+    nr = 1.0 / sqrt(nr);
+#pragma unroll
+    for (int i = 0; i < MN; ++i) y[i] *= nr;
+  }
+  const double sg = (y[0] < 0.0) ? -1.0 : 1.0;
+  double last = 0.0;
+#pragma unroll
+  for (int i = 0; i < MN; ++i) {
+    if (i < n) coefs[i] = sg * y[i];
+    if (i == n - 1) last = sg * y[i];
+  }
+  return last;
+}
+
 __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const cf64* h2, int j, int i0,
                                                           double* alpha, double* beta, double* inv, double* coefs,
                                                           double* out) {
@@ -681,7 +775,7 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
     if (fabs(q) < 1e-300) q = -1e-300;
     cnt += q < 0;
     for (int i = 1; i < n; ++i) {
-      q = (sa[i] - x) - sb[i - 1] * sb[i - 1] / q;
+      q = (sa[i] - x) - sb[i - 1] * sb[i - 1] * recip_nr(q);
       if (fabs(q) < 1e-300) q = -1e-300;
       cnt += q < 0;
     }
@@ -693,7 +787,14 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
     lo = nlo;
     hi = nhi;
   }
-  if (lane == 0) {
+  if (lane == 0 && n <= 24) {
+    const double lam = 0.5 * (lo + hi);
+    const double tiny = fmax(2.2e-16 * sc, 1e-300);
+    const double last = (n <= 8) ? tri_eigvec_reg<8>(sa, sb, n, lam, tiny, coefs)
+                                 : tri_eigvec_reg<24>(sa, sb, n, lam, tiny, coefs);
+    out[2] = lam;
+    out[3] = last;
+  } else if (lane == 0) {
     const double lam = 0.5 * (lo + hi);
     lam_s = lam;
     const double tiny = fmax(2.2e-16 * sc, 1e-300);
