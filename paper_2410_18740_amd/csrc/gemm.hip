@@ -52,9 +52,19 @@ static __device__ __forceinline__ __bf16 bf_neg(__bf16 x) {
   return __builtin_bit_cast(__bf16, (unsigned short)(b ^ 0x8000u));
 }
 
+// Operand loads through global-address-space pointers: the operand pointers
+// come from the job tables, so without the cast they would be generic (flat)
+// loads, which also count against the LDS wait counter and so would make every
+// wait for the current tile's LDS reads wait for the next tile's prefetch too.
+template <typename CT> struct RawOf;
+template <> struct RawOf<cf32> { typedef float __attribute__((ext_vector_type(2))) T; };
+template <> struct RawOf<cf64> { typedef double __attribute__((ext_vector_type(2))) T; };
+
 template <typename CT, bool CONJ>
-static __device__ __forceinline__ CT ld_c(const CT* p) {
-  CT v = *p;
+static __device__ __forceinline__ CT ld_g(const void* base, int64_t idx) {
+  using R = typename RawOf<CT>::T;
+  const __attribute__((address_space(1))) R* p = (const __attribute__((address_space(1))) R*)base;
+  CT v = __builtin_bit_cast(CT, p[idx]);
   if (CONJ) v.y = -v.y;
   return v;
 }
@@ -98,8 +108,6 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
   GemmSeg sg = segs[job.seg0];
   CT ra[NA], rb[NB];
   auto load_tile = [&]() {
-    const CT* __restrict__ A = reinterpret_cast<const CT*>(sg.A);
-    const CT* __restrict__ B = reinterpret_cast<const CT*>(sg.B);
     const int K = sg.K;
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
@@ -109,7 +117,8 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
       else     { kk = idx / BM; mm = idx % BM; }
       const int gm = m0 + mm, gk = ld_k0 + kk;
       CT v = czero<CT>();
-      if (gm < M && gk < K) v = TA ? ld_c<CT, true>(A + (int64_t)gk * sg.lda + gm) : A[(int64_t)gm * sg.lda + gk];
+      if (gm < M && gk < K)
+        v = TA ? ld_g<CT, true>(sg.A, (int64_t)gk * sg.lda + gm) : ld_g<CT, false>(sg.A, (int64_t)gm * sg.lda + gk);
       ra[t] = v;
     }
 #pragma unroll
@@ -120,7 +129,8 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
       else     { nn = idx / BK; kk = idx % BK; }
       const int gn = n0 + nn, gk = ld_k0 + kk;
       CT v = czero<CT>();
-      if (gn < N && gk < K) v = TB ? ld_c<CT, true>(B + (int64_t)gn * sg.ldb + gk) : B[(int64_t)gk * sg.ldb + gn];
+      if (gn < N && gk < K)
+        v = TB ? ld_g<CT, true>(sg.B, (int64_t)gn * sg.ldb + gk) : ld_g<CT, false>(sg.B, (int64_t)gk * sg.ldb + gn);
       rb[t] = v;
     }
     // advance to the next tile
