@@ -670,3 +670,43 @@ def test_energy_variance_against_dense_states():
     h2_ref = np.linalg.norm(H @ Psi) ** 2 / n2
     e, h2, var = dmrg.energy_variance(state, Ws, iso)
     assert abs(e - e_ref) < 1e-10 * max(1, abs(e_ref)) and abs(h2 - h2_ref) < 1e-10 * h2_ref
+
+
+def test_cz_hamiltonian_annihilates_the_transformed_gaussian_state():
+    """Sec. II.C.2: exp(-i kappa prod X) maps the Gaussian state to the zero
+    mode of the literal Hamiltonian with y = (X, P + xi).  On a 14-photon box
+    (three modes, r <= 0.35) <H> of the transformed exact amplitudes is at the
+    box's truncation level, while the opposite sign of kappa, or the
+    untransformed state, leave an energy of order kappa^2."""
+    from oracle import cz
+    N, B, kappa = 3, 14, 0.3
+    r, U = W.make_problem(N, 12, (0.2, 0.35))
+    al, be, ga = gbs.coefficients(r, U)
+    psi = gbs.exact_amplitudes(r, U, B).reshape(-1)
+    x, V = np.linalg.eigh(operators.quadratures(B)[0])
+    V3 = np.kron(np.kron(V, V), V)
+    phase = np.exp(-1j * kappa * np.einsum("a,b,c->abc", x, x, x)).reshape(-1)
+    phi = V3 @ (phase * (V3.conj().T @ psi))
+    assert abs(cz.expectation_literal(al, be, ga, kappa, B, phi)) < 1e-6
+    assert cz.expectation_literal(al, be, ga, -kappa, B, phi) > 0.05
+    assert cz.expectation_literal(al, be, ga, kappa, B, psi) > 0.01
+    assert abs(cz.expectation_literal(al, be, ga, 0.0, B, psi)) < 1e-9
+
+
+def test_cz_mpo_contracts_to_the_dense_hamiltonian():
+    """The block MPO (Gaussian middle-site MPO + the H_1 and H_2 automata)
+    contracts to PHP of the literal form; at kappa = 0 it is the Gaussian
+    quadrature-form PHP; the integer structure has the stated bond dimensions."""
+    from oracle import cz
+    for N, D in ((3, 4), (4, 3), (2, 5)):
+        r, U = W.make_problem(N, 11, (0.3, 0.6))
+        al, be, ga, ops = cz.site_operators(r, U, D)
+        for kappa in (0.0, 0.35):
+            Hm = mpo.to_dense(cz.cores(al, be, ga, kappa, ops))
+            Hd = cz.dense_php(al, be, ga, kappa, D)
+            assert np.abs(Hm - Hd).max() < 1e-12
+        assert np.abs(cz.dense_php(al, be, ga, 0.0, D) - dense.php_quadrature(al, be, ga, D)).max() < 1e-12
+        w, kinds = cz.structure(N)
+        wg = mpo.bond_dims(N)
+        assert w == [wg[t] + (0 if t in (0, N) else 4 + 4 * t) for t in range(N + 1)]
+        assert all(k.shape == (w[s], w[s + 1]) for s, k in enumerate(kinds))
