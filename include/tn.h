@@ -98,18 +98,28 @@ typedef struct {
   const double* U;    /* [N*N*2] host, interleaved complex, unitary to 1e-10 */
   const double* iso;  /* NULL (initial basis = first d Fock states, SM Sec. 6) or
                          [N][D_raw][d] complex host isometries, W^dag W = I to 1e-10 */
+  double kappa;       /* 0: GBS.  Otherwise the global CZ gate exp(-i kappa prod X)
+                         follows the Gaussian circuit (Sec. II.C.2, eq. GlobalCZgate):
+                         P_i -> P_i + kappa prod_{n != i} X_n in the parent Hamiltonian
+                         (eq. nonGBSHamiltonian); finite, and N >= 2 */
 } tn_problem;
 
 tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** out);
 /* Integer structure: w[N+1] bond dimensions; kinds (may be NULL) receives the
  * concatenated per-site kind tables (w[s] x w[s+1], row-major): 0 absent,
- * 1 identity, 2 X, 3 P, 4 S_s, 5 c_X X + c_P P, 6 scalar * identity. */
+ * 1 identity, 2 X, 3 P, 4 S_s, 5 c_X X + c_P P, 6 scalar * identity, and for
+ * kappa != 0: 7 X^2, 8 XP + PX, 9 c_1 X^2 + c_2 (XP + PX).  With kappa != 0 the
+ * MPO is the block sum of the Gaussian middle-site MPO (SM Sec. 8) and two
+ * left-to-right blocks for the terms of order kappa and kappa^2; bond t (0 < t
+ * < N) holds the Gaussian channels, then [A0, AF, (AX2 i, APt i, AI i), i <= t],
+ * then [B0, BF, (BX i), i <= t]: w_t = w_t(Gaussian) + 4 + 4 t. */
 tn_status tn_mpo_structure(const tn_mpo* mpo, int32_t* w, int8_t* kinds);
 /* Coefficients alpha, beta, gamma (each N*N doubles; any pointer may be NULL). */
 tn_status tn_mpo_coefficients(const tn_mpo* mpo, double* alpha, double* beta, double* gamma);
 /* Current isometries [N][D_raw][d] complex (host). */
 tn_status tn_mpo_isometries(const tn_mpo* mpo, double* iso);
-/* Local operators of site s in the current basis: [3][d][d] complex (X, P, S). */
+/* Local operators of site s in the current basis: [5][d][d] complex
+ * (X, P, S, X^2, XP + PX; products formed at D_raw + 4, SM Sec. 5). */
 tn_status tn_mpo_site_ops(const tn_mpo* mpo, int32_t site, double* ops);
 void tn_mpo_destroy(tn_mpo* mpo);
 

@@ -35,7 +35,7 @@ class tn_allocator(C.Structure):
 class tn_problem(C.Structure):
     _fields_ = [("N", C.c_int32), ("D_raw", C.c_int32), ("d", C.c_int32),
                 ("r", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double)),
-                ("iso", C.POINTER(C.c_double))]
+                ("iso", C.POINTER(C.c_double)), ("kappa", C.c_double)]
 
 
 class tn_sweep_opts(C.Structure):

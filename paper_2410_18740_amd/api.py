@@ -95,7 +95,7 @@ class Context:
 class MPO:
     """Middle-site MPO of PHP for per-mode squeezing r and interferometer U."""
 
-    def __init__(self, ctx: Context, r, U, D_raw: int, d: int | None = None, iso=None):
+    def __init__(self, ctx: Context, r, U, D_raw: int, d: int | None = None, iso=None, kappa: float = 0.0):
         self.ctx = ctx
         r = np.ascontiguousarray(r, dtype=np.float64)
         U = np.ascontiguousarray(U, dtype=np.complex128)
@@ -105,8 +105,9 @@ class MPO:
         self._r = r
         self._U = U.view(np.float64).copy()
         self._iso = None if iso is None else np.ascontiguousarray(iso, dtype=np.complex128).view(np.float64).copy()
+        self.kappa = float(kappa)
         prob = L.tn_problem(N, D_raw, d, L.dptr(self._r), L.dptr(self._U),
-                            None if self._iso is None else L.dptr(self._iso))
+                            None if self._iso is None else L.dptr(self._iso), self.kappa)
         h = C.c_void_p()
         ctx.check(L.lib().tn_mpo_build(ctx.h, C.byref(prob), C.byref(h)))
         self.h = h
@@ -136,7 +137,8 @@ class MPO:
         return out
 
     def site_ops(self, s: int):
-        out = np.zeros((3, self.d, self.d), dtype=np.complex128)
+        """(X, P, S, X^2, XP + PX) of site s in the current basis."""
+        out = np.zeros((5, self.d, self.d), dtype=np.complex128)
         self.ctx.check(L.lib().tn_mpo_site_ops(self.h, s, L.dptr(out.view(np.float64))))
         return out
 

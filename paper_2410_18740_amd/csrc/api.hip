@@ -175,6 +175,95 @@ static int chan(int N, int t, ChanType ty, int k = 0) {
   }
 }
 
+// kind codes: 1 I, 2 X, 3 P, 4 S, 5 c1 X + c2 P, 6 c1 I, 7 X^2, 8 XP + PX, 9 c1 X^2 + c2 (XP + PX)
+static CoreEntry make_entry(int r, int c, int kind, double c1, double c2) {
+  CoreEntry e{r, c, kind, {0, 0, 0, 0, 0, 0}};
+  switch (kind) {
+    case 1: e.c[0] = 1.0; break;
+    case 2: e.c[1] = 1.0; break;
+    case 3: e.c[2] = 1.0; break;
+    case 4: e.c[3] = 1.0; break;
+    case 5: e.c[1] = c1; e.c[2] = c2; break;
+    case 6: e.c[0] = c1; break;
+    case 7: e.c[4] = 1.0; break;
+    case 8: e.c[5] = 1.0; break;
+    case 9: e.c[4] = c1; e.c[5] = c2; break;
+  }
+  return e;
+}
+
+// bond dimension with the global-CZ blocks: the Gaussian channels, then
+// [A0, AF, (AX2 i, APt i, AI i) for i <= t] and [B0, BF, (BX i) for i <= t]
+static int bond_dim_cz(int N, int t) {
+  if (t == 0 || t == N) return 1;
+  return bond_dim(N, t) + 4 + 4 * t;
+}
+
+// The global-CZ terms kappa H_1 + kappa^2 H_2 (Sec. II.C.2, eq. nonGBSHamiltonian;
+// the purple, blue and magenta MPOs of SM Sec. 8) as two left-to-right
+// automata appended to the Gaussian channels of each bond:
+//   H_1 = Tr(gamma) prod X + sum_i beta_ii P_i prod' X
+//         + sum_{i != j} (gamma_ij X_i^2 + beta_ij/2 (XP + PX)_i) prod'' X,
+//   H_2 = 1/2 sum_i beta_ii prod' X^2 + sum_{i < j} beta_ij X_i X_j prod'' X^2.
+// A0 / B0: background only so far; AF / BF: term complete; AX2 i / APt i: X^2 or
+// XP + PX placed at site i, identity partner to come; AI i: identity placed at
+// site i, partner to come; BX i: X placed at site i, X partner to come.
+static void cz_entries(int N, int s, const std::vector<double>& be, const std::vector<double>& ga, double kappa,
+                       std::vector<CoreEntry>& E) {
+  auto B = [&](int i, int j) { return be[(i - 1) * N + (j - 1)]; };
+  auto G = [&](int i, int j) { return ga[(i - 1) * N + (j - 1)]; };
+  const int tl = s - 1, tr = s;
+  const bool last = s == N;
+  // channel index at bond t of a block label (-1 if the bond lacks it)
+  auto a_base = [&](int t) { return bond_dim(N, t); };
+  auto b_base = [&](int t) { return bond_dim(N, t) + 2 + 3 * t; };
+  auto A0 = [&](int t) { return (t == 0) ? 0 : (t == N ? -1 : a_base(t)); };
+  auto AF = [&](int t) { return (t == N) ? 0 : (t == 0 ? -1 : a_base(t) + 1); };
+  auto AX2 = [&](int t, int i) { return (t > 0 && t < N && i >= 1 && i <= t) ? a_base(t) + 2 + 3 * (i - 1) : -1; };
+  auto APt = [&](int t, int i) { return (t > 0 && t < N && i >= 1 && i <= t) ? a_base(t) + 3 + 3 * (i - 1) : -1; };
+  auto AI = [&](int t, int i) { return (t > 0 && t < N && i >= 1 && i <= t) ? a_base(t) + 4 + 3 * (i - 1) : -1; };
+  auto B0 = [&](int t) { return (t == 0) ? 0 : (t == N ? -1 : b_base(t)); };
+  auto BF = [&](int t) { return (t == N) ? 0 : (t == 0 ? -1 : b_base(t) + 1); };
+  auto BX = [&](int t, int i) { return (t > 0 && t < N && i >= 1 && i <= t) ? b_base(t) + 2 + (i - 1) : -1; };
+  auto put = [&](int r, int c, int kind, double c1 = 0.0, double c2 = 0.0) {
+    if (r < 0 || c < 0) return;
+    E.push_back(make_entry(r, c, kind, c1, c2));
+  };
+  const double k = kappa;
+  double trg = 0.0;
+  for (int i = 1; i <= N; ++i) trg += G(i, i);
+  // H_1 block
+  if (!last) {
+    put(A0(tl), A0(tr), 2);
+    put(A0(tl), AX2(tr, s), 7);
+    put(A0(tl), APt(tr, s), 8);
+    put(A0(tl), AI(tr, s), 1);
+  }
+  put(A0(tl), AF(tr), 5, s == 1 ? k * trg : 0.0, k * B(s, s));
+  if (s > 1) put(AF(tl), AF(tr), 2);
+  for (int i = 1; i < s; ++i) {
+    if (!last) {
+      put(AX2(tl, i), AX2(tr, i), 2);
+      put(APt(tl, i), APt(tr, i), 2);
+      put(AI(tl, i), AI(tr, i), 2);
+    }
+    put(AX2(tl, i), AF(tr), 6, k * G(i, s));
+    put(APt(tl, i), AF(tr), 6, 0.5 * k * B(i, s));
+    put(AI(tl, i), AF(tr), 9, k * G(s, i), 0.5 * k * B(s, i));
+  }
+  // H_2 block
+  if (!last) {
+    put(B0(tl), B0(tr), 7);
+    put(B0(tl), BX(tr, s), 2);
+  }
+  put(B0(tl), BF(tr), 6, 0.5 * k * k * B(s, s));
+  if (s > 1) put(BF(tl), BF(tr), 7);
+  for (int i = 1; i < s; ++i) {
+    if (!last) put(BX(tl, i), BX(tr, i), 7);
+    put(BX(tl, i), BF(tr), 5, k * k * B(i, s), 0.0);
+  }
+}
+
 // entries of core s (1-based) following the paper's L_s / M_{N_m} / R_s construction
 static std::vector<CoreEntry> core_entries(int N, int s, const std::vector<double>& al, const std::vector<double>& be,
                                            const std::vector<double>& ga) {
@@ -185,16 +274,7 @@ static std::vector<CoreEntry> core_entries(int N, int s, const std::vector<doubl
   std::vector<CoreEntry> E;
   auto put = [&](int r, int c, int kind, double cx = 0.0, double cp = 0.0) {
     if (r < 0 || c < 0) return;
-    CoreEntry e{r, c, kind, {0, 0, 0, 0}};
-    switch (kind) {
-      case 1: e.c[0] = 1.0; break;
-      case 2: e.c[1] = 1.0; break;
-      case 3: e.c[2] = 1.0; break;
-      case 4: e.c[3] = 1.0; break;
-      case 5: e.c[1] = cx; e.c[2] = cp; break;
-      case 6: e.c[0] = cx; break;
-    }
-    E.push_back(e);
+    E.push_back(make_entry(r, c, kind, cx, cp));
   };
   const int tl = s - 1, tr = s;  // row bond, column bond
   put(chan(N, tl, CH_S), chan(N, tr, CH_S), 1);
@@ -283,7 +363,7 @@ static std::vector<cd> matmul(const std::vector<cd>& A, const std::vector<cd>& B
   return C;
 }
 
-// X, P, S at dimension D built from products at D+4 (SM Sec. 5)
+// X, P, S, X^2, XP + PX at dimension D, products formed at D+4 (SM Sec. 5)
 static void build_raw_ops(int D, double a_ss, double b_ss, double g_ss, std::vector<cd>& out) {
   const int Db = D + 4;
   std::vector<cd> X(Db * Db, 0.0), P(Db * Db, 0.0);
@@ -298,7 +378,7 @@ static void build_raw_ops(int D, double a_ss, double b_ss, double g_ss, std::vec
   }
   auto XX = matmul(X, X, Db, Db, Db), PP = matmul(P, P, Db, Db, Db);
   auto XP = matmul(X, P, Db, Db, Db), PX = matmul(P, X, Db, Db, Db);
-  out.assign(3 * D * D, 0.0);
+  out.assign((size_t)NOPS * D * D, 0.0);
   for (int i = 0; i < D; ++i)
     for (int j = 0; j < D; ++j) {
       const size_t b = (size_t)i * Db + j;
@@ -307,15 +387,17 @@ static void build_raw_ops(int D, double a_ss, double b_ss, double g_ss, std::vec
       cd s = 0.5 * (a_ss * XX[b] + b_ss * PP[b] + g_ss * (XP[b] + PX[b]));
       if (i == j) s -= 0.5;
       out[2 * D * D + i * D + j] = s;
+      out[3 * D * D + i * D + j] = XX[b];
+      out[4 * D * D + i * D + j] = XP[b] + PX[b];
     }
 }
 
 static void project_ops(const std::vector<cd>& raw, const std::vector<cd>& W, int D, int d, std::vector<cd>& out) {
-  out.assign(3 * d * d, 0.0);
+  out.assign((size_t)NOPS * d * d, 0.0);
   std::vector<cd> Wh(d * D);
   for (int i = 0; i < D; ++i)
     for (int j = 0; j < d; ++j) Wh[j * D + i] = std::conj(W[i * d + j]);
-  for (int o = 0; o < 3; ++o) {
+  for (int o = 0; o < NOPS; ++o) {
     std::vector<cd> op(raw.begin() + o * D * D, raw.begin() + (o + 1) * D * D);
     auto t = matmul(op, W, D, D, d);
     auto r = matmul(Wh, t, d, D, d);
@@ -325,37 +407,37 @@ static void project_ops(const std::vector<cd>& raw, const std::vector<cd>& W, in
 
 void tn_mpo::upload_site(int s) {
   const size_t dd = (size_t)d * d, DD = (size_t)D_raw * D_raw;
-  std::vector<cf64> h64(3 * dd);
-  std::vector<cf32> h32(3 * dd);
-  for (size_t i = 0; i < 3 * dd; ++i) {
+  std::vector<cf64> h64(NOPS * dd);
+  std::vector<cf32> h32(NOPS * dd);
+  for (size_t i = 0; i < NOPS * dd; ++i) {
     h64[i] = make_double2(loc_ops[s][i].real(), loc_ops[s][i].imag());
     h32[i] = make_float2((float)loc_ops[s][i].real(), (float)loc_ops[s][i].imag());
   }
-  HIPCHK(hipMemcpy(d_ops64 + (size_t)s * 3 * dd, h64.data(), 3 * dd * sizeof(cf64), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(d_ops32 + (size_t)s * 3 * dd, h32.data(), 3 * dd * sizeof(cf32), hipMemcpyHostToDevice));
-  std::vector<cf64> r64(3 * DD);
-  std::vector<cf32> r32(3 * DD);
-  for (size_t i = 0; i < 3 * DD; ++i) {
+  HIPCHK(hipMemcpy(d_ops64 + (size_t)s * NOPS * dd, h64.data(), NOPS * dd * sizeof(cf64), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_ops32 + (size_t)s * NOPS * dd, h32.data(), NOPS * dd * sizeof(cf32), hipMemcpyHostToDevice));
+  std::vector<cf64> r64(NOPS * DD);
+  std::vector<cf32> r32(NOPS * DD);
+  for (size_t i = 0; i < NOPS * DD; ++i) {
     r64[i] = make_double2(raw_ops[s][i].real(), raw_ops[s][i].imag());
     r32[i] = make_float2((float)raw_ops[s][i].real(), (float)raw_ops[s][i].imag());
   }
-  HIPCHK(hipMemcpy(d_raw64 + (size_t)s * 3 * DD, r64.data(), 3 * DD * sizeof(cf64), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(d_raw32 + (size_t)s * 3 * DD, r32.data(), 3 * DD * sizeof(cf32), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_raw64 + (size_t)s * NOPS * DD, r64.data(), NOPS * DD * sizeof(cf64), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d_raw32 + (size_t)s * NOPS * DD, r32.data(), NOPS * DD * sizeof(cf32), hipMemcpyHostToDevice));
   std::vector<cf64> w64((size_t)D_raw * d);
   for (size_t i = 0; i < w64.size(); ++i) w64[i] = make_double2(iso[s][i].real(), iso[s][i].imag());
   HIPCHK(hipMemcpy(d_iso + (size_t)s * D_raw * d, w64.data(), w64.size() * sizeof(cf64), hipMemcpyHostToDevice));
 }
 
 const void* tn_mpo::op_ptr(int prec, int site, int k, bool raw) const {
-  if (k < 1 || k > 3) return nullptr;
+  if (k < 1 || k > NOPS) return nullptr;
   if (raw) {
     const size_t DD = (size_t)D_raw * D_raw;
-    return prec == PREC_FP64 ? (const void*)(d_raw64 + ((size_t)site * 3 + (k - 1)) * DD)
-                             : (const void*)(d_raw32 + ((size_t)site * 3 + (k - 1)) * DD);
+    return prec == PREC_FP64 ? (const void*)(d_raw64 + ((size_t)site * NOPS + (k - 1)) * DD)
+                             : (const void*)(d_raw32 + ((size_t)site * NOPS + (k - 1)) * DD);
   }
   const size_t dd = (size_t)d * d;
-  return prec == PREC_FP64 ? (const void*)(d_ops64 + ((size_t)site * 3 + (k - 1)) * dd)
-                           : (const void*)(d_ops32 + ((size_t)site * 3 + (k - 1)) * dd);
+  return prec == PREC_FP64 ? (const void*)(d_ops64 + ((size_t)site * NOPS + (k - 1)) * dd)
+                           : (const void*)(d_ops32 + ((size_t)site * NOPS + (k - 1)) * dd);
 }
 
 static void mpo_free(tn_mpo* m) {
@@ -383,6 +465,8 @@ extern "C" tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** 
   if (D < 1 || D > 64) TN_THROW(TN_EINVAL, "D_raw must be in [1, 64]");
   if (d < 1 || d > D) TN_THROW(TN_EINVAL, "d must satisfy 1 <= d <= D_raw");
   if (!prob->r || !prob->U) TN_THROW(TN_EINVAL, "r and U are required");
+  if (!std::isfinite(prob->kappa)) TN_THROW(TN_EINVAL, "non-finite kappa");
+  if (prob->kappa != 0.0 && N < 2) TN_THROW(TN_EINVAL, "the global CZ Hamiltonian needs N >= 2");
   for (int j = 0; j < N; ++j)
     if (!std::isfinite(prob->r[j])) TN_THROW(TN_EINVAL, "non-finite squeezing parameter");
   std::vector<cd> U(N * N);
@@ -452,12 +536,15 @@ extern "C" tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** 
       m->gamma[i * N + j] = 0.25 * (Vi[i * n2 + N + j] + Vi[(N + j) * n2 + i]);
     }
   // structure and entries
+  m->kappa = prob->kappa;
+  const bool cz = prob->kappa != 0.0;
   m->w.resize(N + 1);
-  for (int t = 0; t <= N; ++t) m->w[t] = bond_dim(N, t);
+  for (int t = 0; t <= N; ++t) m->w[t] = cz ? bond_dim_cz(N, t) : bond_dim(N, t);
   m->kinds.resize(N);
   m->entries.resize(N);
   for (int s = 0; s < N; ++s) {
     m->entries[s] = core_entries(N, s + 1, m->alpha, m->beta, m->gamma);
+    if (cz) cz_entries(N, s + 1, m->beta, m->gamma, prob->kappa, m->entries[s]);
     m->kinds[s].assign((size_t)m->w[s] * m->w[s + 1], 0);
     for (auto& e : m->entries[s]) m->kinds[s][(size_t)e.row * m->w[s + 1] + e.col] = (int8_t)e.kind;
   }
@@ -469,10 +556,10 @@ extern "C" tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** 
     build_raw_ops(D, m->alpha[s * N + s], m->beta[s * N + s], m->gamma[s * N + s], m->raw_ops[s]);
     project_ops(m->raw_ops[s], m->iso[s], D, d, m->loc_ops[s]);
   }
-  m->d_ops64 = (cf64*)dev_alloc(ctx, (size_t)N * 3 * d * d * sizeof(cf64));
-  m->d_ops32 = (cf32*)dev_alloc(ctx, (size_t)N * 3 * d * d * sizeof(cf32));
-  m->d_raw64 = (cf64*)dev_alloc(ctx, (size_t)N * 3 * D * D * sizeof(cf64));
-  m->d_raw32 = (cf32*)dev_alloc(ctx, (size_t)N * 3 * D * D * sizeof(cf32));
+  m->d_ops64 = (cf64*)dev_alloc(ctx, (size_t)N * NOPS * d * d * sizeof(cf64));
+  m->d_ops32 = (cf32*)dev_alloc(ctx, (size_t)N * NOPS * d * d * sizeof(cf32));
+  m->d_raw64 = (cf64*)dev_alloc(ctx, (size_t)N * NOPS * D * D * sizeof(cf64));
+  m->d_raw32 = (cf32*)dev_alloc(ctx, (size_t)N * NOPS * D * D * sizeof(cf32));
   m->d_iso = (cf64*)dev_alloc(ctx, (size_t)N * D * d * sizeof(cf64));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   for (int s = 0; s < N; ++s) m->upload_site(s);

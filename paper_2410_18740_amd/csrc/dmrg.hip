@@ -360,8 +360,9 @@ static void mixed_envs(tn_ctx* c, int prec, const std::vector<PlanL>& Ls, const 
 // device operators of one site by index; entry 0 (the identity) is never read
 using OpTable = std::vector<const void*>;
 static OpTable site_ops(const tn_mpo* mpo, int sprec, int site) {
-  return {nullptr, mpo->op_ptr(sprec, site, 1, false), mpo->op_ptr(sprec, site, 2, false),
-          mpo->op_ptr(sprec, site, 3, false)};
+  OpTable t(NOPS + 1, nullptr);
+  for (int k = 1; k <= NOPS; ++k) t[k] = mpo->op_ptr(sprec, site, k, false);
+  return t;
 }
 
 static void run_ops(tn_ctx* c, int sprec, const OpTable& ops, const Plan& P, char* Y, char* T, size_t nel, int chi_l,
@@ -638,8 +639,8 @@ static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_
   // re-project the local operators and upload (ops, raw ops, isometry)
   {
     const auto& raw = mpo->raw_ops[s];
-    std::vector<cd> out(3 * (size_t)d * d, 0.0);
-    for (int o2 = 0; o2 < 3; ++o2)
+    std::vector<cd> out((size_t)NOPS * d * d, 0.0);
+    for (int o2 = 0; o2 < NOPS; ++o2)
       for (int a = 0; a < d; ++a)
         for (int b = 0; b < d; ++b) {
           cd acc = 0.0;
@@ -787,16 +788,16 @@ static void product_ops(const tn_mpo* mpo, int s, std::vector<cd>& Q) {
     if (a == 0) return i == j ? cd(1.0) : cd(0.0);
     return raw[(size_t)(a - 1) * D * D + (size_t)i * D + j];
   };
-  Q.assign((size_t)16 * d * d, 0.0);
+  Q.assign((size_t)(NOPS + 1) * (NOPS + 1) * d * d, 0.0);
   std::vector<cd> RW((size_t)D * d), RRW((size_t)D * d);
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b <= NOPS; ++b) {
     for (int i = 0; i < D; ++i)
       for (int j = 0; j < d; ++j) {
         cd t = 0.0;
         for (int k = 0; k < D; ++k) t += R(b, i, k) * W[(size_t)k * d + j];
         RW[(size_t)i * d + j] = t;
       }
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a <= NOPS; ++a) {
       for (int i = 0; i < D; ++i)
         for (int j = 0; j < d; ++j) {
           cd t = 0.0;
@@ -807,7 +808,7 @@ static void product_ops(const tn_mpo* mpo, int s, std::vector<cd>& Q) {
         for (int j = 0; j < d; ++j) {
           cd t = 0.0;
           for (int k = 0; k < D; ++k) t += std::conj(W[(size_t)k * d + i]) * RRW[(size_t)k * d + j];
-          Q[((size_t)(a * 4 + b) * d + i) * d + j] = t;
+          Q[((size_t)(a * (NOPS + 1) + b) * d + i) * d + j] = t;
         }
     }
   }
@@ -820,11 +821,11 @@ static double h2_fp64(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m) {
   for (int t = 0; t <= N; ++t) maxw = std::max(maxw, (size_t)mpo->w[t] * mpo->w[t] * m->dims[t] * m->dims[t]);
   cf64* La = wsT<cf64>(c, "h2:La", maxw);
   cf64* Lb = wsT<cf64>(c, "h2:Lb", maxw);
-  cf64* Qd = wsT<cf64>(c, "h2:Q", (size_t)16 * d * d);
+  cf64* Qd = wsT<cf64>(c, "h2:Q", (size_t)(NOPS + 1) * (NOPS + 1) * d * d);
   HIPCHK(launch_set_one(La, PREC_FP64, st));
   const size_t budget = (size_t)8 << 30;  // Y + T buffers per group
   std::vector<cd> Q;
-  std::vector<cf64> Qh((size_t)16 * d * d);
+  std::vector<cf64> Qh((size_t)(NOPS + 1) * (NOPS + 1) * d * d);
   for (int s = 0; s < N; ++s) {
     const int cl = m->dims[s], cr = m->dims[s + 1];
     const int wi = mpo->w[s], wo = mpo->w[s + 1];
@@ -832,17 +833,17 @@ static double h2_fp64(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m) {
     for (size_t i = 0; i < Q.size(); ++i) Qh[i] = make_double2(Q[i].real(), Q[i].imag());
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(Qd, Qh.data(), Qh.size() * sizeof(cf64), hipMemcpyHostToDevice));
-    OpTable ops(16, nullptr);
-    for (int k = 1; k < 16; ++k) ops[k] = Qd + (size_t)k * d * d;
+    OpTable ops((NOPS + 1) * (NOPS + 1), nullptr);
+    for (int k = 1; k < (NOPS + 1) * (NOPS + 1); ++k) ops[k] = Qd + (size_t)k * d * d;
     // terms grouped by the first layer's output channel
     std::vector<std::vector<Term2>> by_u(wo);
     for (const auto& e1 : mpo->entries[s])
       for (const auto& e2 : mpo->entries[s])
-        for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a <= NOPS; ++a) {
           if (e1.c[a] == 0.0) continue;
-          for (int b = 0; b < 4; ++b) {
+          for (int b = 0; b <= NOPS; ++b) {
             if (e2.c[b] == 0.0) continue;
-            by_u[e1.col].push_back({e1.row * wi + e2.row, e1.col * wo + e2.col, a * 4 + b, 0, e1.c[a] * e2.c[b]});
+            by_u[e1.col].push_back({e1.row * wi + e2.row, e1.col * wo + e2.col, a * (NOPS + 1) + b, 0, e1.c[a] * e2.c[b]});
           }
         }
     std::vector<const void*> lin((size_t)wi * wi);

@@ -58,11 +58,13 @@ template <typename T> T* wsT(tn_ctx* c, const std::string& name, size_t count) {
 void upload(tn_ctx* c, void* dst, const void* src, size_t bytes);
 void download(tn_ctx* c, void* dst, const void* src, size_t bytes);  // synchronising
 
-// entry decomposition of a core block into the basis {I, X, P, S}
+// entry decomposition of a core block into the basis {I, X, P, S, X^2, XP + PX}
+// local operators of a site: 1 X, 2 P, 3 S, 4 X^2, 5 XP + PX (index 0 is the identity)
+constexpr int NOPS = 5;
 struct CoreEntry {
   int row, col;
   int kind;
-  double c[4];
+  double c[NOPS + 1];  // coefficients of I, X, P, S, X^2, XP + PX
 };
 
 struct tn_mpo {
@@ -75,16 +77,17 @@ struct tn_mpo {
   std::vector<cd> U;
   std::vector<double> alpha, beta, gamma;        // N x N
   std::vector<std::vector<cd>> iso;              // per site D_raw x d
-  std::vector<std::vector<cd>> raw_ops;          // per site 3 x D_raw x D_raw (X, P, S)
-  std::vector<std::vector<cd>> loc_ops;          // per site 3 x d x d
-  cf64* d_ops64 = nullptr;   // [N][3][d][d]
+  double kappa = 0.0;                            // global-CZ strength (0: GBS)
+  std::vector<std::vector<cd>> raw_ops;          // per site NOPS x D_raw x D_raw
+  std::vector<std::vector<cd>> loc_ops;          // per site NOPS x d x d
+  cf64* d_ops64 = nullptr;   // [N][NOPS][d][d]
   cf32* d_ops32 = nullptr;
-  cf64* d_raw64 = nullptr;   // [N][3][D][D]
+  cf64* d_raw64 = nullptr;   // [N][NOPS][D][D]
   cf32* d_raw32 = nullptr;
   cf64* d_iso = nullptr;     // [N][D][d]
   uint64_t version = 1;
   void upload_site(int s);
-  const void* op_ptr(int prec, int site, int kind_xps, bool raw) const;  // kind 1:X 2:P 3:S
+  const void* op_ptr(int prec, int site, int k, bool raw) const;  // k in 1..NOPS
 };
 
 struct tn_mps {
@@ -110,7 +113,7 @@ struct PlanL {  // effective left channel: mixture of original channels
 };
 struct PlanTerm {
   int ych;  // index into PlanL / Y buffers
-  int a, b; // 0 I, 1 X, 2 P, 3 S on leg 0 / leg 1
+  int a, b; // 0 I, 1 X, 2 P, 3 S, 4 X^2, 5 XP + PX on leg 0 / leg 1
   double c;
 };
 struct PlanT {

@@ -1,8 +1,8 @@
 // Contraction planner and executor for the effective operator of a one- or
 // two-site window of the MPO, and for environment updates.
 //
-// Every core entry is a combination of the four local operators {I, X, P, S}
-// (coefficient vector c[4]); the window operator is therefore
+// Every core entry is a combination of the local operators {I, X, P, S, X^2,
+// XP + PX} (coefficient vector c); the window operator is therefore
 //   O[l][n] = sum_{a,b} c_{l n a b} op_a (x) op_b,
 // with l a left-environment channel and n a right-environment channel.  The
 // planner turns these terms into
@@ -25,7 +25,7 @@ std::vector<Term2> window_terms(const tn_mpo* mpo, int site, int nsites) {
   std::map<std::tuple<int, int, int, int>, double> acc;
   if (nsites == 1) {
     for (const auto& e : mpo->entries[site])
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a <= NOPS; ++a)
         if (e.c[a] != 0.0) acc[{e.row, e.col, a, 0}] += e.c[a];
   } else {
     const auto& E1 = mpo->entries[site];
@@ -36,9 +36,9 @@ std::vector<Term2> window_terms(const tn_mpo* mpo, int site, int nsites) {
       auto it = by_row.find(e1.col);
       if (it == by_row.end()) continue;
       for (const CoreEntry* e2 : it->second)
-        for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a <= NOPS; ++a) {
           if (e1.c[a] == 0.0) continue;
-          for (int b = 0; b < 4; ++b) {
+          for (int b = 0; b <= NOPS; ++b) {
             if (e2->c[b] == 0.0) continue;
             acc[{e1.row, e2->col, a, b}] += e1.c[a] * e2->c[b];
           }
@@ -315,7 +315,7 @@ void WindowOp::apply(const cf64* x, cf64* y) {
 static void counts(const tn_mpo* mpo, int site, int& n_op, int& n_sc) {
   n_op = n_sc = 0;
   for (auto k : mpo->kinds[site]) {
-    if (k >= 2 && k <= 5) ++n_op;
+    if ((k >= 2 && k <= 5) || (k >= 7 && k <= 9)) ++n_op;
     else if (k == 6) ++n_sc;
   }
 }
