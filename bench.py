@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--form", default="fp32", choices=list(FORMS))
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-lbo", action="store_true")
+    ap.add_argument("--kappa", type=float, default=0.0,
+                    help="global CZ gate strength after the Gaussian circuit (0: GBS)")
     ap.add_argument("--max-matvecs", type=int, default=16)
     ap.add_argument("--lbo-matvecs", type=int, default=0, help="matvec cap of each LBO solve (0: --max-matvecs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -65,10 +67,10 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, r, U, budget_s=15.0):
+def cpu_baseline(w, r, U, budget_s=15.0, kappa=0.0):
     """The FP64 oracle's two-site matvec on the middle window of the same
     workload, timed on the host cores."""
-    from oracle import gbs, operators, mpo as omp, dmrg as odmrg, flops as oflops
+    from oracle import gbs, operators, mpo as omp, dmrg as odmrg, flops as oflops, cz
     import workloads as W
     try:
         from threadpoolctl import threadpool_info
@@ -79,9 +81,14 @@ def cpu_baseline(w, r, U, budget_s=15.0):
     al, be, ga = gbs.coefficients(r, U)
     iso = np.zeros((D, d), dtype=complex)
     iso[:d, :d] = np.eye(d)
-    ops = [tuple(operators.project(o, iso) for o in operators.local_operators(D, al[s, s], be[s, s], ga[s, s]))
-           for s in range(N)]
-    Ws = omp.cores(al, be, ga, ops)
+    if kappa == 0.0:
+        ops = [tuple(operators.project(o, iso) for o in operators.local_operators(D, al[s, s], be[s, s], ga[s, s]))
+               for s in range(N)]
+        Ws = omp.cores(al, be, ga, ops)
+    else:
+        ops = [tuple(operators.project(o, iso) for o in cz.local_ops(D, al[s, s], be[s, s], ga[s, s]))
+               for s in range(N)]
+        Ws = cz.cores(al, be, ga, kappa, ops)
     site = N // 2 - 1
     dims = W.bond_dims(N, d, chi)
     cl, cr = dims[site], dims[site + 2]
@@ -89,7 +96,7 @@ def cpu_baseline(w, r, U, budget_s=15.0):
     Le = rng.standard_normal((Ws[site].shape[0], cl, cl)) + 1j * rng.standard_normal((Ws[site].shape[0], cl, cl))
     Re = rng.standard_normal((Ws[site + 1].shape[1], cr, cr)) + 1j * rng.standard_normal((Ws[site + 1].shape[1], cr, cr))
     th = rng.standard_normal((cl, d, d, cr)) + 1j * rng.standard_normal((cl, d, d, cr))
-    wst, kinds = omp.structure(N)
+    wst, kinds = omp.structure(N) if kappa == 0.0 else cz.structure(N)
     fl = oflops.matvec_flops(d, cl, cr, wst[site], wst[site + 2], kinds[site], kinds[site + 1])
     n, t0 = 0, time.perf_counter()
     while True:
@@ -175,7 +182,7 @@ def to_target(a):
     res = {}
     for form in ("fp64", "fp32", "bf16x3"):
         prec = FORMS[form]
-        mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
+        mpo = P.MPO(ctx, r, U, w.D_raw, w.d, kappa=a.kappa)
         mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
         sw = P.SweepOpts(chi_max=w.chi, krylov_max=24, max_matvecs=a.max_matvecs)
         torch.cuda.synchronize()
@@ -443,7 +450,7 @@ def to_target_relative(a):
     res = {}
     for form in ("fp64", "fp32", "bf16x3"):
         prec = FORMS[form]
-        mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
+        mpo = P.MPO(ctx, r, U, w.D_raw, w.d, kappa=a.kappa)
         mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
         sw = P.SweepOpts(chi_max=w.chi, krylov_max=24, max_matvecs=a.max_matvecs)
         torch.cuda.synchronize()
@@ -538,7 +545,7 @@ def main():
     # suffice inside sweeps (the FP64 <H> after each sweep is the judge).
     tol = a.tol if a.tol is not None else (1e-8 if prec == 0 else 1e-6)
     ctx = P.Context(0)
-    mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
+    mpo = P.MPO(ctx, r, U, w.D_raw, w.d, kappa=a.kappa)
     mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
     opts = P.SweepOpts(chi_max=w.chi, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec,
                        lbo=0 if a.no_lbo else 1, compute_energy=1, lbo_matvecs=a.lbo_matvecs)
@@ -572,7 +579,8 @@ def main():
     achieved = (pr["flops_l"] + pr["flops_r"]) / (gemm_ms * 1e-3) / 1e12
     peak = PEAKS[a.form]
     matvec_ms = sum(pr[k] for k in ("ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce"))
-    traffic = gemm_traffic(a.form, a.workload)
+    # the committed counter passes cover the GBS Hamiltonian only
+    traffic = gemm_traffic(a.form, a.workload) if a.kappa == 0.0 else None
     tri_n = max(1.0, pr["tridiag_launches"])
     tri_avg_s = pr["ms_tridiag"] * 1e-3 / tri_n
     tri_bytes = pr["bytes_tridiag"] / tri_n
@@ -585,7 +593,7 @@ def main():
     # dispatch gaps included in the per-launch average)
     tri_total_ms = pr["ms_tridiag"]
     roof_tri = {"bound": "hbm", "achieved": tri_gbs, "peak": 8000.0, "unit": "GB/s", "frac": tri_gbs / 8000.0,
-                "traffic": tridiag_traffic(a.form, a.workload), "kernel": "tridiag_col (one Householder column of the truncation's "
+                "traffic": tridiag_traffic(a.form, a.workload) if a.kappa == 0.0 else None, "kernel": "tridiag_col (one Householder column of the truncation's "
                 "Gram matrix, one launch per column: bound by launch latency)",
                 "avg_launch_us": tri_avg_s * 1e6, "algorithmic_bytes_per_launch": tri_bytes,
                 "launches": int(pr["tridiag_launches"]), "total_ms": tri_total_ms}
@@ -629,13 +637,14 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[a.form],
         "data": "synthetic (seeded Haar interferometer and squeezing, random-normal initial MPS)",
         "config": {"workload": a.workload, "N": w.N, "D_raw": w.D_raw, "d": w.d, "chi": w.chi,
-                   "form": a.form + ("" if a.no_lbo else "+lbo"), "lanczos_tol": tol},
+                   "form": a.form + ("" if a.no_lbo else "+lbo"), "lanczos_tol": tol,
+                   **({"kappa": a.kappa} if a.kappa else {})},
         "roofline": roof_main,
         "roofline_secondary": roof_other,
         "extra": extra,
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, r, U)
+        out["cpu_baseline"] = cpu_baseline(w, r, U, kappa=a.kappa)
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -5,15 +5,16 @@ real flops.  Counts depend only on shapes and on the MPO kind table:
               + sum_{t in {s, s+1}} [8 d^3 chi_l chi_r n_op(t) + 8 d^2 chi_l chi_r n_sc(t)]
   env(s):     8 (w_{s-1} chi_l^2 d chi_r + n_op(s) d^2 chi_l chi_r
                  + n_sc(s) d chi_l chi_r + w_s chi_l d chi_r^2)
-where n_op counts operator blocks (kinds 2-5) and n_sc scalar blocks (kind 6)
-of the core; identity blocks count nothing.  chi_l, chi_r are the outer bonds
+where n_op counts operator blocks (kinds 2-5, and 7-9 of the global-CZ
+Hamiltonian: X^2, XP + PX and their combinations) and n_sc scalar blocks
+(kind 6) of the core; identity blocks count nothing.  chi_l, chi_r are the outer bonds
 of the window (the matvec) or of the site (the environment update).
 """
 from __future__ import annotations
 
 
 def core_counts(kind_table):
-    n_op = int(sum(1 for v in kind_table.reshape(-1) if 2 <= int(v) <= 5))
+    n_op = int(sum(1 for v in kind_table.reshape(-1) if 2 <= int(v) <= 5 or 7 <= int(v) <= 9))
     n_sc = int(sum(1 for v in kind_table.reshape(-1) if int(v) == 6))
     return n_op, n_sc
 
