@@ -19,6 +19,10 @@ Modules
   sampler    Philox4x32-10 and sequential conditional sampling
   mlp        learned warm-start network, forward/backward in FP64
   flops      algorithmic FLOP accounting
+  cutoff     Fock-cutoff error bounds and the effective cutoff
+  cz         global-CZ (non-Gaussian) parent Hamiltonian and its MPO
+  plbo       gate-parameterised local basis: transformed operators by
+             the definition, slot environments, gradients, Adam
 
 Parity status: every function is pinned by a CPU test in tests/ except those
 whose module docstring says "parity unpinned".

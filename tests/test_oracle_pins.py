@@ -710,3 +710,175 @@ def test_cz_mpo_contracts_to_the_dense_hamiltonian():
         wg = mpo.bond_dims(N)
         assert w == [wg[t] + (0 if t in (0, N) else 4 + 4 * t) for t in range(N + 1)]
         assert all(k.shape == (w[s], w[s + 1]) for s, k in enumerate(kinds))
+
+
+# ------------------------------------------------------------------ pLBO (Sec. III.B)
+def _plbo_blocks(d):
+    from oracle import plbo
+    return plbo.quadratic_blocks(d)
+
+
+def test_plbo_single_gates_have_their_closed_forms():
+    """Each gate of eq. pLBOUnitary alone, built by expm of its generator,
+    transforms the quadratures as the textbook relations say: displacement
+    shifts X, P by sqrt2 alpha; squeezing (phi = 0) scales X by e^-r and P by
+    e^r; rotation turns (X, P); the quadratic phase adds s X to P; the cubic
+    phase adds sqrt2 gamma X^2 to P; the Kerr gate multiplies <m|X|n> by
+    exp(i kappa (n^2 - m^2)).  A wrong sign or factor in any generator fails."""
+    from oracle import plbo
+    d = 7
+    X, P, X2, P2, Pt = _plbo_blocks(d)
+    I = np.eye(d)
+
+    def one(j, v):
+        q = np.zeros(8)
+        q[j] = v
+        return plbo.transformed_ops(q, d, 1.0, 1.0, 0.0)
+
+    Xt, Ptl, _, X2t, _ = one(0, 0.3)
+    assert np.abs(Xt - (X + math.sqrt(2) * 0.3 * I)).max() < 1e-12
+    assert np.abs(X2t - (X2 + 2 * math.sqrt(2) * 0.3 * X + 0.18 * I)).max() < 1e-12
+    Xt, Ptl, *_ = one(1, -0.25)
+    assert np.abs(Ptl - (P - math.sqrt(2) * 0.25 * I)).max() < 1e-12
+    Xt, Ptl, *_ = one(2, 0.4)
+    assert np.abs(Xt - math.exp(-0.4) * X).max() < 1e-12 and np.abs(Ptl - math.exp(0.4) * P).max() < 1e-12
+    Xt, Ptl, *_ = one(4, 0.7)
+    c, s = math.cos(0.7), math.sin(0.7)
+    assert np.abs(Xt - (c * X - s * P)).max() < 1e-12 and np.abs(Ptl - (c * P + s * X)).max() < 1e-12
+    Xt, Ptl, *_ = one(5, 0.3)
+    assert np.abs(Xt - X).max() < 1e-12 and np.abs(Ptl - (P + 0.3 * X)).max() < 1e-12
+    Xt, Ptl, *_ = one(6, 0.1)
+    assert np.abs(Xt - X).max() < 1e-12 and np.abs(Ptl - (P + math.sqrt(2) * 0.1 * X2)).max() < 1e-12
+    n = np.arange(d)
+    Xt, *_ = one(7, 0.2)
+    assert np.abs(Xt - X * np.exp(1j * 0.2 * (n[None, :] ** 2 - n[:, None] ** 2))).max() < 1e-12
+    # a squeeze along phi = pi/2 exchanges the roles: X rotated by 45 degrees mixes
+    Xt, Ptl, *_ = plbo.transformed_ops([0, 0, 0.4, math.pi, 0, 0, 0, 0], d, 1.0, 1.0, 0.0)
+    assert np.abs(Xt - math.exp(0.4) * X).max() < 1e-12 and np.abs(Ptl - math.exp(-0.4) * P).max() < 1e-12
+
+
+def test_plbo_composite_transform_matches_the_papers_closed_form():
+    """eq. SymplecticBasisTransformation: U^dag a U written out with the
+    Kerr phases, built at d + 4 and truncated (SM Sec. 5), gives the same
+    X, P, X^2, P^2-bearing S and XP + PX as the definition (product of gate
+    exponentials in 200 levels) for composite parameters, to 1e-10."""
+    from oracle import plbo
+    d, Db = 8, 12
+    rng = np.random.default_rng(3)
+    a = np.zeros((Db, Db), complex)
+    for k in range(1, Db):
+        a[k - 1, k] = math.sqrt(k)
+    ad = a.conj().T
+    nn = np.arange(Db, dtype=float)
+    for _ in range(3):
+        ax, ap, r, phi, th, s, g, kap = rng.uniform(-1, 1, 8) * [0.4, 0.4, 0.5, 3, 3, 0.3, 0.1, 0.1]
+        e1, e2 = np.exp(1j * th), np.exp(1j * (phi - th))
+        c1 = (1 + 0.5j * s) * e1 * math.cosh(r) + 0.5j * s * e2 * math.sinh(r)
+        c2 = (1 - 0.5j * s) * e2 * math.sinh(r) - 0.5j * s * e1 * math.cosh(r)
+        c3 = e1 * math.cosh(r) + e2 * math.sinh(r)
+        K1 = np.diag(np.exp(1j * kap * (2 * nn - 1)))
+        K3 = np.diag(np.exp(4j * kap * (nn - 1)))
+        At = (c1 * a @ K1 - c2 * K1.conj() @ ad
+              + 0.5j * g * c3 * (np.diag(2 * nn + 1) + a @ a @ K3 + K3.conj() @ ad @ ad)
+              + (ax + 1j * ap) * np.eye(Db))
+        Xb = (At + At.conj().T) / math.sqrt(2)
+        Pb = -1j * (At - At.conj().T) / math.sqrt(2)
+        cut = lambda M: M[:d, :d]
+        want = (cut(Xb), cut(Pb), cut(0.5 * (1.1 * Xb @ Xb + 0.8 * Pb @ Pb + 0.3 * (Xb @ Pb + Pb @ Xb)) - 0.5 * np.eye(Db)),
+                cut(Xb @ Xb), cut(Xb @ Pb + Pb @ Xb))
+        got = plbo.transformed_ops([ax, ap, r, phi, th, s, g, kap], d, 1.1, 0.8, 0.3)
+        for w, o in zip(want, got):
+            assert np.abs(w - o).max() < 1e-10
+
+
+def test_plbo_definition_is_converged_in_the_fock_cutoff():
+    """The d x d transformed operators do not move when the expm space grows
+    from 200 (the default) to 256 levels, at the edge of the test parameter
+    range (the cubic phase spreads the basis states most)."""
+    from oracle import plbo
+    p = [0.3, -0.2, 0.45, 0.7, 0.5, 0.2, 0.1, 0.06]
+    a = plbo.transformed_ops(p, 10, 1.2, 0.9, 0.2)
+    b = plbo.transformed_ops(p, 10, 1.2, 0.9, 0.2, L=256)
+    assert max(np.abs(x - y).max() for x, y in zip(a, b)) < 1e-10
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.3])
+def test_plbo_slot_environments_reproduce_the_energy(kappa):
+    """E = sum_k <G_k, O_k>: with G_k from the core environment of a site and
+    the slot coefficients of its core, the site energy equals <psi|H|psi> of
+    the dense MPO and MPS, for the Fock operators and for pLBO operators at
+    that site (Gaussian and global-CZ MPOs)."""
+    from oracle import plbo, cz
+    N, d, site = 4, 4, 2
+    r, U = W.make_problem(N, 5, (0.3, 0.6))
+    al, be, ga = gbs.coefficients(r, U)
+    rng = np.random.default_rng(8)
+    dims = [1, 3, 5, 3, 1]
+    mps = [rng.normal(size=(dims[s], d, dims[s + 1])) + 1j * rng.normal(size=(dims[s], d, dims[s + 1]))
+           for s in range(N)]
+    p = [0.2, -0.1, 0.3, 0.4, 0.2, 0.1, 0.05, 0.04]
+    ops = [cz.local_ops(d, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+    ops[site] = plbo.transformed_ops(p, d, al[site, site], be[site, site], ga[site, site])
+    Ws = cz.cores(al, be, ga, kappa, ops) if kappa else mpo.cores(al, be, ga, [o[:3] for o in ops])
+    psi = M.to_dense(mps)
+    E = np.real(psi.conj() @ mpo.to_dense(Ws) @ psi)
+    Ls = dmrg.left_envs(mps, Ws)
+    Rs = dmrg.right_envs(mps, Ws)
+    Gf = plbo.core_environment(Ls[site], mps[site], Rs[site + 1])
+    mk = (plbo.cz_core_maker(al, be, ga, kappa, site) if kappa else plbo.gaussian_core_maker(al, be, ga, site))
+    G = plbo.slot_gradients(Gf, plbo.slot_coefficients(mk, d))
+    assert abs(plbo.site_energy(G, ops[site]) - E) < 1e-9 * max(1.0, abs(E))
+
+
+def test_plbo_parameter_gradient_closed_forms():
+    """At p = 0 the derivatives of the operators are closed forms: d/dalpha_x
+    gives (sqrt2 I, 0, S', 2 sqrt2 X, 2 sqrt2 P) and d/dtheta gives
+    (-P, X, ., -(XP+PX), 2(X^2 - P^2)).  The five-point difference of the
+    site energy matches Re <G, dO> for a random G."""
+    from oracle import plbo
+    d, a_ss, b_ss, g_ss = 6, 1.3, 0.7, 0.2
+    rng = np.random.default_rng(4)
+    G = rng.normal(size=(6, d, d)) + 1j * rng.normal(size=(6, d, d))
+    X, P, X2, P2, Pt = _plbo_blocks(d)
+    g = plbo.param_gradient(G, np.zeros(8), d, a_ss, b_ss, g_ss, L=64)
+    r2 = math.sqrt(2)
+
+    def dE(dX, dP, dX2, dP2, dPt):
+        dS = 0.5 * (a_ss * dX2 + b_ss * dP2 + g_ss * dPt)
+        return sum(np.real(np.sum(G[k + 1] * o)) for k, o in enumerate((dX, dP, dS, dX2, dPt)))
+
+    Z = np.zeros((d, d))
+    assert abs(g[0] - dE(r2 * np.eye(d), Z, 2 * r2 * X, Z, 2 * r2 * P)) < 1e-8
+    assert abs(g[1] - dE(Z, r2 * np.eye(d), Z, 2 * r2 * P, 2 * r2 * X)) < 1e-8
+    assert abs(g[4] - dE(-P, X, -Pt, Pt, 2 * (X2 - P2))) < 1e-8
+
+
+def test_plbo_adam_first_step_moves_each_free_parameter_by_lr():
+    """Adam's bias correction makes the first update lr * g / (|g| + eps): a
+    step of lr against the sign of every free gradient component, none on
+    masked ones."""
+    from oracle import plbo
+    g0 = np.array([0.5, -2.0, 1e-3, 3.0, -0.1, 0.2, 7.0, -4.0])
+    mask = [1, 1, 1, 1, 0, 1, 1, 1]
+    p, st = plbo.adam(np.zeros(8), lambda q: g0, 1, 0.01, mask=mask)
+    want = np.where(np.array(mask, bool), -0.01 * np.sign(g0), 0.0)
+    assert np.abs(p - want).max() < 1e-7 and st[2] == 1
+
+
+def test_plbo_product_of_squeezed_vacua_is_exact_with_one_basis_state():
+    """With no interferometer the output state is a product of squeezed vacua,
+    so a one-state pLBO basis S(r_i e^{i phi})|0> on every mode is exact and
+    its energy is 0 for the right orientation of the squeeze, while the Fock
+    vacuum (p = 0) sits at the sum of the single-mode energies > 0."""
+    from oracle import plbo
+    r = np.array([0.5, 0.3])
+    U = np.eye(2, dtype=complex)
+    al, be, ga = gbs.coefficients(r, U)
+    best = []
+    for phi in (0.0, math.pi):
+        ops = [plbo.transformed_ops([0, 0, r[s], phi, 0, 0, 0, 0], 1, al[s, s], be[s, s], ga[s, s]) for s in range(2)]
+        Ws = mpo.cores(al, be, ga, [o[:3] for o in ops])
+        best.append(np.real(mpo.to_dense(Ws)[0, 0]))
+    assert min(best) < 1e-10 and max(best) > 0.1
+    ops0 = [plbo.transformed_ops(np.zeros(8), 1, al[s, s], be[s, s], ga[s, s]) for s in range(2)]
+    assert np.real(mpo.to_dense(mpo.cores(al, be, ga, [o[:3] for o in ops0]))[0, 0]) > 0.1
