@@ -236,6 +236,68 @@ tn_status tn_energy_variance(tn_ctx* ctx, const tn_mpo* mpo, const tn_mps* mps, 
 tn_status tn_lbo_step(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, int32_t site, const tn_sweep_opts* opts,
                       double* discarded);
 
+/* ------------------------------------------------------------------ gate-parameterised local basis
+ * Sec. III.B (eq. pLBOUnitary, eq. SymplecticBasisTransformation; SM Sec. 5).
+ * The basis of mode i is U_i|m>, m < d, with
+ *   U = D(alpha) S(r e^{i phi}) R(theta) P2(s) P3(gamma) K(kappa),
+ * parameters p = (alpha_x, alpha_p, r, phi, theta, s, gamma, kappa), alpha =
+ * alpha_x + i alpha_p, in the gate conventions D = exp(alpha a^dag - alpha^* a),
+ * S(z) = exp((z^* a^2 - z a^dag^2)/2), R = exp(i theta n),
+ * P2 = exp(i s (a + a^dag)^2 / 4), P3 = exp(i gamma (a + a^dag)^3 / 6),
+ * K = exp(i kappa n^2).  The site operators are the blocks <m|U^dag O U|n>
+ * built from the closed form of U^dag a U at d + 4 levels and truncated to d.
+ * Parameter arrays are host doubles [N][TN_PLBO_NPARAM]. */
+#define TN_PLBO_NPARAM 8
+
+typedef struct {
+  int32_t steps;      /* Adam steps on the site's parameters per visit, >= 0 */
+  int32_t matvecs;    /* single-site Lanczos matvecs in the current basis before them (0: none) */
+  double lr;          /* Adam step size > 0 */
+  double beta1, beta2;/* Adam moment decays in [0, 1) */
+  double eps;         /* Adam denominator guard > 0 */
+  uint32_t mask;      /* bit j set: parameter j is optimised (0xFF: all eight) */
+} tn_plbo_opts;
+
+/* Host only, no GPU work.  ops: [5][d][d] complex (interleaved doubles) =
+ * (X, P, S, X^2, XP + PX) in the basis of params (8 doubles), S =
+ * (a_ss X^2 + b_ss P^2 + g_ss (XP + PX))/2 - 1/2; dops (may be NULL):
+ * [8][5][d][d] complex, their derivatives in the parameters.  TN_EINVAL on
+ * d outside [1, 64], NULL params/ops or non-finite inputs. */
+tn_status tn_plbo_ops(int32_t d, const double* params, double a_ss, double b_ss, double g_ss, double* ops,
+                      double* dops);
+/* Host only.  iso: [D][d] complex, <n|U|m> for n < D, m < d: the gates applied
+ * to |m> in `levels` Fock levels (levels >= D; each exponential by a Taylor
+ * series over sub-steps of unit norm), then cut to D rows.  TN_EINVAL on
+ * d < 1, D < d, D > 4096, levels outside [D, 8192] or non-finite params. */
+tn_status tn_plbo_fock_isometry(int32_t D, int32_t d, const double* params, int32_t levels, double* iso);
+/* Switch the MPO to gate-parameterised bases with the given parameters (NULL:
+ * all zero, i.e. the Fock basis) and reset the Adam moments.  From then on the
+ * site operators follow the parameters, linear LBO is refused (TN_ESTATE) and
+ * the Fock image of each basis (tn_mpo_isometries, observables) is recomputed
+ * on demand.  TN_EINVAL on a NULL handle or non-finite parameters. */
+tn_status tn_plbo_enable(tn_mpo* mpo, const double* params);
+/* Current parameters [N][8]; TN_ESTATE if the MPO has no parameterised basis. */
+tn_status tn_plbo_params(const tn_mpo* mpo, double* params);
+/* Slot environments and gradient at `site` in `precision`, for x = the site
+ * tensor divided by its norm and the environments of the other tensors as
+ * they are (when `site` is the orthogonality centre, E below is <H>):
+ *   G (may be NULL): host [6][d][d] complex, G_k[n'][n] = dE/dO_k[n'][n] for
+ *     the slots (I, X, P, S, X^2, XP + PX), so E = Re sum_k <G_k, O_k>;
+ *   energy: E = <x|H_eff|x> at the current parameters;
+ *   grad (may be NULL): host [8], dE/dp_j.
+ * Environments are built or reused as for tn_lbo_step. */
+tn_status tn_plbo_site_gradient(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, int32_t site, int32_t precision, double* G,
+                                double* energy, double* grad);
+/* One two-site sweep (as tn_dmrg_sweep, opts->lbo must be 0) in which every
+ * visit of a centre site first runs the pLBO step: popts->matvecs Lanczos
+ * matvecs on the single-site tensor, its slot environments, and popts->steps
+ * Adam steps on the site's masked parameters (moments kept per site across
+ * sweeps).  gain (may be NULL) receives the sum over visits of the site-energy
+ * decrease from the parameter steps.  TN_ESTATE if the MPO has no
+ * parameterised basis; TN_EINVAL on bad options. */
+tn_status tn_plbo_sweep(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, const tn_sweep_opts* opts, const tn_plbo_opts* popts,
+                        tn_sweep_stats* out, double* gain);
+
 /* ------------------------------------------------------------------ observables
  * Single-mode photon-number marginals P_j(n), j < n_modes, n < D_raw, in FP64
  * (eq. ReducedDensityMatrix, eq. InverseBasisTransformation).  out: host

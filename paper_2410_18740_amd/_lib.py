@@ -65,6 +65,11 @@ class tn_solve_opts(C.Structure):
                 ("bulk_tol", C.c_double), ("refine_tol", C.c_double), ("sweep", tn_sweep_opts)]
 
 
+class tn_plbo_opts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("matvecs", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("mask", C.c_uint32)]
+
+
 class tn_solve_result(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("refine_sweeps", C.c_int32), ("reached", C.c_int32), ("pad_", C.c_int32),
                 ("energy", C.c_double), ("seconds", C.c_double), ("t_target", C.c_double),
@@ -134,6 +139,12 @@ def lib():
         "tn_cutoff_report": (i32, [i32, P(dbl), P(dbl), i32, i32, dbl, P(dbl), P(i32), P(dbl)]),
         "tn_ws_initial_state": (i32, [i32, i32, i32, i32, P(C.c_float), C.c_uint64, dbl, P(dbl), P(i32), P(dbl),
                                       szt, P(szt)]),
+        "tn_plbo_ops": (i32, [i32, P(dbl), dbl, dbl, dbl, P(dbl), P(dbl)]),
+        "tn_plbo_fock_isometry": (i32, [i32, i32, P(dbl), i32, P(dbl)]),
+        "tn_plbo_enable": (i32, [vp, P(dbl)]),
+        "tn_plbo_params": (i32, [vp, P(dbl)]),
+        "tn_plbo_site_gradient": (i32, [vp, vp, vp, i32, i32, P(dbl), P(dbl), P(dbl)]),
+        "tn_plbo_sweep": (i32, [vp, vp, vp, P(tn_sweep_opts), P(tn_plbo_opts), P(tn_sweep_stats), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

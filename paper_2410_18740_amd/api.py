@@ -267,6 +267,92 @@ def lbo_step(ctx: Context, mpo: MPO, mps: MPS, site: int, opts: SweepOpts) -> fl
     return disc.value
 
 
+PLBO_NPARAM = 8
+
+
+class PlboOpts:
+    """Per-visit pLBO step: Lanczos matvecs on the centre tensor, then Adam
+    steps on the masked parameters (bit j of mask: parameter j)."""
+    steps: int = 10
+    matvecs: int = 0
+    lr: float = 0.02
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    mask: int = 0xFF
+
+    def __init__(self, **kw):
+        for k, v in kw.items():
+            if not hasattr(self, k):
+                raise AttributeError(k)
+            setattr(self, k, v)
+
+    def c(self):
+        return L.tn_plbo_opts(self.steps, self.matvecs, self.lr, self.beta1, self.beta2, self.eps, self.mask)
+
+
+def plbo_ops(d: int, params, a_ss: float, b_ss: float, g_ss: float, derivatives: bool = False):
+    """(X, P, S, X^2, XP + PX) in the gate-parameterised basis, [5][d][d]
+    complex; with derivatives also d/dp_j of each, [8][5][d][d]."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    ops = np.zeros((5, d, d), dtype=np.complex128)
+    dops = np.zeros((PLBO_NPARAM, 5, d, d), dtype=np.complex128) if derivatives else None
+    st = L.lib().tn_plbo_ops(d, L.dptr(p), a_ss, b_ss, g_ss, L.dptr(ops.view(np.float64)),
+                             L.dptr(dops.view(np.float64)) if derivatives else None)
+    if st != L.TN_OK:
+        raise TnError(st, "tn_plbo_ops: bad arguments")
+    return (ops, dops) if derivatives else ops
+
+
+def plbo_fock_isometry(D: int, d: int, params, levels: int | None = None):
+    """<n|U|m> for n < D, m < d, [D][d] complex."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    W = np.zeros((D, d), dtype=np.complex128)
+    lv = max(D, d) + 192 if levels is None else levels
+    st = L.lib().tn_plbo_fock_isometry(D, d, L.dptr(p), lv, L.dptr(W.view(np.float64)))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_plbo_fock_isometry: bad arguments")
+    return W
+
+
+def plbo_enable(ctx: Context, mpo: MPO, params=None):
+    """Switch mpo to gate-parameterised bases ([N][8] parameters, None: zeros)."""
+    if params is None:
+        ctx.check(L.lib().tn_plbo_enable(mpo.h, None))
+    else:
+        p = np.ascontiguousarray(params, dtype=np.float64).reshape(mpo.N, PLBO_NPARAM)
+        ctx.check(L.lib().tn_plbo_enable(mpo.h, L.dptr(p)))
+
+
+def plbo_params(ctx: Context, mpo: MPO):
+    p = np.zeros((mpo.N, PLBO_NPARAM))
+    ctx.check(L.lib().tn_plbo_params(mpo.h, L.dptr(p)))
+    return p
+
+
+def plbo_site_gradient(ctx: Context, mpo: MPO, mps: MPS, site: int, precision: int = FP64):
+    """(G [6][d][d] complex, energy, grad [8]) at the orthogonality centre."""
+    G = np.zeros((6, mpo.d, mpo.d), dtype=np.complex128)
+    e = C.c_double()
+    g = np.zeros(PLBO_NPARAM)
+    ctx.check(L.lib().tn_plbo_site_gradient(ctx.h, mpo.h, mps.h, site, precision, L.dptr(G.view(np.float64)),
+                                            C.byref(e), L.dptr(g)))
+    return G, e.value, g
+
+
+def plbo_sweep(ctx: Context, mpo: MPO, mps: MPS, opts: SweepOpts, popts: PlboOpts) -> dict:
+    """One two-site sweep with a pLBO step at every centre visit; the stats
+    dict gains "plbo_gain" (summed site-energy decrease of the parameter steps)."""
+    st = L.tn_sweep_stats()
+    o = opts.c()
+    po = popts.c()
+    g = C.c_double()
+    ctx.check(L.lib().tn_plbo_sweep(ctx.h, mpo.h, mps.h, C.byref(o), C.byref(po), C.byref(st), C.byref(g)))
+    out = st.as_dict()
+    out["plbo_gain"] = g.value
+    return out
+
+
 def marginals(ctx: Context, mps: MPS, mpo: MPO, n_modes: int | None = None):
     n = mps.N if n_modes is None else n_modes
     out = np.zeros((n, mpo.D_raw))

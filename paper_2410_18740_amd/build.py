@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtn.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gemm.hip", "ops.hip", "eig.hip", "plan.hip", "api.hip", "dmrg.hip", "sample.hip", "mlp.hip"]
+SOURCES = ["gemm.hip", "ops.hip", "eig.hip", "plan.hip", "api.hip", "dmrg.hip", "sample.hip", "mlp.hip", "plbo.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed FP32 (v_pk_*_f32) code generation
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

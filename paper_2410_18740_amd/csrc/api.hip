@@ -592,6 +592,11 @@ extern "C" tn_status tn_mpo_coefficients(const tn_mpo* mpo, double* a, double* b
 
 extern "C" tn_status tn_mpo_isometries(const tn_mpo* mpo, double* iso) {
   if (!mpo || !iso) return TN_EINVAL;
+  try {
+    plbo_sync_iso(mpo);
+  } catch (const TnError& e) {
+    return e.code;
+  }
   size_t o = 0;
   for (int s = 0; s < mpo->N; ++s)
     for (auto& z : mpo->iso[s]) { iso[o++] = z.real(); iso[o++] = z.imag(); }

@@ -674,6 +674,164 @@ static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_
   return disc;
 }
 
+// ------------------------------------------------------------------ gate-parameterised basis (Sec. III.B)
+static void plbo_set_site(tn_mpo* mpo, int s) {
+  const int N = mpo->N;
+  const size_t ss = (size_t)s * N + s;
+  plbo_local_ops(mpo->d, mpo->pp[s].data(), mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], mpo->loc_ops[s], nullptr);
+  mpo->iso_stale[s] = true;
+  mpo->upload_site(s);
+  mpo->version++;
+}
+
+// The Fock image U[:D, :d] of every basis changed since the last call (a
+// cache of the parameters, recomputed before photon-number observables).
+void plbo_sync_iso(const tn_mpo* cmpo) {
+  tn_mpo* mpo = const_cast<tn_mpo*>(cmpo);
+  if (!mpo->plbo) return;
+  const int levels = std::max(mpo->D_raw, mpo->d) + 192;
+  for (int s = 0; s < mpo->N; ++s) {
+    if (!mpo->iso_stale[s]) continue;
+    plbo_fock_isometry(mpo->D_raw, mpo->d, mpo->pp[s].data(), levels, mpo->iso[s]);
+    mpo->upload_site(s);
+    mpo->iso_stale[s] = false;
+  }
+}
+
+// G[k][n'][n] = dE/dO_k[n'][n], k = 0..NOPS (slot 0: identity), of the single-
+// site window at s for the tensor x (chi_l x d x chi_r): E = <x|H_eff|x> is
+// sum_k <G_k, O_k> with O_0 = I.  From the window operator's own plan: each
+// right entry r adds src_r R_r with src_r = Y_i (identity) or
+// sum_t c_t O_{a_t} Y_{i_t}, so G_{a_t} += c_t sum_{a,b} conj(U_r[a][n'][b]) Y_{i_t}[a][n][b]
+// with U_r = x R_r^H.
+static void plbo_slot_envs(tn_ctx* c, const tn_mpo* mpo, tn_mps* m, int s, int prec, const cf64* x,
+                           std::vector<cd>& G) {
+  const int d = mpo->d, cl = m->dims[s], cr = m->dims[s + 1];
+  const int sprec = prec == PREC_FP64 ? PREC_FP64 : PREC_FP32;
+  const size_t eb = elem_bytes(sprec);
+  WindowOp op;
+  op.setup(c, mpo, s, 1, prec, cl, cr, env_ptrs(m, mpo, true, s, prec), env_ptrs(m, mpo, false, s + 1, prec), false,
+           "pg");
+  op.apply_left(x);
+  const size_t n = op.n;
+  const int nR = (int)op.plan.R.size();
+  char* U = (char*)ws_get(c, "pg:U", (size_t)std::max(1, nR) * n * eb);
+  std::vector<GemmJob> jobs;
+  std::vector<GemmSeg> segs;
+  for (int r = 0; r < nR; ++r) {
+    segs.push_back({op.xin, op.rptr[r], cr, cr, cr, 0});
+    jobs.push_back({U + (size_t)r * n * eb, cr, cl * d, cr, r, 1});
+  }
+  gemm_batch(c, prec, 0, 1, jobs, segs, cl * d, cr, "pg:g");
+  std::vector<SlotJob> sj;
+  std::vector<std::pair<int, double>> meta;
+  for (int r = 0; r < nR; ++r) {
+    const auto& R = op.plan.R[r];
+    const char* Ur = U + (size_t)r * n * eb;
+    if (R.kind == 0) {
+      sj.push_back({Ur, op.ybuf + (size_t)R.idx * n * eb});
+      meta.push_back({0, 1.0});
+    } else {
+      for (const auto& t : op.plan.T[R.idx].terms) {
+        if (t.b != 0) TN_THROW(TN_EINVAL, "single-site plan with a second leg");
+        sj.push_back({Ur, op.ybuf + (size_t)t.ych * n * eb});
+        meta.push_back({t.a, t.c});
+      }
+    }
+  }
+  G.assign((size_t)(NOPS + 1) * d * d, 0.0);
+  if (sj.empty()) return;
+  SlotJob* dj = wsT<SlotJob>(c, "pg:jobs", sj.size());
+  cf64* part = wsT<cf64>(c, "pg:part", sj.size() * d * d);
+  upload(c, dj, sj.data(), sj.size() * sizeof(SlotJob));
+  HIPCHK(launch_slot_gram(sprec, dj, (int)sj.size(), cl, d, cr, part, c->stream));
+  std::vector<cf64> h(sj.size() * d * d);
+  download(c, h.data(), part, h.size() * sizeof(cf64));
+  for (size_t j = 0; j < sj.size(); ++j)
+    for (int e = 0; e < d * d; ++e)
+      G[(size_t)meta[j].first * d * d + e] += meta[j].second * cd(h[j * d * d + e].x, h[j * d * d + e].y);
+}
+
+// E(p) = Re sum_k <G_k, O_k(p)> and its gradient in the parameters of site s
+static double plbo_energy_grad(const tn_mpo* mpo, int s, const std::vector<cd>& G, const double* p, double* grad) {
+  const int d = mpo->d, N = mpo->N;
+  const size_t ss = (size_t)s * N + s, dd = (size_t)d * d;
+  std::vector<cd> ops, dops;
+  plbo_local_ops(d, p, mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], ops, grad ? &dops : nullptr);
+  double e = 0.0;
+  for (int i = 0; i < d; ++i) e += G[(size_t)i * d + i].real();
+  for (int k = 1; k <= NOPS; ++k)
+    for (size_t q = 0; q < dd; ++q) e += (G[k * dd + q] * ops[(k - 1) * dd + q]).real();
+  if (grad)
+    for (int j = 0; j < TN_PLBO_NPARAM; ++j) {
+      double g = 0.0;
+      for (int k = 1; k <= NOPS; ++k)
+        for (size_t q = 0; q < dd; ++q) g += (G[k * dd + q] * dops[((size_t)j * NOPS + k - 1) * dd + q]).real();
+      grad[j] = g;
+    }
+  return e;
+}
+
+struct PlboStep {
+  double e0 = 0.0, e1 = 0.0;  // site energy before and after the parameter steps
+  int64_t mv = 0;
+};
+
+// One visit of site s (the orthogonality centre): optional single-site Lanczos
+// in the current basis, slot environments, then Adam (Kingma & Ba) steps on
+// the site's parameters with the tensor held fixed (Sec. III.B: per-site
+// gradient optimisation sweeping like single-site DMRG).
+static PlboStep plbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_opts& o, const tn_plbo_opts& po) {
+  PlboStep R;
+  const int d = mpo->d, cl = m->dims[s], cr = m->dims[s + 1];
+  const int64_t n = (int64_t)cl * d * cr;
+  if (po.matvecs > 0) {
+    WindowOp op;
+    op.setup(c, mpo, s, 1, o.precision, cl, cr, env_ptrs(m, mpo, true, s, o.precision),
+             env_ptrs(m, mpo, false, s + 1, o.precision), false, "plz");
+    LzResult lz = lanczos(c, [&](const cf64* x, cf64* y) { op.apply(x, y); }, m->A[s], n, o.tol, o.krylov_max,
+                          po.matvecs, matvec_unit(o.precision));
+    c->lz_iters += lz.matvecs;
+    c->lz_full += lz.full_passes;
+    R.mv = lz.matvecs;
+  }
+  const double nr = dev_norm2(c, m->A[s], n);
+  if (!(nr > 0.0) || !std::isfinite(nr)) TN_THROW(TN_ENUMERIC, "zero or non-finite centre tensor");
+  HIPCHK(launch_scale_host(m->A[s], m->A[s], 1.0 / std::sqrt(nr), n, c->stream));
+  std::vector<cd> G;
+  plbo_slot_envs(c, mpo, m, s, o.precision, m->A[s], G);
+  auto& p = mpo->pp[s];
+  auto& mm = mpo->pm[s];
+  auto& vv = mpo->pv[s];
+  double g[TN_PLBO_NPARAM];
+  R.e0 = plbo_energy_grad(mpo, s, G, p.data(), nullptr);
+  for (int it = 0; it < po.steps; ++it) {
+    plbo_energy_grad(mpo, s, G, p.data(), g);
+    const int t = ++mpo->pt[s];
+    const double c1 = 1.0 - std::pow(po.beta1, t), c2 = 1.0 - std::pow(po.beta2, t);
+    for (int j = 0; j < TN_PLBO_NPARAM; ++j) {
+      if (!((po.mask >> j) & 1u)) continue;
+      mm[j] = po.beta1 * mm[j] + (1.0 - po.beta1) * g[j];
+      vv[j] = po.beta2 * vv[j] + (1.0 - po.beta2) * g[j] * g[j];
+      p[j] -= po.lr * (mm[j] / c1) / (std::sqrt(vv[j] / c2) + po.eps);
+    }
+  }
+  R.e1 = plbo_energy_grad(mpo, s, G, p.data(), nullptr);
+  for (int j = 0; j < TN_PLBO_NPARAM; ++j)
+    if (!std::isfinite(p[j])) TN_THROW(TN_ENUMERIC, "non-finite basis parameter");
+  if (po.steps > 0) plbo_set_site(mpo, s);
+  return R;
+}
+
+static void check_plbo_opts(const tn_plbo_opts* po) {
+  if (!po) TN_THROW(TN_EINVAL, "null pLBO options");
+  if (po->steps < 0 || po->matvecs < 0) TN_THROW(TN_EINVAL, "steps and matvecs must be >= 0");
+  if (!(po->lr > 0.0) || !std::isfinite(po->lr)) TN_THROW(TN_EINVAL, "lr must be positive");
+  if (!(po->beta1 >= 0.0 && po->beta1 < 1.0) || !(po->beta2 >= 0.0 && po->beta2 < 1.0))
+    TN_THROW(TN_EINVAL, "beta1 and beta2 must be in [0, 1)");
+  if (!(po->eps > 0.0)) TN_THROW(TN_EINVAL, "eps must be positive");
+}
+
 // ------------------------------------------------------------------ one two-site update
 struct StepStats {
   double disc = 0, lam = 0, t_heff = 0, t_lz = 0, t_svd = 0, t_env = 0, heff_flops = 0, env_flops = 0;
@@ -782,6 +940,29 @@ static double energy_fp64(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double*
 // workspace budget.
 static void product_ops(const tn_mpo* mpo, int s, std::vector<cd>& Q) {
   const int D = mpo->D_raw, d = mpo->d;
+  if (mpo->plbo) {
+    // gate-parameterised basis: O_a O_b of the exact operator blocks at d + 8
+    // levels (O_b moves a state below d by at most four levels, so every
+    // intermediate state is inside), truncated to d
+    const int e = d + 8, N = mpo->N;
+    const size_t ss = (size_t)s * N + s, ee = (size_t)e * e;
+    std::vector<cd> big;
+    plbo_local_ops(e, mpo->pp[s].data(), mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], big, nullptr);
+    auto B = [&](int a, int i, int j) -> cd {
+      if (a == 0) return i == j ? cd(1.0) : cd(0.0);
+      return big[(size_t)(a - 1) * ee + (size_t)i * e + j];
+    };
+    Q.assign((size_t)(NOPS + 1) * (NOPS + 1) * d * d, 0.0);
+    for (int a = 0; a <= NOPS; ++a)
+      for (int b = 0; b <= NOPS; ++b)
+        for (int i = 0; i < d; ++i)
+          for (int j = 0; j < d; ++j) {
+            cd t = 0.0;
+            for (int k = 0; k < e; ++k) t += B(a, i, k) * B(b, k, j);
+            Q[((size_t)(a * (NOPS + 1) + b) * d + i) * d + j] = t;
+          }
+    return;
+  }
   const auto& raw = mpo->raw_ops[s];
   const auto& W = mpo->iso[s];
   auto R = [&](int a, int i, int j) -> cd {
@@ -890,11 +1071,13 @@ static void check_pair(const tn_mpo* mpo, const tn_mps* m) {
   if (mpo->d != m->d) TN_THROW(TN_EINVAL, "MPO and MPS have different local dimension");
 }
 
-static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o, tn_sweep_stats* out) {
+static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o, tn_sweep_stats* out,
+                       const tn_plbo_opts* po = nullptr, double* plbo_gain = nullptr) {
   const double tstart = wall();
   tn_sweep_stats S{};
   S.energy = NAN;
   if (m->N < 2) TN_THROW(TN_EINVAL, "a sweep needs N >= 2");
+  if (o.lbo && mpo->plbo) TN_THROW(TN_ESTATE, "linear LBO on an MPO with a gate-parameterised basis");
   if (m->center != 0) canonicalize(c, m);
   ensure_right_envs(m, mpo, o.precision, &S.env_flops);
   const int N = m->N;
@@ -911,12 +1094,21 @@ static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o
     S.t_env += t.t_env;
     S.last_eigenvalue = t.lam;
   };
+  auto plbo_visit = [&](int site) {
+    const double t0 = wall();
+    const PlboStep P = plbo_site(c, mpo, m, site, o, *po);
+    S.matvecs += P.mv;
+    if (plbo_gain) *plbo_gain += P.e0 - P.e1;
+    S.t_lbo += wall() - t0;
+  };
   for (int s = 0; s <= N - 2; ++s) {
+    if (po) plbo_visit(s);
     if (o.lbo) { const double t0 = wall(); S.lbo_discarded += lbo_site(c, mpo, m, s, o, o.precision, &S.matvecs); S.t_lbo += wall() - t0; }
     acc(two_site(c, mpo, m, s, +1, o));
     m->center = s + 1;
   }
   for (int s = N - 2; s >= 0; --s) {
+    if (po) plbo_visit(s + 1);
     if (o.lbo) { const double t0 = wall(); S.lbo_discarded += lbo_site(c, mpo, m, s + 1, o, o.precision, &S.matvecs); S.t_lbo += wall() - t0; }
     acc(two_site(c, mpo, m, s, -1, o));
     m->center = s;
@@ -1160,5 +1352,75 @@ extern "C" tn_status tn_cgemm(tn_ctx* c, int32_t prec, int32_t ta, int32_t tb, i
   if (prec < 0 || prec > 2) TN_THROW(TN_EINVAL, "unknown precision");
   if (lda < (ta ? M : K) || ldb < (tb ? K : N) || ldc < N) TN_THROW(TN_EINVAL, "leading dimension too small");
   gemm1(c, prec, ta ? 1 : 0, tb ? 1 : 0, C, ldc, M, N, A, lda, B, ldb, K, 0, "api:gemm");
+  TN_GUARD_END(c)
+}
+
+// ------------------------------------------------------------------ gate-parameterised basis entry points
+extern "C" tn_status tn_plbo_enable(tn_mpo* mpo, const double* params) {
+  if (!mpo) return TN_EINVAL;
+  tn_ctx* c = mpo->ctx;
+  TN_GUARD_BEGIN
+  const int N = mpo->N;
+  if (params)
+    for (size_t i = 0; i < (size_t)N * TN_PLBO_NPARAM; ++i)
+      if (!std::isfinite(params[i])) TN_THROW(TN_EINVAL, "non-finite basis parameter");
+  mpo->plbo = true;
+  mpo->pp.assign(N, {});
+  mpo->pm.assign(N, {});
+  mpo->pv.assign(N, {});
+  mpo->pt.assign(N, 0);
+  mpo->iso_stale.assign(N, true);
+  for (int s = 0; s < N; ++s) {
+    for (int j = 0; j < TN_PLBO_NPARAM; ++j) mpo->pp[s][j] = params ? params[(size_t)s * TN_PLBO_NPARAM + j] : 0.0;
+    plbo_set_site(mpo, s);
+  }
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_plbo_params(const tn_mpo* mpo, double* params) {
+  if (!mpo || !params) return TN_EINVAL;
+  if (!mpo->plbo) return TN_ESTATE;
+  for (int s = 0; s < mpo->N; ++s)
+    for (int j = 0; j < TN_PLBO_NPARAM; ++j) params[(size_t)s * TN_PLBO_NPARAM + j] = mpo->pp[s][j];
+  return TN_OK;
+}
+
+extern "C" tn_status tn_plbo_site_gradient(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int32_t site, int32_t precision,
+                                           double* G, double* energy, double* grad) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !m || !energy) TN_THROW(TN_EINVAL, "null argument");
+  check_pair(mpo, m);
+  if (!mpo->plbo) TN_THROW(TN_ESTATE, "the MPO has no gate-parameterised basis");
+  if (precision < 0 || precision > 2) TN_THROW(TN_EINVAL, "unknown precision");
+  if (site < 0 || site >= m->N) TN_THROW(TN_EINVAL, "site out of range");
+  ensure_right_envs(m, mpo, precision, nullptr);
+  for (int t = 0; t < site; ++t)
+    if (!m->Lok[t + 1]) update_left_env(m, mpo, t, precision, nullptr);
+  const int d = mpo->d;
+  const int64_t n = (int64_t)m->dims[site] * d * m->dims[site + 1];
+  cf64* x = wsT<cf64>(c, "pgrad:x", n);
+  const double nr = dev_norm2(c, m->A[site], n);
+  if (!(nr > 0.0) || !std::isfinite(nr)) TN_THROW(TN_ENUMERIC, "zero or non-finite centre tensor");
+  HIPCHK(launch_scale_host(x, m->A[site], 1.0 / std::sqrt(nr), n, c->stream));
+  std::vector<cd> Gh;
+  plbo_slot_envs(c, mpo, m, site, precision, x, Gh);
+  *energy = plbo_energy_grad(mpo, site, Gh, mpo->pp[site].data(), grad);
+  if (G) std::memcpy(G, Gh.data(), Gh.size() * sizeof(cd));
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_plbo_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts* o,
+                                   const tn_plbo_opts* po, tn_sweep_stats* out, double* gain) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  if (!mpo || !m) TN_THROW(TN_EINVAL, "null handle");
+  check_opts(o);
+  check_plbo_opts(po);
+  check_pair(mpo, m);
+  if (!mpo->plbo) TN_THROW(TN_ESTATE, "the MPO has no gate-parameterised basis");
+  double g = 0.0;
+  sweep_impl(c, mpo, m, *o, out, po, &g);
+  if (gain) *gain = g;
   TN_GUARD_END(c)
 }

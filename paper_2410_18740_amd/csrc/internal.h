@@ -80,6 +80,12 @@ struct tn_mpo {
   double kappa = 0.0;                            // global-CZ strength (0: GBS)
   std::vector<std::vector<cd>> raw_ops;          // per site NOPS x D_raw x D_raw
   std::vector<std::vector<cd>> loc_ops;          // per site NOPS x d x d
+  // gate-parameterised local basis (Sec. III.B): when plbo is set, loc_ops of
+  // every site come from its eight parameters and iso is their Fock image
+  bool plbo = false;
+  std::vector<std::array<double, TN_PLBO_NPARAM>> pp, pm, pv;  // parameters, Adam moments
+  std::vector<int> pt;                                          // Adam step count per site
+  std::vector<bool> iso_stale;                                  // Fock image not yet recomputed
   cf64* d_ops64 = nullptr;   // [N][NOPS][d][d]
   cf32* d_ops32 = nullptr;
   cf64* d_raw64 = nullptr;   // [N][NOPS][D][D]
@@ -153,13 +159,33 @@ struct WindowOp {
   void* partials = nullptr; // split-K partials
   int nsplit = 1;
   size_t n = 0;
+  char* ybuf = nullptr;            // left-contracted tensors Y[i] = L_i x, one per plan.L entry
+  std::vector<const void*> rptr;   // right environment (plain or mixed) of each plan.R entry
   double fl_L = 0, fl_R = 0, fl_all = 0, by_L = 0, by_R = 0;
   void setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int prec_, int chi_l_, int chi_r_,
              const std::vector<const void*>& envL, const std::vector<const void*>& envRt, bool raw_leg0,
              const std::string& tag);
   void apply(const cf64* x, cf64* y);
+  void apply_left(const cf64* x);  // only the conversion of x and the left contraction into ybuf
 };
 
 size_t elem_bytes(int prec);
+
+// ------------------------------------------------------------------ gate-parameterised basis
+// ops = (X, P, S, X^2, XP + PX) in the basis of parameters p, NOPS x d x d;
+// dops (optional) = their derivatives, [TN_PLBO_NPARAM][NOPS][d][d]
+void plbo_local_ops(int d, const double* p, double a_ss, double b_ss, double g_ss, std::vector<cd>& ops,
+                    std::vector<cd>* dops);
+// W[n][m] = <n|U|m>, n < D, m < d, from the gates applied in `levels` Fock levels
+void plbo_fock_isometry(int D, int d, const double* p, int levels, std::vector<cd>& W);
+// recompute the Fock image (iso) of every gate-parameterised basis changed since the last call
+void plbo_sync_iso(const tn_mpo* mpo);
+struct SlotJob {
+  const void* U;  // x R^H (chi_l x d x chi_r)
+  const void* Y;  // L x   (chi_l x d x chi_r)
+};
+// out[j][n'][n] = sum_{a,b} conj(U_j[a][n'][b]) Y_j[a][n][b], FP64
+hipError_t launch_slot_gram(int sprec, const SlotJob* d_jobs, int njobs, int cl, int d, int cr, cf64* out,
+                            hipStream_t st);
 double matvec_flops_formula(const tn_mpo* mpo, int site, int chi_l, int chi_r);
 double env_flops_formula(const tn_mpo* mpo, int site, int chi_l, int chi_r);

@@ -384,6 +384,7 @@ __global__ void rho_scale_kernel(const cf64* C, int D, double s, cf64* out) {
 extern "C" tn_status tn_rdm(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int32_t n_modes, double* out) {
   if (!c) return TN_EINVAL;
   TN_GUARD_BEGIN
+  if (mpo) plbo_sync_iso(mpo);
   if (!m || !mpo || !out) TN_THROW(TN_EINVAL, "null argument");
   if (m->N != mpo->N || m->d != mpo->d) TN_THROW(TN_EINVAL, "MPO and MPS do not match");
   if (m->center != 0) TN_THROW(TN_ESTATE, "the MPS must be right-canonical with its centre at site 0");

@@ -192,6 +192,8 @@ void WindowOp::setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int pre
   char* Y = (char*)ws_get(ctx, tag + ":Y", std::max<size_t>(1, plan.L.size()) * n * eb);
   char* T = (char*)ws_get(ctx, tag + ":T", std::max<size_t>(1, plan.T.size()) * n * eb);
   xin = ws_get(ctx, tag + ":xin", n * eb);
+  ybuf = Y;
+  rptr = Rptr;
   // split-K for the right contraction
   const int BMr = (gprec == PREC_FP64) ? 64 : 128, BNr = BMr;
   const int Mr = chi_l * ds * dt;
@@ -278,6 +280,12 @@ void WindowOp::setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int pre
   if (!mixjobsR.empty())
     HIPCHK(launch_envmix(sprec, (MixJob*)(dd + o_mj) + mixjobs.size(), (int)mixjobsR.size(), (MixTerm*)(dd + o_mt),
                          (int64_t)chi_r * chi_r, ctx->stream));
+}
+
+void WindowOp::apply_left(const cf64* x) {
+  const int sprec = (prec == PREC_FP64) ? PREC_FP64 : PREC_FP32;
+  HIPCHK(launch_convert(sprec, xin, PREC_FP64, x, (int64_t)n, ctx->stream));
+  HIPCHK(launch_cgemm(prec, 0, 0, d_jobL, njobL, d_segL, chi_l, ds * dt * chi_r, 0, ctx->stream));
 }
 
 void WindowOp::apply(const cf64* x, cf64* y) {

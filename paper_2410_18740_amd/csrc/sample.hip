@@ -151,6 +151,7 @@ static void check_obs(const tn_mps* m, const tn_mpo* mpo) {
   if (!m || !mpo) TN_THROW(TN_EINVAL, "null handle");
   if (m->N != mpo->N || m->d != mpo->d) TN_THROW(TN_EINVAL, "MPO and MPS do not match");
   if (m->center != 0) TN_THROW(TN_ESTATE, "the MPS must be right-canonical with its centre at site 0");
+  plbo_sync_iso(mpo);
 }
 
 extern "C" tn_status tn_marginals(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int32_t n_modes, double* out) {

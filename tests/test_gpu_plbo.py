@@ -1,0 +1,194 @@
+"""GPU parity of the gate-parameterised local basis (pLBO, Sec. III.B) with the
+oracle: slot environments G_k = dE/dO_k of a site and the parameter gradient
+(Gaussian and global-CZ MPOs, FP64 and FP32), <H> and sigma_H^2 of a state in
+pLBO bases, the product-of-squeezed-vacua case where a two-state basis is
+exact, photon-number marginals through the Fock image of the bases, and the
+energy gain of pLBO sweeps over the Fock basis of the same size."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gbs, cz, mpo as ompo, dmrg as odmrg, plbo
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2410_18740_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _params(N, rng, scale=1.0):
+    return rng.uniform(-1, 1, (N, 8)) * np.array([0.3, 0.3, 0.4, 3, 3, 0.2, 0.08, 0.05]) * scale
+
+
+def _oracle_cores(r, U, kappa, params, d):
+    al, be, ga = gbs.coefficients(r, U)
+    N = len(r)
+    ops = [plbo.transformed_ops(params[s], d, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+    if kappa:
+        return al, be, ga, ops, cz.cores(al, be, ga, kappa, ops)
+    return al, be, ga, ops, ompo.cores(al, be, ga, [o[:3] for o in ops])
+
+
+def _rand_mps(N, d, chi, rng):
+    dims = [1] + [min(chi, d ** min(s + 1, N - s - 1)) for s in range(N - 1)] + [1]
+    return [rng.normal(size=(dims[s], d, dims[s + 1])) + 1j * rng.normal(size=(dims[s], d, dims[s + 1]))
+            for s in range(N)]
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.3])
+@pytest.mark.parametrize("N,d,chi,sites", [(5, 4, 6, (0, 2, 4)), (7, 3, 9, (1, 3, 5))])
+def test_plbo_slot_environments_and_gradient(ctx, kappa, N, d, chi, sites):
+    """G_k from the window operator's plan (left-contracted Y and right-
+    contracted U = x R^H) against the oracle's core environment and slot
+    coefficients; E = sum_k <G_k, O_k>; the parameter gradient against the
+    oracle's differences of that energy."""
+    import paper_2410_18740_amd as P
+    rng = np.random.default_rng(N + d + int(10 * kappa))
+    r, U = W.make_problem(N, 30 + N, (0.3, 0.7))
+    params = _params(N, rng)
+    al, be, ga, ops, Ws = _oracle_cores(r, U, kappa, params, d)
+    tensors = _rand_mps(N, d, chi, rng)
+    m = P.MPO(ctx, r, U, d + 2, d, kappa=kappa)
+    P.plbo_enable(ctx, m, params)
+    mps = P.MPS(ctx, tensors)
+    Ls = odmrg.left_envs(tensors, Ws)
+    Rs = odmrg.right_envs(tensors, Ws)
+    for site in sites:
+        x2 = float(np.sum(np.abs(tensors[site]) ** 2))
+        Gf = plbo.core_environment(Ls[site], tensors[site], Rs[site + 1]) / x2
+        mk = (plbo.cz_core_maker(al, be, ga, kappa, site) if kappa else plbo.gaussian_core_maker(al, be, ga, site))
+        Gref = plbo.slot_gradients(Gf, plbo.slot_coefficients(mk, d))
+        Eref = plbo.site_energy(Gref, ops[site])
+        scale = np.abs(Gref).max()
+        for prec, tol in ((P.FP64, 1e-11), (P.FP32, 2e-5)):
+            G, E, g = P.plbo_site_gradient(ctx, m, mps, site, prec)
+            assert np.abs(G - Gref).max() < tol * scale, (site, prec)
+            assert abs(E - Eref) < tol * max(1.0, abs(Eref)) * 10, (site, prec)
+        gref = plbo.param_gradient(Gref, params[site], d, al[site, site], be[site, site], ga[site, site], L=160)
+        _, _, g = P.plbo_site_gradient(ctx, m, mps, site, P.FP64)
+        assert np.abs(g - gref).max() < 1e-7 * max(1.0, np.abs(gref).max()), site
+
+
+def test_plbo_energy_and_variance_match_oracle(ctx):
+    """<H> of an MPS in pLBO bases equals the oracle's contraction with the
+    transformed operators; sigma_H^2 uses products of exact operator blocks,
+    equal to the oracle's variance with the MPS embedded in d + 8 levels."""
+    import paper_2410_18740_amd as P
+    N, d, chi = 5, 3, 6
+    rng = np.random.default_rng(77)
+    r, U = W.make_problem(N, 41, (0.3, 0.6))
+    params = _params(N, rng, 0.5)
+    al, be, ga, ops, Ws = _oracle_cores(r, U, 0.0, params, d)
+    tensors = _rand_mps(N, d, chi, rng)
+    m = P.MPO(ctx, r, U, d + 2, d)
+    P.plbo_enable(ctx, m, params)
+    mps = P.MPS(ctx, tensors)
+    mps.canonicalize()
+    e, _ = P.energy(ctx, m, mps)
+    assert abs(e - odmrg.energy(tensors, Ws)) < 1e-10 * max(1.0, abs(e))
+    _, h2_gpu, var_gpu = P.energy_variance(ctx, m, mps)
+    e8 = d + 8
+    ops8 = [plbo.transformed_ops(params[s], e8, al[s, s], be[s, s], ga[s, s]) for s in range(N)]
+    Ws8 = ompo.cores(al, be, ga, [o[:3] for o in ops8])
+    emb = [np.eye(e8, d, dtype=complex)] * N
+    _, h2, var = odmrg.energy_variance(tensors, Ws8, emb)
+    assert abs(h2_gpu - h2) < 1e-9 * max(1.0, h2)
+    assert abs(var_gpu - var) < 1e-9 * max(1.0, h2)
+
+
+def test_plbo_squeezed_product_state_becomes_exact(ctx):
+    """No interferometer: the state is a product of squeezed vacua.  With two
+    basis states per mode and only (r, phi) free, pLBO sweeps drive <H> from
+    the Fock-basis value to ~0, and the photon-number marginals through the
+    Fock image of the learned bases are the single-mode squeezed-vacuum
+    distributions (even photon numbers only)."""
+    import paper_2410_18740_amd as P
+    r = np.array([0.5, 0.3, 0.4])
+    U = np.eye(3, dtype=complex)
+    N, d, D = 3, 2, 16
+    m = P.MPO(ctx, r, U, D, d)
+    P.plbo_enable(ctx, m)
+    rng = np.random.default_rng(2)
+    mps = P.MPS(ctx, [rng.normal(size=(1, d, 1)) + 0j for _ in range(N)])
+    o = P.SweepOpts()
+    o.chi_max, o.tol = 1, 1e-12
+    po = P.PlboOpts(steps=30, lr=0.05, mask=0b1100)
+    first = None
+    for _ in range(12):
+        st = P.plbo_sweep(ctx, m, mps, o, po)
+        first = st["energy"] if first is None else first
+    assert first > 1e-3
+    assert st["energy"] < 1e-7, st["energy"]
+    p = P.plbo_params(ctx, m)
+    # the squeeze magnitude reaches the instance's (phi picks the orientation)
+    assert np.abs(np.abs(p[:, 2]) - r).max() < 1e-3
+    marg = P.marginals(ctx, mps, m)
+    for s in range(N):
+        want = gbs.single_mode_probabilities(abs(p[s, 2]), D)
+        assert np.abs(marg[s] - want / want.sum()).max() < 1e-6, s
+        assert np.abs(marg[s][1::2]).max() < 1e-9
+
+
+def test_plbo_sweeps_beat_the_fock_basis_of_the_same_size(ctx):
+    """Haar GBS instance: pLBO sweeps reach a lower <H> than Fock-basis DMRG
+    with the same d and chi (the gate parameters only add freedom), and the
+    reported energy is the oracle's <H> of the exported MPS with operators
+    rebuilt from the returned parameters."""
+    import paper_2410_18740_amd as P
+    N, d, chi = 6, 3, 9
+    r, U = W.make_problem(N, 12, (0.4, 0.6))
+    rng = np.random.default_rng(5)
+    o = P.SweepOpts()
+    o.chi_max, o.tol = chi, 1e-11
+
+    def fresh():
+        return P.MPS(ctx, [rng.normal(size=t.shape) + 1j * rng.normal(size=t.shape)
+                           for t in _rand_mps(N, d, chi, rng)])
+
+    mf = P.MPO(ctx, r, U, 12, d)
+    sf = fresh()
+    for _ in range(6):
+        ef = P.dmrg_sweep(ctx, mf, sf, o)["energy"]
+    mp = P.MPO(ctx, r, U, 12, d)
+    P.plbo_enable(ctx, mp)
+    sp = fresh()
+    po = P.PlboOpts(steps=15, lr=0.03, matvecs=8)
+    gains = []
+    for _ in range(8):
+        st = P.plbo_sweep(ctx, mp, sp, o, po)
+        gains.append(st["plbo_gain"])
+    ep = st["energy"]
+    print(f"Fock basis <H> = {ef:.6e}, pLBO <H> = {ep:.6e}, gains {gains}")
+    assert ep < 0.8 * ef, (ep, ef)
+    assert sum(gains) > 0
+    params = P.plbo_params(ctx, mp)
+    *_, Ws = _oracle_cores(r, U, 0.0, params, d)
+    assert abs(odmrg.energy(sp.export(), Ws) - ep) < 1e-9 * max(1.0, abs(ep))
+
+
+def test_plbo_state_errors(ctx):
+    import paper_2410_18740_amd as P
+    r, U = W.make_problem(3, 1, (0.3, 0.5))
+    m = P.MPO(ctx, r, U, 6, 3)
+    mps = P.MPS(ctx, _rand_mps(3, 3, 3, np.random.default_rng(0)))
+    o = P.SweepOpts()
+    with pytest.raises(P.TnError):
+        P.plbo_params(ctx, m)
+    with pytest.raises(P.TnError):
+        P.plbo_sweep(ctx, m, mps, o, P.PlboOpts())
+    P.plbo_enable(ctx, m)
+    o.lbo = 1
+    with pytest.raises(P.TnError):
+        P.plbo_sweep(ctx, m, mps, o, P.PlboOpts())
+    o.lbo = 0
+    with pytest.raises(P.TnError):
+        P.plbo_sweep(ctx, m, mps, o, P.PlboOpts(lr=0.0))
+    bad = np.zeros((3, 8))
+    bad[1, 2] = np.inf
+    with pytest.raises(P.TnError):
+        P.plbo_enable(ctx, m, bad)

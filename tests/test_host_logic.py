@@ -112,3 +112,68 @@ def test_cutoff_report_rejects_bad_arguments():
             P.cutoff_report(r, U, **kw)
     with pytest.raises(P.TnError):
         P.cutoff_report(np.array([0.3, np.nan]), U, 2)
+
+
+# ------------------------------------------------------------------ gate-parameterised basis (host part)
+def _plbo_params(rng):
+    return rng.uniform(-1, 1, 8) * [0.4, 0.4, 0.5, 3, 3, 0.3, 0.1, 0.1]
+
+
+@pytest.mark.parametrize("d", [1, 4, 9])
+def test_plbo_operators_match_oracle(d):
+    """The library's closed form at d + 4 levels (eq. SymplecticBasisTransformation)
+    against the oracle's product of gate exponentials in 200 levels."""
+    import paper_2410_18740_amd as P
+    from oracle import plbo
+    rng = np.random.default_rng(10 + d)
+    for _ in range(2):
+        p = _plbo_params(rng)
+        got = P.plbo_ops(d, p, 1.1, 0.8, 0.3)
+        ref = plbo.transformed_ops(p, d, 1.1, 0.8, 0.3)
+        for k in range(5):
+            assert np.abs(got[k] - ref[k]).max() < 1e-11, (d, k)
+
+
+def test_plbo_parameter_derivatives_match_oracle_differences():
+    """Forward-mode derivatives of the operators, contracted with a random slot
+    environment, against the oracle's five-point differences of the energy."""
+    import paper_2410_18740_amd as P
+    from oracle import plbo
+    d, a, b, g = 6, 1.3, 0.7, 0.2
+    rng = np.random.default_rng(21)
+    p = _plbo_params(rng)
+    G = rng.normal(size=(6, d, d)) + 1j * rng.normal(size=(6, d, d))
+    _, dops = P.plbo_ops(d, p, a, b, g, derivatives=True)
+    got = np.array([sum(np.real(np.sum(G[k + 1] * dops[j, k])) for k in range(5)) for j in range(8)])
+    ref = plbo.param_gradient(G, p, d, a, b, g, L=160)
+    assert np.abs(got - ref).max() < 1e-7 * max(1.0, np.abs(ref).max())
+
+
+def test_plbo_fock_isometry_matches_oracle():
+    """<n|U|m>, n < D: the library's banded Taylor exponentials against the
+    oracle's dense expm; the columns are orthonormal when D holds the basis."""
+    import paper_2410_18740_amd as P
+    from oracle import plbo
+    rng = np.random.default_rng(5)
+    for d, D in ((1, 10), (5, 24)):
+        p = _plbo_params(rng)
+        W = P.plbo_fock_isometry(D, d, p)
+        assert np.abs(W - plbo.fock_isometry(p, D, d)).max() < 1e-11
+    W = P.plbo_fock_isometry(60, 5, p)
+    assert np.abs(W.conj().T @ W - np.eye(5)).max() < 1e-9
+
+
+def test_plbo_host_entry_points_reject_bad_arguments():
+    import paper_2410_18740_amd as P
+    with pytest.raises(P.TnError):
+        P.plbo_ops(0, np.zeros(8), 1, 1, 0)
+    with pytest.raises(P.TnError):
+        P.plbo_ops(65, np.zeros(8), 1, 1, 0)
+    bad = np.zeros(8)
+    bad[3] = np.nan
+    with pytest.raises(P.TnError):
+        P.plbo_ops(4, bad, 1, 1, 0)
+    with pytest.raises(P.TnError):
+        P.plbo_fock_isometry(3, 4, np.zeros(8))
+    with pytest.raises(P.TnError):
+        P.plbo_fock_isometry(8, 4, np.zeros(8), levels=4)
