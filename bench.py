@@ -47,6 +47,19 @@ def parse():
                     help="with --to-target: E* = the plain FP64 form's energy after --max-sweeps sweeps (or sweep "
                          "change < 1e-12); report each form's time to E* + 1e-8 and to E* (1 + 1e-4), (1 + 1e-2)")
     ap.add_argument("--max-sweeps", type=int, default=12)
+    ap.add_argument("--plbo", action="store_true",
+                    help="gate-parameterised basis: Fock DMRG at small chi, pLBO sweeps, DMRG at the workload's chi; "
+                         "against the same schedule without the pLBO stage")
+    ap.add_argument("--plbo-chi", type=int, default=0, help="bond dimension of the first two stages (0: 2 d)")
+    ap.add_argument("--plbo-sweeps", type=int, default=6)
+    ap.add_argument("--plbo-steps", type=int, default=10)
+    ap.add_argument("--plbo-lr", type=float, default=0.02)
+    ap.add_argument("--plbo-matvecs", type=int, default=8)
+    ap.add_argument("--final-sweeps", type=int, default=4)
+    ap.add_argument("--plbo-init", default="analytic", choices=["analytic", "zero"],
+                    help="starting parameters of the pLBO run: the Gaussian optimal (Williamson) squeezing of each "
+                         "mode's reduced covariance, or the Fock basis")
+    ap.add_argument("--plbo-mask", type=lambda x: int(x, 0), default=0xFF)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB copy before the timed sweeps (PMC counter scaling)")
     ap.add_argument("--cutoff-report", action="store_true",
@@ -485,6 +498,77 @@ def to_target_relative(a):
     ctx.close()
 
 
+def plbo_bench(a):
+    """The three-stage procedure recommended for pLBO (Sec. V, optimisation
+    strategies): DMRG at chi = O(d), pLBO sweeps (Sec. III.B) at that chi,
+    then DMRG at the workload's chi in the learned bases.  References: the
+    same schedule without the pLBO stage in the Fock basis of the same size
+    d, and in the Gaussian optimal squeezed basis (r = |zeta|, phi = arg zeta
+    of each mode's Williamson decomposition, Sec. III.A.1), which is also the
+    pLBO start with --plbo-init analytic.  All run in the --form arithmetic
+    with no linear LBO; <H> is the FP64 value after each sweep."""
+    import torch
+    import paper_2410_18740_amd as P
+    import workloads as W
+    w = W.WORKLOADS[a.workload]
+    r, U = W.workload_problem(a.workload)
+    prec = FORMS[a.form]
+    tol = a.tol if a.tol is not None else (1e-8 if prec == 0 else 1e-6)
+    chi_s = a.plbo_chi or 2 * w.d
+    ctx = P.Context(0)
+    small = P.SweepOpts(chi_max=chi_s, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec)
+    big = P.SweepOpts(chi_max=w.chi, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec)
+    po = P.PlboOpts(steps=a.plbo_steps, lr=a.plbo_lr, matvecs=a.plbo_matvecs, mask=a.plbo_mask)
+    zeta = P.ws_gaussian_params(r, U).astype(np.float64)
+    ana = np.zeros((w.N, 8))
+    ana[:, 2] = np.hypot(zeta[:, 0], zeta[:, 1])
+    ana[:, 3] = np.arctan2(zeta[:, 1], zeta[:, 0])
+    runs = {}
+    for name, init in (("fock", None), ("analytic", ana), ("plbo", ana if a.plbo_init == "analytic" else None)):
+        mpo = P.MPO(ctx, r, U, w.D_raw, w.d, kappa=a.kappa)
+        P.plbo_enable(ctx, mpo, init)
+        mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
+        trace, stages = [], {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            trace.append(("dmrg_small", P.dmrg_sweep(ctx, mpo, mps, small)))
+        stages["dmrg_small"] = time.perf_counter() - t0
+        if name == "plbo":
+            t1 = time.perf_counter()
+            for _ in range(a.plbo_sweeps):
+                trace.append(("plbo", P.plbo_sweep(ctx, mpo, mps, small, po)))
+            stages["plbo"] = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        for _ in range(a.final_sweeps):
+            trace.append(("dmrg_big", P.dmrg_sweep(ctx, mpo, mps, big)))
+        torch.cuda.synchronize()
+        stages["dmrg_big"] = time.perf_counter() - t2
+        stages["total"] = time.perf_counter() - t0
+        res = {"energy": trace[-1][1]["energy"], "energy_trace": [t[1]["energy"] for t in trace],
+               "stage_seconds": stages}
+        pl = [t[1] for t in trace if t[0] == "plbo"]
+        if pl:
+            res["plbo_sweep_seconds"] = [s["t_total"] for s in pl]
+            res["plbo_visit_seconds"] = [s["t_lbo"] for s in pl]
+            res["plbo_gain"] = [s["plbo_gain"] for s in pl]
+            p = P.plbo_params(ctx, mpo)
+            res["params_abs_max"] = dict(zip(("alpha_x", "alpha_p", "r", "phi", "theta", "s", "gamma", "kappa"),
+                                             np.abs(p).max(axis=0).round(4).tolist()))
+        runs[name] = res
+        print(f"{name}: <H> = {res['energy']:.6e} stages {', '.join(f'{k} {v:.2f}s' for k, v in stages.items())}",
+              file=sys.stderr, flush=True)
+        del mps, mpo
+    line = {"mode": "plbo", "workload": a.workload, "kappa": a.kappa, "form": a.form, "d": w.d, "chi_small": chi_s,
+            "chi": w.chi, "plbo_sweeps": a.plbo_sweeps, "plbo_steps": a.plbo_steps, "plbo_lr": a.plbo_lr,
+            "plbo_matvecs": a.plbo_matvecs, "plbo_mask": a.plbo_mask, "plbo_init": a.plbo_init,
+            "final_sweeps": a.final_sweeps, "runs": runs,
+            "energy_ratio_plbo_over_fock": runs["plbo"]["energy"] / runs["fock"]["energy"],
+            "energy_ratio_plbo_over_analytic": runs["plbo"]["energy"] / runs["analytic"]["energy"]}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def cutoff_summary(r, U, d: int, D_raw: int, tol: float = 1e-12):
     """eps, its eps_D bounds and the effective cutoffs of the Gaussian optimal
     basis with d kept states per mode (library host code)."""
@@ -519,6 +603,12 @@ def main():
             warmstart_mesh(a)
         else:
             warmstart_eval(a)
+        return
+    if a.plbo:
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        plbo_bench(a)
         return
     if a.to_target:
         if a.gpus != 1:

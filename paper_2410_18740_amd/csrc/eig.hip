@@ -27,8 +27,10 @@ template <int JT>
 __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain, int64_t strideA, int n,
                                                       double* __restrict__ evals, cf64* __restrict__ Vout,
                                                       int64_t strideV, int descending) {
-  __shared__ cf64 A[JAC_N][JAC_N];
-  __shared__ cf64 V[JAC_N][JAC_N];
+  // one padding column: the column updates walk down a column, and rows one
+  // element apart in stride fall on different LDS banks
+  __shared__ cf64 A[JAC_N][JAC_N + 1];
+  __shared__ cf64 V[JAC_N][JAC_N + 1];
   __shared__ double rot[JAC_N / 2][4];  // cs, sn, cos(phi), sin(phi)
   __shared__ int pr[JAC_N / 2][2];
   __shared__ double red[2][JT / 64];
@@ -57,6 +59,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain
   }
   __syncthreads();
   const int npairs = n2 / 2;
+  double off_prev = INFINITY;  // thread 0 only
   for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
     for (int r = 0; r < n2 - 1; ++r) {
       if (tid < npairs) {
@@ -138,7 +141,10 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain
         o += red[0][w];
         d += red[1][w];
       }
-      done = (o <= 1e-31 * d) || (o < 1e-300);
+      // converged, or at the rounding floor: the off-diagonal mass has stopped
+      // falling quadratically although it is already at the 1e-12 level
+      done = (o <= 1e-31 * d) || (o < 1e-300) || (o <= 1e-24 * d && o > 0.25 * off_prev);
+      off_prev = o;
     }
     __syncthreads();
     if (done) break;

@@ -214,6 +214,7 @@ def _spectrum_matrix(m, n, rng, decay=0.7, rank=None):
 
 @pytest.mark.parametrize("m,n,chi,decay,rank", [
     (30, 30, 16, 0.6, None),     # Jacobi path
+    (32, 24, 20, 0.8, 10),       # Jacobi path, numerically null cluster (stops at the rounding floor)
     (36, 36, 16, 0.6, None),     # tridiagonal path, small
     (8, 512, 8, 0.5, None),      # edge window, Jacobi path
     (100, 90, 40, 0.9, None),    # tridiagonal path, ragged

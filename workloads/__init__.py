@@ -114,6 +114,11 @@ WORKLOADS = {
     # where <H> <= 1e-8 is reachable at chi 128.
     "mesh_n32_d16to8_chi128": Workload("mesh_n32_d16to8_chi128", 32, 16, 8, 128, 2, (0.1, 0.2),
                                        kind="brickwork", mps_seed=1002, sweeps=4, tol=1e-10),
+    # Basis-limited case for the gate-parameterised basis: a 4-layer mesh keeps
+    # the entanglement low enough for chi 32, while r ~ U[0.6, 0.9] puts a few
+    # per cent of each mode's weight beyond the first 4 Fock states.
+    "mesh_n32_d4_chi32": Workload("mesh_n32_d4_chi32", 32, 16, 4, 32, 3, (0.6, 0.9),
+                                  kind="brickwork", mps_seed=1003, sweeps=4, tol=1e-10),
     # 48 modes, raw cutoff 24 compressed to 10, chi 256.
     "gbs_n48_d24to10_chi256": Workload("gbs_n48_d24to10_chi256", 48, 24, 10, 256, 4, (1.0, 1.5),
                                        mps_seed=1004, sweeps=4, tol=1e-10),
