@@ -15,15 +15,22 @@
 
 static __device__ __forceinline__ double wave_sum_d(double v) { return wave_reduce_sum(v); }
 
-// round-robin pairing (circle method) over n2 (even) indices
+// round-robin pairing (circle method) over n2 (even) indices; r, k < n2 - 1
 static __device__ __forceinline__ void rr_pair(int r, int k, int n2, int& p, int& q) {
   const int m = n2 - 1;
-  if (k == 0) { p = r % m; q = m; }
-  else { p = (r + k) % m; q = (r - k + m) % m; }
+  if (k == 0) { p = r; q = m; }
+  else {
+    p = r + k;
+    if (p >= m) p -= m;
+    q = r - k;
+    if (q < 0) q += m;
+  }
   if (p > q) { int t = p; p = q; q = t; }
 }
 
-template <int JT>
+// RS: power-of-two row span >= n2 of the update loops, so that the (pair,
+// row) index of a work item comes from a shift and a mask
+template <int JT, int RS>
 __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain, int64_t strideA, int n,
                                                       double* __restrict__ evals, cf64* __restrict__ Vout,
                                                       int64_t strideV, int descending) {
@@ -84,8 +91,9 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain
       }
       __syncthreads();
       // column update: A <- A J, V <- V J with J = [[cs, sn], [-sn e^{-i phi}, cs e^{-i phi}]]
-      for (int e = tid; e < npairs * n2; e += JT) {
-        const int k = e / n2, row = e % n2;
+      for (int e = tid; e < npairs * RS; e += JT) {
+        const int k = e / RS, row = e & (RS - 1);
+        if (row >= n2) continue;
         const double cs = rot[k][0], sn = rot[k][1];
         if (sn == 0.0) continue;
         const int p = pr[k][0], q = pr[k][1];
@@ -101,8 +109,9 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain
       }
       __syncthreads();
       // row update: A <- J^H A, J^H = [[cs, -sn e^{i phi}], [sn, cs e^{i phi}]]
-      for (int e = tid; e < npairs * n2; e += JT) {
-        const int k = e / n2, col = e % n2;
+      for (int e = tid; e < npairs * RS; e += JT) {
+        const int k = e / RS, col = e & (RS - 1);
+        if (col >= n2) continue;
         const double cs = rot[k][0], sn = rot[k][1];
         if (sn == 0.0) continue;
         const int p = pr[k][0], q = pr[k][1];
@@ -168,7 +177,12 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain
 hipError_t launch_jacobi(const cf64* A, int64_t strideA, int n, int batch, double* evals, cf64* V, int64_t strideV,
                          int descending, hipStream_t st) {
   if (n < 1 || n > JAC_N || batch <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_kernel<256>, dim3(batch), dim3(256), 0, st, A, strideA, n, evals, V, strideV, descending);
+  if (n <= 32)
+    hipLaunchKernelGGL((jacobi_kernel<256, 32>), dim3(batch), dim3(256), 0, st, A, strideA, n, evals, V, strideV,
+                       descending);
+  else
+    hipLaunchKernelGGL((jacobi_kernel<256, 64>), dim3(batch), dim3(256), 0, st, A, strideA, n, evals, V, strideV,
+                       descending);
   return hipGetLastError();
 }
 
