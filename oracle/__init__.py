@@ -21,6 +21,8 @@ Modules
   flops      algorithmic FLOP accounting
   cutoff     Fock-cutoff error bounds and the effective cutoff
   cz         global-CZ (non-Gaussian) parent Hamiltonian and its MPO
+  noisy      noisy GBS: uniform-loss covariance, V = Q + C split, displacement
+             matrices, displaced sequential sampling
   plbo       gate-parameterised local basis: transformed operators by
              the definition, slot environments, gradients, Adam
 

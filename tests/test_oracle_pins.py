@@ -882,3 +882,134 @@ def test_plbo_product_of_squeezed_vacua_is_exact_with_one_basis_state():
     assert min(best) < 1e-10 and max(best) > 0.1
     ops0 = [plbo.transformed_ops(np.zeros(8), 1, al[s, s], be[s, s], ga[s, s]) for s in range(2)]
     assert np.real(mpo.to_dense(mpo.cores(al, be, ga, [o[:3] for o in ops0]))[0, 0]) > 0.1
+
+
+# ------------------------------------------------------------------ noisy GBS (Sec. II.F)
+def test_noisy_decomposition_is_pure_plus_classical():
+    """eq. CovarianceDecomposition for uniform loss: Q = covariance(r', U) is
+    pure (all symplectic eigenvalues 1/2), C = V_eta - Q is positive
+    semidefinite with rank N, C = L L^T, and eta = 1 gives Q = V, C = 0."""
+    from oracle import noisy
+    r, U = W.make_problem(5, 3, (0.4, 1.1))
+    for eta in (1.0, 0.9, 0.5):
+        rp, C, L = noisy.decompose_uniform_loss(r, U, eta)
+        Q = gbs.covariance(rp, U)
+        V = noisy.lossy_covariance(r, U, eta)
+        assert np.abs(Q + C - V).max() < 1e-12
+        assert np.abs(noisy.symplectic_eigenvalues(Q) - 0.5).max() < 1e-10
+        ev = np.linalg.eigvalsh(C)
+        assert ev.min() > -1e-12
+        assert np.abs(L @ L.T - C).max() < 1e-12
+        if eta == 1.0:
+            assert np.abs(rp - r).max() < 1e-14 and np.abs(C).max() < 1e-14
+        else:
+            assert (rp < r).all() and (rp > 0).all()
+            assert np.sum(ev > 1e-12) == 5
+    # the symplectic eigenvalues of the lossy V exceed 1/2 (it is mixed)
+    assert noisy.symplectic_eigenvalues(noisy.lossy_covariance(r, U, 0.7)).max() > 0.55
+
+
+def test_noisy_pure_part_has_the_smallest_trace_per_mode():
+    """Per input mode, every pure Q_i = 1/2 diag(q, 1/q) below V_i (V_i - Q_i
+    >= 0) has a trace no smaller than the closed-form choice (scan over q)."""
+    from oracle import noisy
+    for r, eta in ((0.8, 0.6), (0.3, 0.9), (1.2, 0.3)):
+        rp, C, _ = noisy.decompose_uniform_loss(np.array([r]), np.eye(1, dtype=complex), eta)
+        vx, vp = eta * math.exp(-2 * r) + 1 - eta, eta * math.exp(2 * r) + 1 - eta
+        q0 = math.exp(-2 * rp[0])
+        assert q0 <= vx + 1e-14 and 1 / q0 <= vp + 1e-14           # feasible
+        qs = np.linspace(1e-3, 10, 200001)
+        feas = (qs <= vx) & (1 / qs <= vp)
+        best = np.min(qs[feas] + 1 / qs[feas])
+        assert best >= q0 + 1 / q0 - 1e-12 and best - (q0 + 1 / q0) < 1e-3
+
+
+def test_displacement_matrix_closed_forms():
+    """<n|D(alpha)|0> is the coherent state e^{-|a|^2/2} a^n/sqrt(n!);
+    D(a) D(b) = e^{(a b^* - a^* b)/2} D(a + b) and D(a) D(-a) = I on the kept
+    levels (expm in 160 levels, |alpha| <= 0.8, 12 kept)."""
+    from oracle import noisy
+    a, b = 0.5 - 0.3j, -0.2 + 0.6j
+    Dm = noisy.displacement_matrix(a, 12)
+    coh = np.array([np.exp(-abs(a) ** 2 / 2) * a ** n / math.sqrt(math.factorial(n)) for n in range(12)])
+    assert np.abs(Dm[:, 0] - coh).max() < 1e-13
+    big = 40
+    Da, Db = noisy.displacement_matrix(a, big), noisy.displacement_matrix(b, big)
+    Dab = noisy.displacement_matrix(a + b, big)
+    ph = np.exp(0.5 * (a * np.conj(b) - np.conj(a) * b))
+    assert np.abs((Da @ Db)[:12, :12] - ph * Dab[:12, :12]).max() < 1e-12
+    assert np.abs((Da @ noisy.displacement_matrix(-a, big))[:12, :12] - np.eye(12)).max() < 1e-12
+
+
+def test_gaussian_photon_distribution_closed_forms():
+    """Squeezed vacuum: the closed form of gbs; thermal: geometric; a rotated
+    squeezed thermal state has the photon numbers of the unrotated one."""
+    from oracle import noisy
+    r = 0.7
+    P = noisy.gaussian_photon_distribution(0.5 * np.diag([math.exp(-2 * r), math.exp(2 * r)]), 20)
+    assert np.abs(P - gbs.single_mode_probabilities(r, 20)).max() < 1e-13
+    nb = 0.8
+    P = noisy.gaussian_photon_distribution((nb + 0.5) * np.eye(2), 20)
+    q = nb / (nb + 1)
+    assert np.abs(P - (1 - q) * q ** np.arange(20)).max() < 1e-13
+    V = np.diag([0.4, 1.9])
+    c, s = math.cos(0.7), math.sin(0.7)
+    R = np.array([[c, -s], [s, c]])
+    assert np.abs(noisy.gaussian_photon_distribution(R @ V @ R.T, 20)
+                  - noisy.gaussian_photon_distribution(V, 20)).max() < 1e-12
+
+
+def test_displaced_pure_part_averages_to_the_lossy_state():
+    """One lossy squeezed mode: averaging the photon distribution of
+    D(alpha)|psi_Q> over alpha ~ N(0, C) (Gauss-Hermite, 80 nodes along the
+    noisy quadrature) gives the photon distribution of V_eta = Q + C."""
+    from oracle import noisy
+    r, eta = np.array([0.9]), 0.6
+    U = np.eye(1, dtype=complex)
+    rp, C, L = noisy.decompose_uniform_loss(r, U, eta)
+    Lb = 120
+    psi = np.zeros(Lb, dtype=complex)
+    psi[:] = 0.0
+    x, wts = np.polynomial.hermite_e.hermegauss(80)        # weight exp(-x^2/2)
+    wts = wts / wts.sum()
+    # pure squeezed vacuum of Q in the x-squeezed convention: S(r') with the
+    # oracle's squeezing sign is checked through its covariance below
+    a = np.zeros((Lb, Lb), dtype=complex)
+    for n in range(1, Lb):
+        a[n - 1, n] = math.sqrt(n)
+    import scipy.linalg as sla
+    vac = np.zeros(Lb, dtype=complex)
+    vac[0] = 1.0
+    psi = sla.expm(0.5 * rp[0] * (a @ a - a.conj().T @ a.conj().T)) @ vac
+    X = (a + a.conj().T) / math.sqrt(2)
+    P_ = -1j * (a - a.conj().T) / math.sqrt(2)
+    Q = gbs.covariance(rp, U)
+    assert abs(np.real(psi.conj() @ (X @ X)[:, :] @ psi) - Q[0, 0]) < 1e-10
+    assert abs(np.real(psi.conj() @ (P_ @ P_) @ psi) - Q[1, 1]) < 1e-10
+    mix = np.zeros(30)
+    for xi, wi in zip(x, wts):
+        alpha = noisy.alphas(np.array([[xi]]), L)[0, 0]
+        phi = noisy.displacement_matrix(alpha, Lb, L=Lb + 80) @ psi
+        mix += wi * np.abs(phi[:30]) ** 2
+    want = noisy.gaussian_photon_distribution(noisy.lossy_covariance(r, U, eta), 30)
+    assert np.abs(mix - want).max() < 1e-10
+
+
+def test_displaced_sampler_reduces_to_the_plain_sampler():
+    """alpha = 0 leaves the sequential sampler unchanged (same Philox stream);
+    for one mode its empirical distribution is |<n|D(alpha)|psi>|^2."""
+    from oracle import noisy, sampler
+    rng = np.random.default_rng(6)
+    t = [rng.normal(size=(1, 5, 3)) + 1j * rng.normal(size=(1, 5, 3)),
+         rng.normal(size=(3, 5, 2)) + 1j * rng.normal(size=(3, 5, 2)),
+         rng.normal(size=(2, 5, 1)) + 1j * rng.normal(size=(2, 5, 1))]
+    t = M.right_canonicalize(t)
+    a = np.zeros((40, 3), dtype=complex)
+    assert np.array_equal(noisy.sample_displaced(t, a, 17, L=40), sampler.sample(t, 40, 17))
+    psi = np.array([0.8, 0.0, 0.6, 0.0], dtype=complex)
+    al = 0.3 + 0.2j
+    smp = noisy.sample_displaced([psi.reshape(1, 4, 1)], np.full((3000, 1), al), 5, L=60)[:, 0]
+    p = np.abs(noisy.displacement_matrix(al, 4, 60) @ psi) ** 2
+    p /= p.sum()
+    hist = np.bincount(smp, minlength=4) / 3000.0
+    assert np.abs(hist - p).max() < 4 * math.sqrt(0.25 / 3000)
