@@ -314,6 +314,31 @@ tn_status tn_marginals(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int32_
 tn_status tn_sample(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
                     int32_t* out);
 
+/* ------------------------------------------------------------------ noisy GBS
+ * Sec. II.F, eq. CovarianceDecomposition: a mixed covariance V = Q + C, Q pure,
+ * C >= 0 the covariance of zero-mean random displacements; a noisy sample is a
+ * photon-number sample of D(alpha)|psi_Q> with alpha ~ N(0, C).
+ *
+ * tn_noise_uniform_loss (host only): for uniform loss eta in (0, 1] after the
+ * squeezers r (N) of the interferometer U (host complex [N][N], interleaved),
+ * V_eta = eta V + (1 - eta) I/2.  The pure part keeps each input mode's
+ * squeezed variance: r_pure[i] = -ln(eta e^{-2 r_i} + 1 - eta)/2, so the MPO
+ * of the pure state is built from (r_pure, U).  L (host [2N][N], quadrature
+ * order x_1..x_N, p_1..p_N) factors C = L L^T.  TN_EINVAL on N outside
+ * [1, 4096], eta outside (0, 1], negative or non-finite r, non-finite U or NULL
+ * pointers.
+ *
+ * tn_sample_displaced: as tn_sample for the state D(alpha_b)|psi>, with
+ * alpha_b,j = (d_x + i d_p)/sqrt2, d = L z_b.  z: device doubles
+ * [n_samples][N], standard normal draws supplied by the caller (the random
+ * numbers of the noise); L: host [2N][N].  The displacement acts on the D_raw
+ * kept Fock levels of each mode (weight it moves beyond them is dropped and
+ * the conditional probabilities renormalised).  Uniform draws and the
+ * inverse-CDF rule are tn_sample's.  Same centre requirement as tn_sample. */
+tn_status tn_noise_uniform_loss(int32_t N, const double* r, const double* U, double eta, double* r_pure, double* L);
+tn_status tn_sample_displaced(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
+                              const double* z, const double* L, int32_t* out);
+
 /* Single-site reduced density matrices rho_j[n][n'] = <n|rho_j|n'> (eq.
  * ReducedDensityMatrix) in the raw Fock basis, FP64, for j < n_modes.  out:
  * host [n_modes][D_raw][D_raw] complex.  Same centre requirement as

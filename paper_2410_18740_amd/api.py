@@ -367,6 +367,44 @@ def sample(ctx: Context, mps: MPS, mpo: MPO, n_samples: int, seed: int):
     return out
 
 
+def noise_uniform_loss(r, U, eta: float):
+    """(r_pure [N], L [2N][N]): the pure part and the displacement factor
+    C = L L^T of uniform loss eta (eq. CovarianceDecomposition)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    Uf = np.ascontiguousarray(U, dtype=np.complex128).view(np.float64)
+    N = len(r)
+    rp = np.zeros(N)
+    Lc = np.zeros((2 * N, N))
+    st = L.lib().tn_noise_uniform_loss(N, L.dptr(r), L.dptr(Uf), eta, L.dptr(rp), L.dptr(Lc))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_noise_uniform_loss: bad arguments")
+    return rp, Lc
+
+
+def sample_displaced(ctx: Context, mps: MPS, mpo: MPO, n_samples: int, seed: int, Lc, z=None):
+    """Noisy-GBS samples: photon numbers of D(alpha_b)|psi> with alpha_b from
+    d = Lc z_b.  z: (n_samples, N) standard normals (device or host); when None
+    they are drawn on the device from a torch generator seeded with `seed`."""
+    torch = _torch()
+    dev = f"cuda:{ctx.device}"
+    if z is None:
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(seed))
+        z = torch.randn((n_samples, mps.N), dtype=torch.float64, device=dev, generator=g)
+    else:
+        z = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64) if not hasattr(z, "device") else z,
+                            dtype=torch.float64).to(dev).contiguous()
+    if tuple(z.shape) != (n_samples, mps.N):
+        raise ValueError("z must have shape (n_samples, N)")
+    Lh = np.ascontiguousarray(Lc, dtype=np.float64)
+    if Lh.shape != (2 * mps.N, mps.N):
+        raise ValueError("Lc must have shape (2N, N)")
+    out = torch.empty((n_samples, mps.N), dtype=torch.int32, device=dev)
+    ctx.check(L.lib().tn_sample_displaced(ctx.h, mps.h, mpo.h, n_samples, C.c_uint64(seed),
+                                          C.c_void_p(z.data_ptr()), L.dptr(Lh), C.c_void_p(out.data_ptr())))
+    return out
+
+
 def _dev(x):
     torch = _torch()
     assert x.is_cuda and x.dtype == torch.complex128 and x.is_contiguous()

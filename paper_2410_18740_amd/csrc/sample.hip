@@ -233,6 +233,162 @@ extern "C" tn_status tn_sample(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, in
   TN_GUARD_END(c)
 }
 
+// ------------------------------------------------------------------ noisy GBS (Sec. II.F)
+// Uniform loss eta after the squeezers: per input mode the lossy variances are
+// (eta e^{-2r} + 1 - eta)/2 (x, squeezed) and (eta e^{2r} + 1 - eta)/2 (p).
+// The pure part keeps the squeezed variance, e^{-2r'} = eta e^{-2r} + 1 - eta,
+// and the classical part C = L L^T puts the remainder c_i on p of input
+// mode i, rotated by the interferometer: L[:, i] = sqrt(c_i) O[:, N + i] with
+// O = [[Re U, -Im U], [Im U, Re U]] (eq. CovarianceDecomposition).
+extern "C" tn_status tn_noise_uniform_loss(int32_t N, const double* r, const double* U, double eta, double* r_pure,
+                                           double* L) {
+  if (N < 1 || N > 4096 || !r || !U || !r_pure || !L) return TN_EINVAL;
+  if (!(eta > 0.0 && eta <= 1.0)) return TN_EINVAL;
+  for (int i = 0; i < N; ++i)
+    if (!std::isfinite(r[i]) || r[i] < 0.0) return TN_EINVAL;
+  for (int64_t i = 0; i < 2ll * N * N; ++i)
+    if (!std::isfinite(U[i])) return TN_EINVAL;
+  std::vector<double> c(N);
+  for (int i = 0; i < N; ++i) {
+    const double vx = eta * std::exp(-2.0 * r[i]) + 1.0 - eta;
+    const double vp = eta * std::exp(2.0 * r[i]) + 1.0 - eta;
+    r_pure[i] = -0.5 * std::log(vx);
+    c[i] = std::max(0.0, 0.5 * (vp - 1.0 / vx));
+  }
+  for (int j = 0; j < N; ++j)
+    for (int i = 0; i < N; ++i) {
+      const double ur = U[2 * ((size_t)j * N + i)], ui = U[2 * ((size_t)j * N + i) + 1];
+      const double sc = std::sqrt(c[i]);
+      L[(size_t)j * N + i] = -ui * sc;
+      L[(size_t)(N + j) * N + i] = ur * sc;
+    }
+  return TN_OK;
+}
+
+// alpha[b][j] = (d_x + i d_p) / sqrt2 with d = L z_b (L: 2N x N, z: B x N)
+__global__ void noise_alpha_kernel(const double* __restrict__ z, const double* __restrict__ L, int64_t B, int N,
+                                   cf64* __restrict__ alpha) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * N) return;
+  const int64_t b = e / N;
+  const int j = (int)(e % N);
+  double dx = 0.0, dp = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double zi = z[b * N + i];
+    dx += L[(int64_t)j * N + i] * zi;
+    dp += L[(int64_t)(N + j) * N + i] * zi;
+  }
+  const double s = 0.70710678118654752440;
+  alpha[e] = make_double2(dx * s, dp * s);
+}
+
+// T2[b][n][j] = sum_k <n|D(alpha_b)|k> T[b][k][j] over the D kept levels: one
+// wavefront per sample.  The matrix is built in LDS row by row from
+//   <0|D|k> = e^{-|alpha|^2/2} (-alpha^*)^k / sqrt(k!),
+//   <n+1|D|k> = (sqrt(k) <n|D|k-1> + alpha <n|D|k>) / sqrt(n+1)
+// (from a D(alpha) = D(alpha) (a + alpha)), lane k holding column k.
+__global__ __launch_bounds__(64) void displace_rows_kernel(const cf64* __restrict__ T, const cf64* __restrict__ alpha,
+                                                           int64_t astride, int B, int D, int cr,
+                                                           cf64* __restrict__ T2) {
+  extern __shared__ unsigned char smraw[];
+  cf64* Dm = reinterpret_cast<cf64*>(smraw);  // D x D
+  const int b = blockIdx.x, lane = threadIdx.x;
+  if (b >= B) return;
+  const cf64 al = alpha[(int64_t)b * astride];
+  if (lane < D) {
+    // (-alpha^*)^k / sqrt(k!) e^{-|alpha|^2/2}
+    const double g = exp(-0.5 * (al.x * al.x + al.y * al.y));
+    double vr = g, vi = 0.0;
+    for (int q = 1; q <= lane; ++q) {
+      const double sq = 1.0 / sqrt((double)q);
+      const double nr = (-al.x * vr - al.y * vi) * sq;  // (-alpha^*) * v: (-ax + i ay)(vr + i vi)
+      const double ni = (-al.x * vi + al.y * vr) * sq;
+      vr = nr;
+      vi = ni;
+    }
+    Dm[lane] = make_double2(vr, vi);
+  }
+  __syncthreads();
+  for (int n = 0; n + 1 < D; ++n) {
+    cf64 v = make_double2(0.0, 0.0);
+    if (lane < D) {
+      const cf64 cur = Dm[n * D + lane];
+      const cf64 left = lane > 0 ? Dm[n * D + lane - 1] : make_double2(0.0, 0.0);
+      const double sk = sqrt((double)lane), inv = 1.0 / sqrt((double)(n + 1));
+      v.x = (sk * left.x + al.x * cur.x - al.y * cur.y) * inv;
+      v.y = (sk * left.y + al.x * cur.y + al.y * cur.x) * inv;
+    }
+    __syncthreads();
+    if (lane < D) Dm[(n + 1) * D + lane] = v;
+    __syncthreads();
+  }
+  const cf64* Tb = T + (int64_t)b * D * cr;
+  cf64* T2b = T2 + (int64_t)b * D * cr;
+  for (int j = lane; j < cr; j += 64) {
+    for (int n = 0; n < D; ++n) {
+      double sr = 0.0, si = 0.0;
+      for (int k = 0; k < D; ++k) {
+        const cf64 m = Dm[n * D + k], t = Tb[(int64_t)k * cr + j];
+        sr += m.x * t.x - m.y * t.y;
+        si += m.x * t.y + m.y * t.x;
+      }
+      T2b[(int64_t)n * cr + j] = make_double2(sr, si);
+    }
+  }
+}
+
+extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int64_t n_samples,
+                                         uint64_t seed, const double* z, const double* L, int32_t* out) {
+  if (!c) return TN_EINVAL;
+  TN_GUARD_BEGIN
+  check_obs(m, mpo);
+  if (!out || !z || !L || n_samples < 1) TN_THROW(TN_EINVAL, "bad output, noise or sample count");
+  const int N = m->N, D = mpo->D_raw;
+  for (int64_t i = 0; i < 2ll * N * N; ++i)
+    if (!std::isfinite(L[i])) TN_THROW(TN_EINVAL, "non-finite noise factor");
+  hipStream_t st = c->stream;
+  int chimax = 1;
+  for (int t = 0; t <= N; ++t) chimax = std::max(chimax, m->dims[t]);
+  const int64_t chunk = std::min<int64_t>(n_samples, std::max<int64_t>(64, (int64_t)(1ll << 31) / ((int64_t)D * chimax * 16)));
+  cf64* Tmp = wsT<cf64>(c, "smp:T", (size_t)chunk * D * chimax);
+  cf64* T2 = wsT<cf64>(c, "smp:T2", (size_t)chunk * D * chimax);
+  cf64* Va = wsT<cf64>(c, "smp:Va", (size_t)chunk * chimax);
+  cf64* Vb = wsT<cf64>(c, "smp:Vb", (size_t)chunk * chimax);
+  cf64* al = wsT<cf64>(c, "smp:al", (size_t)chunk * N);
+  double* dL = wsT<double>(c, "smp:L", 2 * (size_t)N * N);
+  upload(c, dL, L, 2 * (size_t)N * N * sizeof(double));
+  std::vector<cf64*> F(N);
+  for (int s = 0; s < N; ++s) {
+    const size_t nel = (size_t)m->dims[s] * D * m->dims[s + 1];
+    cf64* tmpF = fock_tensor(c, m, mpo, s);
+    F[s] = wsT<cf64>(c, "smp:F" + std::to_string(s), nel);
+    HIPCHK(hipMemcpyAsync(F[s], tmpF, nel * sizeof(cf64), hipMemcpyDeviceToDevice, st));
+  }
+  for (int64_t s0 = 0; s0 < n_samples; s0 += chunk) {
+    const int B = (int)std::min<int64_t>(chunk, n_samples - s0);
+    const int64_t ne = (int64_t)B * N;
+    hipLaunchKernelGGL(noise_alpha_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, z + s0 * N, dL,
+                       (int64_t)B, N, al);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(fill_one_kernel, dim3(std::max(1, (B + 255) / 256)), dim3(256), 0, st, Va, (int64_t)B);
+    for (int s = 0; s < N; ++s) {
+      const int cl = m->dims[s], cr = m->dims[s + 1];
+      std::vector<GemmJob> jobs{{Tmp, (int64_t)D * cr, B, D * cr, 0, 1}};
+      std::vector<GemmSeg> segs{{Va, F[s], cl, (int64_t)D * cr, cl, 0}};
+      gemm_jobs(c, 0, 0, jobs, segs, B, D * cr, "smp:g");
+      hipLaunchKernelGGL(displace_rows_kernel, dim3(B), dim3(64), (size_t)D * D * sizeof(cf64), st, Tmp, al + s,
+                         (int64_t)N, B, D, cr, T2);
+      HIPCHK(hipGetLastError());
+      hipLaunchKernelGGL(sample_step_kernel, dim3((B + 3) / 4), dim3(256), 0, st, T2, B, D, cr, (uint64_t)s0, s, seed,
+                         Vb, out + (size_t)s0 * N, N);
+      HIPCHK(hipGetLastError());
+      std::swap(Va, Vb);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  TN_GUARD_END(c)
+}
+
 // Philox known-answer entry point (device generator check): n counters/keys on host.
 extern "C" tn_status tn_philox4x32_10(tn_ctx* c, const uint32_t* ctr, const uint32_t* key, uint32_t* out, int32_t n) {
   if (!c) return TN_EINVAL;

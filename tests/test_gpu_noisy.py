@@ -1,0 +1,97 @@
+"""GPU parity of noisy-GBS sampling (Sec. II.F, eq. CovarianceDecomposition):
+the pure part of a lossy instance is solved by DMRG, and photon-number samples
+of D(alpha)|psi> with alpha from the classical part follow the oracle's
+displaced sampler stream; their single-mode histograms and mean photon numbers
+match the lossy Gaussian state."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import noisy, gbs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2410_18740_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _pure_state(ctx, r, U, D, chi, sweeps=6):
+    import paper_2410_18740_amd as P
+    m = P.MPO(ctx, r, U, D)
+    N = len(r)
+    mp = P.MPS(ctx, W.random_mps(N, D, chi, 1234))
+    for _ in range(sweeps):
+        st = P.dmrg_sweep(ctx, m, mp, P.SweepOpts(chi_max=chi, tol=1e-12))
+    return m, mp, st["energy"]
+
+
+def test_displaced_samples_follow_the_oracle_stream(ctx):
+    """Same z, same factor L and seed: the library's patterns equal the
+    oracle's displaced sampler (displacement matrices by expm there, by the
+    row recurrence in LDS here) on all but rounding ties."""
+    import paper_2410_18740_amd as P
+    r, U = W.make_problem(4, 0, (0.5, 0.5))
+    eta = 0.7
+    rp, Lc = P.noise_uniform_loss(r, U, eta)
+    rp_o, C, Lo = noisy.decompose_uniform_loss(r, U, eta)
+    assert np.abs(rp - rp_o).max() < 1e-14 and np.abs(Lc @ Lc.T - C).max() < 1e-14
+    m, mp, E = _pure_state(ctx, rp, U, 6, 36)
+    assert E < 1e-3
+    z = np.random.default_rng(9).standard_normal((300, 4))
+    smp = P.sample_displaced(ctx, mp, m, 300, 77, Lc, z=z).cpu().numpy()
+    ref = noisy.sample_displaced(mp.export(), noisy.alphas(z, Lo), 77, L=60)
+    mism = np.mean(np.any(smp != ref, axis=1))
+    assert mism < 0.01, mism
+    # no displacement: the plain sampler's stream
+    plain = P.sample(ctx, mp, m, 300, 77).cpu().numpy()
+    zero = P.sample_displaced(ctx, mp, m, 300, 77, np.zeros((8, 4)), z=z).cpu().numpy()
+    assert np.array_equal(plain, zero)
+
+
+def test_noisy_marginals_match_the_lossy_gaussian_state(ctx):
+    """400k noisy samples of a 4-mode instance with eta = 0.6: every mode's
+    photon-number histogram matches the photon distribution of the 2 x 2 block
+    of V_eta = eta V + (1 - eta) I/2 (5 sigma plus the cutoff's weight), and
+    so do the mean photon numbers (V_jj + V_{N+j,N+j} - 1)/2."""
+    import paper_2410_18740_amd as P
+    r, U = W.make_problem(4, 5, (0.4, 0.6))
+    eta, D, n = 0.6, 10, 400000
+    rp, Lc = P.noise_uniform_loss(r, U, eta)
+    m, mp, E = _pure_state(ctx, rp, U, D, 64)
+    assert E < 1e-6
+    smp = P.sample_displaced(ctx, mp, m, n, 4242, Lc).cpu().numpy()
+    V = noisy.lossy_covariance(r, U, eta)
+    N = 4
+    for j in range(N):
+        V2 = V[np.ix_([j, N + j], [j, N + j])]
+        want = noisy.gaussian_photon_distribution(V2, D)
+        tail = 1.0 - want.sum()
+        hist = np.bincount(smp[:, j], minlength=D)[:D] / n
+        sig = np.sqrt(want * (1 - want) / n)
+        assert np.all(np.abs(hist - want) <= 5 * sig + 2 * tail + 1e-6), (j, hist, want)
+        mean = 0.5 * (V[j, j] + V[N + j, N + j] - 1.0)
+        assert abs(smp[:, j].mean() - mean) < 5 * math.sqrt(want @ (np.arange(D) ** 2) / n) + D * tail + 1e-4
+
+
+def test_noise_entry_points_reject_bad_arguments(ctx):
+    import paper_2410_18740_amd as P
+    r, U = W.make_problem(3, 0, (0.5, 0.5))
+    for eta in (0.0, 1.5, float("nan")):
+        with pytest.raises(P.TnError):
+            P.noise_uniform_loss(r, U, eta)
+    with pytest.raises(P.TnError):
+        P.noise_uniform_loss(np.array([0.3, -0.1, 0.2]), U, 0.5)
+    m, mp, _ = _pure_state(ctx, r, U, 4, 8, sweeps=1)
+    bad = np.zeros((6, 3))
+    bad[0, 0] = np.inf
+    with pytest.raises(P.TnError):
+        P.sample_displaced(ctx, mp, m, 10, 1, bad)
+    with pytest.raises(ValueError):
+        P.sample_displaced(ctx, mp, m, 10, 1, np.zeros((5, 3)))

@@ -177,3 +177,19 @@ def test_plbo_host_entry_points_reject_bad_arguments():
         P.plbo_fock_isometry(3, 4, np.zeros(8))
     with pytest.raises(P.TnError):
         P.plbo_fock_isometry(8, 4, np.zeros(8), levels=4)
+
+
+def test_noise_decomposition_matches_oracle():
+    """Uniform-loss split V_eta = Q + C: the library's pure squeezing and
+    factor L against the oracle (C = L L^T, Q = covariance(r', U))."""
+    import paper_2410_18740_amd as P
+    import workloads as W
+    from oracle import noisy
+    for N, seed, eta in ((3, 1, 0.8), (8, 2, 0.4), (12, 3, 1.0)):
+        r, U = W.make_problem(N, seed, (0.3, 1.2))
+        rp, Lc = P.noise_uniform_loss(r, U, eta)
+        rp_o, C, _ = noisy.decompose_uniform_loss(r, U, eta)
+        assert np.abs(rp - rp_o).max() < 1e-14
+        assert np.abs(Lc @ Lc.T - C).max() < 1e-13
+    with pytest.raises(P.TnError):
+        P.noise_uniform_loss(r, U, 0.0)
