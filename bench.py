@@ -60,6 +60,9 @@ def parse():
                     help="starting parameters of the pLBO run: the Gaussian optimal (Williamson) squeezing of each "
                          "mode's reduced covariance, or the Fock basis")
     ap.add_argument("--plbo-mask", type=lambda x: int(x, 0), default=0xFF)
+    ap.add_argument("--noisy", type=float, default=None, metavar="ETA",
+                    help="noisy GBS with uniform loss ETA: DMRG on the pure part, then plain and displaced sampling")
+    ap.add_argument("--noisy-samples", type=int, default=8192)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB copy before the timed sweeps (PMC counter scaling)")
     ap.add_argument("--cutoff-report", action="store_true",
@@ -569,6 +572,81 @@ def plbo_bench(a):
     ctx.close()
 
 
+def _photon_stats(V):
+    """(sum_j <n_j>, sqrt(sum_j Var n_j)) of a zero-mean Gaussian state from
+    its 2 x 2 output-mode blocks: <n> = (tr V_j - 1)/2, Var n = tr(V_j^2)/2 - 1/4."""
+    N = V.shape[0] // 2
+    mean = var = 0.0
+    for j in range(N):
+        B = V[np.ix_([j, N + j], [j, N + j])]
+        mean += 0.5 * (np.trace(B) - 1.0)
+        var += 0.5 * np.trace(B @ B) - 0.25
+    return float(mean), float(np.sqrt(var))
+
+
+def _cov(r, U):
+    O = np.block([[U.real, -U.imag], [U.imag, U.real]])
+    d2 = np.concatenate([np.exp(-2 * np.asarray(r)), np.exp(2 * np.asarray(r))])
+    return 0.5 * (O * d2[None, :]) @ O.T
+
+
+def noisy_bench(a):
+    """Noisy GBS (Sec. II.F): uniform loss eta on the workload's instance,
+    split into a pure part (DMRG, FP32 + LBO sweeps as in the default bench)
+    and classical displacements; times plain and displaced sampling of the
+    same MPS and reports the photon statistics of the pure parts (closed form
+    kept here, Williamson for comparison) and of the lossy state, as the
+    paper's table of photon-number expectations does for Borealis."""
+    import torch
+    import paper_2410_18740_amd as P
+    import workloads as W
+    w = W.WORKLOADS[a.workload]
+    r, U = W.workload_problem(a.workload)
+    eta = a.noisy
+    rp, Lc = P.noise_uniform_loss(r, U, eta)
+    vx, vp = eta * np.exp(-2 * r) + 1 - eta, eta * np.exp(2 * r) + 1 - eta
+    r_w = 0.25 * np.log(vp / vx)                  # Williamson pure part of each input mode
+    V = _cov(r, U)
+    Ve = eta * V + (1 - eta) * 0.5 * np.eye(2 * w.N)
+    table = {"pure_williamson": _photon_stats(_cov(r_w, U)), "pure_kept": _photon_stats(_cov(rp, U)),
+             "lossy": _photon_stats(Ve), "ideal_eta1": _photon_stats(V)}
+    ctx = P.Context(0)
+    mpo = P.MPO(ctx, rp, U, w.D_raw, w.d)
+    mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
+    opts = P.SweepOpts(chi_max=w.chi, tol=1e-6, krylov_max=24, max_matvecs=a.max_matvecs, precision=FORMS[a.form],
+                       lbo=0 if a.no_lbo else 1, compute_energy=1)
+    t0 = time.perf_counter()
+    for i in range(max(1, a.steps)):
+        s = P.dmrg_sweep(ctx, mpo, mps, opts)
+        print(f"pure-part sweep {i}: <H> = {s['energy']:.6e}", file=sys.stderr, flush=True)
+    t_dmrg = time.perf_counter() - t0
+    n = a.noisy_samples
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    z = torch.randn((n, w.N), dtype=torch.float64, device="cuda:0", generator=g)
+    P.sample(ctx, mps, mpo, 256, 1)
+    P.sample_displaced(ctx, mps, mpo, 256, 1, Lc, z=z[:256])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plain = P.sample(ctx, mps, mpo, n, 7)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    noisy = P.sample_displaced(ctx, mps, mpo, n, 7, Lc, z=z)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    tot_p = plain.sum(dim=1).double().cpu().numpy()
+    tot_n = noisy.sum(dim=1).double().cpu().numpy()
+    line = {"mode": "noisy", "workload": a.workload, "eta": eta, "form": a.form, "N": w.N, "D_raw": w.D_raw,
+            "d": w.d, "chi": w.chi, "r_pure_mean": float(np.mean(rp)), "r_mean": float(np.mean(r)),
+            "photon_expectation_sum_pm_sd": {k: [round(v[0], 4), round(v[1], 4)] for k, v in table.items()},
+            "pure_part": {"energy": s["energy"], "sweeps": max(1, a.steps), "seconds": t_dmrg},
+            "samples": n, "plain_samples_per_s": n / (t2 - t1), "displaced_samples_per_s": n / (t3 - t2),
+            "sampled_total_photons": {"pure_part": [float(tot_p.mean()), float(tot_p.std())],
+                                      "noisy": [float(tot_n.mean()), float(tot_n.std())]}}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def cutoff_summary(r, U, d: int, D_raw: int, tol: float = 1e-12):
     """eps, its eps_D bounds and the effective cutoffs of the Gaussian optimal
     basis with d kept states per mode (library host code)."""
@@ -603,6 +681,12 @@ def main():
             warmstart_mesh(a)
         else:
             warmstart_eval(a)
+        return
+    if a.noisy is not None:
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        noisy_bench(a)
         return
     if a.plbo:
         if a.gpus != 1:

@@ -324,6 +324,27 @@ __global__ __launch_bounds__(64) void displace_rows_kernel(const cf64* __restric
   }
   const cf64* Tb = T + (int64_t)b * D * cr;
   cf64* T2b = T2 + (int64_t)b * D * cr;
+  if (D <= 16) {
+    // column j of T held in registers, read once; Dm entries are LDS broadcasts
+    for (int j = lane; j < cr; j += 64) {
+      cf64 t[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) t[k] = k < D ? Tb[(int64_t)k * cr + j] : make_double2(0.0, 0.0);
+      for (int n = 0; n < D; ++n) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          if (k < D) {
+            const cf64 m = Dm[n * D + k];
+            sr += m.x * t[k].x - m.y * t[k].y;
+            si += m.x * t[k].y + m.y * t[k].x;
+          }
+        }
+        T2b[(int64_t)n * cr + j] = make_double2(sr, si);
+      }
+    }
+    return;
+  }
   for (int j = lane; j < cr; j += 64) {
     for (int n = 0; n < D; ++n) {
       double sr = 0.0, si = 0.0;

@@ -32,26 +32,28 @@ def _pure_state(ctx, r, U, D, chi, sweeps=6):
     return m, mp, st["energy"]
 
 
-def test_displaced_samples_follow_the_oracle_stream(ctx):
+@pytest.mark.parametrize("N,D,chi", [(4, 6, 36), (3, 18, 24)])
+def test_displaced_samples_follow_the_oracle_stream(ctx, N, D, chi):
     """Same z, same factor L and seed: the library's patterns equal the
     oracle's displaced sampler (displacement matrices by expm there, by the
-    row recurrence in LDS here) on all but rounding ties."""
+    row recurrence in LDS here) on all but rounding ties; D = 6 takes the
+    register path of the displacement kernel, D = 18 the general one."""
     import paper_2410_18740_amd as P
-    r, U = W.make_problem(4, 0, (0.5, 0.5))
+    r, U = W.make_problem(N, 0, (0.5, 0.5))
     eta = 0.7
     rp, Lc = P.noise_uniform_loss(r, U, eta)
     rp_o, C, Lo = noisy.decompose_uniform_loss(r, U, eta)
     assert np.abs(rp - rp_o).max() < 1e-14 and np.abs(Lc @ Lc.T - C).max() < 1e-14
-    m, mp, E = _pure_state(ctx, rp, U, 6, 36)
+    m, mp, E = _pure_state(ctx, rp, U, D, chi)
     assert E < 1e-3
-    z = np.random.default_rng(9).standard_normal((300, 4))
+    z = np.random.default_rng(9).standard_normal((300, N))
     smp = P.sample_displaced(ctx, mp, m, 300, 77, Lc, z=z).cpu().numpy()
-    ref = noisy.sample_displaced(mp.export(), noisy.alphas(z, Lo), 77, L=60)
+    ref = noisy.sample_displaced(mp.export(), noisy.alphas(z, Lo), 77, L=D + 60)
     mism = np.mean(np.any(smp != ref, axis=1))
     assert mism < 0.01, mism
     # no displacement: the plain sampler's stream
     plain = P.sample(ctx, mp, m, 300, 77).cpu().numpy()
-    zero = P.sample_displaced(ctx, mp, m, 300, 77, np.zeros((8, 4)), z=z).cpu().numpy()
+    zero = P.sample_displaced(ctx, mp, m, 300, 77, np.zeros((2 * N, N)), z=z).cpu().numpy()
     assert np.array_equal(plain, zero)
 
 
