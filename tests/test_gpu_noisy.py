@@ -57,6 +57,29 @@ def test_displaced_samples_follow_the_oracle_stream(ctx, N, D, chi):
     assert np.array_equal(plain, zero)
 
 
+def test_displaced_samples_through_an_lbo_basis(ctx):
+    """d < D_raw: after LBO sweeps the Fock tensors are W_s A_s, and the
+    displaced stream equals the oracle's run on those tensors."""
+    import paper_2410_18740_amd as P
+    from oracle import mps as omps
+    N, D, d, chi = 4, 10, 5, 25
+    r, U = W.make_problem(N, 8, (0.5, 0.7))
+    rp, Lc = P.noise_uniform_loss(r, U, 0.6)
+    _, _, Lo = noisy.decompose_uniform_loss(r, U, 0.6)
+    m = P.MPO(ctx, rp, U, D, d)
+    mp = P.MPS(ctx, W.random_mps(N, d, chi, 99))
+    o = P.SweepOpts()
+    o.chi_max, o.tol, o.lbo = chi, 1e-12, 1
+    for _ in range(4):
+        P.dmrg_sweep(ctx, m, mp, o)
+    z = np.random.default_rng(3).standard_normal((300, N))
+    smp = P.sample_displaced(ctx, mp, m, 300, 5, Lc, z=z).cpu().numpy()
+    F = omps.fock_tensors(mp.export(), list(m.isometries()))
+    ref = noisy.sample_displaced(F, noisy.alphas(z, Lo), 5, L=D + 60)
+    mism = np.mean(np.any(smp != ref, axis=1))
+    assert mism < 0.01, mism
+
+
 def test_noisy_marginals_match_the_lossy_gaussian_state(ctx):
     """400k noisy samples of a 4-mode instance with eta = 0.6: every mode's
     photon-number histogram matches the photon distribution of the 2 x 2 block
