@@ -596,6 +596,8 @@ extern "C" tn_status tn_mpo_isometries(const tn_mpo* mpo, double* iso) {
     plbo_sync_iso(mpo);
   } catch (const TnError& e) {
     return e.code;
+  } catch (const std::exception&) {
+    return TN_ENOMEM;
   }
   size_t o = 0;
   for (int s = 0; s < mpo->N; ++s)
