@@ -29,8 +29,9 @@ static __device__ __forceinline__ void rr_pair(int r, int k, int n2, int& p, int
 }
 
 // RS: power-of-two row span >= n2 of the update loops, so that the (pair,
-// row) index of a work item comes from a shift and a mask
-template <int JT, int RS>
+// row) index of a work item comes from a shift and a mask; IPT work items
+// per thread cover (RS / 2) pairs x RS rows
+template <int JT, int RS, int IPT = (RS / 2) * RS / JT>
 __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain, int64_t strideA, int n,
                                                       double* __restrict__ evals, cf64* __restrict__ Vout,
                                                       int64_t strideV, int descending) {
@@ -38,8 +39,6 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain
   // element apart in stride fall on different LDS banks
   __shared__ cf64 A[JAC_N][JAC_N + 1];
   __shared__ cf64 V[JAC_N][JAC_N + 1];
-  __shared__ double rot[JAC_N / 2][4];  // cs, sn, cos(phi), sin(phi)
-  __shared__ int pr[JAC_N / 2][2];
   __shared__ double red[2][JT / 64];
   __shared__ int done;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -69,67 +68,70 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(const cf64* __restrict__ Ain
   double off_prev = INFINITY;  // thread 0 only
   for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
     for (int r = 0; r < n2 - 1; ++r) {
-      if (tid < npairs) {
-        int p, q;
-        rr_pair(r, tid, n2, p, q);
-        pr[tid][0] = p; pr[tid][1] = q;
-        double cs = 1.0, sn = 0.0, cph = 1.0, sph = 0.0;
-        if (q < n) {
-          const double app = A[p][p].x, aqq = A[q][q].x;
-          const cf64 apq = A[p][q];
-          const double b = sqrt(cabs2(apq));
-          if (b > 1e-300 && b * b > 1e-34 * (app * app + aqq * aqq)) {
-            const double zeta = (aqq - app) / (2.0 * b);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            cs = 1.0 / sqrt(1.0 + t * t);
-            sn = t * cs;
-            cph = apq.x / b;
-            sph = apq.y / b;
+      // every work item (pair k, row or column index) computes its pair's
+      // rotation from the pivots into registers, so the rotation parameters
+      // make no LDS round trip; one barrier separates the pivot reads from
+      // the column update
+      int pp[IPT], qq[IPT], ix[IPT];
+      double cs[IPT], sn[IPT], cph[IPT], sph[IPT];
+#pragma unroll
+      for (int t = 0; t < IPT; ++t) {
+        const int e = tid + JT * t;
+        const int k = e / RS;
+        ix[t] = e & (RS - 1);
+        cs[t] = 1.0; sn[t] = 0.0; cph[t] = 1.0; sph[t] = 0.0;
+        pp[t] = 0; qq[t] = 0;
+        if (k < npairs && ix[t] < n2) {
+          int p, q;
+          rr_pair(r, k, n2, p, q);
+          pp[t] = p; qq[t] = q;
+          if (q < n) {
+            const double app = A[p][p].x, aqq = A[q][q].x;
+            const cf64 apq = A[p][q];
+            const double b = sqrt(cabs2(apq));
+            if (b > 1e-300 && b * b > 1e-34 * (app * app + aqq * aqq)) {
+              const double zeta = (aqq - app) / (2.0 * b);
+              const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+              cs[t] = 1.0 / sqrt(1.0 + tt * tt);
+              sn[t] = tt * cs[t];
+              cph[t] = apq.x / b;
+              sph[t] = apq.y / b;
+            }
           }
         }
-        rot[tid][0] = cs; rot[tid][1] = sn; rot[tid][2] = cph; rot[tid][3] = sph;
       }
       __syncthreads();
       // column update: A <- A J, V <- V J with J = [[cs, sn], [-sn e^{-i phi}, cs e^{-i phi}]]
-      for (int e = tid; e < npairs * RS; e += JT) {
-        const int k = e / RS, row = e & (RS - 1);
-        if (row >= n2) continue;
-        const double cs = rot[k][0], sn = rot[k][1];
-        if (sn == 0.0) continue;
-        const int p = pr[k][0], q = pr[k][1];
-        const cf64 em = make_double2(rot[k][2], -rot[k][3]);  // e^{-i phi}
+#pragma unroll
+      for (int t = 0; t < IPT; ++t) {
+        if (sn[t] == 0.0) continue;
+        const int p = pp[t], q = qq[t], row = ix[t];
+        const cf64 em = make_double2(cph[t], -sph[t]);  // e^{-i phi}
         cf64 xp = A[row][p], xq = A[row][q];
         cf64 xqe = cmul(xq, em);
-        A[row][p] = make_double2(cs * xp.x - sn * xqe.x, cs * xp.y - sn * xqe.y);
-        A[row][q] = make_double2(sn * xp.x + cs * xqe.x, sn * xp.y + cs * xqe.y);
+        A[row][p] = make_double2(cs[t] * xp.x - sn[t] * xqe.x, cs[t] * xp.y - sn[t] * xqe.y);
+        A[row][q] = make_double2(sn[t] * xp.x + cs[t] * xqe.x, sn[t] * xp.y + cs[t] * xqe.y);
         xp = V[row][p]; xq = V[row][q];
         xqe = cmul(xq, em);
-        V[row][p] = make_double2(cs * xp.x - sn * xqe.x, cs * xp.y - sn * xqe.y);
-        V[row][q] = make_double2(sn * xp.x + cs * xqe.x, sn * xp.y + cs * xqe.y);
+        V[row][p] = make_double2(cs[t] * xp.x - sn[t] * xqe.x, cs[t] * xp.y - sn[t] * xqe.y);
+        V[row][q] = make_double2(sn[t] * xp.x + cs[t] * xqe.x, sn[t] * xp.y + cs[t] * xqe.y);
       }
       __syncthreads();
-      // row update: A <- J^H A, J^H = [[cs, -sn e^{i phi}], [sn, cs e^{i phi}]]
-      for (int e = tid; e < npairs * RS; e += JT) {
-        const int k = e / RS, col = e & (RS - 1);
-        if (col >= n2) continue;
-        const double cs = rot[k][0], sn = rot[k][1];
-        if (sn == 0.0) continue;
-        const int p = pr[k][0], q = pr[k][1];
-        const cf64 ep = make_double2(rot[k][2], rot[k][3]);  // e^{i phi}
+      // row update: A <- J^H A, J^H = [[cs, -sn e^{i phi}], [sn, cs e^{i phi}]]; the
+      // rotated pair's off-diagonal entries are set to zero and its diagonal made real
+#pragma unroll
+      for (int t = 0; t < IPT; ++t) {
+        if (sn[t] == 0.0) continue;
+        const int p = pp[t], q = qq[t], col = ix[t];
+        const cf64 ep = make_double2(cph[t], sph[t]);  // e^{i phi}
         const cf64 xp = A[p][col], xq = A[q][col];
         const cf64 xqe = cmul(xq, ep);
-        A[p][col] = make_double2(cs * xp.x - sn * xqe.x, cs * xp.y - sn * xqe.y);
-        A[q][col] = make_double2(sn * xp.x + cs * xqe.x, sn * xp.y + cs * xqe.y);
-      }
-      __syncthreads();
-      if (tid < npairs) {
-        const int p = pr[tid][0], q = pr[tid][1];
-        if (rot[tid][1] != 0.0 && q < n) {
-          A[p][q] = czero<cf64>();
-          A[q][p] = czero<cf64>();
-          A[p][p].y = 0.0;
-          A[q][q].y = 0.0;
-        }
+        cf64 np_ = make_double2(cs[t] * xp.x - sn[t] * xqe.x, cs[t] * xp.y - sn[t] * xqe.y);
+        cf64 nq_ = make_double2(sn[t] * xp.x + cs[t] * xqe.x, sn[t] * xp.y + cs[t] * xqe.y);
+        if (col == p) { np_.y = 0.0; nq_ = czero<cf64>(); }
+        if (col == q) { np_ = czero<cf64>(); nq_.y = 0.0; }
+        A[p][col] = np_;
+        A[q][col] = nq_;
       }
       __syncthreads();
     }
@@ -178,10 +180,10 @@ hipError_t launch_jacobi(const cf64* A, int64_t strideA, int n, int batch, doubl
                          int descending, hipStream_t st) {
   if (n < 1 || n > JAC_N || batch <= 0) return hipErrorInvalidValue;
   if (n <= 32)
-    hipLaunchKernelGGL((jacobi_kernel<256, 32>), dim3(batch), dim3(256), 0, st, A, strideA, n, evals, V, strideV,
+    hipLaunchKernelGGL((jacobi_kernel<512, 32>), dim3(batch), dim3(512), 0, st, A, strideA, n, evals, V, strideV,
                        descending);
   else
-    hipLaunchKernelGGL((jacobi_kernel<256, 64>), dim3(batch), dim3(256), 0, st, A, strideA, n, evals, V, strideV,
+    hipLaunchKernelGGL((jacobi_kernel<512, 64>), dim3(batch), dim3(512), 0, st, A, strideA, n, evals, V, strideV,
                        descending);
   return hipGetLastError();
 }
