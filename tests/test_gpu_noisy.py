@@ -120,3 +120,26 @@ def test_noise_entry_points_reject_bad_arguments(ctx):
         P.sample_displaced(ctx, mp, m, 10, 1, bad)
     with pytest.raises(ValueError):
         P.sample_displaced(ctx, mp, m, 10, 1, np.zeros((5, 3)))
+
+
+def test_displaced_stream_at_the_benchmark_size(ctx):
+    """The benchmark configuration of the noisy mode (32 modes, D_raw 16 -> d 8,
+    chi 128, eta = 0.5, FP32 + LBO sweeps of the pure part): 24 displaced
+    samples against the oracle's displaced sampler run on the exported Fock
+    tensors W_s A_s with the same z, factor and seed."""
+    import paper_2410_18740_amd as P
+    from oracle import mps as omps
+    w = W.WORKLOADS["gbs_n32_d16to8_chi128"]
+    r, U = W.workload_problem("gbs_n32_d16to8_chi128")
+    rp, Lc = P.noise_uniform_loss(r, U, 0.5)
+    _, _, Lo = noisy.decompose_uniform_loss(r, U, 0.5)
+    m = P.MPO(ctx, rp, U, w.D_raw, w.d)
+    mp = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
+    o = P.SweepOpts(chi_max=w.chi, tol=1e-6, krylov_max=24, max_matvecs=16, precision=P.FP32, lbo=1)
+    for _ in range(2):
+        P.dmrg_sweep(ctx, m, mp, o)
+    z = np.random.default_rng(31).standard_normal((24, w.N))
+    smp = P.sample_displaced(ctx, mp, m, 24, 8, Lc, z=z).cpu().numpy()
+    F = omps.fock_tensors(mp.export(), list(m.isometries()))
+    ref = noisy.sample_displaced(F, noisy.alphas(z, Lo), 8, L=w.D_raw + 60)
+    assert np.sum(np.any(smp != ref, axis=1)) <= 1

@@ -219,3 +219,28 @@ def test_plbo_state_errors(ctx):
     bad[1, 2] = np.inf
     with pytest.raises(P.TnError):
         P.plbo_enable(ctx, m, bad)
+
+
+def test_plbo_slot_environments_at_the_benchmark_size(ctx):
+    """The configuration of the pLBO stage of the benchmark (32-mode mesh,
+    d = 4, chi = 8, FP32): slot environments at the first, a middle and the
+    last site against the oracle's, with random parameters on every site."""
+    import paper_2410_18740_amd as P
+    w = W.WORKLOADS["mesh_n32_d4_chi32"]
+    r, U = W.workload_problem("mesh_n32_d4_chi32")
+    N, d, chi = w.N, w.d, 8
+    rng = np.random.default_rng(64)
+    params = _params(N, rng, 0.3)
+    al, be, ga, ops, Ws = _oracle_cores(r, U, 0.0, params, d)
+    tensors = [t / np.linalg.norm(t) for t in _rand_mps(N, d, chi, rng)]
+    m = P.MPO(ctx, r, U, w.D_raw, d)
+    P.plbo_enable(ctx, m, params)
+    mps = P.MPS(ctx, tensors)
+    Ls = odmrg.left_envs(tensors, Ws)
+    Rs = odmrg.right_envs(tensors, Ws)
+    for site in (0, 15, 31):
+        x2 = float(np.sum(np.abs(tensors[site]) ** 2))
+        Gf = plbo.core_environment(Ls[site], tensors[site], Rs[site + 1]) / x2
+        Gref = plbo.slot_gradients(Gf, plbo.slot_coefficients(plbo.gaussian_core_maker(al, be, ga, site), d))
+        G, E, _ = P.plbo_site_gradient(ctx, m, mps, site, P.FP32)
+        assert np.abs(G - Gref).max() < 2e-5 * np.abs(Gref).max(), site
