@@ -60,6 +60,7 @@ def parse():
                     help="starting parameters of the pLBO run: the Gaussian optimal (Williamson) squeezing of each "
                          "mode's reduced covariance, or the Fock basis")
     ap.add_argument("--plbo-mask", type=lambda x: int(x, 0), default=0xFF)
+    ap.add_argument("--plbo-optimizer", default="adam", choices=["adam", "lbfgs"])
     ap.add_argument("--noisy", type=float, default=None, metavar="ETA",
                     help="noisy GBS with uniform loss ETA: DMRG on the pure part, then plain and displaced sampling")
     ap.add_argument("--noisy-samples", type=int, default=8192)
@@ -521,7 +522,8 @@ def plbo_bench(a):
     ctx = P.Context(0)
     small = P.SweepOpts(chi_max=chi_s, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec)
     big = P.SweepOpts(chi_max=w.chi, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec)
-    po = P.PlboOpts(steps=a.plbo_steps, lr=a.plbo_lr, matvecs=a.plbo_matvecs, mask=a.plbo_mask)
+    po = P.PlboOpts(steps=a.plbo_steps, lr=a.plbo_lr, matvecs=a.plbo_matvecs, mask=a.plbo_mask,
+                    optimizer=P.PLBO_ADAM if a.plbo_optimizer == "adam" else P.PLBO_LBFGS)
     zeta = P.ws_gaussian_params(r, U).astype(np.float64)
     ana = np.zeros((w.N, 8))
     ana[:, 2] = np.hypot(zeta[:, 0], zeta[:, 1])
@@ -565,6 +567,7 @@ def plbo_bench(a):
     line = {"mode": "plbo", "workload": a.workload, "kappa": a.kappa, "form": a.form, "d": w.d, "chi_small": chi_s,
             "chi": w.chi, "plbo_sweeps": a.plbo_sweeps, "plbo_steps": a.plbo_steps, "plbo_lr": a.plbo_lr,
             "plbo_matvecs": a.plbo_matvecs, "plbo_mask": a.plbo_mask, "plbo_init": a.plbo_init,
+            "plbo_optimizer": a.plbo_optimizer,
             "final_sweeps": a.final_sweeps, "runs": runs,
             "energy_ratio_plbo_over_fock": runs["plbo"]["energy"] / runs["fock"]["energy"],
             "energy_ratio_plbo_over_analytic": runs["plbo"]["energy"] / runs["analytic"]["energy"]}

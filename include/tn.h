@@ -256,7 +256,13 @@ typedef struct {
   double beta1, beta2;/* Adam moment decays in [0, 1) */
   double eps;         /* Adam denominator guard > 0 */
   uint32_t mask;      /* bit j set: parameter j is optimised (0xFF: all eight) */
+  int32_t optimizer;  /* TN_PLBO_ADAM: `steps` Adam steps, moments kept per site;
+                         TN_PLBO_LBFGS: `steps` L-BFGS iterations (8 pairs, Armijo
+                         backtracking on the exact site energy, first step at most lr
+                         per parameter), started afresh at every visit */
 } tn_plbo_opts;
+#define TN_PLBO_ADAM 0
+#define TN_PLBO_LBFGS 1
 
 /* Host only, no GPU work.  ops: [5][d][d] complex (interleaved doubles) =
  * (X, P, S, X^2, XP + PX) in the basis of params (8 doubles), S =
@@ -270,6 +276,13 @@ tn_status tn_plbo_ops(int32_t d, const double* params, double a_ss, double b_ss,
  * series over sub-steps of unit norm), then cut to D rows.  TN_EINVAL on
  * d < 1, D < d, D > 4096, levels outside [D, 8192] or non-finite params. */
 tn_status tn_plbo_fock_isometry(int32_t D, int32_t d, const double* params, int32_t levels, double* iso);
+/* Host only, no GPU work.  Runs opts' optimiser on the energy of one site as a
+ * function of its parameters with the slot environments G (host [6][d][d]
+ * complex, as from tn_plbo_site_gradient) held fixed: params (8, in/out) from
+ * their input values, Adam moments from zero; energy receives the final site
+ * energy.  TN_EINVAL on bad sizes, options or non-finite params. */
+tn_status tn_plbo_minimize(int32_t d, const double* G, double a_ss, double b_ss, double g_ss, const tn_plbo_opts* opts,
+                           double* params, double* energy);
 /* Switch the MPO to gate-parameterised bases with the given parameters (NULL:
  * all zero, i.e. the Fock basis) and reset the Adam moments.  From then on the
  * site operators follow the parameters, linear LBO is refused (TN_ESTATE) and

@@ -69,11 +69,13 @@ def gate_unitary(p, L: int) -> np.ndarray:
     n = np.arange(L, dtype=np.float64)
     al = ax + 1j * ap
     z = r * np.exp(1j * phi)
-    Dg = sla.expm(al * ad - np.conj(al) * a)
-    Sg = sla.expm(0.5 * (np.conj(z) * (a @ a) - z * (ad @ ad)))
+    I = np.eye(L, dtype=np.complex128)
+    # a gate with a zero parameter is the identity (exp of the zero matrix)
+    Dg = sla.expm(al * ad - np.conj(al) * a) if al != 0 else I
+    Sg = sla.expm(0.5 * (np.conj(z) * (a @ a) - z * (ad @ ad))) if z != 0 else I
     Rg = np.diag(np.exp(1j * th * n))
-    P2 = sla.expm(1j * s * _poly_block(L, 2) / 4.0)
-    P3 = sla.expm(1j * g * _poly_block(L, 3) / 6.0)
+    P2 = sla.expm(1j * s * _poly_block(L, 2) / 4.0) if s != 0 else I
+    P3 = sla.expm(1j * g * _poly_block(L, 3) / 6.0) if g != 0 else I
     Kg = np.diag(np.exp(1j * k * n * n))
     return Dg @ Sg @ Rg @ P2 @ P3 @ Kg
 
@@ -166,7 +168,8 @@ def site_energy(G, ops) -> float:
     return float(sum(np.real(np.sum(G[k] * full[k])) for k in range(6)))
 
 
-def param_gradient(G, p, d: int, a_ss: float, b_ss: float, g_ss: float, L: int = 200, h: float = 2e-4):
+def param_gradient(G, p, d: int, a_ss: float, b_ss: float, g_ss: float, L: int = 200, h: float = 2e-4,
+                   which=range(NPARAM)):
     """dE/dp_j by the five-point central difference
     (-f(+2h) + 8 f(+h) - 8 f(-h) + f(-2h)) / (12 h), truncation error O(h^4).
     The Kerr parameter enters through phases exp(i kappa n^2), so its
@@ -175,7 +178,7 @@ def param_gradient(G, p, d: int, a_ss: float, b_ss: float, g_ss: float, L: int =
     p = np.asarray(p, dtype=np.float64)
     f = lambda q: site_energy(G, transformed_ops(q, d, a_ss, b_ss, g_ss, L))
     g = np.zeros(NPARAM)
-    for j in range(NPARAM):
+    for j in which:
         e = np.zeros(NPARAM)
         e[j] = h
         g[j] = (-f(p + 2 * e) + 8 * f(p + e) - 8 * f(p - e) + f(p - 2 * e)) / (12 * h)
@@ -197,3 +200,23 @@ def adam(p, grad_fn, steps: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, ma
         vh = v / (1 - beta2 ** t)
         p = p - np.where(mk, lr * mh / (np.sqrt(vh) + eps), 0.0)
     return p, (m, v, t)
+
+
+def minimize_site(G, p0, d: int, a_ss: float, b_ss: float, g_ss: float, mask, L: int = 200):
+    """Local minimum of the site energy over the masked parameters from p0 by
+    scipy's L-BFGS-B (the optimiser family the paper also reports), with the
+    five-point-difference gradient; returns (p, E)."""
+    import scipy.optimize as so
+    p0 = np.asarray(p0, dtype=np.float64)
+    mk = np.asarray(mask, bool)
+    free = np.flatnonzero(mk)
+
+    def full(x):
+        q = p0.copy()
+        q[free] = x
+        return q
+
+    f = lambda x: site_energy(G, transformed_ops(full(x), d, a_ss, b_ss, g_ss, L))
+    jac = lambda x: param_gradient(G, full(x), d, a_ss, b_ss, g_ss, L, which=free)[free]
+    res = so.minimize(f, p0[free], jac=jac, method="L-BFGS-B", options={"maxiter": 100, "ftol": 1e-15, "gtol": 1e-8})
+    return full(res.x), float(res.fun)

@@ -67,7 +67,7 @@ class tn_solve_opts(C.Structure):
 
 class tn_plbo_opts(C.Structure):
     _fields_ = [("steps", C.c_int32), ("matvecs", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
-                ("beta2", C.c_double), ("eps", C.c_double), ("mask", C.c_uint32)]
+                ("beta2", C.c_double), ("eps", C.c_double), ("mask", C.c_uint32), ("optimizer", C.c_int32)]
 
 
 class tn_solve_result(C.Structure):
@@ -144,6 +144,7 @@ def lib():
         "tn_plbo_ops": (i32, [i32, P(dbl), dbl, dbl, dbl, P(dbl), P(dbl)]),
         "tn_plbo_fock_isometry": (i32, [i32, i32, P(dbl), i32, P(dbl)]),
         "tn_plbo_enable": (i32, [vp, P(dbl)]),
+        "tn_plbo_minimize": (i32, [i32, P(dbl), dbl, dbl, dbl, P(tn_plbo_opts), P(dbl), P(dbl)]),
         "tn_plbo_params": (i32, [vp, P(dbl)]),
         "tn_plbo_site_gradient": (i32, [vp, vp, vp, i32, i32, P(dbl), P(dbl), P(dbl)]),
         "tn_plbo_sweep": (i32, [vp, vp, vp, P(tn_sweep_opts), P(tn_plbo_opts), P(tn_sweep_stats), P(dbl)]),

@@ -270,9 +270,13 @@ def lbo_step(ctx: Context, mpo: MPO, mps: MPS, site: int, opts: SweepOpts) -> fl
 PLBO_NPARAM = 8
 
 
+PLBO_ADAM, PLBO_LBFGS = 0, 1
+
+
 class PlboOpts:
     """Per-visit pLBO step: Lanczos matvecs on the centre tensor, then Adam
-    steps on the masked parameters (bit j of mask: parameter j)."""
+    steps or L-BFGS iterations on the masked parameters (bit j of mask:
+    parameter j)."""
     steps: int = 10
     matvecs: int = 0
     lr: float = 0.02
@@ -280,6 +284,7 @@ class PlboOpts:
     beta2: float = 0.999
     eps: float = 1e-8
     mask: int = 0xFF
+    optimizer: int = PLBO_ADAM
 
     def __init__(self, **kw):
         for k, v in kw.items():
@@ -288,7 +293,8 @@ class PlboOpts:
             setattr(self, k, v)
 
     def c(self):
-        return L.tn_plbo_opts(self.steps, self.matvecs, self.lr, self.beta1, self.beta2, self.eps, self.mask)
+        return L.tn_plbo_opts(self.steps, self.matvecs, self.lr, self.beta1, self.beta2, self.eps, self.mask,
+                              self.optimizer)
 
 
 def plbo_ops(d: int, params, a_ss: float, b_ss: float, g_ss: float, derivatives: bool = False):
@@ -313,6 +319,20 @@ def plbo_fock_isometry(D: int, d: int, params, levels: int | None = None):
     if st != L.TN_OK:
         raise TnError(st, "tn_plbo_fock_isometry: bad arguments")
     return W
+
+
+def plbo_minimize(G, params, a_ss: float, b_ss: float, g_ss: float, opts: PlboOpts):
+    """Host-side optimisation of one site's parameters with its slot
+    environments G ([6][d][d]) fixed: (params [8], final site energy)."""
+    G = np.ascontiguousarray(G, dtype=np.complex128)
+    d = G.shape[1]
+    p = np.array(params, dtype=np.float64)
+    e = C.c_double()
+    o = opts.c()
+    st = L.lib().tn_plbo_minimize(d, L.dptr(G.view(np.float64)), a_ss, b_ss, g_ss, C.byref(o), L.dptr(p), C.byref(e))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_plbo_minimize: bad arguments")
+    return p, e.value
 
 
 def plbo_enable(ctx: Context, mpo: MPO, params=None):

@@ -752,24 +752,9 @@ static void plbo_slot_envs(tn_ctx* c, const tn_mpo* mpo, tn_mps* m, int s, int p
       G[(size_t)meta[j].first * d * d + e] += meta[j].second * cd(h[j * d * d + e].x, h[j * d * d + e].y);
 }
 
-// E(p) = Re sum_k <G_k, O_k(p)> and its gradient in the parameters of site s
-static double plbo_energy_grad(const tn_mpo* mpo, int s, const std::vector<cd>& G, const double* p, double* grad) {
-  const int d = mpo->d, N = mpo->N;
-  const size_t ss = (size_t)s * N + s, dd = (size_t)d * d;
-  std::vector<cd> ops, dops;
-  plbo_local_ops(d, p, mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], ops, grad ? &dops : nullptr);
-  double e = 0.0;
-  for (int i = 0; i < d; ++i) e += G[(size_t)i * d + i].real();
-  for (int k = 1; k <= NOPS; ++k)
-    for (size_t q = 0; q < dd; ++q) e += (G[k * dd + q] * ops[(k - 1) * dd + q]).real();
-  if (grad)
-    for (int j = 0; j < TN_PLBO_NPARAM; ++j) {
-      double g = 0.0;
-      for (int k = 1; k <= NOPS; ++k)
-        for (size_t q = 0; q < dd; ++q) g += (G[k * dd + q] * dops[((size_t)j * NOPS + k - 1) * dd + q]).real();
-      grad[j] = g;
-    }
-  return e;
+static PlboSite plbo_site_of(const tn_mpo* mpo, int s, const std::vector<cd>& G) {
+  const size_t ss = (size_t)s * mpo->N + s;
+  return PlboSite{mpo->d, mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], &G};
 }
 
 struct PlboStep {
@@ -801,22 +786,10 @@ static PlboStep plbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_swe
   std::vector<cd> G;
   plbo_slot_envs(c, mpo, m, s, o.precision, m->A[s], G);
   auto& p = mpo->pp[s];
-  auto& mm = mpo->pm[s];
-  auto& vv = mpo->pv[s];
-  double g[TN_PLBO_NPARAM];
-  R.e0 = plbo_energy_grad(mpo, s, G, p.data(), nullptr);
-  for (int it = 0; it < po.steps; ++it) {
-    plbo_energy_grad(mpo, s, G, p.data(), g);
-    const int t = ++mpo->pt[s];
-    const double c1 = 1.0 - std::pow(po.beta1, t), c2 = 1.0 - std::pow(po.beta2, t);
-    for (int j = 0; j < TN_PLBO_NPARAM; ++j) {
-      if (!((po.mask >> j) & 1u)) continue;
-      mm[j] = po.beta1 * mm[j] + (1.0 - po.beta1) * g[j];
-      vv[j] = po.beta2 * vv[j] + (1.0 - po.beta2) * g[j] * g[j];
-      p[j] -= po.lr * (mm[j] / c1) / (std::sqrt(vv[j] / c2) + po.eps);
-    }
-  }
-  R.e1 = plbo_energy_grad(mpo, s, G, p.data(), nullptr);
+  const PlboSite S = plbo_site_of(mpo, s, G);
+  R.e0 = plbo_site_energy(S, p.data(), nullptr);
+  plbo_optimise(S, po, p.data(), mpo->pm[s].data(), mpo->pv[s].data(), &mpo->pt[s]);
+  R.e1 = plbo_site_energy(S, p.data(), nullptr);
   for (int j = 0; j < TN_PLBO_NPARAM; ++j)
     if (!std::isfinite(p[j])) TN_THROW(TN_ENUMERIC, "non-finite basis parameter");
   if (po.steps > 0) plbo_set_site(mpo, s);
@@ -830,6 +803,7 @@ static void check_plbo_opts(const tn_plbo_opts* po) {
   if (!(po->beta1 >= 0.0 && po->beta1 < 1.0) || !(po->beta2 >= 0.0 && po->beta2 < 1.0))
     TN_THROW(TN_EINVAL, "beta1 and beta2 must be in [0, 1)");
   if (!(po->eps > 0.0)) TN_THROW(TN_EINVAL, "eps must be positive");
+  if (po->optimizer != TN_PLBO_ADAM && po->optimizer != TN_PLBO_LBFGS) TN_THROW(TN_EINVAL, "unknown optimizer");
 }
 
 // ------------------------------------------------------------------ one two-site update
@@ -1405,7 +1379,7 @@ extern "C" tn_status tn_plbo_site_gradient(tn_ctx* c, tn_mpo* mpo, tn_mps* m, in
   HIPCHK(launch_scale_host(x, m->A[site], 1.0 / std::sqrt(nr), n, c->stream));
   std::vector<cd> Gh;
   plbo_slot_envs(c, mpo, m, site, precision, x, Gh);
-  *energy = plbo_energy_grad(mpo, site, Gh, mpo->pp[site].data(), grad);
+  *energy = plbo_site_energy(plbo_site_of(mpo, site, Gh), mpo->pp[site].data(), grad);
   if (G) std::memcpy(G, Gh.data(), Gh.size() * sizeof(cd));
   TN_GUARD_END(c)
 }

@@ -176,6 +176,16 @@ size_t elem_bytes(int prec);
 // dops (optional) = their derivatives, [TN_PLBO_NPARAM][NOPS][d][d]
 void plbo_local_ops(int d, const double* p, double a_ss, double b_ss, double g_ss, std::vector<cd>& ops,
                     std::vector<cd>* dops);
+// the energy of one site as a function of its parameters, the slot
+// environments G ([NOPS + 1][d][d]) held fixed
+struct PlboSite {
+  int d;
+  double a_ss, b_ss, g_ss;
+  const std::vector<cd>* G;
+};
+double plbo_site_energy(const PlboSite& S, const double* p, double* grad);
+// po.steps Adam steps (moments m, v, count t in and out) or L-BFGS iterations
+void plbo_optimise(const PlboSite& S, const tn_plbo_opts& po, double* p, double* m, double* v, int* t);
 // W[n][m] = <n|U|m>, n < D, m < d, from the gates applied in `levels` Fock levels
 void plbo_fock_isometry(int D, int d, const double* p, int levels, std::vector<cd>& W);
 // recompute the Fock image (iso) of every gate-parameterised basis changed since the last call

@@ -194,6 +194,141 @@ void plbo_local_ops(int d, const double* p, double a_ss, double b_ss, double g_s
     }
 }
 
+// ------------------------------------------------------------------ site functional and optimisers
+double plbo_site_energy(const PlboSite& S, const double* p, double* grad) {
+  const int d = S.d;
+  const size_t dd = (size_t)d * d;
+  const std::vector<cd>& G = *S.G;
+  std::vector<cd> ops, dops;
+  plbo_local_ops(d, p, S.a_ss, S.b_ss, S.g_ss, ops, grad ? &dops : nullptr);
+  double e = 0.0;
+  for (int i = 0; i < d; ++i) e += G[(size_t)i * d + i].real();
+  for (int k = 1; k <= NOPS; ++k)
+    for (size_t q = 0; q < dd; ++q) e += (G[k * dd + q] * ops[(k - 1) * dd + q]).real();
+  if (grad)
+    for (int j = 0; j < NP; ++j) {
+      double g = 0.0;
+      for (int k = 1; k <= NOPS; ++k)
+        for (size_t q = 0; q < dd; ++q) g += (G[k * dd + q] * dops[((size_t)j * NOPS + k - 1) * dd + q]).real();
+      grad[j] = g;
+    }
+  return e;
+}
+
+// Adam (Kingma & Ba): moments m, v and step count t carried by the caller.
+// L-BFGS (Nocedal, Math. Comp. 35, 1980: two-loop recursion over the last
+// eight curvature pairs, started afresh on every call) with a backtracking
+// Armijo line search on the exact site energy; a pair whose curvature
+// s^T y is not positive is skipped.  Both move only the masked parameters.
+void plbo_optimise(const PlboSite& S, const tn_plbo_opts& po, double* p, double* m, double* v, int* t) {
+  auto masked = [&](double* g) {
+    for (int j = 0; j < NP; ++j)
+      if (!((po.mask >> j) & 1u)) g[j] = 0.0;
+  };
+  double g[NP];
+  if (po.optimizer == TN_PLBO_ADAM) {
+    for (int it = 0; it < po.steps; ++it) {
+      plbo_site_energy(S, p, g);
+      masked(g);
+      const int tt = ++*t;
+      const double c1 = 1.0 - std::pow(po.beta1, tt), c2 = 1.0 - std::pow(po.beta2, tt);
+      for (int j = 0; j < NP; ++j) {
+        if (!((po.mask >> j) & 1u)) continue;
+        m[j] = po.beta1 * m[j] + (1.0 - po.beta1) * g[j];
+        v[j] = po.beta2 * v[j] + (1.0 - po.beta2) * g[j] * g[j];
+        p[j] -= po.lr * (m[j] / c1) / (std::sqrt(v[j] / c2) + po.eps);
+      }
+    }
+    return;
+  }
+  constexpr int HIST = 8;
+  std::vector<std::array<double, NP>> sk, yk;
+  std::vector<double> rho;
+  double f = plbo_site_energy(S, p, g);
+  masked(g);
+  for (int it = 0; it < po.steps; ++it) {
+    double gmax = 0.0;
+    for (int j = 0; j < NP; ++j) gmax = std::max(gmax, std::fabs(g[j]));
+    if (!(gmax > 0.0)) break;
+    // two-loop recursion: d = -H g
+    double q[NP], al[HIST];
+    for (int j = 0; j < NP; ++j) q[j] = g[j];
+    for (int h = (int)sk.size() - 1; h >= 0; --h) {
+      double a = 0.0;
+      for (int j = 0; j < NP; ++j) a += sk[h][j] * q[j];
+      a *= rho[h];
+      al[h] = a;
+      for (int j = 0; j < NP; ++j) q[j] -= a * yk[h][j];
+    }
+    double gam = 1.0;
+    if (!sk.empty()) {
+      double sy = 0.0, yy = 0.0;
+      for (int j = 0; j < NP; ++j) {
+        sy += sk.back()[j] * yk.back()[j];
+        yy += yk.back()[j] * yk.back()[j];
+      }
+      gam = sy / yy;
+    } else {
+      gam = po.lr / gmax;  // first step: at most lr in any parameter
+    }
+    for (int j = 0; j < NP; ++j) q[j] *= gam;
+    for (size_t h = 0; h < sk.size(); ++h) {
+      double b = 0.0;
+      for (int j = 0; j < NP; ++j) b += yk[h][j] * q[j];
+      b *= rho[h];
+      for (int j = 0; j < NP; ++j) q[j] += sk[h][j] * (al[h] - b);
+    }
+    double dir[NP], slope = 0.0;
+    for (int j = 0; j < NP; ++j) {
+      dir[j] = -q[j];
+      slope += dir[j] * g[j];
+    }
+    if (!(slope < 0.0)) {  // not a descent direction: restart from the scaled gradient
+      sk.clear();
+      yk.clear();
+      rho.clear();
+      for (int j = 0; j < NP; ++j) dir[j] = -(po.lr / gmax) * g[j];
+      slope = 0.0;
+      for (int j = 0; j < NP; ++j) slope += dir[j] * g[j];
+    }
+    double step = 1.0, pn[NP], gn[NP], fn = f;
+    bool ok = false;
+    for (int ls = 0; ls < 40; ++ls) {
+      for (int j = 0; j < NP; ++j) pn[j] = p[j] + step * dir[j];
+      fn = plbo_site_energy(S, pn, gn);
+      if (std::isfinite(fn) && fn <= f + 1e-4 * step * slope) {
+        ok = true;
+        break;
+      }
+      step *= 0.5;
+    }
+    if (!ok) break;
+    masked(gn);
+    std::array<double, NP> s1{}, y1{};
+    double sy = 0.0;
+    for (int j = 0; j < NP; ++j) {
+      s1[j] = pn[j] - p[j];
+      y1[j] = gn[j] - g[j];
+      sy += s1[j] * y1[j];
+    }
+    if (sy > 1e-300) {
+      if ((int)sk.size() == HIST) {
+        sk.erase(sk.begin());
+        yk.erase(yk.begin());
+        rho.erase(rho.begin());
+      }
+      sk.push_back(s1);
+      yk.push_back(y1);
+      rho.push_back(1.0 / sy);
+    }
+    for (int j = 0; j < NP; ++j) {
+      p[j] = pn[j];
+      g[j] = gn[j];
+    }
+    f = fn;
+  }
+}
+
 // ------------------------------------------------------------------ Fock image of the basis
 namespace {
 // y = G x for a banded generator stored by diagonals: G[i][i+o] = diag[o + 3][i]
@@ -396,6 +531,29 @@ extern "C" tn_status tn_plbo_fock_isometry(int32_t D, int32_t d, const double* p
     std::vector<cd> W;
     plbo_fock_isometry(D, d, params, levels, W);
     std::memcpy(iso, W.data(), W.size() * sizeof(cd));
+  } catch (...) {
+    return TN_EINVAL;
+  }
+  return TN_OK;
+}
+
+extern "C" tn_status tn_plbo_minimize(int32_t d, const double* G, double a_ss, double b_ss, double g_ss,
+                                      const tn_plbo_opts* opts, double* params, double* energy) {
+  if (d < 1 || d > 64 || !G || !opts || !params || !energy) return TN_EINVAL;
+  if (opts->steps < 0 || !(opts->lr > 0.0) || (opts->optimizer != TN_PLBO_ADAM && opts->optimizer != TN_PLBO_LBFGS))
+    return TN_EINVAL;
+  if (!(opts->beta1 >= 0.0 && opts->beta1 < 1.0) || !(opts->beta2 >= 0.0 && opts->beta2 < 1.0) || !(opts->eps > 0.0))
+    return TN_EINVAL;
+  for (int j = 0; j < NP; ++j)
+    if (!std::isfinite(params[j])) return TN_EINVAL;
+  try {
+    std::vector<cd> Gh((size_t)(NOPS + 1) * d * d);
+    std::memcpy(Gh.data(), G, Gh.size() * sizeof(cd));
+    const PlboSite S{d, a_ss, b_ss, g_ss, &Gh};
+    double m[NP] = {}, v[NP] = {};
+    int t = 0;
+    plbo_optimise(S, *opts, params, m, v, &t);
+    *energy = plbo_site_energy(S, params, nullptr);
   } catch (...) {
     return TN_EINVAL;
   }

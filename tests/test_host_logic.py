@@ -193,3 +193,67 @@ def test_noise_decomposition_matches_oracle():
         assert np.abs(Lc @ Lc.T - C).max() < 1e-13
     with pytest.raises(P.TnError):
         P.noise_uniform_loss(r, U, 0.0)
+
+
+def _plbo_site_G(d=3, seed=12):
+    """Slot environments of site 1 of a random 4-mode MPS (oracle)."""
+    import workloads as W
+    from oracle import plbo, gbs, mpo as ompo, dmrg as odmrg
+    r, U = W.make_problem(4, seed, (0.4, 0.7))
+    al, be, ga = gbs.coefficients(r, U)
+    rng = np.random.default_rng(seed)
+    dims = [1, d, 5, d, 1]
+    t = [rng.normal(size=(dims[s], d, dims[s + 1])) + 1j * rng.normal(size=(dims[s], d, dims[s + 1])) for s in range(4)]
+    ops = [plbo.transformed_ops(np.zeros(8), d, al[s, s], be[s, s], ga[s, s], L=40) for s in range(4)]
+    Ws = ompo.cores(al, be, ga, [o[:3] for o in ops])
+    Gf = plbo.core_environment(odmrg.left_envs(t, Ws)[1], t[1], odmrg.right_envs(t, Ws)[2])
+    Gf /= np.sum(np.abs(t[1]) ** 2)
+    G = plbo.slot_gradients(Gf, plbo.slot_coefficients(plbo.gaussian_core_maker(al, be, ga, 1), d))
+    return G, al[1, 1], be[1, 1], ga[1, 1]
+
+
+def test_plbo_lbfgs_reaches_the_oracle_minimum():
+    """The library's L-BFGS on the site energy (exact derivatives, Armijo
+    backtracking) reaches the minimum value of scipy's L-BFGS-B run by the
+    oracle from the same start.  The parameters themselves are not unique
+    (squeeze, rotation and shear compose to the same Gaussian unitary in
+    many ways), so the check is the energy, and the oracle's energy at the
+    library's parameters."""
+    import paper_2410_18740_amd as P
+    from oracle import plbo
+    G, a, b, g = _plbo_site_G()
+    d = G.shape[1]
+    mask = [0, 0, 1, 1, 1, 1, 0, 0]
+    p0 = np.array([0, 0, 0.05, 0.1, 0.05, 0.02, 0, 0])
+    o = P.PlboOpts(steps=300, lr=0.05, optimizer=P.PLBO_LBFGS, mask=0b111100)
+    p, E = P.plbo_minimize(G, p0, a, b, g, o)
+    pr, Er = plbo.minimize_site(G, p0, d, a, b, g, mask, L=40)
+    E0 = plbo.site_energy(G, plbo.transformed_ops(p0, d, a, b, g, L=40))
+    assert E < E0
+    assert abs(E - Er) < 1e-8 * max(1.0, abs(Er)), (E, Er)
+    assert np.all(p[[0, 1, 6, 7]] == 0.0)
+    # three free parameters (r, phi, theta): the optimum is then unique up to
+    # r -> -r with phi -> phi + pi, and the oracle evaluates the library's point
+    o3 = P.PlboOpts(steps=300, lr=0.05, optimizer=P.PLBO_LBFGS, mask=0b11100)
+    p3, E3 = P.plbo_minimize(G, p0, a, b, g, o3)
+    _, Er3 = plbo.minimize_site(G, p0, d, a, b, g, [0, 0, 1, 1, 1, 0, 0, 0], L=40)
+    assert abs(E3 - Er3) < 1e-8 * max(1.0, abs(Er3)), (E3, Er3)
+    assert abs(plbo.site_energy(G, plbo.transformed_ops(p3, d, a, b, g, L=120)) - E3) < 1e-9 * max(1.0, abs(E3))
+
+
+def test_plbo_adam_steps_match_the_oracle():
+    """Five Adam steps from the same start: the library (exact gradients)
+    and the oracle (five-point differences, Kingma & Ba's update) agree."""
+    import paper_2410_18740_amd as P
+    from oracle import plbo
+    G, a, b, g = _plbo_site_G(seed=13)
+    d = G.shape[1]
+    mask = [0, 0, 1, 1, 1, 1, 0, 0]
+    p0 = np.array([0, 0, 0.05, 0.1, 0.05, 0.02, 0, 0])
+    o = P.PlboOpts(steps=5, lr=0.01, optimizer=P.PLBO_ADAM, mask=0b111100)
+    p, _ = P.plbo_minimize(G, p0, a, b, g, o)
+    pr, _ = plbo.adam(p0, lambda q: plbo.param_gradient(G, q, d, a, b, g, L=40, which=[2, 3, 4, 5]), 5, 0.01,
+                      mask=mask)
+    assert np.abs(p - pr).max() < 1e-9, (p, pr)
+    with pytest.raises(P.TnError):
+        P.plbo_minimize(G, p0, a, b, g, P.PlboOpts(optimizer=7))

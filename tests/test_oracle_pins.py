@@ -1013,3 +1013,16 @@ def test_displaced_sampler_reduces_to_the_plain_sampler():
     p /= p.sum()
     hist = np.bincount(smp, minlength=4) / 3000.0
     assert np.abs(hist - p).max() < 4 * math.sqrt(0.25 / 3000)
+
+
+def test_plbo_site_minimiser_finds_the_squeezed_vacuum():
+    """One squeezed mode, one basis state: the oracle's site minimiser over
+    (r, phi) drives the energy to 0 with |r| equal to the instance's squeezing."""
+    from oracle import plbo
+    r = np.array([0.5])
+    al, be, ga = gbs.coefficients(r, np.eye(1, dtype=complex))
+    G = np.zeros((6, 1, 1), dtype=complex)
+    G[3, 0, 0] = 1.0                        # N = 1: the Hamiltonian is the site operator S
+    mask = [0, 0, 1, 1, 0, 0, 0, 0]
+    p, E = plbo.minimize_site(G, [0, 0, 0.1, 0.3, 0, 0, 0, 0], 1, al[0, 0], be[0, 0], ga[0, 0], mask, L=40)
+    assert abs(E) < 1e-10 and abs(abs(p[2]) - 0.5) < 1e-5
