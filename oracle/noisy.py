@@ -1,6 +1,12 @@
 """Noisy GBS as a pure state plus classical displacements (oracle; test
 infrastructure only).
 
+Two splits are kept: the closed form for uniform loss below, and for a
+general mixed covariance the Williamson decomposition V = S diag(nu, nu) S^T
+with Q = S S^T/2 and C = S (diag(nu, nu) - I/2) S^T (the pure states of the
+first column of the paper's photon table); the pure part's (r, U) comes from
+its eigenvectors (Bloch-Messiah form).
+
 Sec. II.F, eq. CovarianceDecomposition: a mixed covariance V is split as
 V = Q + C with Q the covariance of a pure state and C >= 0 the covariance of
 zero-mean Gaussian random displacements; a sample of the noisy experiment is a
@@ -122,3 +128,76 @@ def gaussian_photon_distribution(V2: np.ndarray, nmax: int, L: int = 160) -> np.
     th = np.diag([(1 - q) * q ** k for k in range(L)])
     rho = S @ th @ S.conj().T
     return np.real(np.diag(rho))[:nmax].copy()
+
+
+# ---------------------------------------------------------------- general split
+def _omega(N):
+    return np.block([[np.zeros((N, N)), np.eye(N)], [-np.eye(N), np.zeros((N, N))]])
+
+
+def williamson(V):
+    """(nu, S) with V = S diag(nu, nu) S^T, S symplectic (S Omega S^T = Omega),
+    quadrature order (x_1..x_N, p_1..p_N): with A = V^{-1/2} Omega V^{-1/2}
+    (real antisymmetric, eigenvalues +-i/nu), an orthogonal K that brings A
+    to [[0, diag(1/nu)], [-diag(1/nu), 0]] gives S = V^{1/2} K diag(nu)^{-1/2}.
+    K's columns come from the eigenvectors of the Hermitian i A (numpy eigh)."""
+    N = V.shape[0] // 2
+    w, E = np.linalg.eigh(V)
+    Vh = (E * np.sqrt(w)) @ E.T
+    Vmh = (E / np.sqrt(w)) @ E.T
+    A = Vmh @ _omega(N) @ Vmh
+    mu, Uc = np.linalg.eigh(1j * A)
+    pos = np.argsort(-mu)[:N]                    # the N positive eigenvalues 1/nu
+    K = np.zeros((2 * N, 2 * N))
+    for c, k in enumerate(pos):
+        K[:, c] = math.sqrt(2.0) * Uc[:, k].real
+        K[:, N + c] = -math.sqrt(2.0) * Uc[:, k].imag
+    nu = 1.0 / mu[pos]
+    S = Vh @ K @ np.diag(np.concatenate([nu, nu]) ** -0.5)
+    return nu, S
+
+
+def decompose_williamson(V):
+    """Pure part Q = S S^T / 2 of the Williamson decomposition and the
+    classical part C = S (diag(nu, nu) - I/2) S^T >= 0 (Sec. II.F, the
+    decomposition of the first column of the paper's photon table)."""
+    nu, S = williamson(V)
+    Q = 0.5 * S @ S.T
+    C = S @ np.diag(np.concatenate([nu, nu]) - 0.5) @ S.T
+    return Q, C
+
+
+def pure_state_parameters(Q):
+    """(r, U) with Q = covariance(r, U) for a pure covariance Q
+    (Bloch-Messiah form): eigenvectors of Q with eigenvalue e^{-2r}/2 <= 1/2
+    give the x-columns (X; Y) of the passive O = [[X, -Y], [Y, X]], their
+    partners -Omega x are the p-columns; a degenerate eigenspace at 1/2 is
+    split into such pairs by Gram-Schmidt."""
+    N = Q.shape[0] // 2
+    Om = _omega(N)
+    w, E = np.linalg.eigh(Q)
+    cols, rs = [], []
+    used = np.zeros((2 * N, 0))
+    for k in np.argsort(w):
+        if len(cols) == N:
+            break
+        v = E[:, k].copy()
+        if used.shape[1]:
+            v -= used @ (used.T @ v)
+        nv = np.linalg.norm(v)
+        if nv < 1e-6 or w[k] > 0.5 + 1e-9:
+            continue
+        v /= nv
+        cols.append(v)
+        rs.append(-0.5 * math.log(2.0 * min(w[k], 0.5)))
+        used = np.column_stack([used, v, -Om @ v])
+    X = np.array([c[:N] for c in cols]).T
+    Y = np.array([c[N:] for c in cols]).T
+    return np.array(rs), X + 1j * Y
+
+
+def factor_psd(C, tol=1e-12):
+    """L (2N x K) with C = L L^T over the eigenvalues above tol * max."""
+    w, E = np.linalg.eigh(0.5 * (C + C.T))
+    keep = w > tol * max(w.max(), 1e-300)
+    return E[:, keep] * np.sqrt(w[keep])[None, :]

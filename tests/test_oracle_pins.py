@@ -1026,3 +1026,47 @@ def test_plbo_site_minimiser_finds_the_squeezed_vacuum():
     mask = [0, 0, 1, 1, 0, 0, 0, 0]
     p, E = plbo.minimize_site(G, [0, 0, 0.1, 0.3, 0, 0, 0, 0], 1, al[0, 0], be[0, 0], ga[0, 0], mask, L=40)
     assert abs(E) < 1e-10 and abs(abs(p[2]) - 0.5) < 1e-5
+
+
+def test_williamson_split_of_a_general_mixed_state():
+    """Williamson decomposition V = S diag(nu, nu) S^T of a mixed covariance
+    (uniform loss plus thermal noise): S is symplectic, nu are the symplectic
+    eigenvalues (moduli of eig(i Omega V)), Q = S S^T/2 is pure and
+    C = V - Q >= 0; for uniform loss alone the pure part's squeezing is the
+    closed form r_W = ln(v_p / v_x)/4 per input mode, and it carries more
+    photons than the minimal-trace split (the order of the paper's table)."""
+    from oracle import noisy
+    r, U = W.make_problem(5, 3, (0.4, 1.1))
+    V = noisy.lossy_covariance(r, U, 0.6) + 0.1 * np.eye(10)
+    nu, S = noisy.williamson(V)
+    Om = noisy._omega(5)
+    assert np.abs(S @ Om @ S.T - Om).max() < 1e-12
+    assert np.abs(S @ np.diag(np.concatenate([nu, nu])) @ S.T - V).max() < 1e-12
+    assert np.abs(np.sort(nu) - noisy.symplectic_eigenvalues(V)[::2]).max() < 1e-10
+    Q, C = noisy.decompose_williamson(V)
+    assert np.abs(noisy.symplectic_eigenvalues(Q) - 0.5).max() < 1e-10
+    assert np.linalg.eigvalsh(C).min() > -1e-12 and np.abs(Q + C - V).max() < 1e-12
+    L = noisy.factor_psd(C)
+    assert np.abs(L @ L.T - C).max() < 1e-12
+    Vl = noisy.lossy_covariance(r, U, 0.6)
+    Ql, _ = noisy.decompose_williamson(Vl)
+    rw, Uw = noisy.pure_state_parameters(Ql)
+    vx, vp = 0.6 * np.exp(-2 * r) + 0.4, 0.6 * np.exp(2 * r) + 0.4
+    assert np.abs(np.sort(rw) - np.sort(0.25 * np.log(vp / vx))).max() < 1e-10
+    rk, _, _ = noisy.decompose_uniform_loss(r, U, 0.6)
+    assert np.sum(np.sinh(rw) ** 2) > np.sum(np.sinh(rk) ** 2)
+
+
+def test_pure_state_parameters_invert_the_covariance():
+    """(r, U) from a pure covariance: covariance(r, U) reproduces it, U is
+    unitary and r matches the squeezing as a set; also with unsqueezed modes
+    (a degenerate eigenvalue 1/2)."""
+    from oracle import noisy
+    for r0, seed in (((0.3, 0.8, 0.5, 1.1), 2), ((0.0, 0.6, 0.0), 4)):
+        r0 = np.array(r0)
+        U0 = W.make_problem(len(r0), seed, (0.5, 0.5))[1]
+        Q = gbs.covariance(r0, U0)
+        r, U = noisy.pure_state_parameters(Q)
+        assert np.abs(gbs.covariance(r, U) - Q).max() < 1e-12
+        assert np.abs(U @ U.conj().T - np.eye(len(r0))).max() < 1e-12
+        assert np.abs(np.sort(r) - np.sort(r0)).max() < 1e-10
