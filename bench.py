@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--noisy", type=float, default=None, metavar="ETA",
                     help="noisy GBS with uniform loss ETA: DMRG on the pure part, then plain and displaced sampling")
     ap.add_argument("--noisy-samples", type=int, default=8192)
+    ap.add_argument("--noisy-split", default="kept", choices=["kept", "williamson"],
+                    help="pure part of the split: the minimal-trace closed form for uniform loss, or the Williamson "
+                         "decomposition of the lossy covariance")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB copy before the timed sweeps (PMC counter scaling)")
     ap.add_argument("--cutoff-report", action="store_true",
@@ -607,14 +610,17 @@ def noisy_bench(a):
     r, U = W.workload_problem(a.workload)
     eta = a.noisy
     rp, Lc = P.noise_uniform_loss(r, U, eta)
+    Up = U
     vx, vp = eta * np.exp(-2 * r) + 1 - eta, eta * np.exp(2 * r) + 1 - eta
     r_w = 0.25 * np.log(vp / vx)                  # Williamson pure part of each input mode
     V = _cov(r, U)
     Ve = eta * V + (1 - eta) * 0.5 * np.eye(2 * w.N)
     table = {"pure_williamson": _photon_stats(_cov(r_w, U)), "pure_kept": _photon_stats(_cov(rp, U)),
              "lossy": _photon_stats(Ve), "ideal_eta1": _photon_stats(V)}
+    if a.noisy_split == "williamson":
+        rp, Up, Lc = P.noise_williamson(Ve)          # library split of the lossy covariance
     ctx = P.Context(0)
-    mpo = P.MPO(ctx, rp, U, w.D_raw, w.d)
+    mpo = P.MPO(ctx, rp, Up, w.D_raw, w.d)
     mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
     opts = P.SweepOpts(chi_max=w.chi, tol=1e-6, krylov_max=24, max_matvecs=a.max_matvecs, precision=FORMS[a.form],
                        lbo=0 if a.no_lbo else 1, compute_energy=1)
@@ -626,7 +632,7 @@ def noisy_bench(a):
     n = a.noisy_samples
     g = torch.Generator(device="cuda:0")
     g.manual_seed(11)
-    z = torch.randn((n, w.N), dtype=torch.float64, device="cuda:0", generator=g)
+    z = torch.randn((n, Lc.shape[1]), dtype=torch.float64, device="cuda:0", generator=g)
     P.sample(ctx, mps, mpo, 256, 1)
     P.sample_displaced(ctx, mps, mpo, 256, 1, Lc, z=z[:256])
     torch.cuda.synchronize()
@@ -639,7 +645,8 @@ def noisy_bench(a):
     t3 = time.perf_counter()
     tot_p = plain.sum(dim=1).double().cpu().numpy()
     tot_n = noisy.sum(dim=1).double().cpu().numpy()
-    line = {"mode": "noisy", "workload": a.workload, "eta": eta, "form": a.form, "N": w.N, "D_raw": w.D_raw,
+    line = {"mode": "noisy", "split": a.noisy_split, "noise_rank": int(Lc.shape[1]), "workload": a.workload,
+            "eta": eta, "form": a.form, "N": w.N, "D_raw": w.D_raw,
             "d": w.d, "chi": w.chi, "r_pure_mean": float(np.mean(rp)), "r_mean": float(np.mean(r)),
             "photon_expectation_sum_pm_sd": {k: [round(v[0], 4), round(v[1], 4)] for k, v in table.items()},
             "pure_part": {"energy": s["energy"], "sweeps": max(1, a.steps), "seconds": t_dmrg},

@@ -341,16 +341,29 @@ tn_status tn_sample(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n
  * [1, 4096], eta outside (0, 1], negative or non-finite r, non-finite U or NULL
  * pointers.
  *
+ * tn_noise_williamson (host only): the general split of a mixed covariance V
+ * (host [2N][2N], symmetric, vacuum = I/2) by the Williamson decomposition
+ * V = S diag(nu, nu) S^T: Q = S S^T / 2 (pure; r_pure [N] and U_pure, host
+ * complex [N][N], with Q = 1/2 O diag(e^{-2r}, e^{2r}) O^T as for an ideal
+ * instance) and C = S (diag(nu, nu) - I/2) S^T = L L^T with L host
+ * [2N][K] row-major (capacity 4 N^2 doubles), K = *K columns (the eigenvalues
+ * of C above 1e-12 of the largest eigenvalue of V; K = 0 for a pure V).
+ * TN_EINVAL on N outside [1, 512],
+ * non-finite or non-symmetric V, V not positive definite, or a symplectic
+ * eigenvalue below 1/2 (not a physical state); TN_ENUMERIC if the pure part
+ * cannot be brought to that form.
+ *
  * tn_sample_displaced: as tn_sample for the state D(alpha_b)|psi>, with
  * alpha_b,j = (d_x + i d_p)/sqrt2, d = L z_b.  z: device doubles
- * [n_samples][N], standard normal draws supplied by the caller (the random
- * numbers of the noise); L: host [2N][N].  The displacement acts on the D_raw
+ * [n_samples][K], standard normal draws supplied by the caller (the random
+ * numbers of the noise); L: host [2N][K], 1 <= K <= 2N.  The displacement acts on the D_raw
  * kept Fock levels of each mode (weight it moves beyond them is dropped and
  * the conditional probabilities renormalised).  Uniform draws and the
  * inverse-CDF rule are tn_sample's.  Same centre requirement as tn_sample. */
 tn_status tn_noise_uniform_loss(int32_t N, const double* r, const double* U, double eta, double* r_pure, double* L);
+tn_status tn_noise_williamson(int32_t N, const double* V, double* r_pure, double* U_pure, double* L, int32_t* K);
 tn_status tn_sample_displaced(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
-                              const double* z, const double* L, int32_t* out);
+                              int32_t K, const double* z, const double* L, int32_t* out);
 
 /* Single-site reduced density matrices rho_j[n][n'] = <n|rho_j|n'> (eq.
  * ReducedDensityMatrix) in the raw Fock basis, FP64, for j < n_modes.  out:

@@ -140,7 +140,8 @@ def lib():
         "tn_ws_initial_state": (i32, [i32, i32, i32, i32, P(C.c_float), C.c_uint64, dbl, P(dbl), P(i32), P(dbl),
                                       szt, P(szt)]),
         "tn_noise_uniform_loss": (i32, [i32, P(dbl), P(dbl), dbl, P(dbl), P(dbl)]),
-        "tn_sample_displaced": (i32, [vp, vp, vp, i64, C.c_uint64, vp, P(dbl), vp]),
+        "tn_sample_displaced": (i32, [vp, vp, vp, i64, C.c_uint64, i32, vp, P(dbl), vp]),
+        "tn_noise_williamson": (i32, [i32, P(dbl), P(dbl), P(dbl), P(dbl), P(i32)]),
         "tn_plbo_ops": (i32, [i32, P(dbl), dbl, dbl, dbl, P(dbl), P(dbl)]),
         "tn_plbo_fock_isometry": (i32, [i32, i32, P(dbl), i32, P(dbl)]),
         "tn_plbo_enable": (i32, [vp, P(dbl)]),

@@ -401,26 +401,43 @@ def noise_uniform_loss(r, U, eta: float):
     return rp, Lc
 
 
+def noise_williamson(V):
+    """(r_pure [N], U_pure [N][N], L [2N][K]): the Williamson split of a mixed
+    covariance V = Q + C with Q = covariance(r_pure, U_pure) and C = L L^T."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    N = V.shape[0] // 2
+    rp = np.zeros(N)
+    Up = np.zeros((N, N), dtype=np.complex128)
+    Lc = np.zeros(4 * N * N)
+    K = C.c_int32()
+    st = L.lib().tn_noise_williamson(N, L.dptr(V), L.dptr(rp), L.dptr(Up.view(np.float64)), L.dptr(Lc), C.byref(K))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_noise_williamson: bad covariance")
+    return rp, Up, Lc[: 2 * N * K.value].reshape(2 * N, K.value).copy()
+
+
 def sample_displaced(ctx: Context, mps: MPS, mpo: MPO, n_samples: int, seed: int, Lc, z=None):
     """Noisy-GBS samples: photon numbers of D(alpha_b)|psi> with alpha_b from
-    d = Lc z_b.  z: (n_samples, N) standard normals (device or host); when None
-    they are drawn on the device from a torch generator seeded with `seed`."""
+    d = Lc z_b, Lc of shape (2N, K).  z: (n_samples, K) standard normals
+    (device or host); when None they are drawn on the device from a torch
+    generator seeded with `seed`."""
     torch = _torch()
     dev = f"cuda:{ctx.device}"
+    Lh = np.ascontiguousarray(Lc, dtype=np.float64)
+    if Lh.ndim != 2 or Lh.shape[0] != 2 * mps.N:
+        raise ValueError("Lc must have shape (2N, K)")
+    K = Lh.shape[1]
     if z is None:
         g = torch.Generator(device=dev)
         g.manual_seed(int(seed))
-        z = torch.randn((n_samples, mps.N), dtype=torch.float64, device=dev, generator=g)
+        z = torch.randn((n_samples, K), dtype=torch.float64, device=dev, generator=g)
     else:
         z = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64) if not hasattr(z, "device") else z,
                             dtype=torch.float64).to(dev).contiguous()
-    if tuple(z.shape) != (n_samples, mps.N):
-        raise ValueError("z must have shape (n_samples, N)")
-    Lh = np.ascontiguousarray(Lc, dtype=np.float64)
-    if Lh.shape != (2 * mps.N, mps.N):
-        raise ValueError("Lc must have shape (2N, N)")
+    if tuple(z.shape) != (n_samples, K):
+        raise ValueError("z must have shape (n_samples, K)")
     out = torch.empty((n_samples, mps.N), dtype=torch.int32, device=dev)
-    ctx.check(L.lib().tn_sample_displaced(ctx.h, mps.h, mpo.h, n_samples, C.c_uint64(seed),
+    ctx.check(L.lib().tn_sample_displaced(ctx.h, mps.h, mpo.h, n_samples, C.c_uint64(seed), K,
                                           C.c_void_p(z.data_ptr()), L.dptr(Lh), C.c_void_p(out.data_ptr())))
     return out
 

@@ -265,18 +265,210 @@ extern "C" tn_status tn_noise_uniform_loss(int32_t N, const double* r, const dou
   return TN_OK;
 }
 
-// alpha[b][j] = (d_x + i d_p) / sqrt2 with d = L z_b (L: 2N x N, z: B x N)
-__global__ void noise_alpha_kernel(const double* __restrict__ z, const double* __restrict__ L, int64_t B, int N,
+// Cyclic Jacobi for a complex Hermitian n x n matrix on the host (FP64):
+// A (row-major) is overwritten; w receives the eigenvalues in ascending order
+// and the columns of Z the eigenvectors.  The rotation zeroing a_pq is the one
+// of the device eigensolver (same angle formulas).
+static void herm_eig_host(int n, std::vector<cd> A, std::vector<double>& w, std::vector<cd>& Z) {
+  Z.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  auto at = [&](int i, int j) -> cd& { return A[(size_t)i * n + j]; };
+  for (int i = 0; i < n; ++i) at(i, i) = at(i, i).real();
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) (i == j ? tot : off) += std::norm(at(i, j));
+    if (off <= 1e-30 * (tot + off) || off < 1e-300) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const cd apq = at(p, q);
+        const double b = std::abs(apq), app = at(p, p).real(), aqq = at(q, q).real();
+        if (!(b > 1e-300) || b * b <= 1e-34 * (app * app + aqq * aqq)) continue;
+        const double zeta = (aqq - app) / (2.0 * b);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        const cd em = std::conj(apq) / b, ep = apq / b;  // e^{-i phi}, e^{i phi}
+        for (int r = 0; r < n; ++r) {  // columns: A <- A J, Z <- Z J
+          const cd xp = at(r, p), xq = at(r, q) * em;
+          at(r, p) = c * xp - sn * xq;
+          at(r, q) = sn * xp + c * xq;
+          const cd zp = Z[(size_t)r * n + p], zq = Z[(size_t)r * n + q] * em;
+          Z[(size_t)r * n + p] = c * zp - sn * zq;
+          Z[(size_t)r * n + q] = sn * zp + c * zq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows: A <- J^H A
+          const cd xp = at(p, k), xq = at(q, k) * ep;
+          at(p, k) = c * xp - sn * xq;
+          at(q, k) = sn * xp + c * xq;
+        }
+        at(p, q) = 0.0;
+        at(q, p) = 0.0;
+        at(p, p) = at(p, p).real();
+        at(q, q) = at(q, q).real();
+      }
+  }
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return at(a, a).real() < at(b, b).real(); });
+  w.resize(n);
+  std::vector<cd> Zs((size_t)n * n);
+  for (int c2 = 0; c2 < n; ++c2) {
+    w[c2] = at(ord[c2], ord[c2]).real();
+    for (int r = 0; r < n; ++r) Zs[(size_t)r * n + c2] = Z[(size_t)r * n + ord[c2]];
+  }
+  Z.swap(Zs);
+}
+
+// General split of a mixed covariance (eq. CovarianceDecomposition) by the
+// Williamson decomposition V = S diag(nu, nu) S^T: with A = V^{-1/2} Omega
+// V^{-1/2} (antisymmetric, Omega = [[0, I], [-I, 0]]), an eigenvector a + i b
+// of i A for the eigenvalue 1/nu_k gives the pair of columns sqrt2 a, -sqrt2 b
+// of an orthogonal K with K^T A K = [[0, diag(1/nu)], [-diag(1/nu), 0]], and
+// S = V^{1/2} K diag(nu, nu)^{-1/2}.  Q = S S^T / 2 is pure and
+// C = S (diag(nu, nu) - I/2) S^T >= 0.  The pure part's (r, U): eigenvectors
+// x of Q with eigenvalue e^{-2r}/2 <= 1/2 are the columns (Re U; Im U) of the
+// passive rotation, -Omega x their partners; a degenerate eigenvalue 1/2 is
+// split into such pairs by Gram-Schmidt.
+extern "C" tn_status tn_noise_williamson(int32_t N, const double* V, double* r_pure, double* U_pure, double* L,
+                                         int32_t* K) {
+  if (N < 1 || N > 512 || !V || !r_pure || !U_pure || !L || !K) return TN_EINVAL;
+  const int n = 2 * N;
+  for (int i = 0; i < n * n; ++i)
+    if (!std::isfinite(V[i])) return TN_EINVAL;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (std::fabs(V[i * n + j] - V[j * n + i]) > 1e-10 * (std::fabs(V[i * n + j]) + 1e-300) &&
+          std::fabs(V[i * n + j] - V[j * n + i]) > 1e-14)
+        return TN_EINVAL;
+  try {
+    std::vector<cd> Vc((size_t)n * n);
+    for (int i = 0; i < n * n; ++i) Vc[i] = V[i];
+    std::vector<double> w;
+    std::vector<cd> E;
+    herm_eig_host(n, Vc, w, E);
+    if (!(w[0] > 0.0)) return TN_EINVAL;
+    std::vector<double> Vh((size_t)n * n, 0.0), Vmh((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double e = (E[(size_t)i * n + k] * std::conj(E[(size_t)j * n + k])).real();
+          a += e * std::sqrt(w[k]);
+          b += e / std::sqrt(w[k]);
+        }
+        Vh[(size_t)i * n + j] = a;
+        Vmh[(size_t)i * n + j] = b;
+      }
+    // A = Vmh Omega Vmh; (Omega M)[i][j] = M[i+N][j] (i < N), -M[i-N][j] (i >= N)
+    std::vector<double> OmV((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) OmV[(size_t)i * n + j] = i < N ? Vmh[(size_t)(i + N) * n + j] : -Vmh[(size_t)(i - N) * n + j];
+    std::vector<cd> iA((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double a = 0.0;
+        for (int k = 0; k < n; ++k) a += Vmh[(size_t)i * n + k] * OmV[(size_t)k * n + j];
+        iA[(size_t)i * n + j] = cd(0.0, a);
+      }
+    std::vector<double> mu;
+    std::vector<cd> Uc;
+    herm_eig_host(n, iA, mu, Uc);  // ascending: the last N are the positive 1/nu
+    std::vector<double> nu(N), Kmat((size_t)n * n);
+    for (int c = 0; c < N; ++c) {
+      const int k = n - 1 - c;
+      if (!(mu[k] > 0.0)) return TN_EINVAL;
+      nu[c] = 1.0 / mu[k];
+      if (nu[c] < 0.5 - 1e-9) return TN_EINVAL;  // not a physical covariance
+      for (int i = 0; i < n; ++i) {
+        Kmat[(size_t)i * n + c] = std::sqrt(2.0) * Uc[(size_t)i * n + k].real();
+        Kmat[(size_t)i * n + N + c] = -std::sqrt(2.0) * Uc[(size_t)i * n + k].imag();
+      }
+    }
+    // S = Vh K diag(nu, nu)^{-1/2}
+    std::vector<double> S((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double a = 0.0;
+        for (int k = 0; k < n; ++k) a += Vh[(size_t)i * n + k] * Kmat[(size_t)k * n + j];
+        S[(size_t)i * n + j] = a / std::sqrt(nu[j % N]);
+      }
+    std::vector<cd> Q((size_t)n * n), C((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double q = 0.0, c = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double sk = S[(size_t)i * n + k] * S[(size_t)j * n + k];
+          q += 0.5 * sk;
+          c += (nu[k % N] - 0.5) * sk;
+        }
+        Q[(size_t)i * n + j] = q;
+        C[(size_t)i * n + j] = c;
+      }
+    // pure part (r, U)
+    std::vector<double> wq;
+    std::vector<cd> Eq;
+    herm_eig_host(n, Q, wq, Eq);
+    std::vector<std::vector<double>> basis;
+    int found = 0;
+    for (int k = 0; k < n && found < N; ++k) {
+      if (wq[k] > 0.5 + 1e-9) break;
+      std::vector<double> v(n);
+      for (int i = 0; i < n; ++i) v[i] = Eq[(size_t)i * n + k].real();
+      for (const auto& u : basis) {
+        double dp = 0.0;
+        for (int i = 0; i < n; ++i) dp += u[i] * v[i];
+        for (int i = 0; i < n; ++i) v[i] -= dp * u[i];
+      }
+      double nv = 0.0;
+      for (double x : v) nv += x * x;
+      nv = std::sqrt(nv);
+      if (nv < 1e-6) continue;
+      for (double& x : v) x /= nv;
+      std::vector<double> pv(n);  // -Omega v
+      for (int i = 0; i < n; ++i) pv[i] = i < N ? -v[i + N] : v[i - N];
+      r_pure[found] = -0.5 * std::log(2.0 * std::min(wq[k], 0.5));
+      for (int j = 0; j < N; ++j) {
+        U_pure[2 * ((size_t)j * N + found)] = v[j];
+        U_pure[2 * ((size_t)j * N + found) + 1] = v[N + j];
+      }
+      basis.push_back(v);
+      basis.push_back(pv);
+      ++found;
+    }
+    if (found != N) return TN_ENUMERIC;
+    // C = L L^T over its eigenvalues above 1e-12 of the largest eigenvalue of V
+    // (a pure V leaves K = 0: no classical noise)
+    std::vector<double> wc;
+    std::vector<cd> Ec;
+    herm_eig_host(n, C, wc, Ec);
+    const double thr = 1e-12 * w[n - 1];
+    int kk = 0;
+    for (int k = n - 1; k >= 0; --k)
+      if (wc[k] > thr) ++kk;
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < kk; ++c) {
+        const int k = n - 1 - c;
+        L[(size_t)i * kk + c] = Ec[(size_t)i * n + k].real() * std::sqrt(wc[k]);
+      }
+    *K = kk;
+  } catch (...) {
+    return TN_ENOMEM;
+  }
+  return TN_OK;
+}
+
+// alpha[b][j] = (d_x + i d_p) / sqrt2 with d = L z_b (L: 2N x K, z: B x K)
+__global__ void noise_alpha_kernel(const double* __restrict__ z, const double* __restrict__ L, int64_t B, int N, int K,
                                    cf64* __restrict__ alpha) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= B * N) return;
   const int64_t b = e / N;
   const int j = (int)(e % N);
   double dx = 0.0, dp = 0.0;
-  for (int i = 0; i < N; ++i) {
-    const double zi = z[b * N + i];
-    dx += L[(int64_t)j * N + i] * zi;
-    dp += L[(int64_t)(N + j) * N + i] * zi;
+  for (int i = 0; i < K; ++i) {
+    const double zi = z[b * K + i];
+    dx += L[(int64_t)j * K + i] * zi;
+    dp += L[(int64_t)(N + j) * K + i] * zi;
   }
   const double s = 0.70710678118654752440;
   alpha[e] = make_double2(dx * s, dp * s);
@@ -359,13 +551,14 @@ __global__ __launch_bounds__(64) void displace_rows_kernel(const cf64* __restric
 }
 
 extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int64_t n_samples,
-                                         uint64_t seed, const double* z, const double* L, int32_t* out) {
+                                         uint64_t seed, int32_t K, const double* z, const double* L, int32_t* out) {
   if (!c) return TN_EINVAL;
   TN_GUARD_BEGIN
   check_obs(m, mpo);
   if (!out || !z || !L || n_samples < 1) TN_THROW(TN_EINVAL, "bad output, noise or sample count");
   const int N = m->N, D = mpo->D_raw;
-  for (int64_t i = 0; i < 2ll * N * N; ++i)
+  if (K < 1 || K > 2 * N) TN_THROW(TN_EINVAL, "the noise factor needs 1 <= K <= 2N columns");
+  for (int64_t i = 0; i < 2ll * N * K; ++i)
     if (!std::isfinite(L[i])) TN_THROW(TN_EINVAL, "non-finite noise factor");
   hipStream_t st = c->stream;
   int chimax = 1;
@@ -376,8 +569,8 @@ extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mp
   cf64* Va = wsT<cf64>(c, "smp:Va", (size_t)chunk * chimax);
   cf64* Vb = wsT<cf64>(c, "smp:Vb", (size_t)chunk * chimax);
   cf64* al = wsT<cf64>(c, "smp:al", (size_t)chunk * N);
-  double* dL = wsT<double>(c, "smp:L", 2 * (size_t)N * N);
-  upload(c, dL, L, 2 * (size_t)N * N * sizeof(double));
+  double* dL = wsT<double>(c, "smp:L", 2 * (size_t)N * K);
+  upload(c, dL, L, 2 * (size_t)N * K * sizeof(double));
   std::vector<cf64*> F(N);
   for (int s = 0; s < N; ++s) {
     const size_t nel = (size_t)m->dims[s] * D * m->dims[s + 1];
@@ -388,8 +581,8 @@ extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mp
   for (int64_t s0 = 0; s0 < n_samples; s0 += chunk) {
     const int B = (int)std::min<int64_t>(chunk, n_samples - s0);
     const int64_t ne = (int64_t)B * N;
-    hipLaunchKernelGGL(noise_alpha_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, z + s0 * N, dL,
-                       (int64_t)B, N, al);
+    hipLaunchKernelGGL(noise_alpha_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, z + s0 * K, dL,
+                       (int64_t)B, N, K, al);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(fill_one_kernel, dim3(std::max(1, (B + 255) / 256)), dim3(256), 0, st, Va, (int64_t)B);
     for (int s = 0; s < N; ++s) {

@@ -143,3 +143,32 @@ def test_displaced_stream_at_the_benchmark_size(ctx):
     F = omps.fock_tensors(mp.export(), list(m.isometries()))
     ref = noisy.sample_displaced(F, noisy.alphas(z, Lo), 8, L=w.D_raw + 60)
     assert np.sum(np.any(smp != ref, axis=1)) <= 1
+
+
+def test_williamson_split_samples_match_a_general_mixed_state(ctx):
+    """A mixed covariance that is not uniform loss (loss 0.7 plus thermal
+    noise 0.05 on every mode): the Williamson split's pure part (r, U) is
+    solved by DMRG, the displacement factor has rank 2N, the stream follows
+    the oracle's, and 400k samples reproduce each mode's photon distribution
+    of V."""
+    import paper_2410_18740_amd as P
+    r, U = W.make_problem(4, 6, (0.4, 0.6))
+    N, D, n = 4, 12, 400000
+    V = noisy.lossy_covariance(r, U, 0.7) + 0.05 * np.eye(2 * N)
+    rp, Up, Lc = P.noise_williamson(V)
+    assert Lc.shape == (2 * N, 2 * N)
+    # the Williamson pure part is more squeezed than the minimal one: the
+    # Fock box leaves a larger <H>
+    m, mp, E = _pure_state(ctx, rp, Up, D, 64)
+    assert E < 1e-4
+    z = np.random.default_rng(12).standard_normal((200, 2 * N))
+    smp = P.sample_displaced(ctx, mp, m, 200, 21, Lc, z=z).cpu().numpy()
+    ref = noisy.sample_displaced(mp.export(), noisy.alphas(z, Lc), 21, L=D + 60)
+    assert np.mean(np.any(smp != ref, axis=1)) < 0.01
+    smp = P.sample_displaced(ctx, mp, m, n, 4343, Lc).cpu().numpy()
+    for j in range(N):
+        want = noisy.gaussian_photon_distribution(V[np.ix_([j, N + j], [j, N + j])], D)
+        tail = 1.0 - want.sum()
+        hist = np.bincount(smp[:, j], minlength=D)[:D] / n
+        sig = np.sqrt(want * (1 - want) / n)
+        assert np.all(np.abs(hist - want) <= 5 * sig + 2 * tail + 1e-6), (j, hist, want)

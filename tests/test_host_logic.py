@@ -257,3 +257,26 @@ def test_plbo_adam_steps_match_the_oracle():
     assert np.abs(p - pr).max() < 1e-9, (p, pr)
     with pytest.raises(P.TnError):
         P.plbo_minimize(G, p0, a, b, g, P.PlboOpts(optimizer=7))
+
+
+def test_williamson_split_matches_oracle():
+    """General split of mixed covariances (uniform loss plus thermal noise):
+    the library's pure part reproduces the oracle's Q = S S^T / 2 through
+    covariance(r, U), its factor the oracle's C; a pure V gives K = 0 and
+    its own squeezing back; an unphysical V is rejected."""
+    import paper_2410_18740_amd as P
+    import workloads as W
+    from oracle import noisy, gbs
+    for N, seed, th in ((3, 1, 0.1), (6, 2, 0.0), (10, 3, 0.3)):
+        r, U = W.make_problem(N, seed, (0.3, 1.1))
+        V = noisy.lossy_covariance(r, U, 0.7) + th * np.eye(2 * N)
+        rp, Up, L = P.noise_williamson(V)
+        Q, C = noisy.decompose_williamson(V)
+        assert np.abs(gbs.covariance(rp, Up) - Q).max() < 1e-12
+        assert np.abs(L @ L.T - C).max() < 1e-12
+        assert np.abs(Up @ Up.conj().T - np.eye(N)).max() < 1e-12
+    r, U = W.make_problem(4, 5, (0.3, 1.1))
+    rp, Up, L = P.noise_williamson(gbs.covariance(r, U))
+    assert L.shape == (8, 0) and np.abs(np.sort(rp) - np.sort(r)).max() < 1e-10
+    with pytest.raises(P.TnError):
+        P.noise_williamson(0.3 * np.eye(4))
