@@ -61,6 +61,9 @@ def parse():
                          "mode's reduced covariance, or the Fock basis")
     ap.add_argument("--plbo-mask", type=lambda x: int(x, 0), default=0xFF)
     ap.add_argument("--plbo-optimizer", default="adam", choices=["adam", "lbfgs"])
+    ap.add_argument("--plbo-linear", action="store_true",
+                    help="also run the final stage with a linear isometry over D_raw states and LBO (SM Sec. 6), "
+                         "on the Fock raw basis and on the learned pLBO bases")
     ap.add_argument("--noisy", type=float, default=None, metavar="ETA",
                     help="noisy GBS with uniform loss ETA: DMRG on the pure part, then plain and displaced sampling")
     ap.add_argument("--noisy-samples", type=int, default=8192)
@@ -532,9 +535,14 @@ def plbo_bench(a):
     ana[:, 2] = np.hypot(zeta[:, 0], zeta[:, 1])
     ana[:, 3] = np.arctan2(zeta[:, 1], zeta[:, 0])
     runs = {}
-    for name, init in (("fock", None), ("analytic", ana), ("plbo", ana if a.plbo_init == "analytic" else None)):
+    start = ana if a.plbo_init == "analytic" else None
+    plan = [("fock", None, False, False), ("analytic", ana, False, False), ("plbo", start, True, False)]
+    if a.plbo_linear:
+        plan += [("lbo", None, False, True), ("plbo_lbo", start, True, True)]
+    for name, init, with_plbo, linear in plan:
         mpo = P.MPO(ctx, r, U, w.D_raw, w.d, kappa=a.kappa)
-        P.plbo_enable(ctx, mpo, init)
+        if not (linear and not with_plbo):
+            P.plbo_enable(ctx, mpo, init)
         mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
         trace, stages = [], {}
         torch.cuda.synchronize()
@@ -542,14 +550,20 @@ def plbo_bench(a):
         for _ in range(2):
             trace.append(("dmrg_small", P.dmrg_sweep(ctx, mpo, mps, small)))
         stages["dmrg_small"] = time.perf_counter() - t0
-        if name == "plbo":
+        if with_plbo:
             t1 = time.perf_counter()
             for _ in range(a.plbo_sweeps):
                 trace.append(("plbo", P.plbo_sweep(ctx, mpo, mps, small, po)))
             stages["plbo"] = time.perf_counter() - t1
+        final = big
+        if linear:
+            if with_plbo:
+                P.plbo_linear(ctx, mpo)          # W over the first D_raw pLBO states
+            final = P.SweepOpts(chi_max=w.chi, tol=tol, krylov_max=24, max_matvecs=a.max_matvecs, precision=prec,
+                                lbo=1)
         t2 = time.perf_counter()
         for _ in range(a.final_sweeps):
-            trace.append(("dmrg_big", P.dmrg_sweep(ctx, mpo, mps, big)))
+            trace.append(("dmrg_big", P.dmrg_sweep(ctx, mpo, mps, final)))
         torch.cuda.synchronize()
         stages["dmrg_big"] = time.perf_counter() - t2
         stages["total"] = time.perf_counter() - t0
@@ -573,7 +587,8 @@ def plbo_bench(a):
             "plbo_optimizer": a.plbo_optimizer,
             "final_sweeps": a.final_sweeps, "runs": runs,
             "energy_ratio_plbo_over_fock": runs["plbo"]["energy"] / runs["fock"]["energy"],
-            "energy_ratio_plbo_over_analytic": runs["plbo"]["energy"] / runs["analytic"]["energy"]}
+            "energy_ratio_plbo_over_analytic": runs["plbo"]["energy"] / runs["analytic"]["energy"],
+            "plbo_linear": a.plbo_linear}
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -285,10 +285,22 @@ tn_status tn_plbo_minimize(int32_t d, const double* G, double a_ss, double b_ss,
                            double* params, double* energy);
 /* Switch the MPO to gate-parameterised bases with the given parameters (NULL:
  * all zero, i.e. the Fock basis) and reset the Adam moments.  From then on the
- * site operators follow the parameters, linear LBO is refused (TN_ESTATE) and
+ * site operators follow the parameters, linear LBO is refused (TN_ESTATE)
+ * until tn_plbo_linear puts an isometry on top, and
  * the Fock image of each basis (tn_mpo_isometries, observables) is recomputed
  * on demand.  TN_EINVAL on a NULL handle or non-finite parameters. */
 tn_status tn_plbo_enable(tn_mpo* mpo, const double* params);
+/* SM Sec. 6: put a linear isometry W (D_raw x d) on top of the gate-
+ * parameterised bases.  The raw basis of site i becomes U_i|m>, m < D_raw,
+ * with the pLBO operators on those D_raw states as the raw operators; W
+ * starts at the first d of them (so <H> is unchanged) and is what the LBO
+ * step of tn_dmrg_sweep / tn_plbo_sweep (opts->lbo = 1) optimises, while the
+ * pLBO steps move the parameters with W fixed (gradients through W^dag O W).
+ * Observables use the Fock image U[:D_raw, :D_raw] W.  One-way: TN_ESTATE if
+ * the MPO has no parameterised basis or the isometry is already on. */
+tn_status tn_plbo_linear(tn_mpo* mpo);
+/* W of every site, host [N][D_raw][d] complex; TN_ESTATE unless tn_plbo_linear ran. */
+tn_status tn_plbo_linear_isometries(const tn_mpo* mpo, double* W);
 /* Current parameters [N][8]; TN_ESTATE if the MPO has no parameterised basis. */
 tn_status tn_plbo_params(const tn_mpo* mpo, double* params);
 /* Slot environments and gradient at `site` in `precision`, for x = the site

@@ -147,6 +147,8 @@ def lib():
         "tn_plbo_enable": (i32, [vp, P(dbl)]),
         "tn_plbo_minimize": (i32, [i32, P(dbl), dbl, dbl, dbl, P(tn_plbo_opts), P(dbl), P(dbl)]),
         "tn_plbo_params": (i32, [vp, P(dbl)]),
+        "tn_plbo_linear": (i32, [vp]),
+        "tn_plbo_linear_isometries": (i32, [vp, P(dbl)]),
         "tn_plbo_site_gradient": (i32, [vp, vp, vp, i32, i32, P(dbl), P(dbl), P(dbl)]),
         "tn_plbo_sweep": (i32, [vp, vp, vp, P(tn_sweep_opts), P(tn_plbo_opts), P(tn_sweep_stats), P(dbl)]),
     }

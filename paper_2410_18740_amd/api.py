@@ -344,6 +344,18 @@ def plbo_enable(ctx: Context, mpo: MPO, params=None):
         ctx.check(L.lib().tn_plbo_enable(mpo.h, L.dptr(p)))
 
 
+def plbo_linear(ctx: Context, mpo: MPO):
+    """Put a linear isometry (D_raw x d, optimised by the LBO step) on top of
+    the gate-parameterised bases (SM Sec. 6)."""
+    ctx.check(L.lib().tn_plbo_linear(mpo.h))
+
+
+def plbo_linear_isometries(ctx: Context, mpo: MPO):
+    W = np.zeros((mpo.N, mpo.D_raw, mpo.d), dtype=np.complex128)
+    ctx.check(L.lib().tn_plbo_linear_isometries(mpo.h, L.dptr(W.view(np.float64))))
+    return W
+
+
 def plbo_params(ctx: Context, mpo: MPO):
     p = np.zeros((mpo.N, PLBO_NPARAM))
     ctx.check(L.lib().tn_plbo_params(mpo.h, L.dptr(p)))

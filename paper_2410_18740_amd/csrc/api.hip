@@ -450,6 +450,7 @@ static void mpo_free(tn_mpo* m) {
     dev_free(c, m->d_raw64);
     dev_free(c, m->d_raw32);
     dev_free(c, m->d_iso);
+    dev_free(c, m->d_fock);
   }
   delete m;
 }
@@ -600,8 +601,9 @@ extern "C" tn_status tn_mpo_isometries(const tn_mpo* mpo, double* iso) {
     return TN_ENOMEM;
   }
   size_t o = 0;
+  const bool lin = mpo->plbo && mpo->plbo_lin;  // the Fock image, not the linear isometry
   for (int s = 0; s < mpo->N; ++s)
-    for (auto& z : mpo->iso[s]) { iso[o++] = z.real(); iso[o++] = z.imag(); }
+    for (auto& z : (lin ? mpo->fock[s] : mpo->iso[s])) { iso[o++] = z.real(); iso[o++] = z.imag(); }
   return TN_OK;
 }
 

@@ -636,6 +636,7 @@ static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_
     for (int i = 0; i < D; ++i) Wn[(size_t)i * d + j] = cd(Zh[(size_t)i * D + j].x, Zh[(size_t)i * D + j].y) * ph;
   }
   mpo->iso[s] = Wn;
+  if (mpo->plbo) mpo->iso_stale[s] = true;  // the Fock image follows the new isometry
   // re-project the local operators and upload (ops, raw ops, isometry)
   {
     const auto& raw = mpo->raw_ops[s];
@@ -675,10 +676,40 @@ static double lbo_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, const tn_sweep_
 }
 
 // ------------------------------------------------------------------ gate-parameterised basis (Sec. III.B)
+// loc_ops[s] = W^dag raw W for every operator slot, W = iso[s] (D_raw x d)
+static void project_site(tn_mpo* mpo, int s) {
+  const int D = mpo->D_raw, d = mpo->d;
+  const auto& raw = mpo->raw_ops[s];
+  const auto& W = mpo->iso[s];
+  std::vector<cd> out((size_t)NOPS * d * d, 0.0), t((size_t)D * d);
+  for (int o = 0; o < NOPS; ++o) {
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < d; ++j) {
+        cd a = 0.0;
+        for (int k = 0; k < D; ++k) a += raw[(size_t)o * D * D + (size_t)i * D + k] * W[(size_t)k * d + j];
+        t[(size_t)i * d + j] = a;
+      }
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        cd a = 0.0;
+        for (int k = 0; k < D; ++k) a += std::conj(W[(size_t)k * d + i]) * t[(size_t)k * d + j];
+        out[(size_t)o * d * d + (size_t)i * d + j] = a;
+      }
+  }
+  mpo->loc_ops[s] = out;
+}
+
 static void plbo_set_site(tn_mpo* mpo, int s) {
   const int N = mpo->N;
   const size_t ss = (size_t)s * N + s;
-  plbo_local_ops(mpo->d, mpo->pp[s].data(), mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], mpo->loc_ops[s], nullptr);
+  if (mpo->plbo_lin) {
+    plbo_local_ops(mpo->D_raw, mpo->pp[s].data(), mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], mpo->raw_ops[s],
+                   nullptr);
+    project_site(mpo, s);
+  } else {
+    plbo_local_ops(mpo->d, mpo->pp[s].data(), mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], mpo->loc_ops[s],
+                   nullptr);
+  }
   mpo->iso_stale[s] = true;
   mpo->upload_site(s);
   mpo->version++;
@@ -689,11 +720,29 @@ static void plbo_set_site(tn_mpo* mpo, int s) {
 void plbo_sync_iso(const tn_mpo* cmpo) {
   tn_mpo* mpo = const_cast<tn_mpo*>(cmpo);
   if (!mpo->plbo) return;
-  const int levels = std::max(mpo->D_raw, mpo->d) + 192;
+  const int D = mpo->D_raw, d = mpo->d;
+  const int levels = std::max(D, d) + 192;
   for (int s = 0; s < mpo->N; ++s) {
     if (!mpo->iso_stale[s]) continue;
-    plbo_fock_isometry(mpo->D_raw, mpo->d, mpo->pp[s].data(), levels, mpo->iso[s]);
-    mpo->upload_site(s);
+    if (mpo->plbo_lin) {
+      // Fock image of the raw basis (D x D) times the linear isometry W
+      std::vector<cd> full;
+      plbo_fock_isometry(D, D, mpo->pp[s].data(), levels, full);
+      auto& F = mpo->fock[s];
+      F.assign((size_t)D * d, 0.0);
+      for (int i = 0; i < D; ++i)
+        for (int j = 0; j < d; ++j) {
+          cd a = 0.0;
+          for (int k = 0; k < D; ++k) a += full[(size_t)i * D + k] * mpo->iso[s][(size_t)k * d + j];
+          F[(size_t)i * d + j] = a;
+        }
+      std::vector<cf64> h(F.size());
+      for (size_t i = 0; i < F.size(); ++i) h[i] = make_double2(F[i].real(), F[i].imag());
+      HIPCHK(hipMemcpy(mpo->d_fock + (size_t)s * D * d, h.data(), h.size() * sizeof(cf64), hipMemcpyHostToDevice));
+    } else {
+      plbo_fock_isometry(D, d, mpo->pp[s].data(), levels, mpo->iso[s]);
+      mpo->upload_site(s);
+    }
     mpo->iso_stale[s] = false;
   }
 }
@@ -754,7 +803,12 @@ static void plbo_slot_envs(tn_ctx* c, const tn_mpo* mpo, tn_mps* m, int s, int p
 
 static PlboSite plbo_site_of(const tn_mpo* mpo, int s, const std::vector<cd>& G) {
   const size_t ss = (size_t)s * mpo->N + s;
-  return PlboSite{mpo->d, mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], &G};
+  PlboSite S{mpo->d, mpo->alpha[ss], mpo->beta[ss], mpo->gamma[ss], &G};
+  if (mpo->plbo_lin) {
+    S.D = mpo->D_raw;
+    S.W = &mpo->iso[s];
+  }
+  return S;
 }
 
 struct PlboStep {
@@ -914,7 +968,7 @@ static double energy_fp64(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double*
 // workspace budget.
 static void product_ops(const tn_mpo* mpo, int s, std::vector<cd>& Q) {
   const int D = mpo->D_raw, d = mpo->d;
-  if (mpo->plbo) {
+  if (mpo->plbo && !mpo->plbo_lin) {
     // gate-parameterised basis: O_a O_b of the exact operator blocks at d + 8
     // levels (O_b moves a state below d by at most four levels, so every
     // intermediate state is inside), truncated to d
@@ -1051,7 +1105,8 @@ static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o
   tn_sweep_stats S{};
   S.energy = NAN;
   if (m->N < 2) TN_THROW(TN_EINVAL, "a sweep needs N >= 2");
-  if (o.lbo && mpo->plbo) TN_THROW(TN_ESTATE, "linear LBO on an MPO with a gate-parameterised basis");
+  if (o.lbo && mpo->plbo && !mpo->plbo_lin)
+    TN_THROW(TN_ESTATE, "linear LBO on a gate-parameterised basis needs tn_plbo_linear first");
   if (m->center != 0) canonicalize(c, m);
   ensure_right_envs(m, mpo, o.precision, &S.env_flops);
   const int N = m->N;
@@ -1397,4 +1452,31 @@ extern "C" tn_status tn_plbo_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_s
   sweep_impl(c, mpo, m, *o, out, po, &g);
   if (gain) *gain = g;
   TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_plbo_linear(tn_mpo* mpo) {
+  if (!mpo) return TN_EINVAL;
+  tn_ctx* c = mpo->ctx;
+  TN_GUARD_BEGIN
+  if (!mpo->plbo) TN_THROW(TN_ESTATE, "the MPO has no gate-parameterised basis");
+  if (mpo->plbo_lin) TN_THROW(TN_ESTATE, "the linear isometry is already on");
+  const int N = mpo->N, D = mpo->D_raw, d = mpo->d;
+  if (!mpo->d_fock) mpo->d_fock = (cf64*)dev_alloc(c, (size_t)N * D * d * sizeof(cf64));
+  mpo->plbo_lin = true;
+  mpo->fock.assign(N, {});
+  for (int s = 0; s < N; ++s) {
+    mpo->iso[s].assign((size_t)D * d, 0.0);
+    for (int a = 0; a < d; ++a) mpo->iso[s][(size_t)a * d + a] = 1.0;  // the first d pLBO states
+    plbo_set_site(mpo, s);
+  }
+  TN_GUARD_END(c)
+}
+
+extern "C" tn_status tn_plbo_linear_isometries(const tn_mpo* mpo, double* W) {
+  if (!mpo || !W) return TN_EINVAL;
+  if (!mpo->plbo || !mpo->plbo_lin) return TN_ESTATE;
+  size_t o = 0;
+  for (int s = 0; s < mpo->N; ++s)
+    for (auto& z : mpo->iso[s]) { W[o++] = z.real(); W[o++] = z.imag(); }
+  return TN_OK;
 }

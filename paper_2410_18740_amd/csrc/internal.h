@@ -86,6 +86,13 @@ struct tn_mpo {
   std::vector<std::array<double, TN_PLBO_NPARAM>> pp, pm, pv;  // parameters, Adam moments
   std::vector<int> pt;                                          // Adam step count per site
   std::vector<bool> iso_stale;                                  // Fock image not yet recomputed
+  // pLBO with a linear isometry on top (SM Sec. 6): raw_ops are the pLBO
+  // operators on D_raw basis states, iso the linear isometry W (D_raw x d)
+  // the LBO step optimises, and fock / d_fock the Fock image U[:D, :D] W
+  bool plbo_lin = false;
+  std::vector<std::vector<cd>> fock;
+  cf64* d_fock = nullptr;
+  const cf64* fock_iso() const { return (plbo && plbo_lin) ? d_fock : d_iso; }
   cf64* d_ops64 = nullptr;   // [N][NOPS][d][d]
   cf32* d_ops32 = nullptr;
   cf64* d_raw64 = nullptr;   // [N][NOPS][D][D]
@@ -182,6 +189,8 @@ struct PlboSite {
   int d;
   double a_ss, b_ss, g_ss;
   const std::vector<cd>* G;
+  int D = 0;                            // with W: operators built on D basis states,
+  const std::vector<cd>* W = nullptr;   // then projected, W^dag O W (W: D x d)
 };
 double plbo_site_energy(const PlboSite& S, const double* p, double* grad);
 // po.steps Adam steps (moments m, v, count t in and out) or L-BFGS iterations

@@ -419,7 +419,7 @@ extern "C" tn_status tn_rdm(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int32
       std::vector<GemmJob> jobs;
       std::vector<GemmSeg> segs;
       for (int a = 0; a < cl; ++a) {
-        segs.push_back({mpo->d_iso + (size_t)s * D * d, m->A[s] + (size_t)a * d * cr, d, cr, d, 0});
+        segs.push_back({mpo->fock_iso() + (size_t)s * D * d, m->A[s] + (size_t)a * d * cr, d, cr, d, 0});
         jobs.push_back({F + (size_t)a * D * cr, cr, D, cr, a, 1});
       }
       batch(0, 0, jobs, segs, D, cr);

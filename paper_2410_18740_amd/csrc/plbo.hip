@@ -195,12 +195,41 @@ void plbo_local_ops(int d, const double* p, double a_ss, double b_ss, double g_s
 }
 
 // ------------------------------------------------------------------ site functional and optimisers
+// W^dag O W for each d_big x d_big block of `in` (count blocks) -> d x d blocks
+static void project_blocks(const std::vector<cd>& in, int count, int D, const std::vector<cd>& W, int d,
+                           std::vector<cd>& out) {
+  out.assign((size_t)count * d * d, 0.0);
+  std::vector<cd> t((size_t)D * d);
+  for (int c = 0; c < count; ++c) {
+    const cd* O = in.data() + (size_t)c * D * D;
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < d; ++j) {
+        cd a = 0.0;
+        for (int k = 0; k < D; ++k) a += O[(size_t)i * D + k] * W[(size_t)k * d + j];
+        t[(size_t)i * d + j] = a;
+      }
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        cd a = 0.0;
+        for (int k = 0; k < D; ++k) a += std::conj(W[(size_t)k * d + i]) * t[(size_t)k * d + j];
+        out[((size_t)c * d + i) * d + j] = a;
+      }
+  }
+}
+
 double plbo_site_energy(const PlboSite& S, const double* p, double* grad) {
   const int d = S.d;
   const size_t dd = (size_t)d * d;
   const std::vector<cd>& G = *S.G;
   std::vector<cd> ops, dops;
-  plbo_local_ops(d, p, S.a_ss, S.b_ss, S.g_ss, ops, grad ? &dops : nullptr);
+  if (S.W) {
+    std::vector<cd> big, dbig;
+    plbo_local_ops(S.D, p, S.a_ss, S.b_ss, S.g_ss, big, grad ? &dbig : nullptr);
+    project_blocks(big, NOPS, S.D, *S.W, d, ops);
+    if (grad) project_blocks(dbig, NP * NOPS, S.D, *S.W, d, dops);
+  } else {
+    plbo_local_ops(d, p, S.a_ss, S.b_ss, S.g_ss, ops, grad ? &dops : nullptr);
+  }
   double e = 0.0;
   for (int i = 0; i < d; ++i) e += G[(size_t)i * d + i].real();
   for (int k = 1; k <= NOPS; ++k)

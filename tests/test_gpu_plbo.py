@@ -246,3 +246,68 @@ def test_plbo_slot_environments_at_the_benchmark_size(ctx):
         Gref = plbo.slot_gradients(Gf, plbo.slot_coefficients(plbo.gaussian_core_maker(al, be, ga, site), d))
         G, E, _ = P.plbo_site_gradient(ctx, m, mps, site, P.FP32)
         assert np.abs(G - Gref).max() < 2e-5 * np.abs(Gref).max(), site
+
+
+def test_plbo_with_a_linear_isometry_on_top(ctx):
+    """SM Sec. 6: after pLBO sweeps, a linear isometry W (D_raw x d) over the
+    first D_raw pLBO states starts at the first d of them (<H> unchanged),
+    LBO sweeps then lower <H>, and every reported <H> is the oracle's for site
+    operators W^dag T(p) W with T the transformed operators on D_raw states.
+    The parameter gradient goes through W; marginals use the Fock image
+    U[:D_raw, :D_raw] W."""
+    import paper_2410_18740_amd as P
+    from oracle import mps as omps
+    N, D, d, chi = 5, 6, 3, 9
+    r, U = W.make_problem(N, 14, (0.4, 0.6))
+    al, be, ga = gbs.coefficients(r, U)
+    rng = np.random.default_rng(19)
+    m = P.MPO(ctx, r, U, D, d)
+    P.plbo_enable(ctx, m)
+    mp = P.MPS(ctx, [rng.normal(size=t.shape) + 1j * rng.normal(size=t.shape) for t in _rand_mps(N, d, chi, rng)])
+    o = P.SweepOpts()
+    o.chi_max, o.tol = chi, 1e-11
+    po = P.PlboOpts(steps=15, lr=0.03, matvecs=8)
+    for _ in range(4):
+        e1 = P.plbo_sweep(ctx, m, mp, o, po)["energy"]
+    P.plbo_linear(ctx, m)
+    assert abs(P.energy(ctx, m, mp)[0] - e1) < 1e-10 * max(1.0, abs(e1))
+
+    def oracle_energy():
+        p = P.plbo_params(ctx, m)
+        Wl = P.plbo_linear_isometries(ctx, m)
+        ops = []
+        for s in range(N):
+            T = plbo.transformed_ops(p[s], D, al[s, s], be[s, s], ga[s, s])
+            ops.append(tuple(Wl[s].conj().T @ t @ Wl[s] for t in T[:3]))
+        return odmrg.energy(mp.export(), ompo.cores(al, be, ga, ops)), p, Wl
+
+    o.lbo = 1
+    for _ in range(3):
+        e2 = P.dmrg_sweep(ctx, m, mp, o)["energy"]
+    assert e2 < e1 - 1e-6, (e1, e2)
+    eo, p, Wl = oracle_energy()
+    assert abs(eo - e2) < 1e-9 * max(1.0, abs(e2))
+    for _ in range(2):
+        e3 = P.plbo_sweep(ctx, m, mp, o, po)["energy"]
+    eo, p, Wl = oracle_energy()
+    assert abs(eo - e3) < 1e-9 * max(1.0, abs(e3))
+    assert e3 <= e2 + 1e-6
+    # gradient through W at site 0 (the centre after a sweep)
+    G, E, g = P.plbo_site_gradient(ctx, m, mp, 0, P.FP64)
+    def f(q):
+        T = plbo.transformed_ops(q, D, al[0, 0], be[0, 0], ga[0, 0], L=120)
+        return plbo.site_energy(G, [Wl[0].conj().T @ t @ Wl[0] for t in T])
+    h = 2e-4
+    for j in (2, 3, 5):
+        e = np.zeros(8)
+        e[j] = h
+        fd = (-f(p[0] + 2 * e) + 8 * f(p[0] + e) - 8 * f(p[0] - e) + f(p[0] - 2 * e)) / (12 * h)
+        assert abs(fd - g[j]) < 1e-7 * max(1.0, abs(fd)), (j, fd, g[j])
+    # the Fock image exported for observables is U[:D_raw, :D_raw] W
+    F = [plbo.fock_isometry(p[s], D, D) @ Wl[s] for s in range(N)]
+    assert np.abs(m.isometries() - np.stack(F)).max() < 1e-10
+    # marginals through it (the kept bases carry a little weight beyond the
+    # D_raw Fock levels, which the two normalisations treat differently)
+    marg = P.marginals(ctx, mp, m)
+    ref = omps.marginals(mp.export(), F)
+    assert np.abs(marg - ref).max() < 5e-3
