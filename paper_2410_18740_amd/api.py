@@ -25,7 +25,10 @@ class Context:
     """A library context on one GPU, enqueueing on torch's current stream and
     allocating through torch's caching allocator."""
 
-    def __init__(self, device: int = 0, use_torch_allocator: bool = False):
+    def __init__(self, device: int = 0, use_torch_allocator: bool = False, alloc_gate=None):
+        """alloc_gate (with use_torch_allocator): a callable taking the byte
+        count; when it returns False the allocator reports failure, which
+        lets tests drive the library's out-of-memory path from the host."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP library needs an MI355X")
@@ -39,6 +42,8 @@ class Context:
 
             @C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
             def _a(nbytes, user):
+                if alloc_gate is not None and not alloc_gate(int(nbytes)):
+                    return None
                 try:
                     return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev))
                 except Exception:

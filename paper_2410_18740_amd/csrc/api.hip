@@ -617,14 +617,19 @@ extern "C" tn_status tn_mpo_site_ops(const tn_mpo* mpo, int32_t site, double* op
 extern "C" void tn_mpo_destroy(tn_mpo* mpo) { mpo_free(mpo); }
 
 // ------------------------------------------------------------------ MPS
+// Grows site s to hold elems entries.  The new buffer is taken first and the
+// current tensor copied into it, so a failed allocation (TN_ENOMEM) leaves the
+// MPS exactly as it was.
 void tn_mps::ensure_site(int s, size_t elems) {
   if (cap[s] >= elems && A[s]) return;
+  cf64* p = (cf64*)dev_alloc(ctx, elems * sizeof(cf64));
   if (A[s]) {
+    const size_t keep = std::min(cap[s], elems);
+    HIPCHK(hipMemcpyAsync(p, A[s], keep * sizeof(cf64), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     dev_free(ctx, A[s]);
-    A[s] = nullptr;
   }
-  A[s] = (cf64*)dev_alloc(ctx, elems * sizeof(cf64));
+  A[s] = p;
   cap[s] = elems;
 }
 

@@ -493,6 +493,7 @@ static void* env_buf(tn_mps* m, bool left, int t, size_t bytes) {
     HIPCHK(hipStreamSynchronize(m->ctx->stream));
     dev_free(m->ctx, v[t]);
     v[t] = nullptr;
+    (left ? m->Lok : m->Rok)[t] = false;  // a failed reallocation must not leave a valid flag
   }
   v[t] = dev_alloc(m->ctx, bytes);
   cap[t] = bytes;

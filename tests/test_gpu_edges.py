@@ -81,3 +81,57 @@ def test_abi_rejects_bad_arguments(ctx):
         P.truncate(ctx, torch.ones((3300, 4), dtype=torch.complex128, device="cuda"), 2)
     # the context stays usable after every error
     assert np.isfinite(P.dmrg_sweep(ctx, m4, mp, ok)["energy"])
+
+
+def test_failure_paths_are_reported_and_leave_handles_usable():
+    """Error paths forced from the host: an allocator that refuses gives
+    TN_ENOMEM and the context, MPO and MPS stay usable once it allows again;
+    a matvec cap of 1 is reported as unconverged steps, never silently; a NaN
+    in a host MPS tensor is refused when the MPS is created (TN_EINVAL)."""
+    import paper_2410_18740_amd as P
+    gate = {"open": True}
+    ctx = P.Context(0, use_torch_allocator=True, alloc_gate=lambda nbytes: gate["open"])
+    try:
+        r, U = W.make_problem(6, 3, (0.4, 0.6))
+        m = P.MPO(ctx, r, U, 6)
+        mp = P.MPS(ctx, W.random_mps(6, 6, 8, 5))
+        P.dmrg_sweep(ctx, m, mp, P.SweepOpts(chi_max=8, tol=1e-10))
+        big = P.MPS(ctx, W.random_mps(6, 6, 36, 6))
+        gate["open"] = False
+        with pytest.raises(P.TnError) as ei:
+            P.dmrg_sweep(ctx, m, big, P.SweepOpts(chi_max=36, tol=1e-10))
+        assert ei.value.code == -2             # TN_ENOMEM
+        gate["open"] = True
+        e = P.dmrg_sweep(ctx, m, big, P.SweepOpts(chi_max=36, tol=1e-10))["energy"]
+        assert np.isfinite(e)
+        st = P.dmrg_sweep(ctx, m, mp, P.SweepOpts(chi_max=8, tol=1e-14, max_matvecs=1))
+        assert st["unconverged_steps"] > 0
+        t = W.random_mps(6, 6, 8, 7)
+        t[2] = t[2].copy()
+        t[2][0, 0, 0] = np.nan
+        with pytest.raises(P.TnError) as ei:
+            P.MPS(ctx, t)
+        assert ei.value.code == -1             # TN_EINVAL
+        assert np.isfinite(P.dmrg_sweep(ctx, m, mp, P.SweepOpts(chi_max=8, tol=1e-10))["energy"])
+    finally:
+        ctx.close()
+
+
+def test_checkpoint_export_and_reimport(ctx):
+    """An MPS exported after sweeps and re-created from the host copy has the
+    same FP64 <H>, and one further sweep from either reaches the same <H>."""
+    import paper_2410_18740_amd as P
+    r, U = W.make_problem(5, 8, (0.4, 0.6))
+    m = P.MPO(ctx, r, U, 6)
+    mp = P.MPS(ctx, W.random_mps(5, 6, 16, 3))
+    o = P.SweepOpts(chi_max=16, tol=1e-12)
+    for _ in range(3):
+        P.dmrg_sweep(ctx, m, mp, o)
+    copy = P.MPS(ctx, mp.export())
+    copy.canonicalize()
+    e0, _ = P.energy(ctx, m, mp)
+    e1, _ = P.energy(ctx, m, copy)
+    assert abs(e0 - e1) < 1e-12 * max(1.0, abs(e0))
+    a = P.dmrg_sweep(ctx, m, mp, o)["energy"]
+    b = P.dmrg_sweep(ctx, m, copy, o)["energy"]
+    assert abs(a - b) < 1e-9 * max(1.0, abs(a))
