@@ -133,6 +133,60 @@ def cpu_baseline(w, r, U, budget_s=15.0, kappa=0.0):
                       f"of the same workload, {dt:.1f} s"}
 
 
+def _cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_noisy(fock_tensors, Lc, budget_s=12.0):
+    """The oracle's displaced sequential sampler (expm displacement matrices)
+    on the same Fock tensors, timed on the host cores for a bounded number of
+    samples."""
+    from oracle import noisy
+    N = len(fock_tensors)
+    rng = np.random.default_rng(0)
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and n < 64:
+        z = rng.standard_normal((1, Lc.shape[1]))
+        noisy.sample_displaced(fock_tensors, noisy.alphas(z, Lc), n, L=fock_tensors[0].shape[1] + 60)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "samples/s", "cores": _cores(), "kind": "oracle",
+            "sample": f"{n} displaced samples of the same {N}-mode MPS, {dt:.1f} s"}
+
+
+def cpu_baseline_plbo(r, U, d, chi, params, budget_s=12.0):
+    """One pLBO site visit of the oracle (slot environments of a middle site
+    from dense environments, then the parameter gradient by differences),
+    timed on the host cores."""
+    from oracle import plbo, gbs, mpo as ompo, dmrg as odmrg
+    import workloads as W
+    N = len(r)
+    al, be, ga = gbs.coefficients(r, U)
+    rng = np.random.default_rng(0)
+    dims = W.bond_dims(N, d, chi)
+    t = [rng.standard_normal((dims[s], d, dims[s + 1])) + 1j * rng.standard_normal((dims[s], d, dims[s + 1]))
+         for s in range(N)]
+    t = [x / np.linalg.norm(x) for x in t]
+    site = N // 2
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and n < 8:
+        ops = [plbo.transformed_ops(params[s], d, al[s, s], be[s, s], ga[s, s], L=60) for s in range(N)]
+        Ws = ompo.cores(al, be, ga, [o[:3] for o in ops])
+        Gf = plbo.core_environment(odmrg.left_envs(t[:site], Ws[:site])[-1], t[site],
+                                   odmrg.right_envs(t[site + 1:], Ws[site + 1:])[0])
+        G = plbo.slot_gradients(Gf, plbo.slot_coefficients(plbo.gaussian_core_maker(al, be, ga, site), d))
+        plbo.param_gradient(G, params[site], d, al[site, site], be[site, site], ga[site, site], L=60)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "site visits/s", "cores": _cores(), "kind": "oracle",
+            "sample": f"{n} oracle site visits (slot environments and gradient) at site {site} of the {N}-mode "
+                      f"chain, d {d}, chi {chi}, {dt:.1f} s"}
+
+
 def copy_calibration(nbytes: int = 256 << 20, reps: int = 4):
     """A plain copy of known size (torch's elementwise negation: nbytes read,
     nbytes written) for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -588,7 +642,10 @@ def plbo_bench(a):
             "final_sweeps": a.final_sweeps, "runs": runs,
             "energy_ratio_plbo_over_fock": runs["plbo"]["energy"] / runs["fock"]["energy"],
             "energy_ratio_plbo_over_analytic": runs["plbo"]["energy"] / runs["analytic"]["energy"],
-            "plbo_linear": a.plbo_linear}
+            "plbo_linear": a.plbo_linear,
+            "gpu_site_visits_per_s": (2 * (w.N - 1) * a.plbo_sweeps) / max(1e-12, sum(runs["plbo"]["plbo_visit_seconds"]))}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_plbo(r, U, w.d, chi_s, np.zeros((w.N, 8)))
     print(json.dumps(line), flush=True)
     ctx.close()
 
@@ -668,6 +725,9 @@ def noisy_bench(a):
             "samples": n, "plain_samples_per_s": n / (t2 - t1), "displaced_samples_per_s": n / (t3 - t2),
             "sampled_total_photons": {"pure_part": [float(tot_p.mean()), float(tot_p.std())],
                                       "noisy": [float(tot_n.mean()), float(tot_n.std())]}}
+    if not a.no_cpu_baseline:
+        F = [np.einsum("nm,amb->anb", Wf, A) for Wf, A in zip(mpo.isometries(), mps.export())]
+        line["cpu_baseline"] = cpu_baseline_noisy(F, Lc)
     print(json.dumps(line), flush=True)
     ctx.close()
 
