@@ -172,3 +172,29 @@ def test_williamson_split_samples_match_a_general_mixed_state(ctx):
         hist = np.bincount(smp[:, j], minlength=D)[:D] / n
         sig = np.sqrt(want * (1 - want) / n)
         assert np.all(np.abs(hist - want) <= 5 * sig + 2 * tail + 1e-6), (j, hist, want)
+
+
+def test_displaced_samples_through_gate_parameterised_bases(ctx):
+    """The pure part solved in pLBO bases: the sampler's Fock tensors use the
+    Fock image of the learned bases, and the displaced stream equals the
+    oracle's run on U(p)[:D, :d] A_s with U(p) from the oracle's gate
+    exponentials."""
+    import paper_2410_18740_amd as P
+    from oracle import mps as omps, plbo
+    N, D, d, chi = 4, 12, 3, 9
+    r, U = W.make_problem(N, 10, (0.4, 0.6))
+    rp, Lc = P.noise_uniform_loss(r, U, 0.7)
+    _, _, Lo = noisy.decompose_uniform_loss(r, U, 0.7)
+    m = P.MPO(ctx, rp, U, D, d)
+    P.plbo_enable(ctx, m)
+    mp = P.MPS(ctx, W.random_mps(N, d, chi, 4))
+    o = P.SweepOpts()
+    o.chi_max, o.tol = chi, 1e-11
+    for _ in range(4):
+        P.plbo_sweep(ctx, m, mp, o, P.PlboOpts(steps=15, lr=0.03, matvecs=8))
+    p = P.plbo_params(ctx, m)
+    z = np.random.default_rng(2).standard_normal((200, N))
+    smp = P.sample_displaced(ctx, mp, m, 200, 9, Lc, z=z).cpu().numpy()
+    F = omps.fock_tensors(mp.export(), [plbo.fock_isometry(p[s], D, d) for s in range(N)])
+    ref = noisy.sample_displaced(F, noisy.alphas(z, Lo), 9, L=D + 60)
+    assert np.mean(np.any(smp != ref, axis=1)) < 0.01
