@@ -701,6 +701,8 @@ def noisy_bench(a):
         s = P.dmrg_sweep(ctx, mpo, mps, opts)
         print(f"pure-part sweep {i}: <H> = {s['energy']:.6e}", file=sys.stderr, flush=True)
     t_dmrg = time.perf_counter() - t0
+    if a.copy_calibration:
+        copy_calibration()
     n = a.noisy_samples
     g = torch.Generator(device="cuda:0")
     g.manual_seed(11)
