@@ -3,7 +3,7 @@ squeezed modes, r ~ U[1.0, 1.5], cutoff 12 compressed to a 3-dim local
 basis): training data from plain DMRG + LBO runs, the MLP trained by the
 library's kernels, and what the trained network gains over the method
 without it -- the learned local bases against the first Fock states at a fixed
-basis -- plus the <H> judge and its fallback."""
+basis -- plus the <H> check that keeps or drops the learned start."""
 import math
 
 import numpy as np
