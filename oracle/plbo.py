@@ -220,3 +220,16 @@ def minimize_site(G, p0, d: int, a_ss: float, b_ss: float, g_ss: float, mask, L:
     jac = lambda x: param_gradient(G, full(x), d, a_ss, b_ss, g_ss, L, which=free)[free]
     res = so.minimize(f, p0[free], jac=jac, method="L-BFGS-B", options={"maxiter": 100, "ftol": 1e-15, "gtol": 1e-8})
     return full(res.x), float(res.fun)
+
+
+def effective_cutoff(p, d: int, D_max: int, tol: float, L: int = 200) -> int:
+    """Effective cutoff of a pLBO basis (Sec. III.A, eq. Effectivecutoff, as
+    used for the pLBO bases of the paper's pLBO figure): the smallest D in
+    [d, D_max] at which the first d basis vectors U|m>, cut to D Fock rows,
+    are orthonormal within tol; -1 if none."""
+    V = fock_isometry(p, D_max, d, L=max(L, D_max + 64))
+    for D in range(d, D_max + 1):
+        Vd = V[:D]
+        if np.abs(Vd.conj().T @ Vd - np.eye(d)).max() <= tol:
+            return D
+    return -1

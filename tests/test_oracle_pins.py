@@ -1070,3 +1070,20 @@ def test_pure_state_parameters_invert_the_covariance():
         assert np.abs(gbs.covariance(r, U) - Q).max() < 1e-12
         assert np.abs(U @ U.conj().T - np.eye(len(r0))).max() < 1e-12
         assert np.abs(np.sort(r) - np.sort(r0)).max() < 1e-10
+
+
+def test_plbo_effective_cutoff_special_cases():
+    """The pLBO basis's effective cutoff: the Fock basis (p = 0) needs exactly
+    d levels; a pure squeeze S(r e^{i phi}) gives the squeezed basis's
+    effective cutoff of the analytic-basis report (cutoff.effective_cutoff,
+    built independently); a displacement needs more levels than no
+    displacement."""
+    from oracle import plbo, cutoff
+    assert plbo.effective_cutoff(np.zeros(8), 5, 60, 1e-10) == 5
+    for r, phi in ((0.5, 0.0), (0.8, 1.1)):
+        p = np.zeros(8)
+        p[2], p[3] = r, phi
+        assert plbo.effective_cutoff(p, 4, 120, 1e-10) == cutoff.effective_cutoff(r * np.exp(1j * phi), 4, 120, 1e-10)
+    q = np.zeros(8)
+    q[0] = 0.5
+    assert plbo.effective_cutoff(q, 4, 120, 1e-10) > 4
