@@ -632,6 +632,10 @@ def plbo_bench(a):
             p = P.plbo_params(ctx, mpo)
             res["params_abs_max"] = dict(zip(("alpha_x", "alpha_p", "r", "phi", "theta", "s", "gamma", "kappa"),
                                              np.abs(p).max(axis=0).round(4).tolist()))
+            # effective cutoff of the learned bases (eq. Effectivecutoff, tol 1e-10)
+            de = np.array([P.plbo_effective_cutoff(w.d, p[s_], 512, 1e-10) for s_ in range(w.N)])
+            res["effective_cutoff"] = {"min": int(de.min()), "median": float(np.median(de)), "max": int(de.max()),
+                                       "d": w.d, "tol": 1e-10}
         runs[name] = res
         print(f"{name}: <H> = {res['energy']:.6e} stages {', '.join(f'{k} {v:.2f}s' for k, v in stages.items())}",
               file=sys.stderr, flush=True)

@@ -276,6 +276,12 @@ tn_status tn_plbo_ops(int32_t d, const double* params, double a_ss, double b_ss,
  * series over sub-steps of unit norm), then cut to D rows.  TN_EINVAL on
  * d < 1, D < d, D > 4096, levels outside [D, 8192] or non-finite params. */
 tn_status tn_plbo_fock_isometry(int32_t D, int32_t d, const double* params, int32_t levels, double* iso);
+/* Host only.  Effective cutoff of the basis of params (Sec. III.A, eq.
+ * Effectivecutoff): *D_eff = the smallest D <= D_max at which the first d
+ * basis vectors, cut to D Fock rows, are orthonormal within tol
+ * (max |V^dag V - 1|), or -1 if none.  TN_EINVAL on d < 1, D_max outside
+ * [d, 4096], tol <= 0 or non-finite params. */
+tn_status tn_plbo_effective_cutoff(int32_t d, const double* params, int32_t D_max, double tol, int32_t* D_eff);
 /* Host only, no GPU work.  Runs opts' optimiser on the energy of one site as a
  * function of its parameters with the slot environments G (host [6][d][d]
  * complex, as from tn_plbo_site_gradient) held fixed: params (8, in/out) from

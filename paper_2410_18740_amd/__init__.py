@@ -7,7 +7,7 @@ from .api import (Context, MPO, MPS, SweepOpts, dmrg_sweep, dmrg_solve, energy, 
                   heff_apply, env_update, truncate, cgemm, philox4x32_10, matvec_flops, env_flops, rdm,
                   squeezed_basis, MLP, ws_features, ws_targets, ws_initial_state, ws_gaussian_params, cutoff_report,
                   noise_uniform_loss, noise_williamson, sample_displaced,
-                  PlboOpts, PLBO_ADAM, PLBO_LBFGS, plbo_ops, plbo_minimize, plbo_fock_isometry, plbo_enable, plbo_linear, plbo_linear_isometries, plbo_params, plbo_site_gradient, plbo_sweep,
+                  PlboOpts, PLBO_ADAM, PLBO_LBFGS, plbo_ops, plbo_minimize, plbo_fock_isometry, plbo_effective_cutoff, plbo_enable, plbo_linear, plbo_linear_isometries, plbo_params, plbo_site_gradient, plbo_sweep,
                   FP64, FP32, BF16X3)
 from ._lib import TnError, LIB_PATH
 
@@ -15,5 +15,5 @@ __all__ = ["Context", "MPO", "MPS", "SweepOpts", "dmrg_sweep", "dmrg_solve", "en
            "sample", "heff_apply", "env_update", "truncate", "cgemm", "philox4x32_10", "matvec_flops",
            "env_flops", "rdm", "squeezed_basis", "MLP", "ws_features", "ws_targets", "ws_initial_state", "ws_gaussian_params", "cutoff_report",
            "noise_uniform_loss", "noise_williamson", "sample_displaced",
-           "PlboOpts", "PLBO_ADAM", "PLBO_LBFGS", "plbo_ops", "plbo_minimize", "plbo_fock_isometry", "plbo_enable", "plbo_linear", "plbo_linear_isometries", "plbo_params", "plbo_site_gradient", "plbo_sweep",
+           "PlboOpts", "PLBO_ADAM", "PLBO_LBFGS", "plbo_ops", "plbo_minimize", "plbo_fock_isometry", "plbo_effective_cutoff", "plbo_enable", "plbo_linear", "plbo_linear_isometries", "plbo_params", "plbo_site_gradient", "plbo_sweep",
            "FP64", "FP32", "BF16X3", "TnError", "LIB_PATH"]

@@ -144,6 +144,7 @@ def lib():
         "tn_noise_williamson": (i32, [i32, P(dbl), P(dbl), P(dbl), P(dbl), P(i32)]),
         "tn_plbo_ops": (i32, [i32, P(dbl), dbl, dbl, dbl, P(dbl), P(dbl)]),
         "tn_plbo_fock_isometry": (i32, [i32, i32, P(dbl), i32, P(dbl)]),
+        "tn_plbo_effective_cutoff": (i32, [i32, P(dbl), i32, dbl, P(i32)]),
         "tn_plbo_enable": (i32, [vp, P(dbl)]),
         "tn_plbo_minimize": (i32, [i32, P(dbl), dbl, dbl, dbl, P(tn_plbo_opts), P(dbl), P(dbl)]),
         "tn_plbo_params": (i32, [vp, P(dbl)]),

@@ -340,6 +340,17 @@ def plbo_minimize(G, params, a_ss: float, b_ss: float, g_ss: float, opts: PlboOp
     return p, e.value
 
 
+def plbo_effective_cutoff(d: int, params, D_max: int = 256, tol: float = 1e-10) -> int:
+    """Smallest Fock cutoff at which the first d pLBO basis vectors are
+    orthonormal within tol (-1 if none up to D_max)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    out = C.c_int32()
+    st = L.lib().tn_plbo_effective_cutoff(d, L.dptr(p), D_max, tol, C.byref(out))
+    if st != L.TN_OK:
+        raise TnError(st, "tn_plbo_effective_cutoff: bad arguments")
+    return out.value
+
+
 def plbo_enable(ctx: Context, mpo: MPO, params=None):
     """Switch mpo to gate-parameterised bases ([N][8] parameters, None: zeros)."""
     if params is None:

@@ -588,3 +588,34 @@ extern "C" tn_status tn_plbo_minimize(int32_t d, const double* G, double a_ss, d
   }
   return TN_OK;
 }
+
+// Effective cutoff of the basis (eq. Effectivecutoff): the smallest D at which
+// the first d basis vectors, cut to D Fock rows, are orthonormal within tol.
+extern "C" tn_status tn_plbo_effective_cutoff(int32_t d, const double* params, int32_t D_max, double tol,
+                                              int32_t* D_eff) {
+  if (d < 1 || D_max < d || D_max > 4096 || !params || !D_eff || !(tol > 0.0)) return TN_EINVAL;
+  for (int j = 0; j < NP; ++j)
+    if (!std::isfinite(params[j])) return TN_EINVAL;
+  try {
+    std::vector<cd> W;
+    plbo_fock_isometry(D_max, d, params, D_max + 192, W);
+    std::vector<cd> G((size_t)d * d, 0.0);
+    *D_eff = -1;
+    for (int D = 1; D <= D_max; ++D) {
+      const cd* row = W.data() + (size_t)(D - 1) * d;
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) G[(size_t)i * d + j] += std::conj(row[i]) * row[j];
+      if (D < d) continue;
+      double dev = 0.0;
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) dev = std::max(dev, std::abs(G[(size_t)i * d + j] - (i == j ? 1.0 : 0.0)));
+      if (dev <= tol) {
+        *D_eff = D;
+        break;
+      }
+    }
+  } catch (...) {
+    return TN_ENOMEM;
+  }
+  return TN_OK;
+}

@@ -280,3 +280,18 @@ def test_williamson_split_matches_oracle():
     assert L.shape == (8, 0) and np.abs(np.sort(rp) - np.sort(r)).max() < 1e-10
     with pytest.raises(P.TnError):
         P.noise_williamson(0.3 * np.eye(4))
+
+
+def test_plbo_effective_cutoff_matches_oracle():
+    """Effective cutoff of pLBO bases: library (banded Taylor exponentials)
+    against the oracle (dense expm), for the Fock basis, squeezes and
+    composite parameters."""
+    import paper_2410_18740_amd as P
+    from oracle import plbo
+    rng = np.random.default_rng(31)
+    cases = [np.zeros(8), np.array([0, 0, 0.6, 0.4, 0, 0, 0, 0])] + [_plbo_params(rng) for _ in range(3)]
+    for p in cases:
+        for d in (1, 4):
+            assert P.plbo_effective_cutoff(d, p, 120, 1e-10) == plbo.effective_cutoff(p, d, 120, 1e-10), (d, p)
+    with pytest.raises(P.TnError):
+        P.plbo_effective_cutoff(4, np.zeros(8), 3)
