@@ -320,6 +320,116 @@ def test_lanczos_matches_eigh():
     assert np.linalg.norm(A @ x - lam * x) < 1e-10
 
 
+def _haar_isometry(m, k, rng):
+    Z = rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k))
+    Q, R = np.linalg.qr(Z)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))[None, :]
+
+
+def test_truncation_keeps_the_known_singular_values():
+    """theta = V1 diag(sigma) V2^dag with chosen sigma (Sec. II.C truncation):
+    the kept values are sigma[:chi] renormalised, the discarded weight is
+    sum sigma[chi:]^2 / sum sigma^2, and by Eckart-Young the kept factors
+    rebuild the best rank-chi approximation, whose squared error is exactly
+    the discarded sum; a relative cut sigma_cut keeps the values above
+    sigma_cut * sigma_0, and at least one."""
+    rng = np.random.default_rng(21)
+    cl, d, cr = 5, 3, 4
+    m, n = cl * d, d * cr
+    sigma = np.sort(rng.uniform(0.05, 2.0, 12))[::-1]
+    V1, V2 = _haar_isometry(m, 12, rng), _haar_isometry(n, 12, rng)
+    M0 = (V1 * sigma) @ V2.conj().T
+    theta = M0.reshape(cl, d, d, cr)
+    tot = float(np.sum(sigma ** 2))
+    for chi in (1, 5, 12, 20):
+        U, S, Vh, disc = dmrg.truncate(theta, chi)
+        k = min(chi, 12)
+        assert len(S) == k
+        kept = sigma[:k]
+        assert np.abs(S - kept / np.linalg.norm(kept)).max() < 1e-12
+        assert abs(disc - float(np.sum(sigma[k:] ** 2)) / tot) < 1e-13
+        assert np.abs(U.conj().T @ U - np.eye(k)).max() < 1e-12
+        assert np.abs(Vh @ Vh.conj().T - np.eye(k)).max() < 1e-12
+        err = np.linalg.norm(M0 - (U * (S * np.linalg.norm(kept))) @ Vh) ** 2
+        assert abs(err - float(np.sum(sigma[k:] ** 2))) < 1e-11
+    cut = 0.5 * (sigma[3] + sigma[4]) / sigma[0]
+    assert len(dmrg.truncate(theta, 12, sigma_cut=cut)[1]) == 4
+    assert len(dmrg.truncate(theta, 12, sigma_cut=2.0)[1]) == 1
+
+
+def test_two_site_matvec_matches_brute_force_loops():
+    """eq. of the two-site effective Hamiltonian: theta' = L W1 W2 R theta,
+    each output element summed by explicit loops over every index on a tiny
+    case with all dimensions distinct, so a transposed or swapped leg fails;
+    with Hermitian L, R (in their bra/ket legs) and W (in s, s') the map is
+    Hermitian."""
+    rng = np.random.default_rng(5)
+    a, wl, wm, wr, d, b = 2, 3, 2, 4, 3, 2
+    c = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    L, W1, W2, R, th = c(wl, a, a), c(wl, wm, d, d), c(wm, wr, d, d), c(wr, b, b), c(a, d, d, b)
+    got = dmrg.heff_matvec(L, W1, W2, R, th)
+    want = np.zeros((a, d, d, b), dtype=np.complex128)
+    for i in range(a):
+        for s in range(d):
+            for t in range(d):
+                for j in range(b):
+                    acc = 0j
+                    for l in range(wl):
+                        for m_ in range(wm):
+                            for n_ in range(wr):
+                                for i2 in range(a):
+                                    for s2 in range(d):
+                                        for t2 in range(d):
+                                            for j2 in range(b):
+                                                acc += (L[l, i, i2] * W1[l, m_, s, s2] * W2[m_, n_, t, t2]
+                                                        * R[n_, j, j2] * th[i2, s2, t2, j2])
+                    want[i, s, t, j] = acc
+    assert np.abs(got - want).max() < 1e-12
+    # single-site form: L W1 R1 on A, with R1 on W1's right bond
+    A, R1 = c(a, d, b), R[:wm]
+    want1 = np.zeros((a, d, b), dtype=np.complex128)
+    for i, s, j in np.ndindex(a, d, b):
+        want1[i, s, j] = sum(L[l, i, i2] * W1[l, m_, s, s2] * R1[m_, j, j2] * A[i2, s2, j2]
+                             for l in range(wl) for m_ in range(wm)
+                             for i2 in range(a) for s2 in range(d) for j2 in range(b))
+    assert np.abs(dmrg.heff_matvec_single(L, W1, R1, A) - want1).max() < 1e-12
+    herm = lambda X: X + np.conj(np.swapaxes(X, -1, -2))
+    L, W1, W2, R = herm(L), herm(W1), herm(W2), herm(R)
+    n = a * d * d * b
+    H = np.stack([dmrg.heff_matvec(L, W1, W2, R, e.reshape(a, d, d, b)).ravel() for e in np.eye(n)], axis=1)
+    assert np.abs(H - H.conj().T).max() < 1e-12
+
+
+def test_environment_updates_match_brute_force_loops():
+    """Left and right environment updates (Sec. II.C sweeps): every element
+    summed by explicit loops over the bra site tensor conj(A), the MPO core W
+    and the ket A, all dimensions distinct; contracting a left environment
+    with the right one of the same bond gives the same number at any bond."""
+    rng = np.random.default_rng(6)
+    a, wl, wr, d, b = 2, 3, 4, 3, 5
+    c = lambda *s: rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    L, R, W, A = c(wl, a, a), c(wr, b, b), c(wl, wr, d, d), c(a, d, b)
+    wantL = np.zeros((wr, b, b), dtype=np.complex128)
+    for m_, j, j2 in np.ndindex(wr, b, b):
+        wantL[m_, j, j2] = sum(np.conj(A[i, s, j]) * L[l, i, i2] * W[l, m_, s, s2] * A[i2, s2, j2]
+                               for l in range(wl) for i in range(a) for i2 in range(a)
+                               for s in range(d) for s2 in range(d))
+    assert np.abs(dmrg.env_left_update(L, A, W) - wantL).max() < 1e-12
+    wantR = np.zeros((wl, a, a), dtype=np.complex128)
+    for l, i, i2 in np.ndindex(wl, a, a):
+        wantR[l, i, i2] = sum(np.conj(A[i, s, j]) * W[l, n_, s, s2] * R[n_, j, j2] * A[i2, s2, j2]
+                              for n_ in range(wr) for j in range(b) for j2 in range(b)
+                              for s in range(d) for s2 in range(d))
+    assert np.abs(dmrg.env_right_update(R, A, W) - wantR).max() < 1e-12
+    # <L_s, R_s> is the same scalar at every bond s of a chain
+    N, dd, chi = 4, 3, 3
+    mps_ = [c(1 if s == 0 else chi, dd, 1 if s == N - 1 else chi) for s in range(N)]
+    Ws = [c(1 if s == 0 else 2, 1 if s == N - 1 else 2, dd, dd) for s in range(N)]
+    Ls, Rs = dmrg.left_envs(mps_, Ws), dmrg.right_envs(mps_, Ws)
+    vals = [np.sum(Ls[s] * Rs[s]) for s in range(N + 1)]
+    assert max(abs(v - vals[0]) for v in vals) < 1e-10 * abs(vals[0])
+
+
 # --------------------------------------------------------------- flops
 def test_flop_formula_counts_naive_contraction():
     """The matvec formula equals the multiply-adds of the naive 4-stage
