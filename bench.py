@@ -72,6 +72,10 @@ def parse():
                          "decomposition of the lossy covariance")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB copy before the timed sweeps (PMC counter scaling)")
+    ap.add_argument("--peak", action="store_true",
+                    help="GEMM microbenchmark: the library's complex GEMM in each form and torch's real GEMMs "
+                         "at large square sizes, against the published matrix-core peaks")
+    ap.add_argument("--peak-n", type=int, default=4096, help="--peak: size of the square complex GEMM")
     ap.add_argument("--cutoff-report", action="store_true",
                     help="cutoff errors of the Gaussian optimal basis for every named workload (host only)")
     ap.add_argument("--warmstart", action="store_true",
@@ -186,6 +190,95 @@ def cpu_baseline_plbo(r, U, d, chi, params, budget_s=12.0):
     return {"value": n / dt, "unit": "site visits/s", "cores": _cores(), "kind": "oracle",
             "sample": f"{n} oracle site visits (slot environments and gradient) at site {site} of the {N}-mode "
                       f"chain, d {d}, chi {chi}, {dt:.1f} s"}
+
+
+def _host_info():
+    """CPU model (from /proc/cpuinfo) and the BLAS numpy is built with."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cfg = np.show_config(mode="dicts")
+        blas = cfg["Build Dependencies"]["blas"]
+        info["blas"] = f"{blas.get('name', '?')} {blas.get('version', '')}".strip()
+    except Exception:
+        pass
+    info["nproc"] = os.cpu_count()
+    return info
+
+
+def _gpu_info():
+    """Device name, compute units and the current clock levels (rocm-smi)."""
+    import subprocess
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    info = {"name": pr.name, "compute_units": pr.multi_processor_count}
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
+        cards = json.loads(out.stdout)
+        first = cards[sorted(cards)[0]]
+        info["clocks"] = {k: v for k, v in first.items() if "clk" in k.lower()}
+    except Exception:
+        info["clocks"] = None
+    return info
+
+
+def peak_bench(a):
+    """Achievable matrix-core rates at large square sizes: the library's
+    complex GEMM (tn_cgemm) in each form, algorithmic flops 8 n^3, and torch's
+    real GEMMs (2 n^3) as the vendor library's reference, each timed with
+    events over a few launches after a warm-up."""
+    import torch
+    import paper_2410_18740_amd as P
+    torch.backends.cuda.matmul.allow_tf32 = False
+    ctx = P.Context(0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    n, reps = a.peak_n, 5
+    out = {"metric": "matrix-core GEMM rate", "unit": "TFLOP/s", "n_gpus": 1, "rows": {}}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    for form, prec in FORMS.items():
+        dt = torch.complex128 if prec == 0 else torch.complex64
+        A = torch.randn((n, n), dtype=dt, device="cuda", generator=g)
+        B = torch.randn((n, n), dtype=dt, device="cuda", generator=g)
+        t = timed(lambda: P.cgemm(ctx, A, B, prec))
+        rate = 8.0 * n ** 3 / t / 1e12
+        out["rows"][f"tn_cgemm_{form}"] = {"n": n, "s": t, "tflops": rate, "published_peak": PEAKS[form],
+                                           "frac": rate / PEAKS[form]}
+        print(f"tn_cgemm {form} n={n}: {rate:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        del A, B
+        torch.cuda.empty_cache()
+    m = 2 * n
+    for name, dt, peak in (("fp32", torch.float32, 157.3), ("fp64", torch.float64, 78.6),
+                           ("bf16", torch.bfloat16, 2500.0)):
+        X = torch.randn((m, m), dtype=dt, device="cuda", generator=g)
+        Y = torch.randn((m, m), dtype=dt, device="cuda", generator=g)
+        t = timed(lambda: torch.matmul(X, Y))
+        rate = 2.0 * m ** 3 / t / 1e12
+        out["rows"][f"torch_matmul_{name}"] = {"n": m, "s": t, "tflops": rate, "published_peak": peak,
+                                               "frac": rate / peak}
+        print(f"torch.matmul {name} n={m}: {rate:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        del X, Y
+        torch.cuda.empty_cache()
+    out["gpu"] = _gpu_info()
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def copy_calibration(nbytes: int = 256 << 20, reps: int = 4):
@@ -765,6 +858,12 @@ def main():
     if a.cutoff_report:
         cutoff_report_all()
         return
+    if a.peak:
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        peak_bench(a)
+        return
     if a.warmstart:
         if a.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
@@ -880,6 +979,16 @@ def main():
         "gemm_algorithmic_bytes_per_launch": (pr["bytes_l"] + pr["bytes_r"]) / max(1, launches),
         "matvec_phase_ms": {k: pr[k] / max(1, pr["matvecs"]) for k in
                             ("ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce")},
+        # FP64 truncation: implementation flops of its dense stages (Gram GEMM,
+        # tridiagonalisation of the full trailing block, back-transform, second
+        # factor; bisection and inverse iteration not counted), kept out of value
+        "truncation": {
+            "implementation_gflop_per_sweep": sum(s["svd_flops"] for s in stats) / a.steps / 1e9,
+            "fp64_tflops": sum(s["svd_flops"] for s in stats) / max(1e-9, sum(s["t_svd"] for s in stats)) / 1e12,
+            "fp64_peak": PEAKS["fp64"],
+            "share_of_sweep": sum(s["t_svd"] for s in stats) / wall,
+        },
+        "gpu": _gpu_info(),
     }
     if a.compare:
         for f, p in FORMS.items():
@@ -911,6 +1020,7 @@ def main():
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r, U, kappa=a.kappa)
+        out["cpu_baseline"].update(_host_info())
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -170,6 +170,10 @@ typedef struct {
   double heff_flops;           /* algorithmic flops of all two-site matvecs */
   double env_flops;            /* algorithmic flops of all environment updates */
   double t_heff, t_lanczos, t_svd, t_env, t_lbo, t_energy, t_total; /* seconds */
+  double svd_flops;            /* implementation flops of the truncations' dense stages:
+                                  Gram GEMM, Householder tridiagonalisation of the full
+                                  trailing block, back-transform and second factor
+                                  (bisection, inverse iteration and Jacobi not counted) */
 } tn_sweep_stats;
 
 tn_status tn_dmrg_sweep(tn_ctx* ctx, tn_mpo* mpo, tn_mps* mps, const tn_sweep_opts* opts, tn_sweep_stats* out);

@@ -52,7 +52,7 @@ class tn_sweep_stats(C.Structure):
                 ("heff_flops", C.c_double), ("env_flops", C.c_double),
                 ("t_heff", C.c_double), ("t_lanczos", C.c_double), ("t_svd", C.c_double),
                 ("t_env", C.c_double), ("t_lbo", C.c_double), ("t_energy", C.c_double),
-                ("t_total", C.c_double)]
+                ("t_total", C.c_double), ("svd_flops", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}

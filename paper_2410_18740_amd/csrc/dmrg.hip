@@ -212,6 +212,7 @@ static double matvec_unit(int prec) {
 struct TruncOut {
   int k = 0;
   double disc = 0.0;
+  double flops = 0.0;  // implementation flops of the dense stages (see truncate_dev)
   std::vector<double> sv;
 };
 
@@ -300,6 +301,19 @@ static TruncOut truncate_dev(tn_ctx* c, int m, int n, const cf64* theta, int chi
   cf64* Z = nullptr;
   int ldz = 0;
   herm_top(c, G, p, kk, ev, Z, ldz);
+  // implementation flops of the dense stages as this path performs them (real
+  // flops, complex multiply-add = 8): the Gram GEMM (8 p^2 q, q the other
+  // side), the tridiagonalisation (24 r^2 for the column with r trailing rows:
+  // the rank-2 update of the whole trailing block and the product with the
+  // reflector), the back-transform (16 r per reflector and eigenvector) and the
+  // second factor (8 k p q).  Bisection, inverse iteration and the Jacobi route
+  // (p <= 32) are not counted.
+  {
+    const double pd = p, qd = dir > 0 ? n : m, kd = kk;
+    double f = 8.0 * pd * pd * qd + 8.0 * kd * pd * qd;
+    if (p > 32) f += 24.0 * (pd - 1.0) * pd * (2.0 * pd - 1.0) / 6.0 + 8.0 * kd * pd * (pd - 1.0);
+    out.flops = f;
+  }
   int k = kk;
   if (sigma_cut > 0.0) {
     int cnt = 0;
@@ -863,7 +877,7 @@ static void check_plbo_opts(const tn_plbo_opts* po) {
 
 // ------------------------------------------------------------------ one two-site update
 struct StepStats {
-  double disc = 0, lam = 0, t_heff = 0, t_lz = 0, t_svd = 0, t_env = 0, heff_flops = 0, env_flops = 0;
+  double disc = 0, lam = 0, t_heff = 0, t_lz = 0, t_svd = 0, t_env = 0, heff_flops = 0, env_flops = 0, svd_flops = 0;
   int64_t mv = 0;
   bool conv = true;
 };
@@ -899,6 +913,7 @@ static StepStats two_site(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int s, int dir, con
   TruncOut t = truncate_dev(c, mm, nn, th, o.chi_max, o.sigma_cut, dir, left, right);
   const double t2 = wall();
   S.t_svd = t2 - t1;
+  S.svd_flops = t.flops;
   S.disc = t.disc;
   const int k = t.k;
   m->ensure_site(s, (size_t)mm * k);
@@ -1121,6 +1136,7 @@ static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o
     S.t_heff += t.t_heff;
     S.t_lanczos += t.t_lz;
     S.t_svd += t.t_svd;
+    S.svd_flops += t.svd_flops;
     S.t_env += t.t_env;
     S.last_eigenvalue = t.lam;
   };

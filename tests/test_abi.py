@@ -42,3 +42,36 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
         assert "no CPU fallback" in str(e)
     else:
         raise AssertionError("expected a loud failure")
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every structure the binding mirrors has the header's size and field
+    offsets: a small C program built with gcc from include/tn.h prints
+    sizeof and offsetof, compared with ctypes'."""
+    import shutil
+    import subprocess
+    import pytest
+    from paper_2410_18740_amd import _lib as L
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    structs = [getattr(L, n) for n in dir(L)
+               if n.startswith("tn_") and isinstance(getattr(L, n), type) and issubclass(getattr(L, n), ctypes.Structure)]
+    assert len(structs) >= 7
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HDR}"', "int main(void) {"]
+    for S in structs:
+        lines.append(f'  printf("{S.__name__} size %zu\\n", sizeof({S.__name__}));')
+        for f, _ in S._fields_:
+            lines.append(f'  printf("{S.__name__} {f} %zu\\n", offsetof({S.__name__}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True, capture_output=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, val = ln.split()
+        got[(name, field)] = int(val)
+    for S in structs:
+        assert got[(S.__name__, "size")] == ctypes.sizeof(S), S.__name__
+        for f, _ in S._fields_:
+            assert got[(S.__name__, f)] == getattr(S, f).offset, (S.__name__, f)

@@ -100,3 +100,34 @@ def test_sampler_matches_oracle_stream(ctx, four_mode):
     ref = sampler.sample(t, 400, 2004)
     mism = np.mean(np.any(smp != ref, axis=1))
     assert mism < 0.01, mism
+
+
+def test_sweep_reports_truncation_flops(ctx):
+    """The sweep's svd_flops is the sum over its 2(N-1) truncations of the
+    dense stages' implementation flops for the shapes the sweep visits
+    (6 modes, d 6, chi 48: Gram sizes 6 to 216, both eigensolver routes)."""
+    import paper_2410_18740_amd as P
+    N, d, chi = 6, 6, 48
+    U = W.haar_unitary(N, np.random.default_rng(3))
+    r = np.full(N, 0.5)
+    mpo = P.MPO(ctx, r, U, d)
+    mps = P.MPS(ctx, W.random_mps(N, d, chi, 7))
+    st = P.dmrg_sweep(ctx, mpo, mps, P.SweepOpts(chi_max=chi, precision=P.FP64, tol=1e-8, max_matvecs=8))
+    dims = W.bond_dims(N, d, chi)
+
+    def flops(p, q, k):
+        f = 8.0 * p * p * q + 8.0 * k * p * q
+        if p > 32:
+            f += 24.0 * (p - 1) * p * (2 * p - 1) / 6.0 + 8.0 * k * p * (p - 1)
+        return f
+
+    # the left-to-right half takes the Gram matrix on the left side (p = m),
+    # the right-to-left half on the right side (p = n)
+    want = 0.0
+    for s in range(N - 1):
+        m, n = dims[s] * d, d * dims[s + 2]
+        k = max(1, min(chi, m, n))
+        want += flops(m, n, k) + flops(n, m, k)
+    print(f"svd_flops {st['svd_flops']:.6e} want {want:.6e}")
+    assert abs(st["svd_flops"] - want) <= 1e-12 * want
+    assert st["t_svd"] > 0.0
