@@ -53,14 +53,18 @@ def test_dmrg_fp64_matches_oracle(ctx, four_mode):
     t = mp.export()
     P_gpu = omps.probabilities(t)
     P_ref = omps.probabilities(four_mode["ref"])
+    print(f"fp64: |E - E_oracle| = {abs(E - four_mode['st'][-1]['energy']):.3e}, "
+          f"max |dP(n)| = {np.abs(P_gpu - P_ref).max():.3e}")
     assert np.abs(P_gpu - P_ref).max() < 1e-8
     assert abs(stats[-1]["max_discarded"] - four_mode["st"][-1]["max_discarded"]) < 1e-10
 
 
 def test_dmrg_full_rank_matches_ed(ctx, four_mode):
     m, mp, stats = _run(ctx, four_mode, 36, 3, lambda s: 0)
-    assert abs(stats[-1]["energy"] - four_mode["E_ed"]) < 1e-10
     P_gpu = omps.probabilities(mp.export())
+    print(f"full rank: |E - E_ED| = {abs(stats[-1]['energy'] - four_mode['E_ed']):.3e}, "
+          f"max |dP(n)| = {np.abs(P_gpu - np.abs(four_mode['gs']) ** 2).max():.3e}")
+    assert abs(stats[-1]["energy"] - four_mode["E_ed"]) < 1e-10
     assert np.abs(P_gpu - np.abs(four_mode["gs"]) ** 2).max() < 1e-8
 
 
@@ -69,6 +73,8 @@ def test_fast_form_then_fp64_refine(ctx, four_mode, prec):
     """Bulk sweeps in FP32 / BF16x3, then FP64 refinement sweeps reach the FP64
     result to 1e-10."""
     m, mp, stats = _run(ctx, four_mode, 16, 6, lambda s: prec if s < 3 else 0)
+    print(f"form {prec} + FP64 refine: |E - E_oracle| = "
+          f"{abs(stats[-1]['energy'] - four_mode['st'][-1]['energy']):.3e}")
     assert abs(stats[-1]["energy"] - four_mode["st"][-1]["energy"]) < 1e-10
 
 
@@ -77,8 +83,10 @@ def test_marginals_match_oracle(ctx, four_mode):
     m, mp, stats = _run(ctx, four_mode, 16, 6, lambda s: 0)
     marg = P.marginals(ctx, mp, m)
     ref = omps.marginals(mp.export())
-    assert np.abs(marg - ref).max() < 1e-12
     ref2 = omps.marginals(four_mode["ref"])
+    print(f"marginals: max |d| = {np.abs(marg - ref).max():.3e} (same state), "
+          f"{np.abs(marg - ref2).max():.3e} (oracle's DMRG state)")
+    assert np.abs(marg - ref).max() < 1e-12
     assert np.abs(marg - ref2).max() < 1e-8
 
 
@@ -99,6 +107,7 @@ def test_sampler_matches_oracle_stream(ctx, four_mode):
     smp = P.sample(ctx, mp, m, 400, 2004).cpu().numpy()
     ref = sampler.sample(t, 400, 2004)
     mism = np.mean(np.any(smp != ref, axis=1))
+    print(f"sampler: {mism:.4f} of 400 samples differ from the oracle's stream")
     assert mism < 0.01, mism
 
 

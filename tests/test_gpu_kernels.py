@@ -173,6 +173,7 @@ def test_heff_full_size_sampled(ctx):
         val = np.tensordot(T, Re[:, b, :], axes=([0, 1], [1, 0]))
         errs.append(abs(out[a, s, t, b] - val) / (abs(val) + 1e-30))
     scale = np.abs(out).max()
+    print(f"full-size FP32 matvec: median relative error {np.median(errs):.3e} over 48 sampled entries")
     assert np.median(errs) < 1e-4
     # absolute error relative to the output scale (cancellation makes single relative errors noisy)
     assert max(abs(out[0, 0, 0, 0]), 1.0) > 0
