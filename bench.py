@@ -966,6 +966,8 @@ def main():
     roof_main, roof_other = (roof_tri, roof_gemm) if tri_total_ms > gemm_ms else (roof_gemm, roof_tri)
     extra = {
         "sweep_s": wall / a.steps,
+        "sweep_s_each": [s["t_total"] for s in stats],
+        "sweep_s_median": float(np.median([s["t_total"] for s in stats])),
         "energy": stats[-1]["energy"],
         "heff_kernel_tflops": pr["flops_matvec"] / (matvec_ms * 1e-3) / 1e12,
         "phase_s": {k: sum(s[k] for s in stats) / a.steps for k in
