@@ -214,18 +214,26 @@ def _host_info():
 
 
 def _gpu_info():
-    """Device name, compute units and the current clock levels (rocm-smi)."""
-    import subprocess
+    """Device name, compute units and the current clock levels, read from the
+    driver's sysfs DPM tables (the level marked '*'); no other program is run."""
+    import glob
     import torch
     pr = torch.cuda.get_device_properties(0)
     info = {"name": pr.name, "compute_units": pr.multi_processor_count}
-    try:
-        out = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=30)
-        cards = json.loads(out.stdout)
-        first = cards[sorted(cards)[0]]
-        info["clocks"] = {k: v for k, v in first.items() if "clk" in k.lower()}
-    except Exception:
-        info["clocks"] = None
+    clocks = {}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        cur = {}
+        for kind in ("sclk", "mclk"):
+            try:
+                with open(os.path.join(dev, f"pp_dpm_{kind}")) as f:
+                    for line in f:
+                        if line.rstrip().endswith("*"):
+                            cur[kind] = line.split(":", 1)[1].strip(" *\n")
+            except OSError:
+                pass
+        if cur:
+            clocks[os.path.basename(os.path.dirname(dev))] = cur
+    info["clocks"] = clocks or None
     return info
 
 
