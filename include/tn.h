@@ -65,6 +65,14 @@ const char* tn_version(void);
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the legacy default stream).  alloc may be NULL. */
 tn_status tn_ctx_create(int device, void* hip_stream, const tn_allocator* alloc, tn_ctx** out);
+/* Close a context: drain its stream and free its workspaces.  MPO, MPS and
+ * network handles made on it may be destroyed before or after this call, in
+ * any order: the context's host object lives until the last of them is
+ * destroyed, and destroying a handle after the context touches no stream.
+ * The allocator's callbacks must stay callable until then.  Every other call
+ * that is given a closed context, or a handle whose context is closed where it
+ * would touch the device, returns TN_ESTATE.  Passing the pointer after the
+ * context and all its handles are gone is undefined, as for any freed object. */
 void tn_ctx_destroy(tn_ctx* ctx);
 /* Message of the last failing call on this context ("" if none). */
 const char* tn_last_error(const tn_ctx* ctx);
@@ -133,6 +141,27 @@ tn_status tn_mps_bond_dims(const tn_mps* mps, int32_t* bond_dims);
 /* Copy all site tensors to host (complex128, concatenated).  cap in doubles;
  * *needed receives the required size (call with host_buf = NULL to query). */
 tn_status tn_mps_export(tn_ctx* ctx, const tn_mps* mps, double* host_buf, size_t cap, size_t* needed);
+/* Checkpoint and resume (the state of a run that a later process continues):
+ * tn_mps_checkpoint writes one flat host buffer of doubles: a header [magic
+ * 1414415184, format 1, N, d, orthogonality centre (-1 unknown), completed
+ * sweeps, D_raw (0 when mpo is NULL), 0], the bond dimensions [N + 1], the site
+ * tensors (complex128, concatenated in site order) and, when mpo is given,
+ * that MPO's isometries [N][D_raw][d] complex (as tn_mpo_isometries gives
+ * them; gate parameters of a pLBO basis are saved with tn_plbo_params).
+ * cap in doubles; *needed receives the size (buf = NULL to query).  Synchronises
+ * the stream.  TN_EINVAL if mpo and mps do not match or cap is too small.
+ * tn_mps_import rebuilds an MPS handle from such a buffer of exactly `len`
+ * doubles, with the same tensors, centre and sweep counter, so a sweep on it
+ * continues the saved run; iso (NULL or host [N][D_raw][d] complex) receives
+ * the isometries for tn_problem.iso, and info (NULL or [2]) receives D_raw and
+ * the centre.  The tensors are taken to be in the canonical form the header
+ * records.  TN_EINVAL for a bad magic, format, size or non-finite tensor.
+ * tn_mps_sweeps: completed sweeps of this MPS (tn_dmrg_sweep, tn_dmrg_solve
+ * and tn_plbo_sweep count), restored by tn_mps_import. */
+tn_status tn_mps_checkpoint(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, double* buf, size_t cap,
+                            size_t* needed);
+tn_status tn_mps_import(tn_ctx* ctx, const double* buf, size_t len, tn_mps** out, double* iso, int32_t* info);
+tn_status tn_mps_sweeps(const tn_mps* mps, int64_t* sweeps);
 /* Right-canonicalise (sites N-1..1) and normalise; orthogonality centre at 0. */
 tn_status tn_mps_canonicalize(tn_ctx* ctx, tn_mps* mps);
 void tn_mps_destroy(tn_mps* mps);
@@ -376,9 +405,15 @@ tn_status tn_sample(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n
  * cannot be brought to that form.
  *
  * tn_sample_displaced: as tn_sample for the state D(alpha_b)|psi>, with
- * alpha_b,j = (d_x + i d_p)/sqrt2, d = L z_b.  z: device doubles
- * [n_samples][K], standard normal draws supplied by the caller (the random
- * numbers of the noise); L: host [2N][K], 1 <= K <= 2N.  The displacement acts on the D_raw
+ * alpha_b,j = (d_x + i d_p)/sqrt2, d = L z_b (Sec. II.F: a noisy sample is a
+ * sample of a randomly displaced pure state, alpha ~ N(0, C), C = L L^T).
+ * z: device doubles [n_samples][K] of standard normal draws supplied by the
+ * caller, or NULL: the library then draws z[b][i] itself by the Box-Muller
+ * transform z = sqrt(-2 ln u1) cos(2 pi u2) of one Philox4x32-10 block with
+ * counter (sample lo, sample hi, i, 1) and key (seed lo, seed hi), u1 =
+ * (53 bits of words 0-1 + 1) / 2^53 in (0, 1], u2 = (53 bits of words 2-3) /
+ * 2^53 (the bit layout of tn_sample's uniforms).  L: host [2N][K],
+ * 1 <= K <= 2N.  The displacement acts on the D_raw
  * kept Fock levels of each mode (weight it moves beyond them is dropped and
  * the conditional probabilities renormalised).  Uniform draws and the
  * inverse-CDF rule are tn_sample's.  Same centre requirement as tn_sample. */

@@ -77,14 +77,16 @@ def alphas(z, L):
     return (d[:, :N] + 1j * d[:, N:]) / math.sqrt(2.0)
 
 
-def sample_displaced(fock_tensors, alpha, seed: int, L: int = 160):
+def sample_displaced(fock_tensors, alpha, seed: int, L: int = 160, with_ties: bool = False):
     """Samples of D(alpha_b)|psi> for each row alpha_b: the sequential
     conditional sampler of oracle.sampler (same Philox uniforms and inverse-CDF
     rule) with each site's Fock tensor replaced by D(alpha_{b,s}) A^F_s over the
-    D kept Fock levels."""
+    D kept Fock levels.  With with_ties, also each sample's first rounding-tie
+    site (N if none), as in oracle.sampler.sample."""
     alpha = np.asarray(alpha)
     B, N = alpha.shape
     out = np.zeros((B, N), dtype=np.int64)
+    first_tie = np.full(B, N, dtype=np.int64)
     cache = {}
     for b in range(B):
         v = np.ones(1, dtype=np.complex128)
@@ -97,17 +99,18 @@ def sample_displaced(fock_tensors, alpha, seed: int, L: int = 160):
             T = cache[key] @ T
             p = np.sum(np.abs(T) ** 2, axis=1)
             u = sampler.uniform(b, s, seed) * p.sum()
-            cum = np.cumsum(p)
-            pick = D - 1
-            for n in range(D):
-                if cum[n] >= u and p[n] > 0:
-                    pick = n
-                    break
-            while pick > 0 and not p[pick] > 0:
-                pick -= 1
+            pick, tie = sampler.pick_outcome(p, u)
+            if tie and first_tie[b] == N:
+                first_tie[b] = s
             out[b, s] = pick
             v = T[pick] / np.sqrt(p[pick])
-    return out
+    return (out, first_tie) if with_ties else out
+
+
+def library_normals(n_samples: int, K: int, seed: int):
+    """z[b][i] = oracle.sampler.normal(b, i, seed): the noise draws the library
+    makes itself when the caller passes none."""
+    return np.array([[sampler.normal(b, i, seed) for i in range(K)] for b in range(n_samples)])
 
 
 def gaussian_photon_distribution(V2: np.ndarray, nmax: int, L: int = 160) -> np.ndarray:

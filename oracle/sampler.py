@@ -13,6 +13,8 @@ as (x0 >> 5) * 2^26 + (x1 >> 6), divided by 2^53.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 M0, M1 = 0xD2511F53, 0xCD9E8D57
@@ -43,25 +45,69 @@ def uniform(sample: int, site: int, seed: int) -> float:
     return (a * 67108864.0 + b) / 9007199254740992.0
 
 
-def sample(fock_tensors, n_samples: int, seed: int):
+def normal(sample: int, col: int, seed: int) -> float:
+    """A standard normal draw for noise column `col` of sample `sample`: the
+    Box-Muller transform (Box & Muller, Ann. Math. Statist. 29, 1958)
+    z = sqrt(-2 ln u1) cos(2 pi u2) of the uniforms u1 in (0, 1] (words 0-1,
+    53 bits, plus one) and u2 in [0, 1) (words 2-3) of the Philox block with
+    counter (sample lo, sample hi, col, 1); the last counter word keeps these
+    blocks apart from the photon-number draws."""
+    out = philox4x32_10((sample & MASK, (sample >> 32) & MASK, col, 1), (seed & MASK, (seed >> 32) & MASK))
+    u1 = ((out[0] >> 5) * 67108864.0 + (out[1] >> 6) + 1.0) / 9007199254740992.0
+    u2 = ((out[2] >> 5) * 67108864.0 + (out[3] >> 6)) / 9007199254740992.0
+    return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
+TIE = 1e-12
+
+
+def pick_outcome(p, u):
+    """The smallest n whose cumulative probability reaches u (u already scaled
+    by sum p), skipping zero-probability outcomes; and whether the draw is a
+    rounding tie, i.e. u lies within TIE * sum p of a cumulative sum, where a
+    different rounding of the probabilities may pick the neighbour."""
+    cum = np.cumsum(p)
+    pick = len(p) - 1
+    for n in range(len(p)):
+        if cum[n] >= u and p[n] > 0:
+            pick = n
+            break
+    while pick > 0 and not p[pick] > 0:
+        pick -= 1
+    tie = bool(np.min(np.abs(cum - u)) < TIE * max(float(cum[-1]), 1e-300))
+    return pick, tie
+
+
+def sample(fock_tensors, n_samples: int, seed: int, with_ties: bool = False):
     """Samples (n_samples x N ints) from right-canonical Fock-basis tensors
-    A^F_s[a, n, b] with the norm on site 0; probabilities in FP64."""
+    A^F_s[a, n, b] with the norm on site 0; probabilities in FP64.  With
+    with_ties, also the first site of each sample whose draw is a rounding
+    tie (N if none): outcomes up to that site are determined exactly."""
     N = len(fock_tensors)
     out = np.zeros((n_samples, N), dtype=np.int64)
+    first_tie = np.full(n_samples, N, dtype=np.int64)
     for b in range(n_samples):
         v = np.ones(1, dtype=np.complex128)
         for s, A in enumerate(fock_tensors):
             T = np.tensordot(v, A, axes=([0], [0]))      # (D, chi_r)
             p = np.sum(np.abs(T) ** 2, axis=1)
             u = uniform(b, s, seed) * p.sum()
-            cum = np.cumsum(p)
-            pick = len(p) - 1
-            for n in range(len(p)):
-                if cum[n] >= u and p[n] > 0:
-                    pick = n
-                    break
-            while pick > 0 and not p[pick] > 0:
-                pick -= 1
+            pick, tie = pick_outcome(p, u)
+            if tie and first_tie[b] == N:
+                first_tie[b] = s
             out[b, s] = pick
             v = T[pick] / np.sqrt(p[pick])
-    return out
+    return (out, first_tie) if with_ties else out
+
+
+def stream_mismatches(got, ref, first_tie):
+    """Samples of `got` that differ from the oracle stream `ref` before the
+    oracle's first rounding tie in that sample (the count that must be 0),
+    and the number of samples that hold a tie at all."""
+    got = np.asarray(got)
+    bad = 0
+    for b in range(ref.shape[0]):
+        t = int(first_tie[b])
+        if np.any(got[b, :t] != ref[b, :t]):
+            bad += 1
+    return bad, int(np.sum(first_tie < ref.shape[1]))

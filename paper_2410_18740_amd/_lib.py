@@ -108,6 +108,9 @@ def lib():
         "tn_mps_bond_dims": (i32, [vp, P(i32)]),
         "tn_mps_export": (i32, [vp, vp, P(dbl), szt, P(szt)]),
         "tn_mps_canonicalize": (i32, [vp, vp]),
+        "tn_mps_checkpoint": (i32, [vp, vp, vp, P(dbl), szt, P(szt)]),
+        "tn_mps_import": (i32, [vp, P(dbl), szt, P(vp), P(dbl), P(i32)]),
+        "tn_mps_sweeps": (i32, [vp, P(i64)]),
         "tn_mps_destroy": (None, [vp]),
         "tn_dmrg_sweep": (i32, [vp, vp, vp, P(tn_sweep_opts), P(tn_sweep_stats)]),
         "tn_energy": (i32, [vp, vp, vp, P(dbl), P(dbl)]),

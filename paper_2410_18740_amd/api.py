@@ -198,6 +198,37 @@ class MPS:
     def canonicalize(self):
         self.ctx.check(L.lib().tn_mps_canonicalize(self.ctx.h, self.h))
 
+    @property
+    def sweeps(self) -> int:
+        n = C.c_int64()
+        self.ctx.check(L.lib().tn_mps_sweeps(self.h, C.byref(n)))
+        return n.value
+
+    def checkpoint(self, mpo: "MPO | None" = None) -> np.ndarray:
+        """The flat FP64 checkpoint buffer (tensors, centre, sweep counter and,
+        with mpo, its isometries)."""
+        need = C.c_size_t()
+        mh = None if mpo is None else mpo.h
+        self.ctx.check(L.lib().tn_mps_checkpoint(self.ctx.h, self.h, mh, None, 0, C.byref(need)))
+        buf = np.zeros(need.value, dtype=np.float64)
+        self.ctx.check(L.lib().tn_mps_checkpoint(self.ctx.h, self.h, mh, L.dptr(buf), need.value, C.byref(need)))
+        return buf
+
+    @classmethod
+    def from_checkpoint(cls, ctx: Context, buf):
+        """(MPS, isometries [N][D_raw][d] or None) from a checkpoint buffer."""
+        buf = np.ascontiguousarray(buf, dtype=np.float64)
+        N, d, D = int(buf[2]), int(buf[3]), int(buf[6])
+        iso = np.zeros((N, max(D, 1), d), dtype=np.complex128)
+        info = np.zeros(2, dtype=np.int32)
+        h = C.c_void_p()
+        ctx.check(L.lib().tn_mps_import(ctx.h, L.dptr(buf), buf.size, C.byref(h), L.dptr(iso.view(np.float64)),
+                                        L.dptr(info, C.c_int32)))
+        self = cls.__new__(cls)
+        self.ctx, self.N, self.d, self.h = ctx, N, d, h
+        ctx._children.add(self)
+        return self, (iso if D > 0 else None)
+
     def _release(self):
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             L.lib().tn_mps_destroy(self.h)
@@ -447,26 +478,24 @@ def noise_williamson(V):
 def sample_displaced(ctx: Context, mps: MPS, mpo: MPO, n_samples: int, seed: int, Lc, z=None):
     """Noisy-GBS samples: photon numbers of D(alpha_b)|psi> with alpha_b from
     d = Lc z_b, Lc of shape (2N, K).  z: (n_samples, K) standard normals
-    (device or host); when None they are drawn on the device from a torch
-    generator seeded with `seed`."""
+    (device or host); when None the library draws them from its counter-based
+    generator seeded with `seed` (Philox4x32-10 and the Box-Muller transform)."""
     torch = _torch()
     dev = f"cuda:{ctx.device}"
     Lh = np.ascontiguousarray(Lc, dtype=np.float64)
     if Lh.ndim != 2 or Lh.shape[0] != 2 * mps.N:
         raise ValueError("Lc must have shape (2N, K)")
     K = Lh.shape[1]
-    if z is None:
-        g = torch.Generator(device=dev)
-        g.manual_seed(int(seed))
-        z = torch.randn((n_samples, K), dtype=torch.float64, device=dev, generator=g)
-    else:
+    zp = None
+    if z is not None:
         z = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64) if not hasattr(z, "device") else z,
                             dtype=torch.float64).to(dev).contiguous()
-    if tuple(z.shape) != (n_samples, K):
-        raise ValueError("z must have shape (n_samples, K)")
+        if tuple(z.shape) != (n_samples, K):
+            raise ValueError("z must have shape (n_samples, K)")
+        zp = z.data_ptr()
     out = torch.empty((n_samples, mps.N), dtype=torch.int32, device=dev)
     ctx.check(L.lib().tn_sample_displaced(ctx.h, mps.h, mpo.h, n_samples, C.c_uint64(seed), K,
-                                          C.c_void_p(z.data_ptr()), L.dptr(Lh), C.c_void_p(out.data_ptr())))
+                                          C.c_void_p(zp), L.dptr(Lh), C.c_void_p(out.data_ptr())))
     return out
 
 

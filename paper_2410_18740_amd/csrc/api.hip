@@ -98,11 +98,7 @@ extern "C" tn_status tn_ctx_create(int device, void* hip_stream, const tn_alloca
   return TN_OK;
 }
 
-extern "C" void tn_ctx_destroy(tn_ctx* c) {
-  if (!c) return;
-  (void)hipStreamSynchronize(c->stream);
-  for (auto& kv : c->ws) dev_free(c, kv.second.first);
-  c->ws.clear();
+static void ctx_free(tn_ctx* c) {
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->ev_ok) {
     for (int i = 0; i < 8; ++i) (void)hipEventDestroy(c->ev[i]);
@@ -111,11 +107,28 @@ extern "C" void tn_ctx_destroy(tn_ctx* c) {
   }
   delete c;
 }
+void ctx_retain(tn_ctx* c) { ++c->refs; }
+void ctx_release(tn_ctx* c) {
+  if (--c->refs == 0) ctx_free(c);
+}
+
+// Closes the context: its stream is drained and its workspaces freed now; the
+// host object lives on until the last MPO, MPS or network made on it is
+// destroyed, so those handles may be destroyed in any order.
+extern "C" void tn_ctx_destroy(tn_ctx* c) {
+  if (!c || c->closed) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->ws) dev_free(c, kv.second.first);
+  c->ws.clear();
+  c->closed = true;
+  ctx_release(c);
+}
 
 extern "C" const char* tn_last_error(const tn_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   if (out) {
     for (int i = 0; i < 5; ++i) out[i] = c->prof_ms[i];
     out[5] = (double)c->prof_n;
@@ -444,7 +457,7 @@ static void mpo_free(tn_mpo* m) {
   if (!m) return;
   tn_ctx* c = m->ctx;
   if (c) {
-    (void)hipStreamSynchronize(c->stream);
+    if (!c->closed) (void)hipStreamSynchronize(c->stream);
     dev_free(c, m->d_ops64);
     dev_free(c, m->d_ops32);
     dev_free(c, m->d_raw64);
@@ -453,10 +466,12 @@ static void mpo_free(tn_mpo* m) {
     dev_free(c, m->d_fock);
   }
   delete m;
+  if (c) ctx_release(c);
 }
 
 extern "C" tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** out) {
   if (!ctx) return TN_EINVAL;
+  TN_CTX_OPEN(ctx);
   tn_mpo* m = nullptr;
   TN_GUARD_BEGIN
   if (!prob || !out) TN_THROW(TN_EINVAL, "null argument");
@@ -504,6 +519,7 @@ extern "C" tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** 
   }
   m = new tn_mpo();
   m->ctx = ctx;
+  ctx_retain(ctx);
   m->N = N; m->D_raw = D; m->d = d;
   m->r.assign(prob->r, prob->r + N);
   m->U = U;
@@ -592,6 +608,7 @@ extern "C" tn_status tn_mpo_coefficients(const tn_mpo* mpo, double* a, double* b
 }
 
 extern "C" tn_status tn_mpo_isometries(const tn_mpo* mpo, double* iso) {
+  if (mpo && mpo->ctx && mpo->ctx->closed) return TN_ESTATE;
   if (!mpo || !iso) return TN_EINVAL;
   try {
     plbo_sync_iso(mpo);
@@ -635,18 +652,21 @@ void tn_mps::ensure_site(int s, size_t elems) {
 
 static void mps_free(tn_mps* m) {
   if (!m) return;
-  if (m->ctx) {
-    (void)hipStreamSynchronize(m->ctx->stream);
-    for (auto p : m->A) dev_free(m->ctx, p);
-    for (auto p : m->L) dev_free(m->ctx, p);
-    for (auto p : m->Rt) dev_free(m->ctx, p);
+  tn_ctx* c = m->ctx;
+  if (c) {
+    if (!c->closed) (void)hipStreamSynchronize(c->stream);
+    for (auto p : m->A) dev_free(c, p);
+    for (auto p : m->L) dev_free(c, p);
+    for (auto p : m->Rt) dev_free(c, p);
   }
   delete m;
+  if (c) ctx_release(c);
 }
 
 extern "C" tn_status tn_mps_create(tn_ctx* ctx, int32_t N, int32_t d, const int32_t* dims, const double* init,
                                    tn_mps** out) {
   if (!ctx) return TN_EINVAL;
+  TN_CTX_OPEN(ctx);
   tn_mps* m = nullptr;
   TN_GUARD_BEGIN
   if (!out || !dims || !init) TN_THROW(TN_EINVAL, "null argument");
@@ -661,6 +681,7 @@ extern "C" tn_status tn_mps_create(tn_ctx* ctx, int32_t N, int32_t d, const int3
   }
   m = new tn_mps();
   m->ctx = ctx;
+  ctx_retain(ctx);
   m->N = N; m->d = d;
   m->dims.assign(dims, dims + N + 1);
   m->A.assign(N, nullptr);
@@ -690,6 +711,7 @@ extern "C" tn_status tn_mps_bond_dims(const tn_mps* mps, int32_t* dims) {
 
 extern "C" tn_status tn_mps_export(tn_ctx* ctx, const tn_mps* mps, double* buf, size_t cap, size_t* needed) {
   if (!ctx || !mps) return TN_EINVAL;
+  TN_CTX_OPEN(ctx);
   TN_GUARD_BEGIN
   size_t tot = 0;
   for (int s = 0; s < mps->N; ++s) tot += 2 * (size_t)mps->dims[s] * mps->d * mps->dims[s + 1];
@@ -704,6 +726,100 @@ extern "C" tn_status tn_mps_export(tn_ctx* ctx, const tn_mps* mps, double* buf, 
     off += 2 * n;
   }
   TN_GUARD_END(ctx)
+}
+
+// ------------------------------------------------------------------ checkpoint
+// Layout (doubles): [magic, version, N, d, centre, sweeps, D_raw (0: no
+// isometries), 0], bond dimensions [N + 1], the site tensors (complex,
+// concatenated in site order), then the isometries [N][D_raw][d] complex.
+static const double kCkptMagic = 1414415184.0;  // "TNCP" read as a big-endian integer
+static const int kCkptHeader = 8;
+
+static size_t ckpt_tensor_doubles(const std::vector<int>& dims, int N, int d) {
+  size_t tot = 0;
+  for (int s = 0; s < N; ++s) tot += 2 * (size_t)dims[s] * d * dims[s + 1];
+  return tot;
+}
+
+extern "C" tn_status tn_mps_checkpoint(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, double* buf, size_t cap,
+                                       size_t* needed) {
+  if (!ctx || !mps) return TN_EINVAL;
+  TN_CTX_OPEN(ctx);
+  TN_GUARD_BEGIN
+  const int N = mps->N, d = mps->d;
+  if (mpo && (mpo->N != N || mpo->d != d)) TN_THROW(TN_EINVAL, "MPO and MPS do not match");
+  const int D = mpo ? mpo->D_raw : 0;
+  const size_t nt = ckpt_tensor_doubles(mps->dims, N, d);
+  const size_t tot = kCkptHeader + (size_t)(N + 1) + nt + 2 * (size_t)N * D * d;
+  if (needed) *needed = tot;
+  if (!buf) return TN_OK;
+  if (cap < tot) TN_THROW(TN_EINVAL, "checkpoint buffer too small");
+  std::vector<double> iso;
+  if (mpo) {
+    iso.resize(2 * (size_t)N * D * d);
+    const tn_status st = tn_mpo_isometries(mpo, iso.data());
+    if (st != TN_OK) TN_THROW(st, "isometries of the MPO could not be read");
+  }
+  double* h = buf;
+  h[0] = kCkptMagic; h[1] = 1.0; h[2] = N; h[3] = d; h[4] = mps->center; h[5] = (double)mps->sweeps;
+  h[6] = D; h[7] = 0.0;
+  for (int t = 0; t <= N; ++t) h[kCkptHeader + t] = mps->dims[t];
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  size_t off = kCkptHeader + N + 1;
+  for (int s = 0; s < N; ++s) {
+    const size_t n = (size_t)mps->dims[s] * d * mps->dims[s + 1];
+    HIPCHK(hipMemcpy(buf + off, mps->A[s], n * sizeof(cf64), hipMemcpyDeviceToHost));
+    off += 2 * n;
+  }
+  if (mpo) std::memcpy(buf + off, iso.data(), iso.size() * sizeof(double));
+  TN_GUARD_END(ctx)
+}
+
+extern "C" tn_status tn_mps_import(tn_ctx* ctx, const double* buf, size_t len, tn_mps** out, double* iso,
+                                   int32_t* info) {
+  if (!ctx) return TN_EINVAL;
+  TN_CTX_OPEN(ctx);
+  tn_mps* m = nullptr;
+  TN_GUARD_BEGIN
+  if (!buf || !out) TN_THROW(TN_EINVAL, "null argument");
+  *out = nullptr;
+  if (len < (size_t)kCkptHeader + 2) TN_THROW(TN_EINVAL, "checkpoint too short");
+  if (buf[0] != kCkptMagic || buf[1] != 1.0) TN_THROW(TN_EINVAL, "not a version-1 checkpoint");
+  auto as_int = [](double v, double lo, double hi, const char* what) {
+    if (!(v >= lo && v <= hi) || v != std::floor(v)) TN_THROW(TN_EINVAL, std::string("bad ") + what + " in checkpoint");
+    return (int64_t)v;
+  };
+  const int N = (int)as_int(buf[2], 1, 4096, "N");
+  const int d = (int)as_int(buf[3], 1, 64, "d");
+  const int centre = (int)as_int(buf[4], -1, N - 1, "centre");
+  const int64_t sweeps = as_int(buf[5], 0, 9.0e15, "sweep count");
+  const int D = (int)as_int(buf[6], 0, 64, "D_raw");
+  if (D != 0 && D < d) TN_THROW(TN_EINVAL, "D_raw below d in checkpoint");
+  if (len < (size_t)kCkptHeader + N + 1) TN_THROW(TN_EINVAL, "checkpoint too short");
+  std::vector<int32_t> dims(N + 1);
+  for (int t = 0; t <= N; ++t) dims[t] = (int32_t)as_int(buf[kCkptHeader + t], 1, 4096, "bond dimension");
+  std::vector<int> dv(dims.begin(), dims.end());
+  const size_t nt = ckpt_tensor_doubles(dv, N, d);
+  const size_t tot = kCkptHeader + (size_t)(N + 1) + nt + 2 * (size_t)N * D * d;
+  if (len != tot) TN_THROW(TN_EINVAL, "checkpoint length does not match its header");
+  const double* tens = buf + kCkptHeader + N + 1;
+  for (size_t i = 0; i < 2 * (size_t)N * D * d; ++i)
+    if (!std::isfinite(tens[nt + i])) TN_THROW(TN_EINVAL, "non-finite isometry in checkpoint");
+  const tn_status st = tn_mps_create(ctx, N, d, dims.data(), tens, &m);
+  if (st != TN_OK) return st;
+  m->center = centre;
+  m->sweeps = sweeps;
+  if (info) { info[0] = D; info[1] = centre; }
+  if (iso && D > 0) std::memcpy(iso, tens + nt, 2 * (size_t)N * D * d * sizeof(double));
+  *out = m;
+  m = nullptr;
+  TN_GUARD_END(ctx)
+}
+
+extern "C" tn_status tn_mps_sweeps(const tn_mps* mps, int64_t* sweeps) {
+  if (!mps || !sweeps) return TN_EINVAL;
+  *sweeps = mps->sweeps;
+  return TN_OK;
 }
 
 extern "C" void tn_mps_destroy(tn_mps* mps) { mps_free(mps); }

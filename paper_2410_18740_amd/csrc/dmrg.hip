@@ -1163,6 +1163,7 @@ static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o
   m->env_prec = o.precision;
   m->env_version = mpo->version;
   for (int t = 1; t <= N; ++t) m->Lok[t] = false;
+  m->sweeps++;
   if (o.compute_energy) {
     const double t0 = wall();
     S.energy = energy_fp64(c, mpo, m, nullptr);
@@ -1174,6 +1175,7 @@ static void sweep_impl(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts& o
 
 extern "C" tn_status tn_dmrg_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts* o, tn_sweep_stats* out) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !m) TN_THROW(TN_EINVAL, "null handle");
   check_opts(o);
@@ -1185,6 +1187,7 @@ extern "C" tn_status tn_dmrg_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_s
 extern "C" tn_status tn_dmrg_solve(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_solve_opts* so, tn_solve_result* out,
                                    double* etrace, double* ttrace) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !m || !so) TN_THROW(TN_EINVAL, "null argument");
   if (so->max_sweeps < 1) TN_THROW(TN_EINVAL, "max_sweeps must be >= 1");
@@ -1231,7 +1234,10 @@ extern "C" tn_status tn_dmrg_solve(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_s
     if (fp64 && std::fabs(dE) < so->conv_tol * std::max(1.0, std::fabs(E))) break;
     if (!refining) {
       if (dE > 0) ++rises;
-      if (std::fabs(dE) < so->switch_tol * std::max(1.0, std::fabs(E)) || rises >= 2) refining = true;
+      if (std::fabs(dE) < so->switch_tol * std::max(1.0, std::fabs(E)) || rises >= 2) {
+        refining = true;
+        if (so->max_refine == 0) break;  // the bulk form has stagnated and no refinement is allowed
+      }
     } else if (so->bulk_precision != PREC_FP64 && refine_done >= so->max_refine) {
       break;
     }
@@ -1243,6 +1249,7 @@ extern "C" tn_status tn_dmrg_solve(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_s
 
 extern "C" tn_status tn_mps_canonicalize(tn_ctx* c, tn_mps* m) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!m) TN_THROW(TN_EINVAL, "null handle");
   canonicalize(c, m);
@@ -1251,6 +1258,7 @@ extern "C" tn_status tn_mps_canonicalize(tn_ctx* c, tn_mps* m) {
 
 extern "C" tn_status tn_energy(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double* energy, double* norm2) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !m || !energy) TN_THROW(TN_EINVAL, "null argument");
   check_pair(mpo, m);
@@ -1261,6 +1269,7 @@ extern "C" tn_status tn_energy(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, do
 extern "C" tn_status tn_energy_variance(tn_ctx* c, const tn_mpo* mpo, const tn_mps* m, double* energy,
                                         double* h2, double* variance) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !m || !energy || !variance) TN_THROW(TN_EINVAL, "null argument");
   check_pair(mpo, m);
@@ -1276,6 +1285,7 @@ extern "C" tn_status tn_energy_variance(tn_ctx* c, const tn_mpo* mpo, const tn_m
 extern "C" tn_status tn_lbo_step(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int32_t site, const tn_sweep_opts* o,
                                  double* discarded) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !m) TN_THROW(TN_EINVAL, "null handle");
   check_opts(o);
@@ -1307,6 +1317,7 @@ extern "C" tn_status tn_lbo_step(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int32_t site
 extern "C" tn_status tn_heff_apply(tn_ctx* c, const tn_mpo* mpo, int32_t site, int32_t chi_l, int32_t chi_r,
                                    const double* L, const double* R, const double* xin, double* yout, int32_t prec) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !L || !R || !xin || !yout) TN_THROW(TN_EINVAL, "null argument");
   if (site < 0 || site + 1 >= mpo->N) TN_THROW(TN_EINVAL, "window out of range");
@@ -1333,6 +1344,7 @@ extern "C" tn_status tn_env_update(tn_ctx* c, const tn_mpo* mpo, int32_t site, i
                                    int32_t chi_r, const double* env_in, const double* A, double* env_out,
                                    int32_t prec) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !env_in || !A || !env_out) TN_THROW(TN_EINVAL, "null argument");
   if (site < 0 || site >= mpo->N) TN_THROW(TN_EINVAL, "site out of range");
@@ -1368,6 +1380,7 @@ extern "C" tn_status tn_truncate(tn_ctx* c, int32_t m, int32_t n, const double* 
                                  int32_t dir, double* left, double* right, int32_t* k_out, double* sv,
                                  double* discarded) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!theta || !left || !right || !k_out) TN_THROW(TN_EINVAL, "null argument");
   if (m < 1 || n < 1 || chi < 1) TN_THROW(TN_EINVAL, "sizes must be positive");
@@ -1392,6 +1405,7 @@ extern "C" double tn_env_flops(const tn_mpo* mpo, int32_t site, int32_t chi_l, i
 extern "C" tn_status tn_cgemm(tn_ctx* c, int32_t prec, int32_t ta, int32_t tb, int32_t M, int32_t N, int32_t K,
                               const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!A || !B || !C) TN_THROW(TN_EINVAL, "null argument");
   if (M < 1 || N < 1 || K < 1) TN_THROW(TN_EINVAL, "sizes must be positive");
@@ -1403,6 +1417,7 @@ extern "C" tn_status tn_cgemm(tn_ctx* c, int32_t prec, int32_t ta, int32_t tb, i
 
 // ------------------------------------------------------------------ gate-parameterised basis entry points
 extern "C" tn_status tn_plbo_enable(tn_mpo* mpo, const double* params) {
+  if (mpo && mpo->ctx && mpo->ctx->closed) return TN_ESTATE;
   if (!mpo) return TN_EINVAL;
   tn_ctx* c = mpo->ctx;
   TN_GUARD_BEGIN
@@ -1434,6 +1449,7 @@ extern "C" tn_status tn_plbo_params(const tn_mpo* mpo, double* params) {
 extern "C" tn_status tn_plbo_site_gradient(tn_ctx* c, tn_mpo* mpo, tn_mps* m, int32_t site, int32_t precision,
                                            double* G, double* energy, double* grad) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !m || !energy) TN_THROW(TN_EINVAL, "null argument");
   check_pair(mpo, m);
@@ -1459,6 +1475,7 @@ extern "C" tn_status tn_plbo_site_gradient(tn_ctx* c, tn_mpo* mpo, tn_mps* m, in
 extern "C" tn_status tn_plbo_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_sweep_opts* o,
                                    const tn_plbo_opts* po, tn_sweep_stats* out, double* gain) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!mpo || !m) TN_THROW(TN_EINVAL, "null handle");
   check_opts(o);
@@ -1472,6 +1489,7 @@ extern "C" tn_status tn_plbo_sweep(tn_ctx* c, tn_mpo* mpo, tn_mps* m, const tn_s
 }
 
 extern "C" tn_status tn_plbo_linear(tn_mpo* mpo) {
+  if (mpo && mpo->ctx && mpo->ctx->closed) return TN_ESTATE;
   if (!mpo) return TN_EINVAL;
   tn_ctx* c = mpo->ctx;
   TN_GUARD_BEGIN

@@ -26,6 +26,11 @@ struct TnError : std::runtime_error {
   } while (0)
 
 struct tn_ctx {
+  // lifetime: one reference for the caller's handle plus one per MPO, MPS and
+  // network created on it; tn_ctx_destroy closes it and drops the caller's
+  // reference, and the memory goes with the last reference
+  int refs = 1;
+  bool closed = false;
   int device = 0;
   hipStream_t stream = nullptr;
   tn_allocator alloc{};
@@ -49,6 +54,16 @@ struct tn_ctx {
   int64_t lz_iters = 0, lz_full = 0;  // Lanczos iterations, and those orthogonalised against the whole basis
 };
 
+void ctx_retain(tn_ctx* c);
+void ctx_release(tn_ctx* c);
+// entry points taking a context refuse a closed one
+#define TN_CTX_OPEN(c)                                             \
+  do {                                                             \
+    if ((c)->closed) {                                             \
+      (c)->err = "the context has been destroyed";                 \
+      return TN_ESTATE;                                            \
+    }                                                              \
+  } while (0)
 void* dev_alloc(tn_ctx* c, size_t bytes);
 void dev_free(tn_ctx* c, void* p);
 void* ws_get(tn_ctx* c, const std::string& name, size_t bytes);
@@ -110,6 +125,7 @@ struct tn_mps {
   std::vector<cf64*> A;         // device tensors, capacity per site
   std::vector<size_t> cap;      // elements allocated
   int center = -1;              // orthogonality centre (site), -1 unknown
+  int64_t sweeps = 0;           // completed sweeps (checkpoint counter)
   // cached environments (precision env_prec): L[s] at bond s, Rt[s] at bond s (transposed)
   int env_prec = -1;
   const tn_mpo* env_mpo = nullptr;

@@ -168,6 +168,7 @@ static uint64_t splitmix(uint64_t& s) {
 extern "C" tn_status tn_mlp_create(tn_ctx* c, int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed,
                                    tn_mlp** out) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   tn_mlp* M = nullptr;
   TN_GUARD_BEGIN
   if (!out) TN_THROW(TN_EINVAL, "null output");
@@ -176,6 +177,7 @@ extern "C" tn_status tn_mlp_create(tn_ctx* c, int32_t in_dim, int32_t hidden, in
     TN_THROW(TN_EINVAL, "layer sizes out of range");
   M = new tn_mlp();
   M->ctx = c;
+  ctx_retain(c);
   M->in = in_dim; M->hid = hidden; M->out = out_dim;
   mlp_offsets(M);
   M->p = (float*)dev_alloc(c, M->np * sizeof(float));
@@ -201,17 +203,20 @@ extern "C" tn_status tn_mlp_create(tn_ctx* c, int32_t in_dim, int32_t hidden, in
 
 extern "C" void tn_mlp_destroy(tn_mlp* M) {
   if (!M) return;
-  if (M->ctx) {
-    (void)hipStreamSynchronize(M->ctx->stream);
-    dev_free(M->ctx, M->p); dev_free(M->ctx, M->g); dev_free(M->ctx, M->m); dev_free(M->ctx, M->v);
+  tn_ctx* c = M->ctx;
+  if (c) {
+    if (!c->closed) (void)hipStreamSynchronize(c->stream);
+    dev_free(c, M->p); dev_free(c, M->g); dev_free(c, M->m); dev_free(c, M->v);
   }
   delete M;
+  if (c) ctx_release(c);
 }
 
 extern "C" int64_t tn_mlp_num_params(const tn_mlp* M) { return M ? M->np : -1; }
 
 extern "C" tn_status tn_mlp_params(tn_ctx* c, tn_mlp* M, float* get, const float* set) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!M) TN_THROW(TN_EINVAL, "null model");
   if (set) {
@@ -244,6 +249,7 @@ static void mlp_forward(tn_ctx* c, tn_mlp* M, const float* X, int B, float** H1,
 
 extern "C" tn_status tn_mlp_forward(tn_ctx* c, tn_mlp* M, const float* X, int32_t B, float* Yout) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!M || !X || !Yout || B < 1) TN_THROW(TN_EINVAL, "bad arguments");
   float *H1, *H2, *Y;
@@ -292,6 +298,7 @@ static float mlp_backward(tn_ctx* c, tn_mlp* M, const float* X, const float* T, 
 extern "C" tn_status tn_mlp_grad(tn_ctx* c, tn_mlp* M, const float* X, const float* T, int32_t B, float* grads,
                                  float* loss) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!M || !X || !T || B < 1) TN_THROW(TN_EINVAL, "bad arguments");
   const float L = mlp_backward(c, M, X, T, B);
@@ -303,6 +310,7 @@ extern "C" tn_status tn_mlp_grad(tn_ctx* c, tn_mlp* M, const float* X, const flo
 extern "C" tn_status tn_mlp_train_step(tn_ctx* c, tn_mlp* M, const float* X, const float* T, int32_t B, float lr,
                                        float* loss) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!M || !X || !T || B < 1 || !(lr > 0.f)) TN_THROW(TN_EINVAL, "bad arguments");
   const float L = mlp_backward(c, M, X, T, B);
@@ -383,6 +391,7 @@ __global__ void rho_scale_kernel(const cf64* C, int D, double s, cf64* out) {
 }
 extern "C" tn_status tn_rdm(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int32_t n_modes, double* out) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (mpo) plbo_sync_iso(mpo);
   if (!m || !mpo || !out) TN_THROW(TN_EINVAL, "null argument");

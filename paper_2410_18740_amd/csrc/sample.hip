@@ -80,8 +80,12 @@ __global__ __launch_bounds__(256) void sample_step_kernel(const cf64* __restrict
     s = wave_reduce_sum(s);
     if (lane == 0) p[wave][n] = s;
   }
+  // p[wave] is private to this wavefront: a wavefront-level barrier orders
+  // lane 0's writes before the reads (waves past B have already returned, so
+  // no workgroup barrier may follow)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   double tot = 0.0;
   for (int n = 0; n < D; ++n) tot += p[wave][n];
   const double u = philox_uniform(sample0 + (uint64_t)b, (uint32_t)site, seed) * tot;
@@ -156,6 +160,7 @@ static void check_obs(const tn_mps* m, const tn_mpo* mpo) {
 
 extern "C" tn_status tn_marginals(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int32_t n_modes, double* out) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   check_obs(m, mpo);
   if (!out || n_modes < 1 || n_modes > m->N) TN_THROW(TN_EINVAL, "bad output or n_modes");
@@ -197,6 +202,7 @@ extern "C" tn_status tn_marginals(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo,
 extern "C" tn_status tn_sample(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
                                int32_t* out) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   check_obs(m, mpo);
   if (!out || n_samples < 1) TN_THROW(TN_EINVAL, "bad output or sample count");
@@ -457,6 +463,30 @@ extern "C" tn_status tn_noise_williamson(int32_t N, const double* V, double* r_p
   return TN_OK;
 }
 
+// Standard normal draws of the noise: z[b][i] for samples sample0 + b, noise
+// column i, by the Box-Muller transform (Box & Muller, Ann. Math. Statist. 29,
+// 1958) of two uniforms from one Philox4x32-10 block with counter
+// (sample lo, sample hi, i, 1) and key (seed lo, seed hi): u1 in (0, 1] from
+// words 0-1 and u2 in [0, 1) from words 2-3, 53 bits each;
+// z = sqrt(-2 ln u1) cos(2 pi u2).  The last counter word 1 keeps these blocks
+// apart from the photon-number draws, which use 0 there.
+__global__ void noise_normal_kernel(uint64_t seed, uint64_t sample0, int64_t B, int K, double* __restrict__ z) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * K) return;
+  const uint64_t sample = sample0 + (uint64_t)(e / K);
+  const int i = (int)(e % K);
+  u32x4 c;
+  c.v[0] = (uint32_t)sample;
+  c.v[1] = (uint32_t)(sample >> 32);
+  c.v[2] = (uint32_t)i;
+  c.v[3] = 1u;
+  const u32x4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double k53 = 1.0 / 9007199254740992.0;
+  const double u1 = ((double)(r.v[0] >> 5) * 67108864.0 + (double)(r.v[1] >> 6) + 1.0) * k53;
+  const double u2 = ((double)(r.v[2] >> 5) * 67108864.0 + (double)(r.v[3] >> 6)) * k53;
+  z[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+}
+
 // alpha[b][j] = (d_x + i d_p) / sqrt2 with d = L z_b (L: 2N x K, z: B x K)
 __global__ void noise_alpha_kernel(const double* __restrict__ z, const double* __restrict__ L, int64_t B, int N, int K,
                                    cf64* __restrict__ alpha) {
@@ -553,9 +583,10 @@ __global__ __launch_bounds__(64) void displace_rows_kernel(const cf64* __restric
 extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int64_t n_samples,
                                          uint64_t seed, int32_t K, const double* z, const double* L, int32_t* out) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   check_obs(m, mpo);
-  if (!out || !z || !L || n_samples < 1) TN_THROW(TN_EINVAL, "bad output, noise or sample count");
+  if (!out || !L || n_samples < 1) TN_THROW(TN_EINVAL, "bad output, noise factor or sample count");
   const int N = m->N, D = mpo->D_raw;
   if (K < 1 || K > 2 * N) TN_THROW(TN_EINVAL, "the noise factor needs 1 <= K <= 2N columns");
   for (int64_t i = 0; i < 2ll * N * K; ++i)
@@ -570,6 +601,7 @@ extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mp
   cf64* Vb = wsT<cf64>(c, "smp:Vb", (size_t)chunk * chimax);
   cf64* al = wsT<cf64>(c, "smp:al", (size_t)chunk * N);
   double* dL = wsT<double>(c, "smp:L", 2 * (size_t)N * K);
+  double* zdraw = z ? nullptr : wsT<double>(c, "smp:z", (size_t)chunk * K);
   upload(c, dL, L, 2 * (size_t)N * K * sizeof(double));
   std::vector<cf64*> F(N);
   for (int s = 0; s < N; ++s) {
@@ -581,7 +613,14 @@ extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mp
   for (int64_t s0 = 0; s0 < n_samples; s0 += chunk) {
     const int B = (int)std::min<int64_t>(chunk, n_samples - s0);
     const int64_t ne = (int64_t)B * N;
-    hipLaunchKernelGGL(noise_alpha_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, z + s0 * K, dL,
+    const double* zb = z ? z + s0 * K : zdraw;
+    if (!z) {
+      const int64_t nz = (int64_t)B * K;
+      hipLaunchKernelGGL(noise_normal_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, seed, (uint64_t)s0,
+                         (int64_t)B, K, zdraw);
+      HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(noise_alpha_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, zb, dL,
                        (int64_t)B, N, K, al);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(fill_one_kernel, dim3(std::max(1, (B + 255) / 256)), dim3(256), 0, st, Va, (int64_t)B);
@@ -606,6 +645,7 @@ extern "C" tn_status tn_sample_displaced(tn_ctx* c, const tn_mps* m, const tn_mp
 // Philox known-answer entry point (device generator check): n counters/keys on host.
 extern "C" tn_status tn_philox4x32_10(tn_ctx* c, const uint32_t* ctr, const uint32_t* key, uint32_t* out, int32_t n) {
   if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
   TN_GUARD_BEGIN
   if (!ctr || !key || !out || n < 1) TN_THROW(TN_EINVAL, "bad arguments");
   uint32_t* dc = wsT<uint32_t>(c, "px:c", 4 * (size_t)n);

@@ -105,10 +105,11 @@ def test_sampler_matches_oracle_stream(ctx, four_mode):
     m, mp, stats = _run(ctx, four_mode, 16, 4, lambda s: 0)
     t = mp.export()
     smp = P.sample(ctx, mp, m, 400, 2004).cpu().numpy()
-    ref = sampler.sample(t, 400, 2004)
-    mism = np.mean(np.any(smp != ref, axis=1))
-    print(f"sampler: {mism:.4f} of 400 samples differ from the oracle's stream")
-    assert mism < 0.01, mism
+    ref, tie = sampler.sample(t, 400, 2004, with_ties=True)
+    bad, nties = sampler.stream_mismatches(smp, ref, tie)
+    print(f"sampler: {bad} of 400 samples differ from the oracle's stream outside rounding ties "
+          f"({nties} samples hold a tie)")
+    assert bad == 0
 
 
 def test_sweep_reports_truncation_flops(ctx):

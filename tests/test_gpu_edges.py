@@ -134,4 +134,6 @@ def test_checkpoint_export_and_reimport(ctx):
     assert abs(e0 - e1) < 1e-12 * max(1.0, abs(e0))
     a = P.dmrg_sweep(ctx, m, mp, o)["energy"]
     b = P.dmrg_sweep(ctx, m, copy, o)["energy"]
-    assert abs(a - b) < 1e-9 * max(1.0, abs(a))
+    # the re-created copy is re-canonicalised (tensors move by rounding), so
+    # the next sweep agrees to rounding of the converged energy
+    assert abs(a - b) < 1e-12 * max(1.0, abs(a))

@@ -132,18 +132,26 @@ def test_heff_fp64(ctx, case):
 
 
 @pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 3e-5)])
-@pytest.mark.parametrize("case", CASES[1:4])
+@pytest.mark.parametrize("case", CASES)
 def test_heff_fast_forms(ctx, case, prec, tol):
+    """FP32 and BF16x3 matvecs element by element: every output entry within
+    tol * max|ref| of the FP64 oracle."""
     import paper_2410_18740_amd as P
     m, Le, Re, th, ref = _heff_case(ctx, *case, seed=3)
     out = from_dev(P.heff_apply(ctx, m, case[2], to_dev(Le), to_dev(Re), to_dev(th), prec))
-    err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"heff prec={prec} {case} max|d|/max|ref| = {err:.3e}")
     assert err < tol, err
 
 
-def test_heff_full_size_sampled(ctx):
-    """Middle window of the 32-mode, d = 8, chi = 128 workload in FP32, checked
-    on 48 sampled output entries computed one by one by the oracle."""
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 3e-5)])
+def test_heff_full_size_sampled(ctx, prec, tol):
+    """Middle window of the 32-mode, d = 8, chi = 128 workload (the benchmark's
+    shape and launch configuration) in FP32 and BF16x3, checked element by
+    element on 96 output entries that the oracle computes one by one: the
+    corners and edges of the 128 x 64 output tiles (rows 0, 63, 64, 127 of
+    chi_l and columns 0, 63, 64, 127 of chi_r, first and last physical
+    indices) and random entries.  Each must lie within tol * max|out|."""
     import paper_2410_18740_amd as P
     N, D, d, chi = 32, 16, 8, 128
     rng = np.random.default_rng(5)
@@ -161,27 +169,33 @@ def test_heff_full_size_sampled(ctx):
     Le = rand_env(wl, chi, rng)
     Re = rand_env(wr, chi, rng)
     th = rng.standard_normal((chi, d, d, chi)) + 1j * rng.standard_normal((chi, d, d, chi))
-    out = from_dev(P.heff_apply(ctx, m, site, to_dev(Le), to_dev(Re), to_dev(th), P.FP32))
+    out = from_dev(P.heff_apply(ctx, m, site, to_dev(Le), to_dev(Re), to_dev(th), prec))
+    assert np.all(np.isfinite(out))
     W1, W2 = Ws[site], Ws[site + 1]
-    errs = []
-    for _ in range(48):
-        a, s, t, b = (int(rng.integers(0, chi)), int(rng.integers(0, d)), int(rng.integers(0, d)),
-                      int(rng.integers(0, chi)))
+    idx = []
+    for a in (0, 63, 64, 127):
+        for b in (0, 63, 64, 127):
+            idx.append((a, int(rng.integers(0, d)) if (a + b) % 2 else 0, d - 1 if b == 127 else 0, b))
+    edges = [(a, s, t, b) for a in (0, 127) for s in (0, d - 1) for t in (0, d - 1) for b in (0, 127)]
+    idx += edges
+    while len(idx) < 96:
+        idx.append((int(rng.integers(0, chi)), int(rng.integers(0, d)), int(rng.integers(0, d)),
+                    int(rng.integers(0, chi))))
+    scale = np.abs(out).max()
+    worst = 0.0
+    for a, s, t, b in idx:
         T = np.tensordot(Le[:, a, :], th, axes=([1], [0]))            # l u v y
         T = np.tensordot(T, W1[:, :, s, :], axes=([0, 1], [0, 2]))     # v y m
         T = np.tensordot(T, W2[:, :, t, :], axes=([2, 0], [0, 2]))     # y n
         val = np.tensordot(T, Re[:, b, :], axes=([0, 1], [1, 0]))
-        errs.append(abs(out[a, s, t, b] - val) / (abs(val) + 1e-30))
-    scale = np.abs(out).max()
-    print(f"full-size FP32 matvec: median relative error {np.median(errs):.3e} over 48 sampled entries")
-    assert np.median(errs) < 1e-4
-    # absolute error relative to the output scale (cancellation makes single relative errors noisy)
-    assert max(abs(out[0, 0, 0, 0]), 1.0) > 0
+        worst = max(worst, abs(out[a, s, t, b] - val) / scale)
+    print(f"full-size matvec prec={prec}: max |d| / max|out| = {worst:.3e} over {len(idx)} sampled entries")
+    assert worst < tol, worst
 
 
 # ---------------------------------------------------------------- environments
 @pytest.mark.parametrize("N,D,site,cl,cr", [(4, 6, 0, 1, 6), (5, 4, 2, 13, 9), (7, 4, 3, 16, 21), (7, 4, 5, 8, 4)])
-@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 3e-6)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-13), (1, 3e-6), (2, 3e-5)])
 def test_env_updates(ctx, N, D, site, cl, cr, prec, tol):
     import paper_2410_18740_amd as P
     rng = np.random.default_rng(site + 7)
@@ -193,13 +207,15 @@ def test_env_updates(ctx, N, D, site, cl, cr, prec, tol):
     Lin = rand_env(Ws[site].shape[0], cl, rng)
     ref = odmrg.env_left_update(Lin, A, Ws[site])
     out = from_dev(P.env_update(ctx, m, site, +1, to_dev(Lin), to_dev(A), prec))
-    print(f"env left prec={prec} err={np.linalg.norm(out - ref) / np.linalg.norm(ref):.3e}")
-    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < tol
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"env left prec={prec} max|d|/max|ref| = {err:.3e}")
+    assert err < tol
     Rin = rand_env(Ws[site].shape[1], cr, rng)
     ref = odmrg.env_right_update(Rin, A, Ws[site])
     out = from_dev(P.env_update(ctx, m, site, -1, to_dev(Rin), to_dev(A), prec))
-    print(f"env right prec={prec} err={np.linalg.norm(out - ref) / np.linalg.norm(ref):.3e}")
-    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < tol
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"env right prec={prec} max|d|/max|ref| = {err:.3e}")
+    assert err < tol
 
 
 # ---------------------------------------------------------------- truncation

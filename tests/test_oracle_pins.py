@@ -1197,3 +1197,186 @@ def test_plbo_effective_cutoff_special_cases():
     q = np.zeros(8)
     q[0] = 0.5
     assert plbo.effective_cutoff(q, 4, 120, 1e-10) > 4
+
+
+# --------------------------------------------------------------- pins of the
+# optimiser, the joint LBO sweep and the learned product state
+def test_adam_steps_follow_the_kingma_ba_closed_forms():
+    """Adam (Kingma & Ba, Algorithm 1) with bias correction: under a constant
+    gradient every step moves each parameter by exactly lr * g / (|g| + eps),
+    so t steps move it t times that; after one gradient g and then a zero
+    gradient, the second step is lr * (b1 / (1 + b1)) / sqrt(b2 / (1 + b2)) *
+    sign(g) (0.670059 lr for 0.9 / 0.999), and the update is unchanged when
+    every gradient is scaled by a constant (up to eps)."""
+    from oracle import mlp
+    rng = np.random.default_rng(5)
+    params = mlp.init_params(rng, in_dim=5, hidden=7, out_dim=3)
+    p0 = mlp.flatten(params)
+    g = rng.standard_normal(p0.size) * rng.choice([1e-3, 1.0, 30.0], p0.size)
+    grads = mlp.unflatten(g, 5, 7, 3)
+    lr = 1e-2
+    state = (np.zeros_like(p0), np.zeros_like(p0), 0)
+    p = params
+    for t in range(1, 6):
+        p, state = mlp.adam(p, grads, state, lr)
+        moved = mlp.flatten(p) - p0
+        assert np.abs(moved + t * lr * g / (np.abs(g) + 1e-8)).max() < 1e-13
+    assert state[2] == 5
+    # one gradient, then zero: the hand-derived second step
+    state = (np.zeros_like(p0), np.zeros_like(p0), 0)
+    p1, state = mlp.adam(params, grads, state, lr)
+    p2, state = mlp.adam(p1, mlp.unflatten(np.zeros_like(g), 5, 7, 3), state, lr)
+    step2 = mlp.flatten(p2) - mlp.flatten(p1)
+    ratio = (0.9 / 1.9) / math.sqrt(0.999 / 1.999)
+    assert abs(ratio - 0.670059) < 1e-6
+    big = np.abs(g) > 1.0           # where eps is negligible against |g|
+    assert np.abs(step2[big] + lr * ratio * np.sign(g[big])).max() < 1e-8 * lr
+    # scale invariance over a varying gradient sequence
+    seq = [rng.standard_normal(p0.size) for _ in range(4)]
+    outs = []
+    for c in (1.0, 1e3):
+        st = (np.zeros_like(p0), np.zeros_like(p0), 0)
+        q = params
+        for gg in seq:
+            q, st = mlp.adam(q, mlp.unflatten(c * gg, 5, 7, 3), st, lr)
+        outs.append(mlp.flatten(q))
+    # eps / |g| stays below 1e-5 for these draws
+    assert np.abs(outs[0] - outs[1]).max() < 1e-5 * lr
+
+
+def test_initial_product_state_is_thermal_in_the_squeezed_basis():
+    """The learned product state: squared amplitudes are the Boltzmann weights
+    exp(-beta m) / Z over the d kept levels with beta = log(1 + 1/nbar) (a
+    thermal state of mean photon number nbar, eq. diagReducedGaussianDM), and
+    the basis columns are S(zeta)|m> with S(zeta) = exp(1/2 (zeta* a^2 -
+    zeta a^dag^2)) taken by scipy's expm on a large box."""
+    import scipy.linalg
+    from oracle import mlp
+    D, d = 60, 5
+    y = np.array([[0.30, -0.20, math.log1p(0.40)],
+                  [-0.10, 0.45, math.log1p(0.05)],
+                  [0.0, 0.0, math.log1p(1.30)]])
+    isos, amps = mlp.initial_product_state(y, D, d)
+    Db = 200
+    a = np.diag(np.sqrt(np.arange(1, Db)), 1).astype(complex)
+    for yj, Wj, cj in zip(y, isos, amps):
+        nbar = math.expm1(yj[2])
+        beta = math.log(1.0 + 1.0 / nbar)
+        w = np.exp(-beta * np.arange(d))
+        assert np.abs(cj ** 2 - w / w.sum()).max() < 1e-13
+        assert abs(np.sum(cj ** 2) - 1.0) < 1e-14
+        zeta = complex(yj[0], yj[1])
+        S = scipy.linalg.expm(0.5 * (np.conj(zeta) * a @ a - zeta * a.T @ a.T))
+        ref = S[:D, :d]
+        # the cut to D rows is re-orthonormalised; the rows beyond D carry < 1e-12 here
+        assert np.abs(Wj - ref).max() < 1e-10
+        assert np.abs(Wj.conj().T @ Wj - np.eye(d)).max() < 1e-13
+
+
+def test_joint_lbo_sweep_reaches_the_product_state_energy():
+    """dmrg_lbo itself on U = identity with one basis state per mode: the state
+    is a product of single-mode squeezed vacua, so the sweeps must end at the
+    sum of the single-mode ground energies of the cutoff-D problems, with each
+    basis vector the single-mode ground state (Sec. III.A: the optimal local
+    basis of a product state has one element)."""
+    from oracle import lbo
+    N, D, d = 3, 10, 1
+    r = np.array([0.3, 0.5, 0.4])
+    U = np.eye(N, dtype=complex)
+    iso = [np.eye(D)[:, :d].astype(complex) for _ in range(N)]
+    mps_ = [np.ones((1, d, 1), dtype=complex) for _ in range(N)]
+    mps_, iso, st = lbo.dmrg_lbo(mps_, r, U, D, iso, chi=1, sweeps=2)
+    _, _, _, raw = lbo.local_ops(r, U, D)
+    E_single = sum(np.linalg.eigvalsh(raw[s][2])[0] for s in range(N))
+    assert abs(st[-1]["energy"] - E_single) < 1e-10
+    for s in range(N):
+        gs = np.linalg.eigh(raw[s][2])[1][:, 0]
+        assert abs(abs(np.vdot(gs, iso[s][:, 0])) - 1.0) < 1e-8
+
+
+def test_joint_lbo_sweep_finds_the_gaussian_optimal_bases():
+    """dmrg_lbo on a three-mode Haar instance at full bond dimension:
+    * the final MPS is the ground state of PHP in its final bases (dense ED of
+      (W0 x W1 x W2)^dag PHP (W0 x W1 x W2)), which a sweep that built its
+      environments in a stale basis would miss;
+    * the kept bases are the Gaussian optimum of Sec. III.A.1: each mode's
+      reduced density matrix in its kept basis has the spectrum
+      nbar^k / (nbar + 1)^(k + 1) (eq. diagReducedGaussianDM), and the kept
+      basis holds all but the optimal tail sum_{k >= d} lambda_k of the exact
+      state's reduced density matrix (eq. SVDPhysicalDimension), far more than
+      the first d Fock states hold;
+    * the energy lies below the same sweeps' energy in the first d Fock states."""
+    from oracle import lbo, mps as M
+    N, D, d = 3, 10, 5
+    r, U = _small_problem(3, 0, (0.3, 0.25, 0.35))
+    V = gbs.covariance(r, U)
+    al, be, ga, raw = lbo.local_ops(r, U, D)
+    iso0 = [np.eye(D)[:, :d].astype(complex) for _ in range(N)]
+    m0 = W.random_mps(N, d, d, 7)
+    H = dense.php_quadrature(al, be, ga, D)
+
+    def ed_in(iso):
+        Wk = np.kron(np.kron(iso[0], iso[1]), iso[2])
+        return np.linalg.eigvalsh(Wk.conj().T @ H @ Wk)[0]
+
+    # after one sweep the bases still move by much at every step: the last
+    # two-site update (full rank, so exact in its bases) must have used the
+    # basis the LBO step just chose
+    _, iso1, st1 = lbo.dmrg_lbo([a.copy() for a in m0], r, U, D, iso0, chi=d, sweeps=1)
+    assert abs(st1[-1]["energy"] - ed_in(iso1)) < 1e-12
+    m_lbo, iso, st = lbo.dmrg_lbo([a.copy() for a in m0], r, U, D, iso0, chi=d, sweeps=4)
+    E = st[-1]["energy"]
+    assert abs(E - ed_in(iso)) < 1e-12
+    # the Fock-basis run of the same sweeps (no basis update) is worse
+    cores_fock = lbo.cores_in_basis(al, be, ga, raw, iso0)
+    _, st_fock = dmrg.dmrg([a.copy() for a in m0], cores_fock, d, 4, tol=1e-12)
+    assert E < st_fock[-1]["energy"] - 1e-6
+    rho = M.reduced_density_matrices(m_lbo)
+    psi_x = gbs.exact_amplitudes(r, U, 40)      # the box holds all but < 1e-12
+    psi_x = psi_x / np.linalg.norm(psi_x)
+    tail_all = sum(lbo.gaussian_rdm_spectrum(V, i, 60)[d:].sum() for i in range(N))
+    for i in range(N):
+        lam = lbo.gaussian_rdm_spectrum(V, i, d)
+        ev = np.sort(np.linalg.eigvalsh(rho[i]))[::-1]
+        tail = lbo.gaussian_rdm_spectrum(V, i, 60)[d:].sum()
+        # the truncated ground state differs from P psi at first order in the
+        # discarded amplitude, sqrt of all modes' tails together
+        assert np.abs(ev - lam / lam.sum()).max() < 0.1 * math.sqrt(tail_all)
+        rho_x = lbo.rdm_from_dense(psi_x, i)[:D, :D]
+        lost = 1.0 - np.trace(iso[i].conj().T @ rho_x @ iso[i]).real
+        lost_fock = 1.0 - np.trace(rho_x[:d, :d]).real
+        assert lost < 1e-6 + 2 * tail and lost < 0.02 * lost_fock
+
+
+def test_noise_normals_are_standard_normal():
+    """The oracle's noise draws (Box-Muller of Philox blocks): 20000 draws pass
+    a Kolmogorov-Smirnov test against N(0, 1) and have its first four moments;
+    the blocks with last counter word 1 are not the photon-number draws."""
+    import scipy.stats
+    from oracle import sampler
+    z = np.array([sampler.normal(b, i, 77) for b in range(5000) for i in range(4)])
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    n = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    assert abs(np.mean(z ** 3)) < 5 * math.sqrt(15.0 / n)
+    assert abs(np.mean(z ** 4) - 3.0) < 5 * math.sqrt(96.0 / n)
+    u = np.array([sampler.uniform(b, i, 77) for b in range(200) for i in range(4)])
+    zz = z[:800]
+    assert abs(np.corrcoef(u, zz)[0, 1]) < 5 / math.sqrt(800)
+
+
+def test_sampler_reports_rounding_ties():
+    """pick_outcome flags a draw as a tie exactly when u lies within 1e-12 of
+    a cumulative sum; the stream comparison ignores a sample only from its
+    first tie on."""
+    from oracle import sampler
+    p = np.array([0.25, 0.25, 0.5])
+    assert sampler.pick_outcome(p, 0.25) == (0, True)
+    assert sampler.pick_outcome(p, 0.25 + 1e-9) == (1, False)
+    assert sampler.pick_outcome(p, 0.1) == (0, False)
+    assert sampler.pick_outcome(np.array([0.0, 0.5, 0.5]), 0.0) == (1, True)
+    ref = np.array([[1, 2, 3], [1, 2, 3]])
+    got = np.array([[1, 2, 4], [1, 0, 3]])
+    assert sampler.stream_mismatches(got, ref, np.array([2, 3])) == (0 + 1, 1)
+    assert sampler.stream_mismatches(got, ref, np.array([2, 1])) == (0, 2)
