@@ -377,6 +377,22 @@ tn_status tn_marginals(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int32_
  * as tn_marginals. */
 tn_status tn_sample(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
                     int32_t* out);
+/* tn_sample_noalloc: tn_sample for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, outputs (bit for bit) and errors as tn_sample;
+ * it calls no hipMalloc, hipFree or other allocating routine.  Its buffers
+ * (GEMM descriptors, the Fock-basis site tensors W_s A_s, the per-chunk
+ * contractions and left vectors) live in one 64 MiB device array per GPU that
+ * the library holds until the process ends.  Limit: 64 KiB of descriptors plus
+ * sum_s chi_s D_raw chi_{s+1} * 16 bytes of site tensors plus at least one
+ * sample's (D_raw + 2) chi_max * 16 bytes must fit in 64 MiB, else TN_EINVAL
+ * (chunks of samples are sized to what remains).  A gate-parameterised MPO
+ * whose Fock image is stale gives TN_ESTATE (tn_mpo_isometries refreshes it).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (several host threads or streams) race and must be serialised by the
+ * caller. */
+tn_status tn_sample_noalloc(tn_ctx* ctx, const tn_mps* mps, const tn_mpo* mpo, int64_t n_samples, uint64_t seed,
+                            int32_t* out);
 
 /* ------------------------------------------------------------------ noisy GBS
  * Sec. II.F, eq. CovarianceDecomposition: a mixed covariance V = Q + C, Q pure,

@@ -119,6 +119,7 @@ def lib():
         "tn_lbo_step": (i32, [vp, vp, vp, i32, P(tn_sweep_opts), P(dbl)]),
         "tn_marginals": (i32, [vp, vp, vp, i32, P(dbl)]),
         "tn_sample": (i32, [vp, vp, vp, i64, C.c_uint64, vp]),
+        "tn_sample_noalloc": (i32, [vp, vp, vp, i64, C.c_uint64, vp]),
         "tn_heff_apply": (i32, [vp, vp, i32, i32, i32, vp, vp, vp, vp, i32]),
         "tn_env_update": (i32, [vp, vp, i32, i32, i32, i32, vp, vp, vp, i32]),
         "tn_truncate": (i32, [vp, i32, i32, vp, i32, dbl, i32, vp, vp, P(i32), P(dbl), P(dbl)]),

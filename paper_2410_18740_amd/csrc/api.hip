@@ -82,6 +82,7 @@ extern "C" tn_status tn_ctx_create(int device, void* hip_stream, const tn_alloca
     return TN_EINVAL;
   }
   if (hipSetDevice(device) != hipSuccess) return TN_EHIP;
+  if (sample_scratch_setup(device) != TN_OK) return TN_EHIP;
   tn_ctx* c = new tn_ctx();
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);

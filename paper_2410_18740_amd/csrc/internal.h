@@ -54,6 +54,8 @@ struct tn_ctx {
   int64_t lz_iters = 0, lz_full = 0;  // Lanczos iterations, and those orthogonalised against the whole basis
 };
 
+// per-device address of tn_sample_noalloc's scratch, taken with `device` current
+tn_status sample_scratch_setup(int device);
 void ctx_retain(tn_ctx* c);
 void ctx_release(tn_ctx* c);
 // entry points taking a context refuse a closed one

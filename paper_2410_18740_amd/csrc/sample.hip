@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include "internal.h"
 
 #define TN_GUARD_BEGIN try {
@@ -229,6 +230,123 @@ extern "C" tn_status tn_sample(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, in
       std::vector<GemmJob> jobs{{Tmp, (int64_t)D * cr, B, D * cr, 0, 1}};
       std::vector<GemmSeg> segs{{Va, F[s], cl, (int64_t)D * cr, cl, 0}};
       gemm_jobs(c, 0, 0, jobs, segs, B, D * cr, "smp:g");
+      hipLaunchKernelGGL(sample_step_kernel, dim3((B + 3) / 4), dim3(256), 0, st, Tmp, B, D, cr, (uint64_t)s0, s, seed,
+                         Vb, out + (size_t)s0 * N, N);
+      HIPCHK(hipGetLastError());
+      std::swap(Va, Vb);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  TN_GUARD_END(c)
+}
+
+// ------------------------------------------------------------------ sampling without allocation
+// tn_sample_noalloc keeps every buffer tn_sample takes from the context's
+// workspace in one file-scope device array per GPU instead: the GEMM
+// descriptors, the Fock-basis site tensors and the per-chunk contraction and
+// left vectors.  The array's device address comes from hipGetSymbolAddress,
+// taken once per device at context creation with that device current; host
+// code never uses the array's name as an address.
+static constexpr size_t kScratchBytes = 64ull << 20;  // the stated maximum: 64 MiB per GPU
+static constexpr size_t kScratchDesc = 64ull << 10;   // GEMM descriptors at its start
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Called by tn_ctx_create with `device` current.
+tn_status sample_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return TN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return TN_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return TN_EHIP;
+  }
+  g_scratch_ptr[device] = p;
+  return TN_OK;
+}
+
+static void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  void* p = (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+  if (!p) TN_THROW(TN_ESTATE, "no sampling scratch for this device");
+  return p;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// gemm_jobs with the descriptors placed at `desc` (device) instead of a workspace
+static void gemm_jobs_at(tn_ctx* c, char* desc, const std::vector<GemmJob>& jobs, const std::vector<GemmSeg>& segs,
+                         int maxM, int maxN) {
+  const size_t bj = align256(jobs.size() * sizeof(GemmJob));
+  if (bj + segs.size() * sizeof(GemmSeg) > kScratchDesc) TN_THROW(TN_EINVAL, "too many GEMM descriptors for the scratch");
+  HIPCHK(hipMemcpyAsync(desc, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(desc + bj, segs.data(), segs.size() * sizeof(GemmSeg), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_cgemm(PREC_FP64, 0, 0, (GemmJob*)desc, (int)jobs.size(), (GemmSeg*)(desc + bj), maxM, maxN, 0,
+                      c->stream));
+  // the descriptors are rewritten by the next call
+  HIPCHK(hipStreamSynchronize(c->stream));
+}
+
+extern "C" tn_status tn_sample_noalloc(tn_ctx* c, const tn_mps* m, const tn_mpo* mpo, int64_t n_samples,
+                                       uint64_t seed, int32_t* out) {
+  if (!c) return TN_EINVAL;
+  TN_CTX_OPEN(c);
+  TN_GUARD_BEGIN
+  if (!m || !mpo) TN_THROW(TN_EINVAL, "null handle");
+  if (m->N != mpo->N || m->d != mpo->d) TN_THROW(TN_EINVAL, "MPO and MPS do not match");
+  if (m->center != 0) TN_THROW(TN_ESTATE, "the MPS must be right-canonical with its centre at site 0");
+  if (mpo->plbo)
+    for (int s = 0; s < mpo->N; ++s)
+      if (mpo->iso_stale[s]) TN_THROW(TN_ESTATE, "the Fock image of the local bases is stale (tn_mpo_isometries first)");
+  if (!out || n_samples < 1) TN_THROW(TN_EINVAL, "bad output or sample count");
+  const int N = m->N, D = mpo->D_raw, d = mpo->d;
+  hipStream_t st = c->stream;
+  int chimax = 1;
+  for (int t = 0; t <= N; ++t) chimax = std::max(chimax, m->dims[t]);
+  for (int t = 0; t < N; ++t)
+    if (m->dims[t] > 2048) TN_THROW(TN_EINVAL, "bond dimension beyond the scratch's descriptor space");
+  char* base = (char*)scratch_of(c->device);
+  char* desc = base;
+  size_t off = kScratchDesc;
+  std::vector<cf64*> F(N);
+  for (int s = 0; s < N; ++s) {
+    F[s] = (cf64*)(base + off);
+    off += align256((size_t)m->dims[s] * D * m->dims[s + 1] * sizeof(cf64));
+  }
+  const size_t per = sizeof(cf64) * ((size_t)D * chimax + 2 * (size_t)chimax) + 3 * 256;
+  if (off >= kScratchBytes || (kScratchBytes - off) / per < 1)
+    TN_THROW(TN_EINVAL, "the MPS needs " + std::to_string(off + per) + " bytes of scratch, beyond the " +
+                            std::to_string(kScratchBytes) + " of tn_sample_noalloc");
+  const int64_t chunk = std::min<int64_t>(n_samples, (int64_t)((kScratchBytes - off) / per));
+  cf64* Tmp = (cf64*)(base + off);
+  off += align256((size_t)chunk * D * chimax * sizeof(cf64));
+  cf64* Va = (cf64*)(base + off);
+  off += align256((size_t)chunk * chimax * sizeof(cf64));
+  cf64* Vb = (cf64*)(base + off);
+  // Fock-basis site tensors A^F_s[a][n][b] = sum_m W_s[n][m] A_s[a][m][b]
+  for (int s = 0; s < N; ++s) {
+    const int cl = m->dims[s], cr = m->dims[s + 1];
+    std::vector<GemmJob> jobs;
+    std::vector<GemmSeg> segs;
+    for (int a = 0; a < cl; ++a) {
+      segs.push_back({mpo->fock_iso() + (size_t)s * D * d, m->A[s] + (size_t)a * d * cr, d, cr, d, 0});
+      jobs.push_back({F[s] + (size_t)a * D * cr, cr, D, cr, a, 1});
+    }
+    gemm_jobs_at(c, desc, jobs, segs, D, cr);
+  }
+  for (int64_t s0 = 0; s0 < n_samples; s0 += chunk) {
+    const int B = (int)std::min<int64_t>(chunk, n_samples - s0);
+    hipLaunchKernelGGL(fill_one_kernel, dim3(std::max(1, (B + 255) / 256)), dim3(256), 0, st, Va, (int64_t)B);
+    for (int s = 0; s < N; ++s) {
+      const int cl = m->dims[s], cr = m->dims[s + 1];
+      std::vector<GemmJob> jobs{{Tmp, (int64_t)D * cr, B, D * cr, 0, 1}};
+      std::vector<GemmSeg> segs{{Va, F[s], cl, (int64_t)D * cr, cl, 0}};
+      gemm_jobs_at(c, desc, jobs, segs, B, D * cr);
       hipLaunchKernelGGL(sample_step_kernel, dim3((B + 3) / 4), dim3(256), 0, st, Tmp, B, D, cr, (uint64_t)s0, s, seed,
                          Vb, out + (size_t)s0 * N, N);
       HIPCHK(hipGetLastError());
