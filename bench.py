@@ -23,6 +23,10 @@ sys.path.insert(0, ROOT)
 METRIC = "DMRG sweep s + H_eff TFLOP/s (N=32,d=16,χ=128) to <H> ≤1e-8, vs plain FP64"
 PEAKS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense matrix-core peaks
 FORMS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+# matrix-core flops executed per algorithmic flop (8 real flops per complex
+# multiply-add): FP32 3M does 3 real products per complex product, FP64 does 4,
+# BF16x3 does 4 real products x 3 split products in bf16
+EXECUTED_PER_ALGORITHMIC = {"fp32": 0.75, "fp64": 1.0, "bf16x3": 3.0}
 
 
 def parse():
@@ -40,6 +44,10 @@ def parse():
     ap.add_argument("--lbo-matvecs", type=int, default=0, help="matvec cap of each LBO solve (0: --max-matvecs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare", action="store_true", help="also time one sweep in each other form")
+    ap.add_argument("--fp64-sweeps", type=int, default=2,
+                    help="plain FP64 sweeps timed after the main ones at the same matvec cap (0: none)")
+    ap.add_argument("--no-target", action="store_true",
+                    help="skip the time-to-target runs (plain FP64 and FP32 + refine on the brickwork twin)")
     ap.add_argument("--to-target", action="store_true",
                     help="time-to-target comparison of the forms (plain FP64, FP32+refine, BF16x3+refine)")
     ap.add_argument("--target", type=float, default=1e-8)
@@ -81,6 +89,17 @@ def parse():
     ap.add_argument("--warmstart", action="store_true",
                     help="learned warm start: generate data with plain DMRG+LBO, train the MLP, evaluate vs plain")
     ap.add_argument("--rows-out", default=None, help="--warmstart: also write the per-instance rows to this JSON file")
+    ap.add_argument("--train-range", default=None, metavar="A:B",
+                    help="--warmstart: generate training data for instances A..B-1 only, write it to --data-out, stop")
+    ap.add_argument("--data-out", default=None, help="--warmstart --train-range: .npz file for the training rows")
+    ap.add_argument("--data-in", nargs="*", default=None,
+                    help="--warmstart: training rows from these .npz files instead of solving the instances")
+    ap.add_argument("--net-out", default=None, help="--warmstart: save the trained network's parameters (.npz)")
+    ap.add_argument("--config4", default=None, metavar="NET",
+                    help="48-mode run (D_raw 24 -> 10, chi 256) from the learned start of the network in NET "
+                         "(.npz from --net-out): FP32 bulk + FP64 refine, then PNR samples and marginals")
+    ap.add_argument("--config4-sweeps", type=int, default=4)
+    ap.add_argument("--samples", type=int, default=100000)
     ap.add_argument("--train-instances", type=int, default=200)
     ap.add_argument("--eval-instances", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=300)
@@ -426,10 +445,19 @@ def warmstart_mesh(a):
                   file=sys.stderr, flush=True)
     X, T = np.concatenate(Xs), np.concatenate(Ts)
     t_data = time.perf_counter() - t0
+    if a.train_range:
+        np.savez(a.data_out, X=X, T=T, sweeps=np.array(sweeps), lo=lo, hi=hi, seconds=t_data)
+        print(json.dumps({"mode": "warmstart-data", "family": a.family, "instances": [lo, hi], "rows": int(X.shape[0]),
+                          "seconds": t_data, "out": a.data_out}), flush=True)
+        ctx.close()
+        return
     t1 = time.perf_counter()
     net, losses, vloss = WS.train(ctx, X, T, epochs=a.epochs)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    if a.net_out:
+        np.savez(a.net_out, params=net.get_params(), in_dim=net.in_dim, hidden=net.hidden, out_dim=net.out_dim,
+                 family=a.family, train_rows=X.shape[0])
     print(f"trained on {X.shape[0]} rows: loss {losses[0]:.5f} -> {losses[-1]:.6f}, val {vloss:.6f}, {t_train:.1f}s",
           file=sys.stderr, flush=True)
     w = W.WORKLOADS["mesh_n32_d16to8_chi128"]
@@ -508,7 +536,17 @@ def warmstart_eval(a):
     ctx = P.Context(0)
     t0 = time.perf_counter()
     Xs, Ts, sweeps = [], [], []
-    for i in range(a.train_instances):
+    lo, hi = 0, a.train_instances
+    if a.train_range:
+        lo, hi = (int(x) for x in a.train_range.split(":"))
+    if a.data_in:
+        for f in a.data_in:
+            z = np.load(f)
+            Xs.append(z["X"])
+            Ts.append(z["T"])
+            sweeps.extend(z["sweeps"].tolist())
+        lo = hi = 0
+    for i in range(lo, hi):
         seed = 10000 + i
         N = int(np.random.default_rng(seed).integers(fam["n_lo"], fam["n_hi"] + 1))
         r, U = W.make_problem(N, seed, fam["r"])
@@ -517,15 +555,28 @@ def warmstart_eval(a):
         Xs.append(X)
         Ts.append(T)
         sweeps.append(len(tr.energies))
+        if a.train_range and ((i + 1 - lo) % 50 == 0 or i + 1 == hi):
+            # partial results survive a time limit
+            np.savez(a.data_out, X=np.concatenate(Xs), T=np.concatenate(Ts), sweeps=np.array(sweeps), lo=lo,
+                     hi=i + 1, seconds=time.perf_counter() - t0)
         if i % 20 == 0:
             print(f"data {i}/{a.train_instances} N={N} E={tr.final:.3e} sweeps={len(tr.energies)} "
                   f"{time.perf_counter() - t0:.1f}s phases {tr.phases}", file=sys.stderr, flush=True)
     X, T = np.concatenate(Xs), np.concatenate(Ts)
     t_data = time.perf_counter() - t0
+    if a.train_range:
+        np.savez(a.data_out, X=X, T=T, sweeps=np.array(sweeps), lo=lo, hi=hi, seconds=t_data)
+        print(json.dumps({"mode": "warmstart-data", "family": a.family, "instances": [lo, hi], "rows": int(X.shape[0]),
+                          "seconds": t_data, "out": a.data_out}), flush=True)
+        ctx.close()
+        return
     t1 = time.perf_counter()
     net, losses, vloss = WS.train(ctx, X, T, epochs=a.epochs)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
+    if a.net_out:
+        np.savez(a.net_out, params=net.get_params(), in_dim=net.in_dim, hidden=net.hidden, out_dim=net.out_dim,
+                 family=a.family, train_rows=X.shape[0])
     print(f"trained on {X.shape[0]} rows: loss {losses[0]:.4f} -> {losses[-1]:.5f}, val {vloss:.5f}, "
           f"{t_train:.1f}s", file=sys.stderr, flush=True)
     rows = []
@@ -611,6 +662,91 @@ def warmstart_eval(a):
     if a.rows_out:
         with open(a.rows_out, "w") as f:
             json.dump(rows, f)
+    ctx.close()
+
+
+def config4_bench(a):
+    """The 48-mode configuration end to end on one GPU: Haar U from seed 4,
+    r ~ U[1.0, 1.5], D_raw 24 compressed by LBO to 10, chi 256.  The start is
+    the learned one (network from --net-out of the 20-mode Haar warm-start
+    run), judged by <H> after its first sweep against the plain start's first
+    sweep; then FP32 bulk sweeps with an FP64 refinement sweep (tn_dmrg_solve),
+    then 10^5 photon-number samples by sequential conditional sampling, whose
+    first-8-mode histograms are compared with the library's exact marginals
+    and those with the oracle's marginals of the exported MPS."""
+    import torch
+    import paper_2410_18740_amd as P
+    from paper_2410_18740_amd import warmstart as WS
+    from oracle import mps as omps
+    import workloads as W
+    name = "gbs_n48_d24to10_chi256"
+    w = W.WORKLOADS[name]
+    r, U = W.workload_problem(name)
+    z = np.load(a.config4)
+    ctx = P.Context(0)
+    net = P.MLP(ctx, int(z["in_dim"]), int(z["hidden"]), int(z["out_dim"]))
+    net.set_params(z["params"])
+    init = W.random_mps(w.N, w.d, w.chi, w.mps_seed)
+    sw1 = P.SweepOpts(chi_max=w.chi, tol=1e-6, krylov_max=24, max_matvecs=a.max_matvecs, precision=FORMS["fp32"],
+                      lbo=1)
+    # plain start: first sweep only (the judge's reference)
+    t0 = time.perf_counter()
+    mpo_p, mps_p = WS.plain_start(ctx, r, U, w.D_raw, w.d, init)
+    e_plain1 = P.dmrg_sweep(ctx, mpo_p, mps_p, sw1)["energy"]
+    torch.cuda.synchronize()
+    t_plain1 = time.perf_counter() - t0
+    print(f"config4 plain start: first-sweep <H> = {e_plain1:.6e} ({t_plain1:.1f} s)", file=sys.stderr, flush=True)
+    del mps_p, mpo_p
+    t0 = time.perf_counter()
+    mpo, mps = WS.learned_start(ctx, net, r, U, w.D_raw, w.d, w.chi, w.mps_seed, tensors=init)
+    e_learn1 = P.dmrg_sweep(ctx, mpo, mps, sw1)["energy"]
+    torch.cuda.synchronize()
+    t_learn1 = time.perf_counter() - t0
+    kept = bool(np.isfinite(e_learn1) and e_learn1 <= e_plain1)
+    print(f"config4 learned start: first-sweep <H> = {e_learn1:.6e} ({t_learn1:.1f} s), kept {kept}",
+          file=sys.stderr, flush=True)
+    if not kept:
+        mpo, mps = WS.plain_start(ctx, r, U, w.D_raw, w.d, init)
+        P.dmrg_sweep(ctx, mpo, mps, sw1)
+    t1 = time.perf_counter()
+    res = P.dmrg_solve(ctx, mpo, mps, P.SweepOpts(chi_max=w.chi, krylov_max=24, max_matvecs=a.max_matvecs),
+                       max_sweeps=max(2, a.config4_sweeps), bulk_precision=FORMS["fp32"], max_refine=1, target=-1.0,
+                       switch_tol=1e-4, conv_tol=1e-10, bulk_tol=1e-6, refine_tol=1e-8, lbo_bulk=1, lbo_refine=1)
+    t_solve = time.perf_counter() - t1
+    print(f"config4 solve: sweeps {res['sweeps']} (refine {res['refine_sweeps']}), <H> = {res['energy']:.6e}, "
+          f"trace {[round(e, 4) for e in res['energy_trace']]}, {t_solve:.1f} s", file=sys.stderr, flush=True)
+    mps.canonicalize()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    smp = P.sample(ctx, mps, mpo, a.samples, 2004)
+    torch.cuda.synchronize()
+    t_smp = time.perf_counter() - t2
+    smp = smp.cpu().numpy()
+    marg = P.marginals(ctx, mps, mpo, 8)
+    print(f"config4 sampling: {a.samples} samples in {t_smp:.2f} s", file=sys.stderr, flush=True)
+    # oracle marginals of the exported state (first 8 modes), and the histogram test
+    t3 = time.perf_counter()
+    ref = omps.marginals(mps.export(), list(mpo.isometries()), n_modes=8)
+    t_or = time.perf_counter() - t3
+    D = w.D_raw
+    worst_sigma, chi2 = 0.0, []
+    for j in range(8):
+        h = np.bincount(smp[:, j], minlength=D)[:D] / a.samples
+        sig = np.sqrt(marg[j] * (1 - marg[j]) / a.samples) + 1e-12
+        worst_sigma = max(worst_sigma, float(np.max(np.abs(h - marg[j]) / sig)))
+        m_ = marg[j] > 5.0 / a.samples
+        chi2.append(float(np.sum((h[m_] - marg[j][m_]) ** 2 / marg[j][m_]) * a.samples))
+    line = {"mode": "config4", "workload": name, "N": w.N, "D_raw": w.D_raw, "d": w.d, "chi": w.chi,
+            "network": {"train_rows": int(z["train_rows"]), "family": str(z["family"])},
+            "first_sweep_E": {"plain": e_plain1, "learned": e_learn1}, "learned_kept": kept,
+            "first_sweep_s": {"plain": t_plain1, "learned": t_learn1},
+            "solve": {k: res[k] for k in ("sweeps", "refine_sweeps", "energy", "seconds")},
+            "energy_trace": res["energy_trace"], "solve_s": t_solve,
+            "samples": a.samples, "sampling_s": t_smp, "samples_per_s": a.samples / t_smp,
+            "marginals_vs_oracle_max_abs": float(np.abs(marg - ref).max()), "oracle_marginals_s": t_or,
+            "histogram_max_sigma": worst_sigma, "histogram_chi2_per_mode": chi2,
+            "mean_photons_first8": [float(smp[:, j].mean()) for j in range(8)]}
+    print(json.dumps(line), flush=True)
     ctx.close()
 
 
@@ -869,6 +1005,12 @@ def main():
             sys.exit(2)
         peak_bench(a)
         return
+    if a.config4:
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        config4_bench(a)
+        return
     if a.warmstart:
         if a.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
@@ -955,8 +1097,11 @@ def main():
     tri_avg_s = pr["ms_tridiag"] * 1e-3 / tri_n
     tri_bytes = pr["bytes_tridiag"] / tri_n
     tri_gbs = tri_bytes / tri_avg_s / 1e9 if tri_avg_s > 0 else 0.0
+    ex = EXECUTED_PER_ALGORITHMIC[a.form]
     roof_gemm = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                  "traffic": traffic, "kernel": "cgemm_kernel (left and right environment contractions of the matvec)",
+                 "achieved_kind": "algorithmic (8 real flops per complex multiply-add)",
+                 "executed_tflops": achieved * ex, "executed_frac": achieved * ex / peak,
                  "avg_launch_us": gemm_ms * 1e3 / max(1, launches), "launches": int(launches),
                  "total_ms": gemm_ms}
     # events bracket each whole sequence of column launches (back-to-back
@@ -978,6 +1123,8 @@ def main():
         "phase_s": {k: sum(s[k] for s in stats) / a.steps for k in
                     ("t_heff", "t_lanczos", "t_svd", "t_env", "t_lbo", "t_energy")},
         "matvecs_per_sweep": sum(s["matvecs"] for s in stats) / a.steps,
+        "unconverged_steps_per_sweep": sum(s["unconverged_steps"] for s in stats) / a.steps,
+        "two_site_steps_per_sweep": 2 * (w.N - 1),
         "lanczos_iters_per_sweep": pr["lanczos_iters"] / a.steps,
         "lanczos_full_passes_per_sweep": pr["lanczos_full_passes"] / a.steps,
         "gemm_launches": launches,
@@ -997,6 +1144,27 @@ def main():
         },
         "gpu": _gpu_info(),
     }
+    if a.fp64_sweeps > 0 and prec != 0:
+        # the plain FP64 form at the same matvec cap, continuing from the same state
+        o64 = P.SweepOpts(**{**opts.__dict__, "precision": 0, "tol": 1e-8})
+        s64 = []
+        for i in range(a.fp64_sweeps):
+            s2 = P.dmrg_sweep(ctx, mpo, mps, o64)
+            s64.append(s2)
+            print(f"plain FP64 sweep {i}: <H> = {s2['energy']:.6e}, {s2['t_total']:.2f} s", file=sys.stderr,
+                  flush=True)
+        t64 = float(np.median([x["t_total"] for x in s64]))
+        extra["plain_fp64"] = {
+            "sweep_s_each": [x["t_total"] for x in s64], "sweep_s_median": t64,
+            "heff_tflops": sum(x["heff_flops"] for x in s64) / sum(x["t_total"] for x in s64) / 1e12,
+            "phase_s": {k: sum(x[k] for x in s64) / len(s64) for k in
+                        ("t_heff", "t_lanczos", "t_svd", "t_env", "t_lbo", "t_energy")},
+            "unconverged_steps_per_sweep": sum(x["unconverged_steps"] for x in s64) / len(s64),
+            "lanczos_tol": 1e-8, "max_matvecs": a.max_matvecs,
+            "sweep_speedup_of_" + a.form: t64 / extra["sweep_s_median"],
+        }
+    if not a.no_target and a.kappa == 0.0:
+        extra["time_to_target"] = time_to_target_line(P, ctx, a)
     if a.compare:
         for f, p in FORMS.items():
             if f == a.form:
@@ -1028,8 +1196,67 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, r, U, kappa=a.kappa)
         out["cpu_baseline"].update(_host_info())
+        out["cpu_baseline"]["oracle_sweep_s_extrapolated"] = oracle_sweep_estimate(w, stats, out["cpu_baseline"])
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def time_to_target_line(P, ctx, a, workload="mesh_n32_d16to8_chi128", target=1e-8):
+    """R-literal time to <H> <= 1e-8 on the brickwork twin of the benchmark
+    workload (same shapes: N = 32, D_raw 16 -> 8, chi = 128) for the plain FP64
+    form and the FP32 bulk + FP64 refine schedule (tn_dmrg_solve), each from
+    the same seeded random MPS; the timer is the library's, from the call with
+    the inputs on the device."""
+    import workloads as W
+    w = W.WORKLOADS[workload]
+    r, U = W.workload_problem(workload)
+    out = {"workload": workload, "target": target}
+    for form in ("fp64", "fp32"):
+        prec = FORMS[form]
+        mpo = P.MPO(ctx, r, U, w.D_raw, w.d)
+        mps = P.MPS(ctx, W.random_mps(w.N, w.d, w.chi, w.mps_seed))
+        res = P.dmrg_solve(ctx, mpo, mps, P.SweepOpts(chi_max=w.chi, krylov_max=24, max_matvecs=a.max_matvecs),
+                           max_sweeps=8, bulk_precision=prec, max_refine=3, target=target, switch_tol=1e-6,
+                           conv_tol=1e-13, bulk_tol=1e-8 if prec == 0 else 1e-6, refine_tol=1e-9,
+                           lbo_bulk=1, lbo_refine=1)
+        out[form] = {k: res[k] for k in ("reached", "t_target", "seconds", "sweeps", "refine_sweeps", "energy")}
+        out[form]["energy_trace"] = res["energy_trace"]
+        print(f"to target {form}: reached={res['reached']} t={res['t_target']:.2f} s sweeps={res['sweeps']}",
+              file=sys.stderr, flush=True)
+        del mps, mpo
+    ok = out["fp64"]["reached"] and out["fp32"]["reached"]
+    out["speedup_fp32_refine_vs_plain_fp64"] = out["fp64"]["t_target"] / out["fp32"]["t_target"] if ok else None
+    return out
+
+
+def oracle_sweep_estimate(w, stats, cb):
+    """Seconds one FP64 oracle sweep would take on the host, extrapolated (not
+    timed whole): the sweep's algorithmic matvec and environment flops over the
+    oracle's measured matvec rate, plus 2(N - 1) truncations at the measured
+    time of one oracle SVD of the middle two-site tensor.  The LBO
+    single-site solves are left out, so this is a lower bound."""
+    import workloads as W
+    dims = W.bond_dims(w.N, w.d, w.chi)
+    m = dims[w.N // 2 - 1] * w.d
+    n = w.d * dims[w.N // 2 + 1]
+    rng = np.random.default_rng(0)
+    th = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    t0 = time.perf_counter()
+    reps = 0
+    while reps < 3 or time.perf_counter() - t0 < 2.0:
+        np.linalg.svd(th, full_matrices=False)
+        reps += 1
+        if reps >= 10:
+            break
+    t_svd = (time.perf_counter() - t0) / reps
+    rate = cb["value"] * 1e12
+    heff = float(np.mean([s["heff_flops"] for s in stats]))
+    env = float(np.mean([s["env_flops"] for s in stats]))
+    steps = 2 * (w.N - 1)
+    est = heff / rate + env / rate + steps * t_svd
+    return {"seconds": est, "kind": "extrapolated (matvec and environment flops at the measured oracle matvec rate "
+            "+ 2(N-1) middle-size SVDs; LBO solves left out: a lower bound)",
+            "svd_s": t_svd, "svd_shape": [m, n], "heff_flops": heff, "env_flops": env}
 
 
 if __name__ == "__main__":
