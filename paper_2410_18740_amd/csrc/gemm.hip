@@ -69,9 +69,32 @@ static __device__ __forceinline__ CT ld_g(const void* base, int64_t idx) {
   return v;
 }
 
+// Tile order.  Workgroup b runs on XCD b mod 8, and each XCD has its own L2.
+// With the natural order (x = N tile fastest) the tiles of one row of a job
+// share their A panel but sit on different XCDs whenever the row has few N
+// tiles (the right contraction: N = chi_r, two tiles), so each XCD fetches the
+// panel separately.  With xcd_rows set, XCD k instead takes the k-th
+// contiguous eighth of the tiles in natural order, so the N tiles of a row run
+// on one XCD one after the other and the panel is fetched once.  The map from
+// workgroup id to tile is a bijection for any tile count.
+static __device__ __forceinline__ void tile_of(int xcd_rows, int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int id = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  int logical = id;
+  if (xcd_rows) {
+    const int T = gx * gy * gridDim.z;
+    const int q = T >> 3, r = T & 7;
+    const int xcd = id & 7, slot = id >> 3;
+    logical = (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + slot;
+  }
+  bx = logical % gx;
+  by = (logical / gx) % gy;
+  bz = logical / (gx * gy);
+}
+
 template <int PREC, bool TA, bool TB>
 __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const GemmJob* __restrict__ jobs,
-                                                    const GemmSeg* __restrict__ segs, int accumulate) {
+                                                    const GemmSeg* __restrict__ segs, int accumulate, int xcd_rows) {
   using Cfg = GemmCfg<PREC>;
   using CT = typename Cfg::CT;
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, WM = Cfg::WM, WN = Cfg::WN, MB = Cfg::MB;
@@ -84,8 +107,10 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
   __shared__ CT As[2][BK][BM + 1];
   __shared__ CT Bs[2][BK][BN + 1];
 
-  const GemmJob job = jobs[blockIdx.z];
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  int bx, by, bz;
+  tile_of(xcd_rows, bx, by, bz);
+  const GemmJob job = jobs[bz];
+  const int m0 = by * BM, n0 = bx * BN;
   if (m0 >= job.M || n0 >= job.N) return;
   const int M = job.M, N = job.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -320,10 +345,14 @@ static hipError_t launch_prec(int ta, int tb, const GemmJob* jobs, int njobs, co
   if (njobs <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
   dim3 grid((maxN + Cfg::BN - 1) / Cfg::BN, (maxM + Cfg::BM - 1) / Cfg::BM, njobs);
   dim3 block(256);
-  if (!ta && !tb) hipLaunchKernelGGL((cgemm_kernel<PREC, false, false>), grid, block, 0, st, jobs, segs, acc);
-  else if (ta && !tb) hipLaunchKernelGGL((cgemm_kernel<PREC, true, false>), grid, block, 0, st, jobs, segs, acc);
-  else if (!ta && tb) hipLaunchKernelGGL((cgemm_kernel<PREC, false, true>), grid, block, 0, st, jobs, segs, acc);
-  else hipLaunchKernelGGL((cgemm_kernel<PREC, true, true>), grid, block, 0, st, jobs, segs, acc);
+  // rows of at most 8 N tiles keep their tiles on one XCD (see tile_of); wide
+  // rows keep the natural order, which already keeps each B column panel on
+  // one XCD across jobs
+  const int xr = (grid.x >= 2 && grid.x <= 8) ? 1 : 0;
+  if (!ta && !tb) hipLaunchKernelGGL((cgemm_kernel<PREC, false, false>), grid, block, 0, st, jobs, segs, acc, xr);
+  else if (ta && !tb) hipLaunchKernelGGL((cgemm_kernel<PREC, true, false>), grid, block, 0, st, jobs, segs, acc, xr);
+  else if (!ta && tb) hipLaunchKernelGGL((cgemm_kernel<PREC, false, true>), grid, block, 0, st, jobs, segs, acc, xr);
+  else hipLaunchKernelGGL((cgemm_kernel<PREC, true, true>), grid, block, 0, st, jobs, segs, acc, xr);
   return hipGetLastError();
 }
 
