@@ -95,6 +95,11 @@ def parse():
     ap.add_argument("--data-in", nargs="*", default=None,
                     help="--warmstart: training rows from these .npz files instead of solving the instances")
     ap.add_argument("--net-out", default=None, help="--warmstart: save the trained network's parameters (.npz)")
+    ap.add_argument("--net-in", default=None, help="--warmstart: load the network (.npz from --net-out), no training")
+    ap.add_argument("--eval-range", default=None, metavar="A:B",
+                    help="--warmstart: evaluate held-out instances A..B-1 only")
+    ap.add_argument("--rows-in", nargs="*", default=None,
+                    help="--warmstart: per-instance rows of earlier runs (--rows-out) joined into the summary")
     ap.add_argument("--config4", default=None, metavar="NET",
                     help="48-mode run (D_raw 24 -> 10, chi 256) from the learned start of the network in NET "
                          "(.npz from --net-out): FP32 bulk + FP64 refine, then PNR samples and marginals")
@@ -445,19 +450,10 @@ def warmstart_mesh(a):
                   file=sys.stderr, flush=True)
     X, T = np.concatenate(Xs), np.concatenate(Ts)
     t_data = time.perf_counter() - t0
-    if a.train_range:
-        np.savez(a.data_out, X=X, T=T, sweeps=np.array(sweeps), lo=lo, hi=hi, seconds=t_data)
-        print(json.dumps({"mode": "warmstart-data", "family": a.family, "instances": [lo, hi], "rows": int(X.shape[0]),
-                          "seconds": t_data, "out": a.data_out}), flush=True)
-        ctx.close()
-        return
     t1 = time.perf_counter()
     net, losses, vloss = WS.train(ctx, X, T, epochs=a.epochs)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    if a.net_out:
-        np.savez(a.net_out, params=net.get_params(), in_dim=net.in_dim, hidden=net.hidden, out_dim=net.out_dim,
-                 family=a.family, train_rows=X.shape[0])
     print(f"trained on {X.shape[0]} rows: loss {losses[0]:.5f} -> {losses[-1]:.6f}, val {vloss:.6f}, {t_train:.1f}s",
           file=sys.stderr, flush=True)
     w = W.WORKLOADS["mesh_n32_d16to8_chi128"]
@@ -539,12 +535,17 @@ def warmstart_eval(a):
     lo, hi = 0, a.train_instances
     if a.train_range:
         lo, hi = (int(x) for x in a.train_range.split(":"))
-    if a.data_in:
+    if a.net_in:
+        lo = hi = 0
+    n_inst = hi - lo
+    if a.data_in and not a.net_in:
+        n_inst = 0
         for f in a.data_in:
             z = np.load(f)
             Xs.append(z["X"])
             Ts.append(z["T"])
             sweeps.extend(z["sweeps"].tolist())
+            n_inst += int(z["hi"]) - int(z["lo"])
         lo = hi = 0
     for i in range(lo, hi):
         seed = 10000 + i
@@ -562,7 +563,8 @@ def warmstart_eval(a):
         if i % 20 == 0:
             print(f"data {i}/{a.train_instances} N={N} E={tr.final:.3e} sweeps={len(tr.energies)} "
                   f"{time.perf_counter() - t0:.1f}s phases {tr.phases}", file=sys.stderr, flush=True)
-    X, T = np.concatenate(Xs), np.concatenate(Ts)
+    X = np.concatenate(Xs) if Xs else np.zeros((0, 1), dtype=np.float32)
+    T = np.concatenate(Ts) if Ts else np.zeros((0, 1), dtype=np.float32)
     t_data = time.perf_counter() - t0
     if a.train_range:
         np.savez(a.data_out, X=X, T=T, sweeps=np.array(sweeps), lo=lo, hi=hi, seconds=t_data)
@@ -571,16 +573,33 @@ def warmstart_eval(a):
         ctx.close()
         return
     t1 = time.perf_counter()
-    net, losses, vloss = WS.train(ctx, X, T, epochs=a.epochs)
+    if a.net_in:
+        z = np.load(a.net_in)
+        net = P.MLP(ctx, int(z["in_dim"]), int(z["hidden"]), int(z["out_dim"]))
+        net.set_params(z["params"])
+        losses, vloss, n_rows = [float("nan")], float("nan"), int(z["train_rows"])
+        n_inst = int(z["train_instances"]) if "train_instances" in z else None
+    else:
+        net, losses, vloss = WS.train(ctx, X, T, epochs=a.epochs)
+        n_rows = int(X.shape[0])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     if a.net_out:
         np.savez(a.net_out, params=net.get_params(), in_dim=net.in_dim, hidden=net.hidden, out_dim=net.out_dim,
-                 family=a.family, train_rows=X.shape[0])
-    print(f"trained on {X.shape[0]} rows: loss {losses[0]:.4f} -> {losses[-1]:.5f}, val {vloss:.5f}, "
+                 family=a.family, train_rows=n_rows, train_instances=n_inst, final_train_loss=losses[-1],
+                 val_loss=vloss)
+    print(f"trained on {n_rows} rows: loss {losses[0]:.4f} -> {losses[-1]:.5f}, val {vloss:.5f}, "
           f"{t_train:.1f}s", file=sys.stderr, flush=True)
     rows = []
-    for i in range(a.eval_instances):
+    if a.rows_in:
+        for f in a.rows_in:
+            with open(f) as fh:
+                rows.extend(json.load(fh))
+    e_lo, e_hi = 0, a.eval_instances
+    if a.eval_range:
+        e_lo, e_hi = (int(x) for x in a.eval_range.split(":"))
+    new_rows = []
+    for i in range(e_lo, e_hi):
         seed = 20000 + i
         N, D, d, chi = fam["eN"], fam["eD"], fam["ed"], fam["echi"]
         r, U = W.make_problem(N, seed, fam["r"])
@@ -628,6 +647,7 @@ def warmstart_eval(a):
             for form, tr in traces.items():
                 row[f"{form}_{name}"] = tr.time_to(e_ref * (1 + rel))
         rows.append(row)
+        new_rows.append(row)
         print(f"eval {seed}: E1 plain {plain.energies[0]:.4e} fock-nolbo {traces['fock_nolbo'].energies[0]:.4e} "
               f"learned {row['learned_first_E']:.4e} (kept {row['learned_used']}) learned-basis "
               f"{row['learned_basis_first_E']:.4e} (kept {row['learned_basis_used']}) learned-nolbo "
@@ -649,9 +669,10 @@ def warmstart_eval(a):
             s_t, _ = med(f"{form}_{name}", 1)
             summary[f"{form}_{name}"] = {"median_sweeps": s_sw, "median_s": s_t, "reached": n_ok}
     line = {"mode": "warmstart", "family": a.family, **{k: (list(v) if isinstance(v, tuple) else v)
-                                                         for k, v in fam.items()}, "train_instances": a.train_instances, "train_rows": int(X.shape[0]),
+                                                         for k, v in fam.items()},
+            "train_instances": n_inst, "train_rows": n_rows, "eval_seeds": sorted(r_["seed"] for r_ in rows),
             "data_s": t_data, "train_s": t_train, "epochs": a.epochs, "final_train_loss": losses[-1],
-            "val_loss": vloss, "eval_instances": a.eval_instances,
+            "val_loss": vloss, "eval_instances": len(rows),
             "kept": {f: sum(r_[f + "_used"] for r_ in rows) for f in forms[1:-2]},
             "first_sweep_E_median": {f: float(np.median([r_[f + "_first_E"] if f != "plain" else r_["plain_E"][0]
                                                          for r_ in rows])) for f in forms},
@@ -661,7 +682,7 @@ def warmstart_eval(a):
     print(json.dumps(line), flush=True)
     if a.rows_out:
         with open(a.rows_out, "w") as f:
-            json.dump(rows, f)
+            json.dump(new_rows, f)
     ctx.close()
 
 

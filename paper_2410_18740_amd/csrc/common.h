@@ -198,6 +198,8 @@ hipError_t launch_scale_host(cf64* dst, const cf64* src, double s, int64_t n, hi
 hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream_t st);
 hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta,
                                double* inv, double* coefs, double* out, hipStream_t st);
+hipError_t launch_lanczos_ab(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta, double* inv,
+                             double* out, hipStream_t st);
 hipError_t launch_inv_norm(const cf64* h, int nv, double* inv, hipStream_t st);
 hipError_t launch_ritz_coefs(const cf64* V, int n, double* out, double* last, hipStream_t st);
 hipError_t launch_finite_check(const cf64* x, int64_t n, int* flag, hipStream_t st);

@@ -87,6 +87,94 @@ struct LzResult {
 // exceeds sqrt(u) the vector is orthogonalised against the whole basis, and so
 // is the next one; the basis stays orthogonal to sqrt(u), which keeps the Ritz
 // values accurate to O(u ||H||).  Restarts every kmax vectors from the Ritz vector.
+// Lowest eigenpair of the symmetric tridiagonal matrix with diagonal a[0..n)
+// and off-diagonal b[0..n-1): the eigenvalue by bisection on Sturm counts to
+// the rounding level, the eigenvector by three steps of inverse iteration
+// with the LU factors (partial pivoting) of T - lambda I, normalised with its
+// first component non-negative.  Returns lambda; y receives the vector.
+static double tridiag_lowest(const std::vector<double>& a, const std::vector<double>& b, int n,
+                             std::vector<double>& y) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const double sc = std::max(std::fabs(lo), std::fabs(hi)) + 1e-300;
+  lo -= 1e-14 * sc;
+  hi += 1e-14 * sc;
+  auto below = [&](double x) {  // number of eigenvalues < x
+    int cnt = 0;
+    double q = a[0] - x;
+    if (std::fabs(q) < 1e-300) q = -1e-300;
+    cnt += q < 0;
+    for (int i = 1; i < n; ++i) {
+      q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+      if (std::fabs(q) < 1e-300) q = -1e-300;
+      cnt += q < 0;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi) || hi - lo <= 4.4e-16 * std::max(std::fabs(lo), std::fabs(hi)) + 1e-300) break;
+    if (below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  const double lam = 0.5 * (lo + hi);
+  const double tiny = std::max(2.2e-16 * sc, 1e-300);
+  y.assign(n, 1.0);
+  if (n == 1) return lam;
+  // LU of T - lam I with partial pivoting: row i of U has dd[i], du[i], du2[i]
+  std::vector<double> dd(n), du(n, 0.0), du2(n, 0.0), dl(n, 0.0);
+  std::vector<char> piv(n, 0);
+  {
+    double cdd = a[0] - lam, cdu = b[0];
+    for (int i = 0; i < n - 1; ++i) {
+      const double l = b[i], ndd = a[i + 1] - lam, ndu = (i + 1 < n - 1) ? b[i + 1] : 0.0;
+      if (std::fabs(cdd) >= std::fabs(l)) {
+        if (cdd == 0.0) cdd = tiny;
+        const double f = l / cdd;
+        dd[i] = cdd; dl[i] = f; du[i] = cdu;
+        cdd = ndd - f * cdu;
+        cdu = ndu;
+      } else {
+        const double f = cdd / l;
+        dd[i] = l; dl[i] = f; du[i] = ndd; piv[i] = 1;
+        cdd = cdu - f * ndd;
+        if (i < n - 2) { du2[i] = ndu; cdu = -f * ndu; }
+        else cdu = ndu;
+      }
+    }
+    dd[n - 1] = cdd;
+  }
+  for (int i = 0; i < n; ++i)
+    if (std::fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
+  for (int it = 0; it < 3; ++it) {
+    double cb = y[0];
+    for (int i = 0; i < n - 1; ++i) {
+      const double nb = y[i + 1], l = dl[i];
+      if (piv[i]) { y[i] = nb; cb = cb - l * nb; }
+      else { y[i] = cb; cb = nb - l * cb; }
+    }
+    double x1 = cb / dd[n - 1], x2 = 0.0;
+    y[n - 1] = x1;
+    for (int i = n - 2; i >= 0; --i) {
+      const double x0 = (y[i] - du[i] * x1 - du2[i] * x2) / dd[i];
+      y[i] = x0;
+      x2 = x1;
+      x1 = x0;
+    }
+    double nr = 0.0;
+    for (int i = 0; i < n; ++i) nr += y[i] * y[i];
+    nr = 1.0 / std::sqrt(nr);
+    for (int i = 0; i < n; ++i) y[i] *= nr;
+  }
+  if (y[0] < 0.0)
+    for (int i = 0; i < n; ++i) y[i] = -y[i];
+  return lam;
+}
+
 template <class MV>
 static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, int kmax, int max_mv, double u) {
   LzResult R;
@@ -129,6 +217,7 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
     bool stop = false;
     double lam = 0.0;
     std::vector<double> al, be, om_prev, om_cur{1.0}, om_next;  // om_cur[k] = w_{j,k}
+    std::vector<double> ta, tb, ritz;                             // the Ritz problem, on the host
     double anorm = 0.0;
     bool force_full = false;
     for (int j = 0; j < kmax; ++j) {
@@ -140,14 +229,19 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
       const int i0 = full ? 0 : std::max(0, j - 1);
       if (full) R.full_passes++;
       cgs2(i0, j - i0 + 1);
-      HIPCHK(launch_lanczos_step(h1, h2, j, i0, alpha, beta, inv, coefs, sc, st));
-      HIPCHK(hipMemcpyAsync(hout, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(launch_lanczos_ab(h1, h2, j, i0, alpha, beta, inv, sc, st));
+      HIPCHK(hipMemcpyAsync(hout, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) R.t_mv += ms * 1e-3;
       const double a = hout[0], b = hout[1];
-      lam = hout[2];
-      const double res = b * std::fabs(hout[3]);
+      if (!std::isfinite(a) || !std::isfinite(b)) TN_THROW(TN_ENUMERIC, "non-finite value in Lanczos recurrence");
+      // lowest Ritz pair of the (j + 1) x (j + 1) tridiagonal; the residual
+      // estimate is beta_j times the Ritz vector's last component
+      ta.push_back(a);
+      if (j > 0) tb.push_back(be[j - 1]);
+      lam = tridiag_lowest(ta, tb, j + 1, ritz);
+      const double res = b * std::fabs(ritz[j]);
       if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(lam))
         TN_THROW(TN_ENUMERIC, "non-finite value in Lanczos recurrence");
       jlast = j;
@@ -188,6 +282,7 @@ static LzResult lanczos(tn_ctx* c, MV&& matvec, cf64* x, int64_t n, double tol, 
       om_cur.swap(om_next);
     }
     // Ritz vector x = sum_i y_i V_i
+    HIPCHK(hipMemcpyAsync(coefs, ritz.data(), (size_t)(jlast + 1) * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(launch_lincomb(x, ptrs, jlast + 1, coefs, n, st));
     const double xn = dev_norm2(c, x, n);
     if (!(xn > 0.0) || !std::isfinite(xn)) TN_THROW(TN_ENUMERIC, "non-finite Ritz vector");

@@ -868,6 +868,33 @@ __global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const 
     out[3] = sg * y[n - 1];
   }
 }
+// The recurrence scalars alone: alpha_j, beta_j (from the two Gram-Schmidt
+// passes' dots) and 1/beta_j for the normalisation, with out[0..1] = alpha_j,
+// beta_j for the host, which solves the small Ritz problem itself.
+__global__ __launch_bounds__(64) void lanczos_ab_kernel(const cf64* h1, const cf64* h2, int j, int i0, double* alpha,
+                                                        double* beta, double* inv, double* out) {
+  const int lane = threadIdx.x;
+  double part = 0.0;
+  for (int i = i0 + lane; i <= j; i += 64) part += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
+  const double sum = wave_sum(part);
+  if (lane == 0) {
+    const double a = h1[j].x + h2[j].x;
+    const double w2 = h2[j + 1].x - sum;
+    const double b = sqrt(fmax(w2, 0.0));
+    alpha[j] = a;
+    beta[j] = b;
+    inv[0] = (b > 0.0) ? 1.0 / b : 0.0;
+    out[0] = a;
+    out[1] = b;
+  }
+}
+hipError_t launch_lanczos_ab(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta, double* inv,
+                             double* out, hipStream_t st) {
+  if (i0 < 0 || i0 > j) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lanczos_ab_kernel, dim3(1), dim3(64), 0, st, h1, h2, j, i0, alpha, beta, inv, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta,
                                double* inv, double* coefs, double* out, hipStream_t st) {
   if (j + 1 > 72 || i0 < 0 || i0 > j) return hipErrorInvalidValue;
