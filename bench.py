@@ -100,6 +100,9 @@ def parse():
                     help="--warmstart: evaluate held-out instances A..B-1 only")
     ap.add_argument("--rows-in", nargs="*", default=None,
                     help="--warmstart: per-instance rows of earlier runs (--rows-out) joined into the summary")
+    ap.add_argument("--ceiling", action="store_true",
+                    help="--warmstart --net-in: the network's bases against the analytic ones (tn_ws_gaussian_params), "
+                         "both held fixed without LBO, beside the plain start")
     ap.add_argument("--config4", default=None, metavar="NET",
                     help="48-mode run (D_raw 24 -> 10, chi 256) from the learned start of the network in NET "
                          "(.npz from --net-out): FP32 bulk + FP64 refine, then PNR samples and marginals")
@@ -291,8 +294,10 @@ def peak_bench(a):
         B = torch.randn((n, n), dtype=dt, device="cuda", generator=g)
         t = timed(lambda: P.cgemm(ctx, A, B, prec))
         rate = 8.0 * n ** 3 / t / 1e12
+        ex = rate * EXECUTED_PER_ALGORITHMIC[form]
         out["rows"][f"tn_cgemm_{form}"] = {"n": n, "s": t, "tflops": rate, "published_peak": PEAKS[form],
-                                           "frac": rate / PEAKS[form]}
+                                           "frac": rate / PEAKS[form], "executed_tflops": ex,
+                                           "executed_frac": ex / PEAKS[form]}
         print(f"tn_cgemm {form} n={n}: {rate:.1f} TFLOP/s", file=sys.stderr, flush=True)
         del A, B
         torch.cuda.empty_cache()
@@ -577,7 +582,9 @@ def warmstart_eval(a):
         z = np.load(a.net_in)
         net = P.MLP(ctx, int(z["in_dim"]), int(z["hidden"]), int(z["out_dim"]))
         net.set_params(z["params"])
-        losses, vloss, n_rows = [float("nan")], float("nan"), int(z["train_rows"])
+        losses = [float(z["final_train_loss"]) if "final_train_loss" in z else float("nan")]
+        vloss = float(z["val_loss"]) if "val_loss" in z else float("nan")
+        n_rows = int(z["train_rows"])
         n_inst = int(z["train_instances"]) if "train_instances" in z else None
     else:
         net, losses, vloss = WS.train(ctx, X, T, epochs=a.epochs)
@@ -598,6 +605,10 @@ def warmstart_eval(a):
     e_lo, e_hi = 0, a.eval_instances
     if a.eval_range:
         e_lo, e_hi = (int(x) for x in a.eval_range.split(":"))
+    if a.ceiling:
+        warmstart_ceiling(a, ctx, net, fam, e_lo, e_hi)
+        ctx.close()
+        return
     new_rows = []
     for i in range(e_lo, e_hi):
         seed = 20000 + i
@@ -686,6 +697,72 @@ def warmstart_eval(a):
     ctx.close()
 
 
+def warmstart_ceiling(a, ctx, net, fam, e_lo, e_hi):
+    """The network against its ceiling in the form where its bases help (held
+    fixed, no LBO): the network's squeezed bases and the analytic ones read
+    off each mode's reduced covariance (tn_ws_gaussian_params, exact for a
+    Gaussian state), each with the plain random tensors and the same judge
+    (kept if the first-sweep <H> is not above the plain start's), beside the
+    plain start with LBO.  Relative targets from the lowest final energy of
+    the three."""
+    import torch
+    import paper_2410_18740_amd as P
+    from paper_2410_18740_amd import warmstart as WS
+    import workloads as W
+    rows = []
+    for i in range(e_lo, e_hi):
+        seed = 20000 + i
+        N, D, d, chi = fam["eN"], fam["eD"], fam["ed"], fam["echi"]
+        r, U = W.make_problem(N, seed, fam["r"])
+        init = W.random_mps(N, d, chi, seed + 500000)
+        tp = time.perf_counter()
+        mpo, mps = WS.plain_start(ctx, r, U, D, d, init)
+        torch.cuda.synchronize()
+        plain = WS.run_sweeps(ctx, mpo, mps, WS.sweep_opts(chi), a.max_sweeps, conv_tol=1e-10,
+                              init_seconds=time.perf_counter() - tp)
+        del mps, mpo
+        traces, used = {"plain": plain}, {}
+        yan = P.ws_gaussian_params(r, U)
+        for form, prm in (("learned_nolbo", None), ("analytic_nolbo", yan)):
+            tr, u, e1 = WS.solve_with_fallback(ctx, net, r, U, D, d, chi, seed, init, plain.energies[0],
+                                               a.max_sweeps, conv_tol=1e-10, learned_state=False, lbo=False,
+                                               params=prm)
+            traces[form], used[form] = tr, (u, e1)
+        e_ref = min(t.final for t in traces.values())
+        row = {"seed": seed, "e_ref": e_ref}
+        for form, tr in traces.items():
+            row[f"{form}_E"] = tr.energies
+            row[f"{form}_final"] = tr.final
+            if form in used:
+                row[f"{form}_used"], row[f"{form}_first_E"] = used[form]
+            for name, rel in (("1e-2", 1e-2), ("1e-3", 1e-3), ("1e-4", 1e-4)):
+                row[f"{form}_{name}"] = tr.time_to(e_ref * (1 + rel))
+        rows.append(row)
+        print(f"ceiling {seed}: first E plain {plain.energies[0]:.4e} learned {used['learned_nolbo'][1]:.4e} "
+              f"(kept {used['learned_nolbo'][0]}) analytic {used['analytic_nolbo'][1]:.4e} "
+              f"(kept {used['analytic_nolbo'][0]}); final " +
+              " / ".join(f"{k} {t.final:.6e}" for k, t in traces.items()), file=sys.stderr, flush=True)
+    summary = {}
+    for form in ("plain", "learned_nolbo", "analytic_nolbo"):
+        for name in ("1e-2", "1e-3", "1e-4"):
+            ok = [r_[f"{form}_{name}"] for r_ in rows if r_[f"{form}_{name}"][0] is not None]
+            summary[f"{form}_{name}"] = {"median_sweeps": float(np.median([x[0] for x in ok])) if ok else None,
+                                         "median_s": float(np.median([x[1] for x in ok])) if ok else None,
+                                         "reached": len(ok)}
+    line = {"mode": "warmstart-ceiling", "family": a.family, "eval_seeds": [r_["seed"] for r_ in rows],
+            "kept": {f: sum(bool(r_[f + "_used"]) for r_ in rows) for f in ("learned_nolbo", "analytic_nolbo")},
+            "first_sweep_E_median": {f: float(np.median([r_[f + "_first_E"] for r_ in rows]))
+                                     for f in ("learned_nolbo", "analytic_nolbo")},
+            "plain_first_sweep_E_median": float(np.median([r_["plain_E"][0] for r_ in rows])),
+            "final_E_median": {f: float(np.median([r_[f + "_final"] for r_ in rows]))
+                               for f in ("plain", "learned_nolbo", "analytic_nolbo")},
+            "time_to_relative_target": summary}
+    print(json.dumps(line), flush=True)
+    if a.rows_out:
+        with open(a.rows_out, "w") as f:
+            json.dump(rows, f)
+
+
 def config4_bench(a):
     """The 48-mode configuration end to end on one GPU: Haar U from seed 4,
     r ~ U[1.0, 1.5], D_raw 24 compressed by LBO to 10, chi 256.  The start is
@@ -736,12 +813,22 @@ def config4_bench(a):
     t_solve = time.perf_counter() - t1
     print(f"config4 solve: sweeps {res['sweeps']} (refine {res['refine_sweeps']}), <H> = {res['energy']:.6e}, "
           f"trace {[round(e, 4) for e in res['energy_trace']]}, {t_solve:.1f} s", file=sys.stderr, flush=True)
+    refine = None
+    if res["refine_sweeps"] == 0:
+        # the bulk energy was still falling past the switch threshold: end with
+        # the FP64 refinement sweep the configuration asks for
+        t2 = time.perf_counter()
+        s64 = P.dmrg_sweep(ctx, mpo, mps, P.SweepOpts(chi_max=w.chi, tol=1e-8, krylov_max=24,
+                                                      max_matvecs=a.max_matvecs, precision=FORMS["fp64"], lbo=1))
+        refine = {"energy": s64["energy"], "seconds": time.perf_counter() - t2}
+        print(f"config4 FP64 refinement sweep: <H> = {s64['energy']:.6e}, {refine['seconds']:.1f} s", file=sys.stderr,
+              flush=True)
     mps.canonicalize()
     torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    t3s = time.perf_counter()
     smp = P.sample(ctx, mps, mpo, a.samples, 2004)
     torch.cuda.synchronize()
-    t_smp = time.perf_counter() - t2
+    t_smp = time.perf_counter() - t3s
     smp = smp.cpu().numpy()
     marg = P.marginals(ctx, mps, mpo, 8)
     print(f"config4 sampling: {a.samples} samples in {t_smp:.2f} s", file=sys.stderr, flush=True)
@@ -762,7 +849,7 @@ def config4_bench(a):
             "first_sweep_E": {"plain": e_plain1, "learned": e_learn1}, "learned_kept": kept,
             "first_sweep_s": {"plain": t_plain1, "learned": t_learn1},
             "solve": {k: res[k] for k in ("sweeps", "refine_sweeps", "energy", "seconds")},
-            "energy_trace": res["energy_trace"], "solve_s": t_solve,
+            "energy_trace": res["energy_trace"], "solve_s": t_solve, "fp64_refine_sweep": refine,
             "samples": a.samples, "sampling_s": t_smp, "samples_per_s": a.samples / t_smp,
             "marginals_vs_oracle_max_abs": float(np.abs(marg - ref).max()), "oracle_marginals_s": t_or,
             "histogram_max_sigma": worst_sigma, "histogram_chi2_per_mode": chi2,
@@ -1277,7 +1364,8 @@ def oracle_sweep_estimate(w, stats, cb):
     est = heff / rate + env / rate + steps * t_svd
     return {"seconds": est, "kind": "extrapolated (matvec and environment flops at the measured oracle matvec rate "
             "+ 2(N-1) middle-size SVDs; LBO solves left out: a lower bound)",
-            "svd_s": t_svd, "svd_shape": [m, n], "heff_flops": heff, "env_flops": env}
+            "svd_s": t_svd, "svd_shape": [m, n], "heff_flops": heff, "env_flops": env,
+            "heff_tflops_over_sweep": heff / est / 1e12}
 
 
 if __name__ == "__main__":

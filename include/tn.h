@@ -63,7 +63,10 @@ typedef struct {
 const char* tn_version(void);
 
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
- * (a hipStream_t; NULL = the legacy default stream).  alloc may be NULL. */
+ * (a hipStream_t; NULL = the legacy default stream).  alloc may be NULL.
+ * Makes `device` current.  TN_EINVAL for a bad device index or allocator;
+ * TN_EHIP if the device, or the per-device scratch array of
+ * tn_sample_noalloc, cannot be reached. */
 tn_status tn_ctx_create(int device, void* hip_stream, const tn_allocator* alloc, tn_ctx** out);
 /* Close a context: drain its stream and free its workspaces.  MPO, MPS and
  * network handles made on it may be destroyed before or after this call, in

@@ -475,6 +475,8 @@ extern "C" tn_status tn_mpo_build(tn_ctx* ctx, const tn_problem* prob, tn_mpo** 
   TN_CTX_OPEN(ctx);
   tn_mpo* m = nullptr;
   TN_GUARD_BEGIN
+  // a handle left half built by a failure is freed while the error unwinds
+  struct Free { tn_mpo*& h; ~Free() { if (h) mpo_free(h); } } free_on_error{m};
   if (!prob || !out) TN_THROW(TN_EINVAL, "null argument");
   *out = nullptr;
   const int N = prob->N, D = prob->D_raw, d = prob->d;
@@ -670,6 +672,7 @@ extern "C" tn_status tn_mps_create(tn_ctx* ctx, int32_t N, int32_t d, const int3
   TN_CTX_OPEN(ctx);
   tn_mps* m = nullptr;
   TN_GUARD_BEGIN
+  struct Free { tn_mps*& h; ~Free() { if (h) mps_free(h); } } free_on_error{m};
   if (!out || !dims || !init) TN_THROW(TN_EINVAL, "null argument");
   *out = nullptr;
   if (N < 1 || d < 1) TN_THROW(TN_EINVAL, "N and d must be positive");

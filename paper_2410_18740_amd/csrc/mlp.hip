@@ -165,12 +165,15 @@ static uint64_t splitmix(uint64_t& s) {
   return z ^ (z >> 31);
 }
 
+extern "C" void tn_mlp_destroy(tn_mlp* M);
+
 extern "C" tn_status tn_mlp_create(tn_ctx* c, int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed,
                                    tn_mlp** out) {
   if (!c) return TN_EINVAL;
   TN_CTX_OPEN(c);
   tn_mlp* M = nullptr;
   TN_GUARD_BEGIN
+  struct Free { tn_mlp*& h; ~Free() { if (h) tn_mlp_destroy(h); } } free_on_error{M};
   if (!out) TN_THROW(TN_EINVAL, "null output");
   *out = nullptr;
   if (in_dim < 1 || hidden < 1 || out_dim < 1 || in_dim > 4096 || hidden > 4096 || out_dim > 4096)

@@ -149,17 +149,23 @@ def train(ctx, X, T, epochs: int = 200, batch: int = 256, lr: float = 1e-3, seed
 
 def solve_with_fallback(ctx, net, r, U, D: int, d: int, chi: int, seed: int, plain_tensors, plain_first: float,
                         max_sweeps: int, conv_tol: float = 1e-9, stop_at: float | None = None,
-                        learned_state: bool = True, lbo: bool = True):
+                        learned_state: bool = True, lbo: bool = True, params=None):
     """Learned start judged by <H> after its first sweep against the plain
     start's first-sweep energy plain_first; on failure the plain start runs
     and the learned sweep's time is added.  With learned_state False the
     learned bases start from plain_tensors instead of the learned product
     state; with lbo False the learned bases stay fixed (no local basis
     optimisation; the fallback still uses it).  Returns (trace, used_learned,
-    learned first-sweep energy)."""
+    learned first-sweep energy).  With params ([N][3] basis parameters) given
+    instead of net, the start uses those parameters (the analytic ones of
+    tn_ws_gaussian_params: the network's ceiling) under the same judge."""
     import torch
     t0 = time.perf_counter()
-    mpo, mps = learned_start(ctx, net, r, U, D, d, chi, seed, tensors=None if learned_state else plain_tensors)
+    tens = None if learned_state else plain_tensors
+    if params is not None:
+        mpo, mps = start_from_params(ctx, params, r, U, D, d, chi, seed, tensors=tens)
+    else:
+        mpo, mps = learned_start(ctx, net, r, U, D, d, chi, seed, tensors=tens)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     opts = sweep_opts(chi, lbo=lbo)

@@ -113,6 +113,16 @@ def test_failure_paths_are_reported_and_leave_handles_usable():
             P.MPS(ctx, t)
         assert ei.value.code == -1             # TN_EINVAL
         assert np.isfinite(P.dmrg_sweep(ctx, m, mp, P.SweepOpts(chi_max=8, tol=1e-10))["energy"])
+        # creation under a refusing allocator: TN_ENOMEM, nothing left half built
+        gate["open"] = False
+        for make in (lambda: P.MPO(ctx, r, U, 6), lambda: P.MPS(ctx, W.random_mps(6, 6, 8, 5)),
+                     lambda: P.MLP(ctx, 8, 16, 3)):
+            with pytest.raises(P.TnError) as ei:
+                make()
+            assert ei.value.code == -2
+        gate["open"] = True
+        assert np.isfinite(P.dmrg_sweep(ctx, P.MPO(ctx, r, U, 6), P.MPS(ctx, W.random_mps(6, 6, 8, 5)),
+                                        P.SweepOpts(chi_max=8, tol=1e-10))["energy"])
     finally:
         ctx.close()
 
