@@ -47,10 +47,6 @@ static __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& l
   hi = bf_from_bits(hb >> 16);
   lo = bf_from_bits(lb);
 }
-static __device__ __forceinline__ __bf16 bf_neg(__bf16 x) {
-  unsigned short b = __builtin_bit_cast(unsigned short, x);
-  return __builtin_bit_cast(__bf16, (unsigned short)(b ^ 0x8000u));
-}
 
 // Operand loads through global-address-space pointers: the operand pointers
 // come from the job tables, so without the cast they would be generic (flat)
@@ -103,9 +99,18 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
   constexpr int NA = BM * BK / NT, NB = BK * BN / NT;
   // double-buffered LDS tiles, k-major; one barrier per K tile, the next
   // tile's global loads are in flight (in registers) while the current one
-  // feeds the matrix cores
-  __shared__ CT As[2][BK][BM + 1];
-  __shared__ CT Bs[2][BK][BN + 1];
+  // feeds the matrix cores.  BF16x3 keeps its tiles already split: four bf16
+  // planes (hi and lo of the real and imaginary parts), each laid out as
+  // [k / 8][row][k % 8] so that a lane reads its eight k values of one row
+  // for v_mfma_f32_32x32x16_bf16 with one 16-byte load, and each element is
+  // split once per workgroup instead of once per wave that reads it.
+  constexpr bool HSPLIT = PREC == PREC_BF16X3;
+  constexpr int SMB = HSPLIT ? 2 * 4 * BK * (BM + BN) * 2 : 2 * BK * ((BM + 1) + (BN + 1)) * (int)sizeof(CT);
+  __shared__ __align__(16) unsigned char smraw[SMB];
+  auto As = reinterpret_cast<CT(*)[BK][BM + 1]>(smraw);
+  auto Bs = reinterpret_cast<CT(*)[BK][BN + 1]>(smraw + 2 * BK * (BM + 1) * sizeof(CT));
+  auto Ah = reinterpret_cast<__bf16(*)[4][BK / 8][BM][8]>(smraw);
+  auto Bh = reinterpret_cast<__bf16(*)[4][BK / 8][BN][8]>(smraw + 2 * 4 * BK * BM * 2);
 
   int bx, by, bz;
   tile_of(xcd_rows, bx, by, bz);
@@ -175,7 +180,17 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
       int mm, kk;
       if (!TA) { mm = idx / BK; kk = idx % BK; }
       else     { kk = idx / BM; mm = idx % BM; }
-      As[buf][kk][mm] = ra[t];
+      if constexpr (HSPLIT) {
+        __bf16 h, l;
+        split_bf16(ra[t].x, h, l);
+        Ah[buf][0][kk >> 3][mm][kk & 7] = h;
+        Ah[buf][1][kk >> 3][mm][kk & 7] = l;
+        split_bf16(ra[t].y, h, l);
+        Ah[buf][2][kk >> 3][mm][kk & 7] = h;
+        Ah[buf][3][kk >> 3][mm][kk & 7] = l;
+      } else {
+        As[buf][kk][mm] = ra[t];
+      }
     }
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
@@ -183,7 +198,17 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
       int kk, nn;
       if (!TB) { kk = idx / BN; nn = idx % BN; }
       else     { nn = idx / BK; kk = idx % BK; }
-      Bs[buf][kk][nn] = rb[t];
+      if constexpr (HSPLIT) {
+        __bf16 h, l;
+        split_bf16(rb[t].x, h, l);
+        Bh[buf][0][kk >> 3][nn][kk & 7] = h;
+        Bh[buf][1][kk >> 3][nn][kk & 7] = l;
+        split_bf16(rb[t].y, h, l);
+        Bh[buf][2][kk >> 3][nn][kk & 7] = h;
+        Bh[buf][3][kk >> 3][nn][kk & 7] = l;
+      } else {
+        Bs[buf][kk][nn] = rb[t];
+      }
     }
   };
 
@@ -247,26 +272,30 @@ __global__ __launch_bounds__(256, GemmCfg<PREC>::MINB) void cgemm_kernel(const G
       for (int kk = 0; kk < BK; kk += 16) {
         v8bf arh[NI], arl[NI], aih[NI], ail[NI], naih[NI], nail[NI];
         v8bf brh[NJ], brl[NJ], bih[NJ], bil[NJ];
+        // lane l holds row l % 32 and k = kk + 8 (l / 32) + t, t < 8
+        const int kg = (kk >> 3) + (lane >> 5);
+        auto ld8 = [](const __bf16* q) { return *reinterpret_cast<const v8bf*>(q); };
+        auto neg8 = [](v8bf x) {  // flip the sign bit of each bf16
+          typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+          return __builtin_bit_cast(v8bf, __builtin_bit_cast(u4, x) ^ (u4)0x80008000u);
+        };
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            CT v = As[buf][kk + 8 * (lane >> 5) + t][wm0 + 32 * i + (lane & 31)];
-            __bf16 h, l;
-            split_bf16(v.x, h, l); arh[i][t] = h; arl[i][t] = l;
-            split_bf16(v.y, h, l); aih[i][t] = h; ail[i][t] = l;
-            naih[i][t] = bf_neg(h); nail[i][t] = bf_neg(l);
-          }
+          const int m = wm0 + 32 * i + (lane & 31);
+          arh[i] = ld8(Ah[buf][0][kg][m]);
+          arl[i] = ld8(Ah[buf][1][kg][m]);
+          aih[i] = ld8(Ah[buf][2][kg][m]);
+          ail[i] = ld8(Ah[buf][3][kg][m]);
+          naih[i] = neg8(aih[i]);
+          nail[i] = neg8(ail[i]);
         }
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            CT v = Bs[buf][kk + 8 * (lane >> 5) + t][wn0 + 32 * j + (lane & 31)];
-            __bf16 h, l;
-            split_bf16(v.x, h, l); brh[j][t] = h; brl[j][t] = l;
-            split_bf16(v.y, h, l); bih[j][t] = h; bil[j][t] = l;
-          }
+          const int nn = wn0 + 32 * j + (lane & 31);
+          brh[j] = ld8(Bh[buf][0][kg][nn]);
+          brl[j] = ld8(Bh[buf][1][kg][nn]);
+          bih[j] = ld8(Bh[buf][2][kg][nn]);
+          bil[j] = ld8(Bh[buf][3][kg][nn]);
         }
 #pragma unroll
         for (int i = 0; i < NI; ++i)

@@ -147,3 +147,34 @@ def test_checkpoint_export_and_reimport(ctx):
     # the re-created copy is re-canonicalised (tensors move by rounding), so
     # the next sweep agrees to rounding of the converged energy
     assert abs(a - b) < 1e-12 * max(1.0, abs(a))
+
+
+def test_non_finite_operators_give_enumeric_and_leave_the_mps_at_its_last_step(ctx):
+    """A NaN met inside a sweep: a gate-parameterised basis with squeezing
+    r = 800 on one site overflows its operators (cosh r), so the sweep's
+    contractions turn non-finite.  The call returns TN_ENUMERIC, the MPS keeps
+    the tensors of its last completed step (bit for bit, finite, canonical),
+    and the same MPS sweeps normally again with a sound MPO."""
+    import paper_2410_18740_amd as P
+    r, U = W.make_problem(5, 2, (0.4, 0.6))
+    good = P.MPO(ctx, r, U, 6)
+    mp = P.MPS(ctx, W.random_mps(5, 6, 12, 3))
+    opts = P.SweepOpts(chi_max=12, tol=1e-10)
+    e0 = P.dmrg_sweep(ctx, good, mp, opts)["energy"]
+    before = mp.export()
+    bad = P.MPO(ctx, r, U, 6)
+    params = np.zeros((5, 8))
+    params[3, 2] = 800.0
+    P.plbo_enable(ctx, bad, params)
+    with pytest.raises(P.TnError) as ei:
+        P.dmrg_sweep(ctx, bad, mp, opts)
+    assert ei.value.code == -4                  # TN_ENUMERIC
+    after = mp.export()
+    for a, b in zip(before, after):
+        assert np.all(np.isfinite(b))
+        assert np.array_equal(a.view(np.float64), b.view(np.float64))
+    for A in after[1:]:                         # right-canonical behind the centre at site 0
+        M = A.reshape(A.shape[0], -1)
+        assert np.abs(M @ M.conj().T - np.eye(A.shape[0])).max() < 1e-12
+    e1 = P.dmrg_sweep(ctx, good, mp, opts)["energy"]
+    assert np.isfinite(e1) and abs(e1 - e0) <= 1e-2 * abs(e0)
