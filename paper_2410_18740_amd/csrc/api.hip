@@ -93,7 +93,8 @@ extern "C" tn_status tn_ctx_create(int device, void* hip_stream, const tn_alloca
   }
   bool ok = true;
   for (int i = 0; i < 8; ++i) ok = ok && (hipEventCreate(&c->ev[i]) == hipSuccess);
-  for (int i = 0; i < 6; ++i) ok = ok && (hipEventCreate(&c->pev[i]) == hipSuccess);
+  for (auto& ps : c->pslot)
+    for (int i = 0; i < 6; ++i) ok = ok && (hipEventCreate(&ps.e[i]) == hipSuccess);
   c->ev_ok = ok;
   *out = c;
   return TN_OK;
@@ -103,7 +104,8 @@ static void ctx_free(tn_ctx* c) {
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->ev_ok) {
     for (int i = 0; i < 8; ++i) (void)hipEventDestroy(c->ev[i]);
-    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(c->pev[i]);
+    for (auto& ps : c->pslot)
+      for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ps.e[i]);
     for (auto e : c->tri_ev) (void)hipEventDestroy(e);
   }
   delete c;
@@ -127,9 +129,30 @@ extern "C" void tn_ctx_destroy(tn_ctx* c) {
 
 extern "C" const char* tn_last_error(const tn_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+void prof_harvest(tn_ctx* c, tn_ctx::ProfSlot& ps) {
+  HIPCHK(hipEventSynchronize(ps.e[5]));
+  for (int i = 0; i < 5; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ps.e[i], ps.e[i + 1]));
+    c->prof_ms[i] += ms;
+  }
+  for (int i = 0; i < 3; ++i) c->prof_flops[i] += ps.fl[i];
+  c->prof_bytes[0] += ps.by[0];
+  c->prof_bytes[1] += ps.by[1];
+  c->prof_n += 1;
+  ps.pending = false;
+}
+
 extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
   if (!c) return TN_EINVAL;
   TN_CTX_OPEN(c);
+  TN_GUARD_BEGIN
+  // collect the slots still outstanding, oldest first
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int64_t k = std::max<int64_t>(0, c->pseq - tn_ctx::PROF_RING); k < c->pseq; ++k) {
+    auto& ps = c->pslot[k % tn_ctx::PROF_RING];
+    if (ps.pending) prof_harvest(c, ps);
+  }
   if (out) {
     for (int i = 0; i < 5; ++i) out[i] = c->prof_ms[i];
     out[5] = (double)c->prof_n;
@@ -152,6 +175,7 @@ extern "C" tn_status tn_profile(tn_ctx* c, int32_t mode, double* out) {
     c->prof_tri_n = 0;
     c->lz_iters = c->lz_full = 0;
   }
+  TN_GUARD_END(c)
   return TN_OK;
 }
 

@@ -40,9 +40,18 @@ struct tn_ctx {
   double* pinned = nullptr;                             // host pinned scratch (4096 doubles)
   hipEvent_t ev[8];
   bool ev_ok = false;
-  // profiling of the window matvec (HIP events around each launch)
+  // profiling of the window matvec: HIP events around each launch, in a ring
+  // of slots read back once a slot comes round again (or at read-out), so that
+  // profiling adds no wait to the matvec
   bool prof = false;
-  hipEvent_t pev[6];
+  struct ProfSlot {
+    hipEvent_t e[6];
+    double fl[3] = {0, 0, 0}, by[2] = {0, 0};
+    bool pending = false;
+  };
+  static constexpr int PROF_RING = 8;
+  ProfSlot pslot[PROF_RING];
+  int64_t pseq = 0;
   double prof_ms[5] = {0, 0, 0, 0, 0};   // convert, GEMM-L, operators, GEMM-R, reduce
   double prof_flops[3] = {0, 0, 0};      // algorithmic: L-contraction, R-contraction, whole matvec
   int64_t prof_n = 0;
@@ -53,6 +62,9 @@ struct tn_ctx {
   int64_t prof_tri_n = 0;
   int64_t lz_iters = 0, lz_full = 0;  // Lanczos iterations, and those orthogonalised against the whole basis
 };
+
+// add a profiling slot's event times and work counts to the totals (waits for its last event)
+void prof_harvest(tn_ctx* c, tn_ctx::ProfSlot& ps);
 
 // per-device address of tn_sample_noalloc's scratch, taken with `device` current
 tn_status sample_scratch_setup(int device);
@@ -191,6 +203,9 @@ struct WindowOp {
              const std::vector<const void*>& envL, const std::vector<const void*>& envRt, bool raw_leg0,
              const std::string& tag);
   void apply(const cf64* x, cf64* y);
+  // the matvec up to its split-K partials (nsplit parts of n in the storage
+  // precision, not yet summed); x_ready: xin already holds x in that precision
+  void run(const cf64* x, bool x_ready);
   void apply_left(const cf64* x);  // only the conversion of x and the left contraction into ybuf
 };
 

@@ -98,6 +98,7 @@ __global__ __launch_bounds__(256) void opapply_reg_kernel(const OpJob* __restric
                                                            int dt, int chi_r, int bw) {
   using RT = typename real_of<CT>::type;
   extern __shared__ unsigned char smem_raw[];
+  __shared__ int bandS[2];  // one-leg form: bandwidth of the s-leg operator, slots alternate per term
   CT* opa = reinterpret_cast<CT*>(smem_raw);  // ds * ds
   CT* opb = opa + MD * MD;                    // dt * dt
   CT* tmp = opb + MD * MD;                    // [ds][dt][bw] (two legs)
@@ -127,13 +128,25 @@ __global__ __launch_bounds__(256) void opapply_reg_kernel(const OpJob* __restric
     for (int s = 0; s < MD; ++s)
       if (s < ds) acc[s] = dst[col + s * sstride];
   }
+  if (!TWO && tid == 0) { bandS[0] = 0; bandS[1] = 0; }
   for (int k = 0; k < job.nterms; ++k) {
     const OpTerm term = terms[job.t0 + k];
     const CT* src = reinterpret_cast<const CT*>(term.src);
     const CT* oA = reinterpret_cast<const CT*>(term.opA);
     const CT* oB = reinterpret_cast<const CT*>(term.opB);
-    __syncthreads();  // the previous term is done with opa, opb and tmp
-    for (int e = tid; e < ds * ds; e += blockDim.x) opa[e] = oA ? oA[e] : czero<CT>();
+    __syncthreads();  // the previous term is done with opa, opb, tmp and its band slot
+    if (TWO) {
+      for (int e = tid; e < ds * ds; e += blockDim.x) opa[e] = oA ? oA[e] : czero<CT>();
+    } else {
+      // stage the operator and record how far its nonzeros reach from the
+      // diagonal (the Fock-basis operators are banded: |s' - s| <= 2)
+      if (tid == 0) bandS[(k + 1) & 1] = 0;
+      for (int e = tid; e < ds * ds; e += blockDim.x) {
+        const CT o = oA ? oA[e] : czero<CT>();
+        opa[e] = o;
+        if (o.x != (RT)0 || o.y != (RT)0) atomicMax(&bandS[k & 1], abs(e / ds - e % ds));
+      }
+    }
     if (TWO)
       for (int e = tid; e < dt * dt; e += blockDim.x) opb[e] = oB ? oB[e] : czero<CT>();
     CT z[MD];
@@ -168,7 +181,35 @@ __global__ __launch_bounds__(256) void opapply_reg_kernel(const OpJob* __restric
       __syncthreads();  // opa staged
     }
     const RT c = (RT)term.coef;
-    if (oA) {
+    if (!TWO && oA) {
+      // v[s'] = sum_s op[s'][s] z[s] along the diagonals the operator occupies;
+      // for each s' the terms still come in increasing s, and the entries
+      // skipped are zeros, so the sums are those of the dense loop
+      const int band = __builtin_amdgcn_readfirstlane(bandS[k & 1]);
+      CT v[MD];
+#pragma unroll
+      for (int sp = 0; sp < MD; ++sp) v[sp] = czero<CT>();
+#pragma unroll
+      for (int off = -(MD - 1); off <= MD - 1; ++off) {
+        if (off < -band || off > band) continue;
+#pragma unroll
+        for (int sp = 0; sp < MD; ++sp) {
+          const int sc = sp + off;
+          if (sc < 0 || sc >= MD) continue;
+          if (sp < ds && sc < ds) {
+            const CT o = opa[sp * ds + sc];
+            v[sp].x += o.x * z[sc].x - o.y * z[sc].y;
+            v[sp].y += o.x * z[sc].y + o.y * z[sc].x;
+          }
+        }
+      }
+#pragma unroll
+      for (int sp = 0; sp < MD; ++sp)
+        if (sp < ds) {
+          acc[sp].x += c * v[sp].x;
+          acc[sp].y += c * v[sp].y;
+        }
+    } else if (oA) {
 #pragma unroll
       for (int sp = 0; sp < MD; ++sp) {
         if (sp < ds) {
