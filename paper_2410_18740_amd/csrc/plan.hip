@@ -194,12 +194,15 @@ void WindowOp::setup(tn_ctx* c, const tn_mpo* mpo, int site, int nsites, int pre
   xin = ws_get(ctx, tag + ":xin", n * eb);
   ybuf = Y;
   rptr = Rptr;
-  // split-K for the right contraction
-  const int BMr = (gprec == PREC_FP64) ? 64 : 128, BNr = BMr;
+  // split-K for the right contraction: as many splits as fill one round of
+  // workgroups (the GEMM's tiles at its workgroups per CU on 256 CUs) without
+  // starting a second, partly filled round
+  const int BMr = (gprec == PREC_FP64) ? 64 : 128, BNr = 64;
+  const int round = 256 * (gprec == PREC_FP32 ? 3 : 2);
   const int Mr = chi_l * ds * dt;
   const int tiles = ((Mr + BMr - 1) / BMr) * ((chi_r + BNr - 1) / BNr);
   const int nR = (int)plan.R.size();
-  nsplit = std::max(1, std::min(nR, (512 + tiles - 1) / tiles));
+  nsplit = std::max(1, std::min(nR, round / tiles));
   partials = ws_get(ctx, tag + ":part", (size_t)nsplit * n * eb);
   // --- descriptors
   std::vector<GemmJob> jl;
