@@ -335,8 +335,9 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cgemm_fp32_gbs_n32_chi128_traf
 
 def gemm_traffic(form, workload):
     """HBM bytes per launch of the matvec GEMM from the committed rocprofv3
-    --pmc summary, or None when it does not cover this form and workload or the
-    GEMM source has changed since the counters were taken."""
+    --pmc summary, or None when it does not cover this form and workload, or
+    when the GEMM or the planner that shapes its launches (split-K) has changed
+    since the counters were taken."""
     import hashlib
     if form != "fp32" or workload != "gbs_n32_d16to8_chi128" or not os.path.exists(TRAFFIC_SUMMARY):
         return None
@@ -345,9 +346,10 @@ def gemm_traffic(form, workload):
         if ":" in line and line.startswith("- `"):
             k, v = line[3:].split("`", 1)
             vals[k] = v.split(":", 1)[1].strip().strip("`")
-    src = os.path.join(ROOT, "paper_2410_18740_amd", "csrc", "gemm.hip")
-    if vals.get("gemm_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
-        return None
+    for key, name in (("gemm_source_sha256", "gemm.hip"), ("plan_source_sha256", "plan.hip")):
+        src = os.path.join(ROOT, "paper_2410_18740_amd", "csrc", name)
+        if vals.get(key) != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
