@@ -187,3 +187,26 @@ def test_handles_may_outlive_their_context_at_the_abi():
     lib.tn_ctx_destroy(ctx)
     lib.tn_mpo_destroy(mpo)
     lib.tn_mps_destroy(mps)          # the last reference: the context goes here
+
+
+def test_profiling_counts_every_matvec_of_a_sweep(ctx, four_mode):
+    """The matvec profiling (HIP events per launch, kept in a ring of slots that
+    are read back when a slot comes round again or at read-out): after a sweep
+    with profiling on, the read-out covers every matvec of the sweep, with
+    finite non-negative phase times; stopping it resets the counters."""
+    import paper_2410_18740_amd as P
+    mpo = P.MPO(ctx, four_mode["r"], four_mode["U"], 6)
+    mps = P.MPS(ctx, four_mode["m0"])
+    ctx.profile(1)
+    st = P.dmrg_sweep(ctx, mpo, mps, P.SweepOpts(chi_max=16, precision=P.FP32, tol=1e-10, max_matvecs=16))
+    pr = ctx.profile(-1)
+    ctx.profile(0)
+    print(f"sweep matvecs {st['matvecs']}, profiled {pr['matvecs']}, GEMM ms {pr['ms_gemm_l'] + pr['ms_gemm_r']:.3f}")
+    assert st["matvecs"] > 8  # more matvecs than ring slots: slots were reused
+    assert pr["matvecs"] == st["matvecs"]
+    assert pr["lanczos_iters"] == st["matvecs"]
+    for k in ("ms_convert", "ms_gemm_l", "ms_ops", "ms_gemm_r", "ms_reduce"):
+        assert np.isfinite(pr[k]) and pr[k] >= 0.0
+    assert pr["ms_gemm_l"] > 0.0 and pr["ms_gemm_r"] > 0.0 and pr["flops_matvec"] > 0.0
+    z = ctx.profile(-1)
+    assert z["matvecs"] == 0 and z["ms_gemm_l"] == 0.0
