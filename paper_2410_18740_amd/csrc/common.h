@@ -147,9 +147,6 @@ hipError_t launch_reduce_partials(cf64* out, int prec, const void* partials, int
 hipError_t launch_multidot(const cf64* const* vs, int nv, const cf64* w, int64_t n, cf64* partials, int nblocks,
                            hipStream_t st);
 hipError_t launch_multidot_finish(const cf64* partials, int nv, int nblocks, cf64* out, hipStream_t st);
-hipError_t launch_multiaxpy(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, double sign, int64_t n,
-                            hipStream_t st);
-hipError_t launch_scale(cf64* dst, const cf64* src, const double* inv_norm_dev, int64_t n, hipStream_t st);
 hipError_t launch_axpy_dot(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, int64_t n, cf64* partials,
                            int nblocks, hipStream_t st);
 hipError_t launch_axpy_scale(cf64* dst, const cf64* w, const cf64* const* vs, int nv, const cf64* coefs,
@@ -164,8 +161,6 @@ int multidot_blocks(int64_t n);
 // ascending, eigenvectors as columns of V [batch][n][n].
 hipError_t launch_jacobi(const cf64* A, int64_t strideA, int n, int batch, double* evals, cf64* V, int64_t strideV,
                          int descending, hipStream_t st);
-// build a real symmetric tridiagonal (alpha[0..n-1], beta[0..n-2]) as a dense complex matrix
-hipError_t launch_build_tridiag(const double* alpha, const double* beta, int n, cf64* A, hipStream_t st);
 
 // Householder tridiagonalisation of a Hermitian p x p matrix (row-major, in place).
 struct TridiagWork {
@@ -196,12 +191,9 @@ hipError_t launch_transpose_from64(int prec, void* dst, const cf64* src, int bat
 hipError_t launch_transpose_to64(int prec, cf64* dst, const void* src, int batch, int rows, int cols, hipStream_t st);
 hipError_t launch_scale_host(cf64* dst, const cf64* src, double s, int64_t n, hipStream_t st);
 hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream_t st);
-hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta,
-                               double* inv, double* coefs, double* out, hipStream_t st);
 hipError_t launch_lanczos_ab(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta, double* inv,
                              double* out, hipStream_t st);
 hipError_t launch_inv_norm(const cf64* h, int nv, double* inv, hipStream_t st);
-hipError_t launch_ritz_coefs(const cf64* V, int n, double* out, double* last, hipStream_t st);
 hipError_t launch_finite_check(const cf64* x, int64_t n, int* flag, hipStream_t st);
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 hipError_t launch_set_one(void* p, int prec, hipStream_t st);

@@ -188,21 +188,6 @@ hipError_t launch_jacobi(const cf64* A, int64_t strideA, int n, int batch, doubl
   return hipGetLastError();
 }
 
-__global__ void build_tridiag_kernel(const double* alpha, const double* beta, int n, cf64* A) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
-    const int i = e / n, j = e % n;
-    double v = 0.0;
-    if (i == j) v = alpha[i];
-    else if (j == i + 1) v = beta[i];
-    else if (i == j + 1) v = beta[j];
-    A[e] = make_double2(v, 0.0);
-  }
-}
-hipError_t launch_build_tridiag(const double* alpha, const double* beta, int n, cf64* A, hipStream_t st) {
-  hipLaunchKernelGGL(build_tridiag_kernel, dim3((n * n + 255) / 256), dim3(256), 0, st, alpha, beta, n, A);
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ Householder tridiagonalisation
 // One launch per column j.  Every workgroup recomputes (redundantly, from data
 // finalised by the previous launch) w_{j-1} = y_{j-1} - 1/2 tau_{j-1}

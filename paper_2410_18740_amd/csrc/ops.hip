@@ -442,27 +442,6 @@ hipError_t launch_multidot_finish(const cf64* partials, int nv, int nblocks, cf6
   return hipGetLastError();
 }
 
-// w -= sign * sum_v coefs[v] * vs[v]   (coefs on device)
-__global__ void multiaxpy_kernel(cf64* w, const cf64* const* __restrict__ vs, int nv, const cf64* __restrict__ coefs,
-                                 double sign, int64_t n) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-    cf64 acc = w[e];
-    for (int v = 0; v < nv; ++v) {
-      const cf64 c = coefs[v];
-      const cf64 x = vs[v][e];
-      acc.x -= sign * (c.x * x.x - c.y * x.y);
-      acc.y -= sign * (c.x * x.y + c.y * x.x);
-    }
-    w[e] = acc;
-  }
-}
-hipError_t launch_multiaxpy(cf64* w, const cf64* const* vs, int nv, const cf64* coefs, double sign, int64_t n,
-                            hipStream_t st) {
-  if (nv <= 0 || n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(multiaxpy_kernel, dim3(grid_for(n)), dim3(256), 0, st, w, vs, nv, coefs, sign, n);
-  return hipGetLastError();
-}
-
 // Fused first update and second-pass dot products of classical Gram-Schmidt:
 //   w <- w - sum_v coefs[v] vs[v];  partials[v][block] = <vs[v], w> (v < nv),
 //   partials[nv][block] = <w, w>.
@@ -563,18 +542,6 @@ hipError_t launch_axpy_scale(cf64* dst, const cf64* w, const cf64* const* vs, in
   return hipGetLastError();
 }
 
-// dst = src * inv_norm[0]
-__global__ void scale_kernel(cf64* dst, const cf64* src, const double* s, int64_t n) {
-  const double f = s[0];
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    dst[e] = make_double2(src[e].x * f, src[e].y * f);
-}
-hipError_t launch_scale(cf64* dst, const cf64* src, const double* inv_norm_dev, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, src, inv_norm_dev, n);
-  return hipGetLastError();
-}
-
 // dst = sum_v coefs[v] * vs[v]  (real coefficients on device)
 __global__ void lincomb_kernel(cf64* dst, const cf64* const* __restrict__ vs, int nv, const double* __restrict__ c,
                                int64_t n) {
@@ -666,249 +633,6 @@ hipError_t launch_ctranspose(cf64* dst, const cf64* src, int n, int k, hipStream
   hipLaunchKernelGGL(ctranspose_kernel, dim3(grid_for(tot)), dim3(256), 0, st, dst, src, n, k);
   return hipGetLastError();
 }
-// Lanczos step scalars and the projected problem, one wavefront:
-//   alpha_j = Re(h1[j] + h2[j]);  ||w||^2 = <w1, w1> - sum_i |h2_i|^2 (h2[j+1] holds
-//   <w1, w1> from the second Gram-Schmidt pass);  beta_j = ||w||.
-// Then the lowest eigenpair of the (j+1) x (j+1) tridiagonal T_j: 64-way
-// multisection on Sturm counts for the eigenvalue, inverse iteration with
-// partial pivoting (one lane) for the eigenvector, written as Ritz
-// coefficients.  host_out = {alpha, beta, lambda, y_last}.
-// Lowest eigenvector of the n x n tridiagonal (sa, sb) at the eigenvalue lam by
-// three steps of inverse iteration with an LU factorisation with partial
-// pivoting of T - lam I, all in registers (n <= MN): no LDS round trip on the
-// dependent chains.  Writes y (normalised, first component >= 0) to coefs and
-// returns its last component.
-template <int MN>
-static __device__ double tri_eigvec_reg(const double* sa, const double* sb, int n, double lam, double tiny,
-                                        double* coefs) {
-  double dd[MN], du[MN], du2[MN], dl[MN], y[MN];
-  unsigned long long piv = 0;
-#pragma unroll
-  for (int i = 0; i < MN; ++i) {
-    dd[i] = (i < n) ? sa[i] - lam : 1.0;
-    du[i] = (i < n - 1) ? sb[i] : 0.0;
-    dl[i] = du[i];
-    du2[i] = 0.0;
-  }
-  {
-    double cdd = dd[0], cdu = du[0];
-#pragma unroll
-    for (int i = 0; i < MN - 1; ++i) {
-      if (i < n - 1) {
-        const double l = dl[i], ndd = dd[i + 1], ndu = du[i + 1];
-        if (fabs(cdd) >= fabs(l)) {
-          if (cdd == 0.0) cdd = tiny;
-          const double f = l * recip_nr(cdd);
-          dd[i] = cdd;
-          dl[i] = f;
-          du[i] = cdu;
-          cdd = ndd - f * cdu;
-          cdu = ndu;
-        } else {
-          const double f = cdd * recip_nr(l);
-          dd[i] = l;
-          dl[i] = f;
-          du[i] = ndd;
-          piv |= 1ull << i;
-          cdd = cdu - f * ndd;
-          if (i < n - 2) { du2[i] = ndu; cdu = -f * ndu; }
-          else cdu = ndu;
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < MN; ++i)
-      if (i == n - 1) dd[i] = cdd;
-  }
-  // reciprocal pivots
-#pragma unroll
-  for (int i = 0; i < MN; ++i) {
-    double v = dd[i];
-    if (fabs(v) < tiny) v = v >= 0 ? tiny : -tiny;
-    dd[i] = 1.0 / v;
-    y[i] = 1.0;
-  }
-  for (int it = 0; it < 3; ++it) {
-    double cb = y[0];
-#pragma unroll
-    for (int i = 0; i < MN - 1; ++i) {
-      if (i < n - 1) {
-        const double nb = y[i + 1], l = dl[i];
-        if ((piv >> i) & 1ull) { y[i] = nb; cb = cb - l * nb; }
-        else { y[i] = cb; cb = nb - l * cb; }
-      }
-    }
-    double x1 = 0.0, x2 = 0.0;
-#pragma unroll
-    for (int i = MN - 1; i >= 0; --i) {
-      if (i < n) {
-        const double bi = (i == n - 1) ? cb : y[i];
-        const double x0 = (bi - du[i] * x1 - du2[i] * x2) * dd[i];  // du[n-1] = du2[n-2..] = 0
-        y[i] = x0;
-        x2 = x1;
-        x1 = x0;
-      }
-    }
-    double nr = 0.0;
-#pragma unroll
-    for (int i = 0; i < MN; ++i)
-      if (i < n) nr += y[i] * y[i];
-    nr = 1.0 / sqrt(nr);
-#pragma unroll
-    for (int i = 0; i < MN; ++i) y[i] *= nr;
-  }
-  const double sg = (y[0] < 0.0) ? -1.0 : 1.0;
-  double last = 0.0;
-#pragma unroll
-  for (int i = 0; i < MN; ++i) {
-    if (i < n) coefs[i] = sg * y[i];
-    if (i == n - 1) last = sg * y[i];
-  }
-  return last;
-}
-
-__global__ __launch_bounds__(64) void lanczos_step_kernel(const cf64* h1, const cf64* h2, int j, int i0,
-                                                          double* alpha, double* beta, double* inv, double* coefs,
-                                                          double* out) {
-  __shared__ double sa[80], sb[80], y[80], dd[80], du[80], du2[80], dl[80];
-  __shared__ int piv[80];
-  __shared__ double lam_s;
-  const int lane = threadIdx.x;
-  {
-    // ||w||^2 after the second pass = <w, w> - sum_i |h2_i|^2 (lanes in parallel)
-    double part = 0.0;
-    for (int i = i0 + lane; i <= j; i += 64) part += h2[i].x * h2[i].x + h2[i].y * h2[i].y;
-    const double sum = wave_sum(part);
-    if (lane == 0) {
-      const double a = h1[j].x + h2[j].x;
-      const double w2 = h2[j + 1].x - sum;
-      const double b = sqrt(fmax(w2, 0.0));
-      alpha[j] = a;
-      beta[j] = b;
-      inv[0] = (b > 0.0) ? 1.0 / b : 0.0;
-      out[0] = a;
-      out[1] = b;
-    }
-  }
-  __syncthreads();
-  const int n = j + 1;
-  for (int i = lane; i < n; i += 64) { sa[i] = alpha[i]; sb[i] = (i < n - 1) ? beta[i] : 0.0; }
-  __syncthreads();
-  double lo = 1e300, hi = -1e300;
-  for (int i = lane; i < n; i += 64) {
-    const double r = (i > 0 ? fabs(sb[i - 1]) : 0.0) + (i < n - 1 ? fabs(sb[i]) : 0.0);
-    lo = fmin(lo, sa[i] - r);
-    hi = fmax(hi, sa[i] + r);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o, 64));
-    hi = fmax(hi, __shfl_xor(hi, o, 64));
-  }
-  const double sc = fmax(fabs(lo), fabs(hi)) + 1e-300;
-  lo -= 1e-14 * sc;
-  hi += 1e-14 * sc;
-  for (int it = 0; it < 40; ++it) {
-    if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
-    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-    int cnt = 0;
-    double q = sa[0] - x;
-    if (fabs(q) < 1e-300) q = -1e-300;
-    cnt += q < 0;
-    for (int i = 1; i < n; ++i) {
-      q = (sa[i] - x) - sb[i - 1] * sb[i - 1] * recip_nr(q);
-      if (fabs(q) < 1e-300) q = -1e-300;
-      cnt += q < 0;
-    }
-    const unsigned long long le = __ballot(cnt == 0);
-    const int nle = __popcll(le);
-    const double nlo = (nle == 0) ? lo : __shfl(x, nle - 1, 64);
-    const double nhi = (nle == 64) ? hi : __shfl(x, nle, 64);
-    if (!(nhi - nlo < hi - lo)) break;
-    lo = nlo;
-    hi = nhi;
-  }
-  if (lane == 0 && n <= 24) {
-    const double lam = 0.5 * (lo + hi);
-    const double tiny = fmax(2.2e-16 * sc, 1e-300);
-    const double last = (n <= 8) ? tri_eigvec_reg<8>(sa, sb, n, lam, tiny, coefs)
-                                 : tri_eigvec_reg<24>(sa, sb, n, lam, tiny, coefs);
-    out[2] = lam;
-    out[3] = last;
-  } else if (lane == 0) {
-    const double lam = 0.5 * (lo + hi);
-    lam_s = lam;
-    const double tiny = fmax(2.2e-16 * sc, 1e-300);
-    // LU with partial pivoting of T - lam I, the running entries in registers
-    for (int i = 0; i < n; ++i) {
-      dd[i] = sa[i] - lam;
-      du[i] = (i < n - 1) ? sb[i] : 0.0;
-      dl[i] = (i < n - 1) ? sb[i] : 0.0;
-      du2[i] = 0.0;
-      piv[i] = 0;
-    }
-    {
-      double cdd = dd[0], cdu = du[0];
-      for (int i = 0; i < n - 1; ++i) {
-        const double l = dl[i], ndd = dd[i + 1], ndu = du[i + 1];
-        if (fabs(cdd) >= fabs(l)) {
-          if (cdd == 0.0) cdd = tiny;
-          const double f = l / cdd;
-          dd[i] = cdd;
-          dl[i] = f;
-          du[i] = cdu;
-          cdd = ndd - f * cdu;
-          cdu = ndu;
-        } else {
-          const double f = cdd / l;
-          dd[i] = l;
-          dl[i] = f;
-          du[i] = ndd;
-          piv[i] = 1;
-          cdd = cdu - f * ndd;
-          if (i < n - 2) { du2[i] = ndu; cdu = -f * ndu; }
-          else cdu = ndu;
-        }
-      }
-      dd[n - 1] = cdd;
-    }
-    for (int i = 0; i < n; ++i)
-      if (fabs(dd[i]) < tiny) dd[i] = dd[i] >= 0 ? tiny : -tiny;
-    for (int i = 0; i < n; ++i) y[i] = 1.0;
-    for (int it = 0; it < 3; ++it) {
-      double cb = y[0];
-      for (int i = 0; i < n - 1; ++i) {
-        const double nb = y[i + 1], l = dl[i];
-        if (piv[i]) { y[i] = nb; cb = cb - l * nb; }
-        else { y[i] = cb; cb = nb - l * cb; }
-      }
-      double x1 = cb / dd[n - 1];
-      y[n - 1] = x1;
-      double x2 = 0.0;
-      if (n >= 2) {
-        const double x0 = (y[n - 2] - du[n - 2] * x1) / dd[n - 2];
-        y[n - 2] = x0;
-        x2 = x1;
-        x1 = x0;
-      }
-      for (int i = n - 3; i >= 0; --i) {
-        const double x0 = (y[i] - du[i] * x1 - du2[i] * x2) / dd[i];
-        y[i] = x0;
-        x2 = x1;
-        x1 = x0;
-      }
-      double nr = 0.0;
-      for (int i = 0; i < n; ++i) nr += y[i] * y[i];
-      nr = 1.0 / sqrt(nr);
-      for (int i = 0; i < n; ++i) y[i] *= nr;
-    }
-    // sign convention: first component non-negative
-    const double sg = (y[0] < 0.0) ? -1.0 : 1.0;
-    for (int i = 0; i < n; ++i) coefs[i] = sg * y[i];
-    out[2] = lam;
-    out[3] = sg * y[n - 1];
-  }
-}
 // The recurrence scalars alone: alpha_j, beta_j (from the two Gram-Schmidt
 // passes' dots) and 1/beta_j for the normalisation, with out[0..1] = alpha_j,
 // beta_j for the host, which solves the small Ritz problem itself.
@@ -936,13 +660,6 @@ hipError_t launch_lanczos_ab(const cf64* h1, const cf64* h2, int j, int i0, doub
   return hipGetLastError();
 }
 
-hipError_t launch_lanczos_step(const cf64* h1, const cf64* h2, int j, int i0, double* alpha, double* beta,
-                               double* inv, double* coefs, double* out, hipStream_t st) {
-  if (j + 1 > 72 || i0 < 0 || i0 > j) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(64), 0, st, h1, h2, j, i0, alpha, beta, inv, coefs, out);
-  return hipGetLastError();
-}
-
 // inv[0] = 1 / sqrt(h[nv] - sum_{i < nv} |h_i|^2): the norm after a Gram-Schmidt
 // update whose second-pass dots are h[0..nv) and whose <w, w> before it is h[nv]
 __global__ __launch_bounds__(64) void inv_norm_kernel(const cf64* h, int nv, double* inv) {
@@ -957,16 +674,6 @@ __global__ __launch_bounds__(64) void inv_norm_kernel(const cf64* h, int nv, dou
 }
 hipError_t launch_inv_norm(const cf64* h, int nv, double* inv, hipStream_t st) {
   hipLaunchKernelGGL(inv_norm_kernel, dim3(1), dim3(64), 0, st, h, nv, inv);
-  return hipGetLastError();
-}
-// gather real parts of column 0 of an n x n complex matrix (eigenvectors as columns)
-__global__ void ritz_coefs_kernel(const cf64* V, int n, double* out, double* last) {
-  const int i = threadIdx.x;
-  if (i < n) out[i] = V[(int64_t)i * n].x;
-  if (i == 0) last[0] = V[(int64_t)(n - 1) * n].x;
-}
-hipError_t launch_ritz_coefs(const cf64* V, int n, double* out, double* last, hipStream_t st) {
-  hipLaunchKernelGGL(ritz_coefs_kernel, dim3(1), dim3(64), 0, st, V, n, out, last);
   return hipGetLastError();
 }
 // non-finite check: flag[0] = 1 if any entry is NaN/Inf
