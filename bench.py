@@ -431,7 +431,7 @@ def _solve_to(P, ctx, mpo, mps, w_chi, prec, a, target=1e-8):
 
 
 def warmstart_mesh(a):
-    """Learned warm start judged by time to <H> <= 1e-8 on weakly squeezed
+    """Learned warm start measured by time to <H> <= 1e-8 on weakly squeezed
     brickwork meshes (N = 32, cutoff 16 -> 8, chi 128), where the literal
     target is reachable: plain random start vs learned bases + learned product
     state, each with the FP64 and the FP32 + refine schedule.  The learned
@@ -703,7 +703,7 @@ def warmstart_ceiling(a, ctx, net, fam, e_lo, e_hi):
     """The network against its ceiling in the form where its bases help (held
     fixed, no LBO): the network's squeezed bases and the analytic ones read
     off each mode's reduced covariance (tn_ws_gaussian_params, exact for a
-    Gaussian state), each with the plain random tensors and the same judge
+    Gaussian state), each with the plain random tensors and the same acceptance test
     (kept if the first-sweep <H> is not above the plain start's), beside the
     plain start with LBO.  Relative targets from the lowest final energy of
     the three."""
@@ -769,7 +769,7 @@ def config4_bench(a):
     """The 48-mode configuration end to end on one GPU: Haar U from seed 4,
     r ~ U[1.0, 1.5], D_raw 24 compressed by LBO to 10, chi 256.  The start is
     the learned one (network from --net-out of the 20-mode Haar warm-start
-    run), judged by <H> after its first sweep against the plain start's first
+    run), accepted or rejected by <H> after its first sweep against the plain start's first
     sweep; then FP32 bulk sweeps with an FP64 refinement sweep (tn_dmrg_solve),
     then 10^5 photon-number samples by sequential conditional sampling, whose
     first-8-mode histograms are compared with the library's exact marginals
@@ -789,7 +789,7 @@ def config4_bench(a):
     init = W.random_mps(w.N, w.d, w.chi, w.mps_seed)
     sw1 = P.SweepOpts(chi_max=w.chi, tol=1e-6, krylov_max=24, max_matvecs=a.max_matvecs, precision=FORMS["fp32"],
                       lbo=1)
-    # plain start: first sweep only (the judge's reference)
+    # plain start: first sweep only (the acceptance test's reference)
     t0 = time.perf_counter()
     mpo_p, mps_p = WS.plain_start(ctx, r, U, w.D_raw, w.d, init)
     e_plain1 = P.dmrg_sweep(ctx, mpo_p, mps_p, sw1)["energy"]

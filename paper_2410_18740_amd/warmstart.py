@@ -7,9 +7,9 @@ optimal local basis of a Gaussian reduced state (Sec. III.A.1), and the
 thermal occupation nbar_j, whose eigenvalues give a product-state initial MPS.
 Training targets come from the solver itself: plain DMRG + LBO runs, their
 single-site reduced density matrices (tn_rdm) and the moment map
-tn_ws_targets.  <H> after the first sweep judges the learned start; when it
-is worse than the plain start's first sweep, or not finite, the plain start
-is used (and its time is counted).
+tn_ws_targets.  <H> after the first sweep decides whether the learned start
+is kept; when it is worse than the plain start's first sweep, or not finite,
+the plain start is used (and its time is counted).
 
 This module only orders calls into the library; every arithmetic step runs in
 libtn.so (kernels, or host helpers that do no GPU work).
@@ -150,15 +150,15 @@ def train(ctx, X, T, epochs: int = 200, batch: int = 256, lr: float = 1e-3, seed
 def solve_with_fallback(ctx, net, r, U, D: int, d: int, chi: int, seed: int, plain_tensors, plain_first: float,
                         max_sweeps: int, conv_tol: float = 1e-9, stop_at: float | None = None,
                         learned_state: bool = True, lbo: bool = True, params=None):
-    """Learned start judged by <H> after its first sweep against the plain
-    start's first-sweep energy plain_first; on failure the plain start runs
+    """Learned start accepted or rejected by <H> after its first sweep against
+    the plain start's first-sweep energy plain_first; on failure the plain start runs
     and the learned sweep's time is added.  With learned_state False the
     learned bases start from plain_tensors instead of the learned product
     state; with lbo False the learned bases stay fixed (no local basis
     optimisation; the fallback still uses it).  Returns (trace, used_learned,
     learned first-sweep energy).  With params ([N][3] basis parameters) given
     instead of net, the start uses those parameters (the analytic ones of
-    tn_ws_gaussian_params: the network's ceiling) under the same judge."""
+    tn_ws_gaussian_params: the network's ceiling) under the same acceptance test."""
     import torch
     t0 = time.perf_counter()
     tens = None if learned_state else plain_tensors
