@@ -863,7 +863,6 @@ __global__ __launch_bounds__(64) void backtransform_kernel(const cf64* __restric
 // builds T; the apply kernel then costs two passes over a block's reflectors and
 // one batch of reductions per block instead of a dependent chain per reflector.
 constexpr int WY_NB = 16;
-constexpr int WY_T = 512;
 
 __global__ __launch_bounds__(256) void wy_factor_kernel(const cf64* __restrict__ vs, const cf64* __restrict__ taus,
                                                          int p, cf64* __restrict__ Tout) {
@@ -905,14 +904,15 @@ __global__ __launch_bounds__(256) void wy_factor_kernel(const cf64* __restrict__
   for (int q = tid; q < WY_NB * WY_NB; q += 256) out[q] = T[q / WY_NB][q % WY_NB];
 }
 
-// One workgroup of WY_T threads per eigenvector column; thread t keeps rows
-// t + WY_T e (e < MAXE).
+constexpr int WY_RT = 512;
+// Sizes up to 1024: one workgroup of WY_RT threads per eigenvector column;
+// thread t keeps rows t + WY_RT e (e < MAXE) in registers.
 // Blocks are applied last to first: U = Q_0 Q_1 ... X with Q_b = 1 - V_b T_b V_b^H.
 template <int MAXE>
-__global__ __launch_bounds__(WY_T) void wy_apply_kernel(const cf64* __restrict__ vs, const cf64* __restrict__ Tw,
+__global__ __launch_bounds__(WY_RT) void wy_apply_reg_kernel(const cf64* __restrict__ vs, const cf64* __restrict__ Tw,
                                                         int p, const double* __restrict__ X, int k,
                                                         cf64* __restrict__ U) {
-  __shared__ double red[WY_T / 64][2 * WY_NB];
+  __shared__ double red[WY_RT / 64][2 * WY_NB];
   __shared__ cf64 w[WY_NB], w2[WY_NB];
   __shared__ cf64 Ts[WY_NB * WY_NB];
   const int col = blockIdx.x;
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(WY_T) void wy_apply_kernel(const cf64* __restrict__
   cf64 x[MAXE];
 #pragma unroll
   for (int e = 0; e < MAXE; ++e) {
-    const int r = tid + WY_T * e;
+    const int r = tid + WY_RT * e;
     x[e] = make_double2(r < p ? X[(int64_t)col * p + r] : 0.0, 0.0);
   }
   const int nblk = (p - 1 + WY_NB - 1) / WY_NB;
@@ -928,7 +928,7 @@ __global__ __launch_bounds__(WY_T) void wy_apply_kernel(const cf64* __restrict__
     const int j0 = b * WY_NB;
     const int m = min(WY_NB, p - 1 - j0);
     // T_b to LDS (one entry per thread), in flight while the dots are formed
-    for (int q = tid; q < WY_NB * WY_NB; q += WY_T) Ts[q] = Tw[(int64_t)b * WY_NB * WY_NB + q];
+    for (int q = tid; q < WY_NB * WY_NB; q += WY_RT) Ts[q] = Tw[(int64_t)b * WY_NB * WY_NB + q];
     // partial dots v_i^H x over this thread's rows (v_i is zero for r <= j0 + i)
     double pr[WY_NB], pi[WY_NB];
 #pragma unroll
@@ -941,11 +941,101 @@ __global__ __launch_bounds__(WY_T) void wy_apply_kernel(const cf64* __restrict__
       const cf64* vi = vs + (int64_t)(j0 + min(i, m - 1)) * p;
 #pragma unroll
       for (int e = 0; e < MAXE; ++e) {
-        const int r = tid + WY_T * e;
+        const int r = tid + WY_RT * e;
         const cf64 a = vi[min(r, p - 1)];
         const double f = (r < p) ? 1.0 : 0.0;
         pr[i] += f * (a.x * x[e].x + a.y * x[e].y);
         pi[i] += f * (a.x * x[e].y - a.y * x[e].x);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WY_NB; ++i) {
+      const double sr = wave_sum_d(pr[i]);
+      const double si = wave_sum_d(pi[i]);
+      if (lane == 0) {
+        red[wv][2 * i] = sr;
+        red[wv][2 * i + 1] = si;
+      }
+    }
+    __syncthreads();
+    if (tid < WY_NB) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < WY_RT / 64; ++q) {
+        sr += red[q][2 * tid];
+        si += red[q][2 * tid + 1];
+      }
+      w[tid] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (tid < m) {
+      cf64 v = czero<cf64>();
+#pragma unroll
+      for (int l = 0; l < WY_NB; ++l)
+        if (l >= tid && l < m) v = cadd(v, cmul(Ts[tid * WY_NB + l], w[l]));
+      w2[tid] = v;
+    }
+    __syncthreads();
+    // x -= V_b w2
+#pragma unroll
+    for (int i = 0; i < WY_NB; ++i) {
+      const cf64* vi = vs + (int64_t)(j0 + min(i, m - 1)) * p;
+      const cf64 c = (i < m) ? w2[i] : czero<cf64>();
+#pragma unroll
+      for (int e = 0; e < MAXE; ++e) {
+        const int r = tid + WY_RT * e;
+        const cf64 a = vi[min(r, p - 1)];  // rows past p are never stored
+        x[e] = csub(x[e], cmul(c, a));
+      }
+    }
+    __syncthreads();  // w, w2 and red are rewritten by the next block
+  }
+#pragma unroll
+  for (int e = 0; e < MAXE; ++e) {
+    const int r = tid + WY_RT * e;
+    if (r < p) U[(int64_t)r * k + col] = x[e];
+  }
+}
+
+// Larger sizes: one workgroup of WY_T threads per eigenvector column; the
+// column lives in LDS and thread t owns its rows t + WY_T e.  Blocks are
+// applied last to first, as above.  Each block is a chain of dots, one
+// reduction, T w and the update, bound by latency; the rows loop at run time
+// with the block's 16 reflector loads per row in flight, so the registers do
+// not grow with p (the register form spills to scratch beyond p = 1024; up to
+// there it is the faster one).
+constexpr int WY_T = 1024;
+__global__ __launch_bounds__(WY_T) void wy_apply_lds_kernel(const cf64* __restrict__ vs,
+                                                            const cf64* __restrict__ Tw, int p,
+                                                            const double* __restrict__ X, int k,
+                                                            cf64* __restrict__ U) {
+  extern __shared__ unsigned char wy_sm[];
+  cf64* xS = reinterpret_cast<cf64*>(wy_sm);  // the column, p entries
+  __shared__ double red[WY_T / 64][2 * WY_NB];
+  __shared__ cf64 w[WY_NB], w2[WY_NB];
+  __shared__ cf64 Ts[WY_NB * WY_NB];
+  const int col = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int r = tid; r < p; r += WY_T) xS[r] = make_double2(X[(int64_t)col * p + r], 0.0);
+  const int nblk = (p - 1 + WY_NB - 1) / WY_NB;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int j0 = b * WY_NB;
+    const int m = min(WY_NB, p - 1 - j0);
+    // T_b to LDS, in flight while the dots are formed
+    for (int q = tid; q < WY_NB * WY_NB; q += WY_T) Ts[q] = Tw[(int64_t)b * WY_NB * WY_NB + q];
+    // partial dots v_i^H x over this thread's rows.  The stored reflectors
+    // carry explicit zeros above their support; i >= m reads the block's last
+    // reflector (its dot is not used)
+    double pr[WY_NB], pi[WY_NB];
+#pragma unroll
+    for (int i = 0; i < WY_NB; ++i) { pr[i] = 0.0; pi[i] = 0.0; }
+    for (int r = tid; r < p; r += WY_T) {
+      const cf64 xr = xS[r];
+#pragma unroll
+      for (int i = 0; i < WY_NB; ++i) {
+        const cf64 a = vs[(int64_t)(j0 + min(i, m - 1)) * p + r];
+        pr[i] += a.x * xr.x + a.y * xr.y;
+        pi[i] += a.x * xr.y - a.y * xr.x;
       }
     }
 #pragma unroll
@@ -976,25 +1066,20 @@ __global__ __launch_bounds__(WY_T) void wy_apply_kernel(const cf64* __restrict__
       w2[tid] = v;
     }
     __syncthreads();
-    // x -= V_b w2
+    // x -= V_b w2 on this thread's rows
+    for (int r = tid; r < p; r += WY_T) {
+      cf64 xr = xS[r];
 #pragma unroll
-    for (int i = 0; i < WY_NB; ++i) {
-      const cf64* vi = vs + (int64_t)(j0 + min(i, m - 1)) * p;
-      const cf64 c = (i < m) ? w2[i] : czero<cf64>();
-#pragma unroll
-      for (int e = 0; e < MAXE; ++e) {
-        const int r = tid + WY_T * e;
-        const cf64 a = vi[min(r, p - 1)];  // rows past p are never stored
-        x[e] = csub(x[e], cmul(c, a));
+      for (int i = 0; i < WY_NB; ++i) {
+        const cf64 c = (i < m) ? w2[i] : czero<cf64>();
+        const cf64 a = vs[(int64_t)(j0 + min(i, m - 1)) * p + r];
+        xr = csub(xr, cmul(c, a));
       }
+      xS[r] = xr;
     }
-    __syncthreads();  // w, w2 and red are rewritten by the next block
+    __syncthreads();  // w, w2, Ts and red are rewritten by the next block
   }
-#pragma unroll
-  for (int e = 0; e < MAXE; ++e) {
-    const int r = tid + WY_T * e;
-    if (r < p) U[(int64_t)r * k + col] = x[e];
-  }
+  for (int r = tid; r < p; r += WY_T) U[(int64_t)r * k + col] = xS[r];
 }
 
 size_t backtransform_wy_workspace(int p) { return (size_t)((p - 1 + WY_NB - 1) / WY_NB) * WY_NB * WY_NB; }
@@ -1002,15 +1087,14 @@ size_t backtransform_wy_workspace(int p) { return (size_t)((p - 1 + WY_NB - 1) /
 hipError_t launch_backtransform_wy(const cf64* vs, const cf64* taus, int p, const double* X, int k, cf64* U,
                                    cf64* Tws, hipStream_t st) {
   if (p < 2 || k < 1) return hipErrorInvalidValue;
-  if (p > WY_T * 6) return launch_backtransform(vs, taus, p, X, k, U, st);
+  if (p > 3072) return launch_backtransform(vs, taus, p, X, k, U, st);
   const int nblk = (p - 1 + WY_NB - 1) / WY_NB;
   hipLaunchKernelGGL(wy_factor_kernel, dim3(nblk), dim3(256), 0, st, vs, taus, p, Tws);
-  if (p <= WY_T * 2)
-    hipLaunchKernelGGL((wy_apply_kernel<2>), dim3(k), dim3(WY_T), 0, st, vs, Tws, p, X, k, U);
-  else if (p <= WY_T * 4)
-    hipLaunchKernelGGL((wy_apply_kernel<4>), dim3(k), dim3(WY_T), 0, st, vs, Tws, p, X, k, U);
+  if (p <= WY_RT * 2)
+    hipLaunchKernelGGL((wy_apply_reg_kernel<2>), dim3(k), dim3(WY_RT), 0, st, vs, Tws, p, X, k, U);
   else
-    hipLaunchKernelGGL((wy_apply_kernel<6>), dim3(k), dim3(WY_T), 0, st, vs, Tws, p, X, k, U);
+    hipLaunchKernelGGL(wy_apply_lds_kernel, dim3(k), dim3(WY_T), (size_t)p * sizeof(cf64), st, vs, Tws, p, X, k,
+                       U);
   return hipGetLastError();
 }
 
