@@ -199,18 +199,24 @@ hipError_t launch_jacobi(const cf64* A, int64_t strideA, int n, int batch, doubl
 // is issued in one round at the start: the first TRI_UNROLL row elements of
 // each lane, and y_{j-1}, v_{j-1} and row j (staged in LDS).  Workgroup 0 also
 // publishes v_j, tau_j and the diagonal and off-diagonal entries.
-static constexpr int TRI_ROWS = 2;    // rows per workgroup (two wavefronts each)
 static constexpr int TRI_UNROLL = 8;  // row loads in flight per lane
 
-__global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* __restrict__ vs,
+// TRI_ROWS rows per workgroup, two wavefronts each.  Two rows up to p = 1024
+// (three workgroups fit a CU's LDS there); beyond, the three LDS vectors take
+// up to 150 KiB and one workgroup fills the LDS, so it carries eight rows
+// (sixteen wavefronts) to keep the CU busy.
+template <int TRI_ROWS>
+__global__ __launch_bounds__(128 * TRI_ROWS) void tridiag_col(cf64* __restrict__ A, cf64* __restrict__ vs,
                                                     cf64* __restrict__ taus, double* __restrict__ dg,
                                                     double* __restrict__ off, cf64* __restrict__ y, int p, int j) {
   extern __shared__ unsigned char sm_raw[];
   cf64* vS = reinterpret_cast<cf64*>(sm_raw);  // row j, then v_j
   cf64* wS = vS + p;                           // y_{j-1}, then w_{j-1}
   cf64* pS = wS + p;                           // v_{j-1}
-  __shared__ double red[2][4];
-  __shared__ double red2[4];
+  constexpr int TRI_WAVES = 2 * TRI_ROWS, TRI_THREADS = 64 * TRI_WAVES;
+  constexpr int TRI_FILL = TRI_THREADS >= 1024 ? 1 : 1024 / TRI_THREADS;  // vector loads grouped per thread
+  __shared__ double red[2][TRI_WAVES];
+  __shared__ double red2[TRI_WAVES];
   __shared__ double part[TRI_ROWS][2][2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cf64* vprev = (j > 0) ? vs + (int64_t)(j - 1) * p : nullptr;
@@ -238,16 +244,16 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   const cf64 yj = (j > 0) ? yprev[j] : czero<cf64>();
   const cf64 pj = (j > 0) ? vprev[j] : czero<cf64>();
   double re = 0.0, im = 0.0;
-  // each thread owns the entries q = j + tid (mod 256) of the LDS vectors up to
+  // each thread owns the entries q = j + tid (mod TRI_THREADS) of the LDS vectors up to
   // the reflector, so only the two reductions need workgroup barriers
-  // loads of four entries at a time are issued together (clamped addresses,
+  // loads of TRI_FILL entries at a time are issued together (clamped addresses,
   // masked use) so that they share one round trip; the first group is outside
   // any loop, so its loads are in flight together with the row loads above
   auto fill = [&](int q0) {
-    cf64 rr[4], yy[4], vv[4];
+    cf64 rr[TRI_FILL], yy[TRI_FILL], vv[TRI_FILL];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int qc = min(q0 + 256 * t, p - 1);
+    for (int t = 0; t < TRI_FILL; ++t) {
+      const int qc = min(q0 + TRI_THREADS * t, p - 1);
       rr[t] = rowj[qc];
       if (j > 0) {
         yy[t] = yprev[qc];
@@ -255,8 +261,8 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
       }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int q = q0 + 256 * t;
+    for (int t = 0; t < TRI_FILL; ++t) {
+      const int q = q0 + TRI_THREADS * t;
       if (q < p) {
         vS[q] = cconj(rr[t]);
         if (j > 0) {
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
     }
   };
   fill(j + tid);
-  for (int q0 = j + tid + 256 * 4; q0 < p; q0 += 256 * 4) fill(q0);
+  for (int q0 = j + tid + TRI_THREADS * TRI_FILL; q0 < p; q0 += TRI_THREADS * TRI_FILL) fill(q0);
   // ---- w_{j-1} = y_{j-1} - 1/2 tau_{j-1} (y_{j-1}^H v_{j-1}) v_{j-1}
   cf64 c = czero<cf64>();
   if (j > 0) {
@@ -277,10 +283,12 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
     im = wave_sum_d(im);
     if (lane == 0) { red[0][wave] = re; red[1][wave] = im; }
     __syncthreads();
-    const cf64 k = cmul(tprev, make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
-                                            red[1][0] + red[1][1] + red[1][2] + red[1][3]));
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int w = 0; w < TRI_WAVES; ++w) { sr += red[0][w]; si += red[1][w]; }
+    const cf64 k = cmul(tprev, make_double2(sr, si));
     c = make_double2(-0.5 * k.x, -0.5 * k.y);
-    for (int q = j + tid; q < p; q += 256) wS[q] = cadd(wS[q], cmul(c, pS[q]));
+    for (int q = j + tid; q < p; q += TRI_THREADS) wS[q] = cadd(wS[q], cmul(c, pS[q]));
   }
   // ---- column j (rows >= j) with the pending update; reflector
   const cf64 wj = (j > 0) ? cadd(yj, cmul(c, pj)) : czero<cf64>();
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
     return;
   }
   double nrm = 0.0;
-  for (int q = j + tid; q < p; q += 256) {
+  for (int q = j + tid; q < p; q += TRI_THREADS) {
     if (q == j) continue;
     cf64 x = vS[q];
     if (j > 0) x = csub(x, cadd(cmulc(pS[q], wj), cmulc(wS[q], vj)));
@@ -306,7 +314,9 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   cf64 tau, scale;
   double offj;
   {
-    const double xn2 = red2[0] + red2[1] + red2[2] + red2[3];
+    double xn2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < TRI_WAVES; ++w) xn2 += red2[w];
     const cf64 alpha = vS[j + 1];
     double beta;
     if (xn2 == 0.0 && alpha.y == 0.0) {
@@ -392,7 +402,7 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
   // workgroup 0 stores the reflector, tau, and the tridiagonal entries j
   if (blockIdx.x == 0) {
     cf64* vout = vs + (int64_t)j * p;
-    for (int q = tid; q < p; q += 256) {
+    for (int q = tid; q < p; q += TRI_THREADS) {
       cf64 v = czero<cf64>();
       if (q == j + 1) v = make_double2(1.0, 0.0);
       else if (q > j + 1) v = cmul(vS[q], scale);
@@ -409,13 +419,18 @@ __global__ __launch_bounds__(256) void tridiag_col(cf64* __restrict__ A, cf64* _
 hipError_t launch_tridiag(TridiagWork& tw, int p, hipStream_t st) {
   const size_t shm = (size_t)3 * p * sizeof(cf64);
   if (shm > 150 * 1024) return hipErrorInvalidValue;
+  const int R = p <= 1024 ? 2 : 8;  // rows per workgroup
   for (int j = 0; j < p; ++j) {
     const int rows = p - j - 1;
-    // 8 XCDs x enough slots of TRI_ROWS rows for the largest residue class
+    // 8 XCDs x enough slots of R rows for the largest residue class
     const int per_xcd = (rows + 7) / 8;
-    const int slots = std::max(1, (per_xcd + TRI_ROWS - 1) / TRI_ROWS);
-    hipLaunchKernelGGL(tridiag_col, dim3(8 * slots), dim3(256), shm, st, tw.A,
-                       tw.vs, tw.taus, tw.dg, tw.off, tw.y, p, j);
+    const int slots = std::max(1, (per_xcd + R - 1) / R);
+    if (R == 2)
+      hipLaunchKernelGGL(tridiag_col<2>, dim3(8 * slots), dim3(256), shm, st, tw.A, tw.vs, tw.taus, tw.dg, tw.off,
+                         tw.y, p, j);
+    else
+      hipLaunchKernelGGL(tridiag_col<8>, dim3(8 * slots), dim3(1024), shm, st, tw.A, tw.vs, tw.taus, tw.dg, tw.off,
+                         tw.y, p, j);
   }
   return hipGetLastError();
 }
