@@ -286,6 +286,9 @@ hipError_t launch_opapply(int prec, const OpJob* d_jobs, int njobs, const OpTerm
     if (ds <= 8) {
       if (f64) launch_opapply_reg<cf64, 8>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
       else launch_opapply_reg<cf32, 8>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
+    } else if (ds <= 12) {  // d = 10, 12: fewer registers than the 16-state form, more waves
+      if (f64) launch_opapply_reg<cf64, 12>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
+      else launch_opapply_reg<cf32, 12>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
     } else {
       if (f64) launch_opapply_reg<cf64, 16>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
       else launch_opapply_reg<cf32, 16>(d_jobs, njobs, d_terms, chi_l, ds, dt, chi_r, st);
