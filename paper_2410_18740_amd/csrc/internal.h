@@ -203,9 +203,6 @@ struct WindowOp {
              const std::vector<const void*>& envL, const std::vector<const void*>& envRt, bool raw_leg0,
              const std::string& tag);
   void apply(const cf64* x, cf64* y);
-  // the matvec up to its split-K partials (nsplit parts of n in the storage
-  // precision, not yet summed); x_ready: xin already holds x in that precision
-  void run(const cf64* x, bool x_ready);
   void apply_left(const cf64* x);  // only the conversion of x and the left contraction into ybuf
 };
 

@@ -291,7 +291,7 @@ void WindowOp::apply_left(const cf64* x) {
   HIPCHK(launch_cgemm(prec, 0, 0, d_jobL, njobL, d_segL, chi_l, ds * dt * chi_r, 0, ctx->stream));
 }
 
-void WindowOp::run(const cf64* x, bool x_ready) {
+void WindowOp::apply(const cf64* x, cf64* y) {
   hipStream_t st = ctx->stream;
   const int sprec = (prec == PREC_FP64) ? PREC_FP64 : PREC_FP32;
   tn_ctx::ProfSlot* ps = nullptr;
@@ -301,16 +301,17 @@ void WindowOp::run(const cf64* x, bool x_ready) {
   }
   hipEvent_t* ev = ps ? ps->e : nullptr;
   if (ev) HIPCHK(hipEventRecord(ev[0], st));
-  if (!x_ready) HIPCHK(launch_convert(sprec, xin, PREC_FP64, x, (int64_t)n, st));
+  HIPCHK(launch_convert(sprec, xin, PREC_FP64, x, (int64_t)n, st));
   if (ev) HIPCHK(hipEventRecord(ev[1], st));
   HIPCHK(launch_cgemm(prec, 0, 0, d_jobL, njobL, d_segL, chi_l, ds * dt * chi_r, 0, st));
   if (ev) HIPCHK(hipEventRecord(ev[2], st));
   HIPCHK(launch_opapply(sprec, d_opjob, nopjob, d_opterm, chi_l, ds, dt, chi_r, st));
   if (ev) HIPCHK(hipEventRecord(ev[3], st));
   HIPCHK(launch_cgemm(prec, 0, 0, d_jobR, njobR, d_segR, chi_l * ds * dt, chi_r, 0, st));
+  if (ev) HIPCHK(hipEventRecord(ev[4], st));
+  HIPCHK(launch_reduce_partials(y, sprec, partials, nsplit, (int64_t)n, st));
   if (ps) {
-    HIPCHK(hipEventRecord(ev[4], st));
-    HIPCHK(hipEventRecord(ev[5], st));  // moved past the reduction when apply() does it here
+    HIPCHK(hipEventRecord(ev[5], st));
     ps->fl[0] = fl_L;
     ps->fl[1] = fl_R;
     ps->fl[2] = fl_all;
@@ -318,16 +319,6 @@ void WindowOp::run(const cf64* x, bool x_ready) {
     ps->by[1] = by_R;
     ps->pending = true;
   }
-}
-
-void WindowOp::apply(const cf64* x, cf64* y) {
-  hipStream_t st = ctx->stream;
-  const int sprec = (prec == PREC_FP64) ? PREC_FP64 : PREC_FP32;
-  tn_ctx::ProfSlot* ps = ctx->prof ? &ctx->pslot[(ctx->pseq) % tn_ctx::PROF_RING] : nullptr;
-  run(x, false);
-  HIPCHK(launch_reduce_partials(y, sprec, partials, nsplit, (int64_t)n, st));
-  // the slot run() just filled: its last event closes the reduction
-  if (ps) HIPCHK(hipEventRecord(ps->e[5], st));
 }
 
 // ------------------------------------------------------------------ flop formulas
