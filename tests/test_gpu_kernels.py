@@ -281,10 +281,11 @@ def test_truncate_full_size(ctx):
     assert np.abs(left.conj().T @ left - np.eye(128)).max() < 1e-12
 
 
-@pytest.mark.parametrize("m,n,direction", [(1300, 1100, 1), (300, 1300, -1), (2560, 300, 1)])
+@pytest.mark.parametrize("m,n,direction", [(1300, 1100, 1), (300, 1300, -1), (2560, 300, 1), (3100, 300, 1)])
 def test_truncate_gram_beyond_1024(ctx, m, n, direction):
-    """Gram sizes 1300 and 2560 (the 48-mode middle step): Householder rows
-    longer than one 1024-entry chunk, and the wider back-transform forms."""
+    """Gram sizes 1300, 2560 (the 48-mode middle step) and 3100: Householder
+    rows longer than one 1024-entry chunk with eight rows per workgroup, the
+    LDS form of the back-transform, and beyond 3072 its per-reflector form."""
     import paper_2410_18740_amd as P
     rng = np.random.default_rng(m + 7 * n)
     th = _spectrum_matrix(m, n, rng, 0.97)
